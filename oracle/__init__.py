@@ -1,0 +1,299 @@
+"""FP64 CPU oracle of snakuscule evolution -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this package. The product path (the HIP library and its Python binding) never imports,
+links or calls it, and shares no code with it: the C source ``snk_oracle.c`` carries its own
+Philox, Gaussian pre-pass, interpolation, weight function, estimator, update and selection.
+
+This module is argument marshalling around ``libsnk_oracle.so`` (built with plain gcc, OpenMP
+over contours, no fast-math).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "snk_oracle.c")
+_LIB = os.path.join(_HERE, "libsnk_oracle.so")
+
+TRACE_W = 32
+ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CLAMPED = 0, 1, 2, 3, 4, 0x10
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                               "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("spacing", C.c_double * 3), ("sigma_pre", C.c_double),
+                ("i_offset", C.c_double), ("i_scale", C.c_double), ("dR", C.c_double),
+                ("eps0", C.c_double), ("r_min", C.c_double), ("r_max", C.c_double),
+                ("r_init", C.c_double), ("n_dirs", C.c_int32), ("n_rays", C.c_int32),
+                ("n_radial", C.c_int32), ("seed", C.c_uint64), ("conv_tol", C.c_double),
+                ("conv_window", C.c_int32), ("e0", C.c_double), ("flags", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.POINTER
+        d, i64, i32, u32 = C.c_double, C.c_int64, C.c_int32, C.c_uint32
+        vp = C.c_void_p
+        L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        L.orc_uniform.argtypes = [u32]; L.orc_uniform.restype = d
+        L.orc_r_geom_min.argtypes = [C.c_int, d]; L.orc_r_geom_min.restype = d
+        L.orc_weight.argtypes = [C.c_int, d, d, d, P(d)]
+        L.orc_weight_many.argtypes = [C.c_int, vp, i64, d, d, vp]
+        L.orc_prepass.argtypes = [vp, C.c_int, i64, i64, i64, P(_Params), vp]
+        L.orc_interp.argtypes = [vp, i64, i64, i64, C.c_int, d, d, d]; L.orc_interp.restype = d
+        L.orc_rotation.argtypes = [P(_Params), u32, u32, P(d)]
+        L.orc_initial_radius.argtypes = [P(_Params), d]; L.orc_initial_radius.restype = d
+        L.orc_evolve.argtypes = [vp, i64, i64, i64, P(_Params), vp, i64, vp, vp, vp, vp, vp, vp, vp,
+                                 i32, vp, P(i64)]
+        L.orc_evolve.restype = i64
+        L.orc_mc_terms.argtypes = [vp, i64, i64, i64, P(_Params), vp, P(d), d, u32, u32, P(d), vp, vp]
+        L.orc_energy_fixed.argtypes = [C.c_int, d, vp, vp, i64, d, P(d), d]
+        L.orc_energy_fixed.restype = d
+        L.orc_energy_vox.argtypes = [vp, i64, i64, i64, P(_Params), i64, vp, vp, vp, vp]
+        L.orc_cull.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, vp]; L.orc_cull.restype = i64
+        L.orc_cull_ambiguity.argtypes = [P(_Params), i64, vp, vp, vp, d, d, vp]
+        L.orc_cull_ambiguity.restype = i64
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def params_struct(p, r_init: float | None = None) -> _Params:
+    s = _Params()
+    s.dim = int(p.dim)
+    for i in range(3):
+        s.spacing[i] = float(p.spacing[i])
+    s.sigma_pre, s.i_offset, s.i_scale = float(p.sigma_pre), float(p.i_offset), float(p.i_scale)
+    s.dR, s.eps0 = float(p.dR), float(p.eps0)
+    s.r_min, s.r_max = float(p.r_min), float(p.r_max)
+    s.r_init = float(r_init if r_init is not None else getattr(p, "r_init", 0.0))
+    s.n_dirs, s.n_rays, s.n_radial = int(p.n_dirs), int(p.n_rays), int(p.n_radial)
+    s.seed = int(p.seed) & 0xFFFFFFFFFFFFFFFF
+    s.conv_tol, s.conv_window, s.e0, s.flags = float(p.conv_tol), int(p.conv_window), float(p.e0), int(p.flags)
+    return s
+
+
+_DT = {np.dtype(np.uint8): 0, np.dtype(np.uint16): 1, np.dtype(np.float32): 2}
+
+
+# ---------------------------------------------------------------------------------------------
+# elementary pieces
+# ---------------------------------------------------------------------------------------------
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def uniform(x: int) -> float:
+    return lib().orc_uniform(int(x) & 0xFFFFFFFF)
+
+
+def r_geom_min(dim: int, dR: float) -> float:
+    return lib().orc_r_geom_min(int(dim), float(dR))
+
+
+def weight(dim: int, r: float, R: float, dR: float):
+    o = (C.c_double * 3)()
+    lib().orc_weight(int(dim), float(r), float(R), float(dR), o)
+    return o[0], o[1], o[2]
+
+
+def weight_vec(dim: int, r, R: float, dR: float) -> np.ndarray:
+    """S, dS/dr, dS/dR at every radius in r (array of shape r.shape + (3,))."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.empty(r.shape + (3,))
+    lib().orc_weight_many(int(dim), _ptr(r), r.size, float(R), float(dR), _ptr(out))
+    return out
+
+
+def rotation(p, n: int, cid: int) -> np.ndarray:
+    q = (C.c_double * 9)()
+    ps = params_struct(p)
+    lib().orc_rotation(C.byref(ps), int(n), int(cid), q)
+    return np.array(q[:]).reshape(3, 3)
+
+
+def prepass(raw: np.ndarray, p) -> np.ndarray:
+    raw = np.ascontiguousarray(raw)
+    nz, ny, nx = raw.shape
+    J = np.empty(raw.shape, dtype=np.float64)
+    ps = params_struct(p)
+    lib().orc_prepass(_ptr(raw), _DT[raw.dtype], nx, ny, nz, C.byref(ps), _ptr(J))
+    return J
+
+
+def interp(J: np.ndarray, dim: int, v) -> float:
+    nz, ny, nx = J.shape
+    return lib().orc_interp(_ptr(J), nx, ny, nz, int(dim), float(v[0]), float(v[1]),
+                            float(v[2]) if len(v) > 2 else 0.0)
+
+
+def initial_radius(p, r0: float) -> float:
+    ps = params_struct(p)
+    return lib().orc_initial_radius(C.byref(ps), float(r0))
+
+
+def mc_terms(J, p, dirs, c, R, n, cid, want_samples=False):
+    """Monte-Carlo terms of one contour at state (c, R) and iteration n (no update)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    ps = params_struct(p)
+    out = (C.c_double * 17)()
+    cc = (C.c_double * 3)(*[float(v) for v in list(c) + [0.0] * (3 - len(c))])
+    N = p.n_rays * p.n_radial
+    pts = np.zeros((N, 3)) if want_samples else None
+    vals = np.zeros(N) if want_samples else None
+    lib().orc_mc_terms(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), cc, float(R), int(n), int(cid), out,
+                       _ptr(pts) if want_samples else None, _ptr(vals) if want_samples else None)
+    o = np.array(out[:])
+    res = {"A": o[0], "B_R": o[1], "B_c": o[2:5], "scale": o[5], "dEdp": o[6:9], "dEdq": o[9:12],
+           "E": o[12], "g_R": o[13], "g_c": o[14:17]}
+    if want_samples:
+        res["pts"], res["vals"] = pts, vals
+    return res
+
+
+def energy_fixed(dim, dR, pts, vals, scale, c, R) -> float:
+    cc = (C.c_double * 3)(*[float(v) for v in list(c) + [0.0] * (3 - len(c))])
+    return lib().orc_energy_fixed(int(dim), float(dR), _ptr(np.ascontiguousarray(pts)),
+                                  _ptr(np.ascontiguousarray(vals)), len(vals), float(scale), cc, float(R))
+
+
+# ---------------------------------------------------------------------------------------------
+# whole-run driver
+# ---------------------------------------------------------------------------------------------
+
+@dataclass
+class State:
+    c: np.ndarray          # (n, 3) float64 physical
+    R: np.ndarray          # (n,) float64
+    iters: np.ndarray      # (n,) int32
+    status: np.ndarray     # (n,) uint8
+    streak: np.ndarray     # (n,) uint8
+    e_mc: np.ndarray       # (n,) float64
+    ids: np.ndarray        # (n,) uint32
+
+    def copy(self) -> "State":
+        return State(*(np.array(getattr(self, f)) for f in
+                       ("c", "R", "iters", "status", "streak", "e_mc", "ids")))
+
+
+def init_state(p, seeds, r0=None, ids=None) -> State:
+    seeds = np.asarray(seeds, dtype=np.float64)
+    n = len(seeds)
+    c = np.zeros((n, 3))
+    c[:, : seeds.shape[1]] = seeds
+    if p.dim == 2:
+        c[:, 2] = 0.0
+    if r0 is None:
+        r0 = np.full(n, float(p.r_init))
+    R = np.array([initial_radius(p, float(v)) for v in np.broadcast_to(r0, (n,))])
+    ids = np.arange(n, dtype=np.uint32) if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
+    return State(c, R, np.zeros(n, np.int32), np.zeros(n, np.uint8), np.zeros(n, np.uint8),
+                 np.zeros(n), ids)
+
+
+def evolve(J, p, dirs, st: State, n_iter: int, trace: bool = False):
+    """Run up to n_iter further iterations on every ACTIVE contour (in place). Returns
+    (trace array or None, number of contour-iterations run). Raises if the p,q and c,R forms of
+    the gradient ever disagree."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    ps = params_struct(p)
+    n = len(st.R)
+    tr = np.zeros((n, TRACE_W)) if trace else None
+    done = C.c_int64(0)
+    mism = lib().orc_evolve(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), n, _ptr(st.ids), _ptr(st.c),
+                            _ptr(st.R), _ptr(st.iters), _ptr(st.status), _ptr(st.streak), _ptr(st.e_mc),
+                            int(n_iter), _ptr(tr) if trace else None, C.byref(done))
+    if mism:
+        raise AssertionError(f"p,q and c,R gradient forms disagree on {mism} contour-iterations")
+    return tr, int(done.value)
+
+
+def finalize_status(st: State) -> None:
+    """Contours still ACTIVE when evolution ends stopped on the iteration limit."""
+    base = st.status & 0x0F
+    st.status[base == ACTIVE] = (st.status[base == ACTIVE] & CLAMPED) | MAXITER
+
+
+def energy_vox(J, p, c, R):
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    n = len(R)
+    e = np.zeros(n)
+    ea = np.zeros(n)
+    ps = params_struct(p)
+    lib().orc_energy_vox(_ptr(J), nx, ny, nz, C.byref(ps), n, _ptr(c), _ptr(R), _ptr(e), _ptr(ea))
+    return e, ea
+
+
+def cull(p, c, R, e_vox, status, ids):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    e_vox = np.ascontiguousarray(e_vox, dtype=np.float64)
+    status = np.ascontiguousarray(status, dtype=np.uint8)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    keep = np.zeros(len(R), np.uint8)
+    ps = params_struct(p)
+    lib().orc_cull(C.byref(ps), len(R), _ptr(c), _ptr(R), _ptr(e_vox), _ptr(status), _ptr(ids), _ptr(keep))
+    return keep
+
+
+def cull_ambiguity(p, c, R, e_vox, rel_e=1e-4, tol_d=1e-3):
+    amb = np.zeros(len(R), np.uint8)
+    ps = params_struct(p)
+    lib().orc_cull_ambiguity(C.byref(ps), len(R), _ptr(np.ascontiguousarray(c, dtype=np.float64)),
+                             _ptr(np.ascontiguousarray(R, dtype=np.float64)),
+                             _ptr(np.ascontiguousarray(e_vox, dtype=np.float64)), float(rel_e), float(tol_d),
+                             _ptr(amb))
+    return amb
+
+
+def run(raw, p, dirs, seeds, n_iter, r0=None, ids=None):
+    """Whole path: pre-pass, init, evolve n_iter, stop status, exact energy, selection."""
+    J = prepass(raw, p)
+    st = init_state(p, seeds, r0, ids)
+    _, done = evolve(J, p, dirs, st, n_iter)
+    finalize_status(st)
+    e_vox, e_abs = energy_vox(J, p, st.c, st.R)
+    keep = cull(p, st.c, st.R, e_vox, st.status, st.ids)
+    return {"J": J, "state": st, "e_vox": e_vox, "e_abs": e_abs, "keep": keep, "evolved": done}
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())

@@ -1,0 +1,713 @@
+/*
+ * snk_oracle.c -- plain, slow, FP64 CPU oracle of 3D (and 2D) snakuscule evolution.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may link, load or call this file: it is
+ * used by the test suite, by the smoke check and by the CPU-baseline leg of the benchmark. It
+ * shares no source with the HIP library (its own Philox, Gaussian, interpolation, weight
+ * function, estimator, update and selection); only the synthetic inputs are common.
+ *
+ * What it computes, in the paper's order (arXiv 1804.06304, "Three-Dimensional GPU-Accelerated
+ * Active Contours for Automated Localization of Cells in Large Images"):
+ *   - pre-pass: affine intensity map, then a normalised separable Gaussian low-pass
+ *     (Sec. II-E, the low-pass filter that makes Monte-Carlo integration well behaved;
+ *     Results: images resampled to isotropic pixels -- here the spacing h enters the sampler);
+ *   - the discrete energy E(p,q) = ||p - q||^-d * sum_k S(|k - c|) I(k) of Eq. (5)/(6), with the
+ *     four-region weight S of Sec. II-B (inner core -1, ramp of width dr = rho*dR, shell +1,
+ *     outer ramp of width dR) and rho = 2^(-1/d) (Sec. II-A for d = 2, Sec. II-B for d = 3);
+ *   - its gradient in the identifier points p, q (Eqs. (7)-(11)) and the descent step
+ *     p <- p - eps dE/dp, q <- q - eps dE/dq with eps = eps0/sqrt(n) (Eqs. (12)-(15)); the same
+ *     gradient is also formed in (c, R) coordinates and the two are checked against each other;
+ *   - the sums are Monte-Carlo estimates from points uniform in the ball of radius R + dR/2
+ *     (Sec. II-E), drawn as randomly rotated table directions in antithetic pairs with
+ *     r^d-stratified radial points (one reading of the unspecified sampling pattern);
+ *   - stopping on maximum iterations or convergence, overlap competition with the lower energy
+ *     surviving (||c' - c''|| < max(R', R'')*rho), and the energy threshold E0 (Results).
+ *
+ * Parity pins (see the tests): Philox known-answer vectors; the weight function's zero-mean
+ * identity (Sec. II-B); the ideal-blob energy of Eq. (3) and the alpha = d symmetric-slope
+ * normalisation of Eq. (4); finite differences of the same-sample estimator against Eqs. (7)-(11);
+ * the p,q <-> c,R identity; Monte-Carlo unbiasedness against quadrature; the pre-pass against a
+ * library Gaussian filter; exact energy against a brute-force sum; greedy selection on
+ * hand-built cases. End-to-end trajectories are "parity unpinned" beyond these pieces.
+ *
+ * Build: gcc -O2 -std=c11 -fopenmp -fPIC -shared snk_oracle.c -o libsnk_oracle.so -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_ACTIVE 0
+#define ORC_CONVERGED 1
+#define ORC_MAXITER 2
+#define ORC_OUT 3
+#define ORC_NONFINITE 4
+#define ORC_CLAMPED 0x10
+
+#define ORC_TRACE_W 32
+#define ORC_KINK_REL 4e-6
+
+static const double ORC_PI = 3.14159265358979323846;
+
+typedef struct {
+    int32_t dim;
+    double spacing[3];
+    double sigma_pre;
+    double i_offset, i_scale;
+    double dR;
+    double eps0;
+    double r_min, r_max, r_init;
+    int32_t n_dirs, n_rays, n_radial;
+    uint64_t seed;
+    double conv_tol;
+    int32_t conv_window;
+    double e0;
+    int32_t flags;
+} orc_params;
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3",   */
+/* SC'11): ten rounds of two 32x32->64 multiplies with a Weyl-sequence key schedule.           */
+/* ------------------------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform on (0,1): (2*(x >> 9) + 1) * 2^-24, exactly representable in FP32 and FP64. */
+double orc_uniform(uint32_t x)
+{
+    return (2.0 * (double)(x >> 9) + 1.0) * 5.9604644775390625e-08; /* 2^-24 */
+}
+
+static void philox_at(const orc_params *p, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                      uint32_t out[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)(p->seed & 0xffffffffu), (uint32_t)(p->seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* geometry constants                                                                         */
+/* ------------------------------------------------------------------------------------------ */
+
+/* rho = 2^(-1/d): inner and outer regions of equal measure (Sec. II-A, Sec. II-B). */
+static double rho_of(int dim) { return dim == 3 ? pow(2.0, -1.0 / 3.0) : pow(2.0, -0.5); }
+
+/* volume of the unit d-ball */
+static double ball_measure(int dim) { return dim == 3 ? 4.0 * ORC_PI / 3.0 : ORC_PI; }
+
+/* Smallest R for which the four regions of S do not overlap: rho R + dr/2 <= R - dR/2. */
+double orc_r_geom_min(int dim, double dR)
+{
+    double rho = rho_of(dim);
+    return dR * (1.0 + rho) / (2.0 * (1.0 - rho));
+}
+
+static double r_low(const orc_params *p)
+{
+    double g = orc_r_geom_min(p->dim, p->dR);
+    return p->r_min > g ? p->r_min : g;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Weight function S(r; R) of Eq. (5): four regions -- dynamic inner core (-1), fixed-width     */
+/* ramp dr = rho*dR about rho*R, dynamic shell (+1), fixed-width outer ramp dR about R down to  */
+/* zero at R + dR/2. Out: S, dS/dr, dS/dR. Half-open intervals: at a kink the right interval.  */
+/* ------------------------------------------------------------------------------------------ */
+void orc_weight(int dim, double r, double R, double dR, double out[3])
+{
+    double rho = rho_of(dim);
+    double a = rho * R;
+    double dr = rho * dR;
+    double S, Sr, SR;
+    if (r < a - 0.5 * dr) {
+        S = -1.0; Sr = 0.0; SR = 0.0;
+    } else if (r < a + 0.5 * dr) {
+        S = 2.0 * (r - a) / dr; Sr = 2.0 / dr; SR = -2.0 * rho / dr;
+    } else if (r < R - 0.5 * dR) {
+        S = 1.0; Sr = 0.0; SR = 0.0;
+    } else if (r < R + 0.5 * dR) {
+        S = 0.5 - (r - R) / dR; Sr = -1.0 / dR; SR = 1.0 / dR;
+    } else {
+        S = 0.0; Sr = 0.0; SR = 0.0;
+    }
+    out[0] = S; out[1] = Sr; out[2] = SR;
+}
+
+/* S, dS/dr, dS/dR at n radii (out: n x 3). */
+void orc_weight_many(int dim, const double *r, int64_t n, double R, double dR, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) orc_weight(dim, r[i], R, dR, &out[i * 3]);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* pre-pass: J = (raw - i_offset) * i_scale, then a normalised separable Gaussian per axis with */
+/* sigma_a = sigma_pre / h_a and taps |k| <= ceil(3 sigma_a), clamp-to-edge (Sec. II-E).        */
+/* dtype: 0 = uint8, 1 = uint16, 2 = float32.                                                  */
+/* ------------------------------------------------------------------------------------------ */
+static double raw_at(const void *raw, int dtype, int64_t i)
+{
+    if (dtype == 0) return (double)((const uint8_t *)raw)[i];
+    if (dtype == 1) return (double)((const uint16_t *)raw)[i];
+    return (double)((const float *)raw)[i];
+}
+
+static int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static void gauss_axis(double *J, int64_t nx, int64_t ny, int64_t nz, int axis, double sigma)
+{
+    if (!(sigma > 0.0)) return;
+    int64_t n_axis = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    if (n_axis < 2) return;
+    int rad = (int)ceil(3.0 * sigma);
+    double *g = (double *)malloc(sizeof(double) * (2 * rad + 1));
+    double sum = 0.0;
+    for (int k = -rad; k <= rad; ++k) {
+        g[k + rad] = exp(-(double)k * (double)k / (2.0 * sigma * sigma));
+        sum += g[k + rad];
+    }
+    for (int k = 0; k < 2 * rad + 1; ++k) g[k] /= sum;
+    int64_t stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+    int64_t n_lines = nx * ny * nz / n_axis;
+#pragma omp parallel
+    {
+        double *line = (double *)malloc(sizeof(double) * n_axis);
+#pragma omp for schedule(static)
+        for (int64_t li = 0; li < n_lines; ++li) {
+            int64_t base;
+            if (axis == 0) base = li * nx;
+            else if (axis == 1) base = (li / nx) * nx * ny + (li % nx);
+            else base = li;
+            for (int64_t t = 0; t < n_axis; ++t) line[t] = J[base + t * stride];
+            for (int64_t t = 0; t < n_axis; ++t) {
+                double acc = 0.0;
+                for (int k = -rad; k <= rad; ++k) acc += g[k + rad] * line[clampi(t + k, 0, n_axis - 1)];
+                J[base + t * stride] = acc;
+            }
+        }
+        free(line);
+    }
+    free(g);
+}
+
+int orc_prepass(const void *raw, int dtype, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                double *J)
+{
+    int64_t n = nx * ny * nz;
+    for (int64_t i = 0; i < n; ++i) J[i] = (raw_at(raw, dtype, i) - p->i_offset) * p->i_scale;
+    if (p->sigma_pre > 0.0) {
+        gauss_axis(J, nx, ny, nz, 0, p->sigma_pre / p->spacing[0]);
+        gauss_axis(J, nx, ny, nz, 1, p->sigma_pre / p->spacing[1]);
+        if (p->dim == 3) gauss_axis(J, nx, ny, nz, 2, p->sigma_pre / p->spacing[2]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Image value at a non-integer voxel coordinate v: trilinear (bilinear in 2D) interpolation    */
+/* with voxel centres at integer coordinates and the coordinate clamped to [0, n_a - 1].       */
+/* ------------------------------------------------------------------------------------------ */
+static void split_coord(double v, int64_t n, int64_t *i0, int64_t *i1, double *f)
+{
+    if (n == 1) { *i0 = 0; *i1 = 0; *f = 0.0; return; }
+    if (v < 0.0) v = 0.0;
+    if (v > (double)(n - 1)) v = (double)(n - 1);
+    double fl = floor(v);
+    int64_t i = (int64_t)fl;
+    if (i > n - 2) i = n - 2;
+    *i0 = i; *i1 = i + 1; *f = v - (double)i;
+}
+
+double orc_interp(const double *J, int64_t nx, int64_t ny, int64_t nz, int dim, double vx, double vy,
+                  double vz)
+{
+    int64_t x0, x1, y0, y1, z0, z1;
+    double fx, fy, fz;
+    split_coord(vx, nx, &x0, &x1, &fx);
+    split_coord(vy, ny, &y0, &y1, &fy);
+    if (dim == 2) { z0 = z1 = 0; fz = 0.0; }
+    else split_coord(vz, nz, &z0, &z1, &fz);
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? fx : 1.0 - fx) * (dy ? fy : 1.0 - fy) * (dz ? fz : 1.0 - fz);
+                if (w == 0.0) continue;
+                int64_t xi = dx ? x1 : x0, yi = dy ? y1 : y0, zi = dz ? z1 : z0;
+                acc += w * J[(zi * ny + yi) * nx + xi];
+            }
+    return acc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Random rotation of the direction table for (contour id, iteration n): Philox with counter    */
+/* (0, n, id, 0). 3D: Shoemake's uniform unit quaternion (Graphics Gems III, 1992) from three   */
+/* uniforms; 2D: angle 2*pi*U. Q is row-major and acts on column vectors. flags bit 0: Q = I.   */
+/* ------------------------------------------------------------------------------------------ */
+void orc_rotation(const orc_params *p, uint32_t n, uint32_t id, double Q[9])
+{
+    for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    if (p->flags & 1) return;
+    uint32_t x[4];
+    philox_at(p, 0u, n, id, 0u, x);
+    if (p->dim == 2) {
+        double th = 2.0 * ORC_PI * orc_uniform(x[0]);
+        Q[0] = cos(th); Q[1] = -sin(th);
+        Q[3] = sin(th); Q[4] = cos(th);
+        return;
+    }
+    double u1 = orc_uniform(x[0]), u2 = orc_uniform(x[1]), u3 = orc_uniform(x[2]);
+    double a = sqrt(1.0 - u1), b = sqrt(u1);
+    double t1 = 2.0 * ORC_PI * u2, t2 = 2.0 * ORC_PI * u3;
+    double qx = a * sin(t1), qy = a * cos(t1), qz = b * sin(t2), qw = b * cos(t2);
+    Q[0] = 1.0 - 2.0 * (qy * qy + qz * qz); Q[1] = 2.0 * (qx * qy - qw * qz); Q[2] = 2.0 * (qx * qz + qw * qy);
+    Q[3] = 2.0 * (qx * qy + qw * qz); Q[4] = 1.0 - 2.0 * (qx * qx + qz * qz); Q[5] = 2.0 * (qy * qz - qw * qx);
+    Q[6] = 2.0 * (qx * qz - qw * qy); Q[7] = 2.0 * (qy * qz + qw * qx); Q[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* The sample set of one contour-iteration (Sec. II-E): M rays in M/2 antithetic pairs; pair m  */
+/* draws Philox(m, n, id, 1) -> table index k = floor(x0 * D / 2^32) and jitter xi = U(x1); ray  */
+/* direction u = Q T[k] (and -u for its partner); radial point l sits at                        */
+/* s = s_max * ((l + xi) / L)^(1/d), s_max = R + dR/2. Every point is marginally uniform in the  */
+/* ball, so (V/N) * sum f estimates the integral of f over it.                                  */
+/* Callback receives (position offset s*u', direction u', radius s).                            */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    const double *J;
+    int64_t nx, ny, nz;
+    const orc_params *p;
+    const double *dirs;
+} orc_vol;
+
+typedef struct {
+    /* c,R-form sums (unscaled) */
+    double A, BR, Bc[3];
+    double Aabs, BRabs, Bcabs[3];
+    /* p,q-form sums: sum dS/dp_a * I and sum dS/dq_a * I */
+    double Sp[3], Sq[3];
+    /* kink slack (unscaled) */
+    double slBR, slBc[3];
+    int n_kink;
+    int n_samples;
+} orc_sums;
+
+static void accumulate_samples(const orc_vol *vol, const double c[3], double R, uint32_t n, uint32_t id,
+                               orc_sums *sm, double *pts, double *vals)
+{
+    const orc_params *p = vol->p;
+    int dim = p->dim;
+    double Q[9];
+    orc_rotation(p, n, id, Q);
+    double smax = R + 0.5 * p->dR;
+    double rho = rho_of(dim);
+    double a = rho * R, dr = rho * p->dR;
+    double kinks[4] = {a - 0.5 * dr, a + 0.5 * dr, R - 0.5 * p->dR, R + 0.5 * p->dR};
+    int M = p->n_rays, L = p->n_radial;
+    memset(sm, 0, sizeof(*sm));
+    int idx = 0;
+    for (int m = 0; m < M / 2; ++m) {
+        uint32_t x[4];
+        philox_at(p, (uint32_t)m, n, id, 1u, x);
+        uint32_t k = (uint32_t)(((uint64_t)x[0] * (uint64_t)(uint32_t)p->n_dirs) >> 32);
+        double xi = orc_uniform(x[1]);
+        double t[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < dim; ++i) t[i] = vol->dirs[(int64_t)k * dim + i];
+        for (int i = 0; i < dim; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < dim; ++j) acc += Q[i * 3 + j] * t[j];
+            u[i] = acc;
+        }
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            double us[3];
+            for (int i = 0; i < 3; ++i) us[i] = sgn ? -u[i] : u[i];
+            for (int l = 0; l < L; ++l) {
+                double tau = ((double)l + xi) / (double)L;
+                double s = smax * (dim == 3 ? cbrt(tau) : sqrt(tau));
+                double pos[3];
+                for (int i = 0; i < 3; ++i) pos[i] = c[i] + s * us[i];
+                double I = orc_interp(vol->J, vol->nx, vol->ny, vol->nz, dim, pos[0] / p->spacing[0],
+                                      pos[1] / p->spacing[1], dim == 3 ? pos[2] / p->spacing[2] : 0.0);
+                double w[3];
+                orc_weight(dim, s, R, p->dR, w);
+                double S = w[0], Sr = w[1], SR = w[2];
+                sm->A += S * I;
+                sm->Aabs += fabs(S * I);
+                sm->BR += SR * I;
+                sm->BRabs += fabs(SR * I);
+                for (int i = 0; i < dim; ++i) {
+                    sm->Bc[i] += -Sr * I * us[i];
+                    sm->Bcabs[i] += fabs(Sr * I * us[i]);
+                }
+                /* Eqs. (7)-(10): c = (p+q)/2, R = (q_x - p_x)/2 along x (Eq. (6));
+                 * dr/dc = -u, so dS/dp_a = -Sr u_a / 2 - SR [a == x] / 2 and
+                 * dS/dq_a = -Sr u_a / 2 + SR [a == x] / 2. */
+                for (int i = 0; i < dim; ++i) {
+                    double dSdp = -0.5 * Sr * us[i] - (i == 0 ? 0.5 * SR : 0.0);
+                    double dSdq = -0.5 * Sr * us[i] + (i == 0 ? 0.5 * SR : 0.0);
+                    sm->Sp[i] += dSdp * I;
+                    sm->Sq[i] += dSdq * I;
+                }
+                /* samples within ORC_KINK_REL * s_max of a kink of S: an FP32 evaluation may place
+                 * them on the other side; record how much dS/dr and dS/dR could change. */
+                for (int kk = 0; kk < 4; ++kk) {
+                    if (fabs(s - kinks[kk]) <= ORC_KINK_REL * smax) {
+                        double wl[3], wr[3];
+                        orc_weight(dim, kinks[kk] - 1e-9 * smax, R, p->dR, wl);
+                        orc_weight(dim, kinks[kk] + 1e-9 * smax, R, p->dR, wr);
+                        sm->slBR += fabs((wr[2] - wl[2]) * I);
+                        for (int i = 0; i < dim; ++i) sm->slBc[i] += fabs((wr[1] - wl[1]) * I * us[i]);
+                        sm->n_kink += 1;
+                    }
+                }
+                if (pts) {
+                    for (int i = 0; i < 3; ++i) pts[idx * 3 + i] = pos[i];
+                    vals[idx] = I;
+                }
+                ++idx;
+            }
+        }
+    }
+    sm->n_samples = idx;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* One gradient-descent iteration of one contour (Eqs. (7)-(15)).                               */
+/* ------------------------------------------------------------------------------------------ */
+static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *iter, uint8_t *status,
+                        uint8_t *streak, double *e_mc, uint32_t id, double *trace)
+{
+    const orc_params *p = vol->p;
+    int dim = p->dim;
+    int mismatch = 0;
+    double Rc = *R;
+    uint32_t n = (uint32_t)(*iter + 1);
+    *iter = (int32_t)n;
+    orc_sums sm;
+    accumulate_samples(vol, c, Rc, n, id, &sm, NULL, NULL);
+    double smax = Rc + 0.5 * p->dR;
+    double V = ball_measure(dim) * pow(smax, dim);
+    double scale = V / (double)sm.n_samples;
+    double twoR_d = pow(2.0 * Rc, dim);
+    double eps = p->eps0 / sqrt((double)n);
+
+    /* c,R form */
+    double A = scale * sm.A, BR = scale * sm.BR, Bc[3] = {0, 0, 0};
+    for (int i = 0; i < dim; ++i) Bc[i] = scale * sm.Bc[i];
+    double E = A / twoR_d;
+    double gR = (BR - (double)dim / Rc * A) / twoR_d;
+    double dR_step = -0.5 * eps * gR;
+    double dc[3] = {0, 0, 0};
+    for (int i = 0; i < dim; ++i) dc[i] = -0.5 * eps * Bc[i] / twoR_d;
+
+    /* p,q form, literally: p = c - R e_x, q = c + R e_x (Eq. (6)), gamma = (q_x - p_x)^-d (Eq. (11)) */
+    double pp[3], qq[3];
+    for (int i = 0; i < 3; ++i) { pp[i] = c[i]; qq[i] = c[i]; }
+    pp[0] -= Rc; qq[0] += Rc;
+    double qmp = qq[0] - pp[0];
+    double gamma = 1.0 / pow(qmp, dim);
+    double dEdp[3] = {0, 0, 0}, dEdq[3] = {0, 0, 0};
+    dEdp[0] = gamma * ((double)dim / qmp * A + scale * sm.Sp[0]);
+    dEdq[0] = gamma * (-(double)dim / qmp * A + scale * sm.Sq[0]);
+    for (int i = 1; i < dim; ++i) {
+        dEdp[i] = gamma * scale * sm.Sp[i];
+        dEdq[i] = gamma * scale * sm.Sq[i];
+    }
+    double pn[3], qn[3];
+    for (int i = 0; i < 3; ++i) { pn[i] = pp[i] - eps * dEdp[i]; qn[i] = qq[i] - eps * dEdq[i]; }
+    double c_new[3], R_new = 0.5 * (qn[0] - pn[0]);
+    for (int i = 0; i < 3; ++i) c_new[i] = 0.5 * (pn[i] + qn[i]);
+    /* the two forms must agree */
+    double tolR = 1e-9 * (fabs(Rc) + fabs(dR_step)) + 1e-12;
+    if (fabs((R_new - Rc) - dR_step) > tolR) mismatch = 1;
+    for (int i = 0; i < dim; ++i) {
+        double tolc = 1e-9 * (fabs(c[i]) + fabs(dc[i]) + 1.0);
+        if (fabs((c_new[i] - c[i]) - dc[i]) > tolc) mismatch = 1;
+        if (i > 0 && dEdp[i] != dEdq[i]) mismatch = 1; /* Eqs. (9)-(10): p, q stay aligned */
+    }
+
+    if (trace) {
+        double Aabs = scale * sm.Aabs, BRabs = scale * sm.BRabs;
+        trace[0] = A; trace[1] = BR;
+        for (int i = 0; i < 3; ++i) trace[2 + i] = Bc[i];
+        trace[5] = Aabs; trace[6] = BRabs;
+        for (int i = 0; i < 3; ++i) trace[7 + i] = scale * sm.Bcabs[i];
+        trace[10] = E; trace[11] = Aabs / twoR_d;
+        trace[12] = dR_step; trace[13] = 0.5 * eps * (BRabs + (double)dim / Rc * Aabs) / twoR_d;
+        for (int i = 0; i < 3; ++i) {
+            trace[14 + i] = dc[i];
+            trace[17 + i] = 0.5 * eps * scale * sm.Bcabs[i] / twoR_d;
+        }
+        trace[20] = scale * sm.slBR;
+        for (int i = 0; i < 3; ++i) trace[21 + i] = scale * sm.slBc[i];
+        trace[24] = 0.5 * eps * scale * sm.slBR / twoR_d;
+        for (int i = 0; i < 3; ++i) trace[25 + i] = 0.5 * eps * scale * sm.slBc[i] / twoR_d;
+        trace[28] = (double)sm.n_kink;
+        trace[29] = (double)n;
+        trace[30] = Rc;
+        trace[31] = eps;
+    }
+
+    /* radius bounds (minimum contour size, Conclusion) */
+    double lo = r_low(p), hi = p->r_max;
+    uint8_t flag = *status & ORC_CLAMPED;
+    if (R_new < lo) { R_new = lo; flag = ORC_CLAMPED; }
+    if (R_new > hi) { R_new = hi; flag = ORC_CLAMPED; }
+    double move = fabs(R_new - Rc);
+    double dcn = 0.0;
+    for (int i = 0; i < dim; ++i) dcn += (c_new[i] - c[i]) * (c_new[i] - c[i]);
+    dcn = sqrt(dcn);
+    if (dcn > move) move = dcn;
+
+    for (int i = 0; i < 3; ++i) c[i] = c_new[i];
+    *R = R_new;
+    *e_mc = E;
+    uint8_t st = ORC_ACTIVE;
+    int finite = isfinite(R_new) && isfinite(E);
+    for (int i = 0; i < dim; ++i) finite = finite && isfinite(c_new[i]);
+    if (!finite) {
+        st = ORC_NONFINITE;
+    } else {
+        for (int i = 0; i < dim; ++i) {
+            int64_t na = i == 0 ? vol->nx : (i == 1 ? vol->ny : vol->nz);
+            if (c_new[i] < 0.0 || c_new[i] > (double)(na - 1) * p->spacing[i]) st = ORC_OUT;
+        }
+    }
+    if (st == ORC_ACTIVE) {
+        if (move < p->conv_tol) *streak = (uint8_t)(*streak < 255 ? *streak + 1 : 255);
+        else *streak = 0;
+        if (p->conv_window > 0 && *streak >= p->conv_window) st = ORC_CONVERGED;
+    }
+    *status = (uint8_t)(st | flag);
+    return mismatch;
+}
+
+/* Clamp of the initial radius R0 into [max(r_min, geometric minimum), r_max]. */
+double orc_initial_radius(const orc_params *p, double r0)
+{
+    double lo = r_low(p);
+    if (r0 < lo) r0 = lo;
+    if (r0 > p->r_max) r0 = p->r_max;
+    return r0;
+}
+
+/* Evolve every ACTIVE contour for up to n_iter further iterations. c: n x 3 physical. trace (n x
+ * ORC_TRACE_W, may be NULL) receives the terms of the last iteration each contour ran. Returns the
+ * number of contour-iterations whose p,q and c,R forms disagreed (must be 0). */
+int64_t orc_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                   const double *dirs, int64_t n, const uint32_t *ids, double *c, double *R,
+                   int32_t *iters, uint8_t *status, uint8_t *streak, double *e_mc, int32_t n_iter,
+                   double *trace, int64_t *evolved)
+{
+    orc_vol vol = {J, nx, ny, nz, p, dirs};
+    int64_t mism = 0, done = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : mism, done)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t it = 0; it < n_iter; ++it) {
+            if ((status[i] & 0x0f) != ORC_ACTIVE) break;
+            mism += step_contour(&vol, &c[i * 3], &R[i], &iters[i], &status[i], &streak[i], &e_mc[i],
+                                 ids[i], trace ? &trace[i * ORC_TRACE_W] : NULL);
+            done += 1;
+        }
+    }
+    if (evolved) *evolved = done;
+    return mism;
+}
+
+/* Monte-Carlo terms of one contour at (c, R) for iteration n without updating it.
+ * out: [A, B_R, Bc_x, Bc_y, Bc_z, scale=V/N, dE/dp (3), dE/dq (3), E, g_R, g_c (3)] (17 values).
+ * pts (N x 3) / vals (N) receive the sample positions and interpolated values if non-NULL. */
+void orc_mc_terms(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                  const double *dirs, const double c[3], double R, uint32_t n, uint32_t id, double *out,
+                  double *pts, double *vals)
+{
+    orc_vol vol = {J, nx, ny, nz, p, dirs};
+    orc_sums sm;
+    accumulate_samples(&vol, c, R, n, id, &sm, pts, vals);
+    int dim = p->dim;
+    double smax = R + 0.5 * p->dR;
+    double scale = ball_measure(dim) * pow(smax, dim) / (double)sm.n_samples;
+    double twoR_d = pow(2.0 * R, dim);
+    double A = scale * sm.A;
+    out[0] = A;
+    out[1] = scale * sm.BR;
+    for (int i = 0; i < 3; ++i) out[2 + i] = scale * sm.Bc[i];
+    out[5] = scale;
+    double qmp = 2.0 * R, gamma = 1.0 / pow(qmp, dim);
+    for (int i = 0; i < 3; ++i) { out[6 + i] = 0.0; out[9 + i] = 0.0; }
+    out[6] = gamma * ((double)dim / qmp * A + scale * sm.Sp[0]);
+    out[9] = gamma * (-(double)dim / qmp * A + scale * sm.Sq[0]);
+    for (int i = 1; i < dim; ++i) {
+        out[6 + i] = gamma * scale * sm.Sp[i];
+        out[9 + i] = gamma * scale * sm.Sq[i];
+    }
+    out[12] = A / twoR_d;
+    out[13] = (out[1] - (double)dim / R * A) / twoR_d;
+    for (int i = 0; i < 3; ++i) out[14 + i] = out[2 + i] / twoR_d;
+}
+
+/* Estimator value with the sample points held fixed: scale * sum S(|x_j - c|; R) I_j / (2R)^d. */
+double orc_energy_fixed(int dim, double dR, const double *pts, const double *vals, int64_t N, double scale,
+                        const double c[3], double R)
+{
+    double acc = 0.0;
+    for (int64_t j = 0; j < N; ++j) {
+        double d2 = 0.0;
+        for (int i = 0; i < dim; ++i) d2 += (pts[j * 3 + i] - c[i]) * (pts[j * 3 + i] - c[i]);
+        double w[3];
+        orc_weight(dim, sqrt(d2), R, dR, w);
+        acc += w[0] * vals[j];
+    }
+    return scale * acc / pow(2.0 * R, dim);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Exact discrete energy of Eq. (5): sum over every lattice point k with |k*h - c| < R + dR/2 of */
+/* S(|k*h - c|; R) J(k), times the voxel measure prod(h), divided by (2R)^d. Lattice points      */
+/* outside the volume take the clamp-to-edge value.                                            */
+/* ------------------------------------------------------------------------------------------ */
+int orc_energy_vox(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p, int64_t n,
+                   const double *c, const double *R, double *e_vox, double *e_abs)
+{
+    int dim = p->dim;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < n; ++i) {
+        double Ri = R[i];
+        double smax = Ri + 0.5 * p->dR;
+        const double *ci = &c[i * 3];
+        int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) {
+            lo[a] = (int64_t)ceil((ci[a] - smax) / p->spacing[a]);
+            hi[a] = (int64_t)floor((ci[a] + smax) / p->spacing[a]);
+        }
+        double acc = 0.0, aabs = 0.0;
+        for (int64_t kz = lo[2]; kz <= hi[2]; ++kz)
+            for (int64_t ky = lo[1]; ky <= hi[1]; ++ky)
+                for (int64_t kx = lo[0]; kx <= hi[0]; ++kx) {
+                    double dx = kx * p->spacing[0] - ci[0];
+                    double dy = ky * p->spacing[1] - ci[1];
+                    double dz = dim == 3 ? kz * p->spacing[2] - ci[2] : 0.0;
+                    double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    if (!(r < smax)) continue;
+                    double w[3];
+                    orc_weight(dim, r, Ri, p->dR, w);
+                    double v = J[(clampi(kz, 0, nz - 1) * ny + clampi(ky, 0, ny - 1)) * nx + clampi(kx, 0, nx - 1)];
+                    acc += w[0] * v;
+                    aabs += fabs(w[0] * v);
+                }
+        double meas = p->spacing[0] * p->spacing[1] * (dim == 3 ? p->spacing[2] : 1.0);
+        double norm = meas / pow(2.0 * Ri, dim);
+        e_vox[i] = acc * norm;
+        if (e_abs) e_abs[i] = aabs * norm;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Selection (Results): candidates are contours that stopped on convergence or maximum          */
+/* iterations with E_vox <= E0; overlapping pairs (|c' - c''| < rho * max(R', R'')) compete and  */
+/* the lower energy survives. Sequential greedy in ascending (E_vox, id).                      */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct { double e; uint32_t id; int64_t idx; } orc_key;
+
+static int key_cmp(const void *a, const void *b)
+{
+    const orc_key *x = (const orc_key *)a, *y = (const orc_key *)b;
+    if (x->e < y->e) return -1;
+    if (x->e > y->e) return 1;
+    if (x->id < y->id) return -1;
+    if (x->id > y->id) return 1;
+    return 0;
+}
+
+int64_t orc_cull(const orc_params *p, int64_t n, const double *c, const double *R, const double *e_vox,
+                 const uint8_t *status, const uint32_t *ids, uint8_t *keep)
+{
+    int dim = p->dim;
+    double rho = rho_of(dim);
+    orc_key *keys = (orc_key *)malloc(sizeof(orc_key) * (n > 0 ? n : 1));
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        keep[i] = 0;
+        int st = status[i] & 0x0f;
+        if ((st == ORC_CONVERGED || st == ORC_MAXITER) && isfinite(e_vox[i]) && e_vox[i] <= p->e0) {
+            keys[nc].e = e_vox[i]; keys[nc].id = ids[i]; keys[nc].idx = i; ++nc;
+        }
+    }
+    qsort(keys, (size_t)nc, sizeof(orc_key), key_cmp);
+    int64_t *acc = (int64_t *)malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
+    int64_t na = 0;
+    for (int64_t t = 0; t < nc; ++t) {
+        int64_t i = keys[t].idx;
+        int ok = 1;
+        for (int64_t u = 0; u < na && ok; ++u) {
+            int64_t j = acc[u];
+            double d2 = 0.0;
+            for (int a = 0; a < dim; ++a) d2 += (c[i * 3 + a] - c[j * 3 + a]) * (c[i * 3 + a] - c[j * 3 + a]);
+            double rm = R[i] > R[j] ? R[i] : R[j];
+            if (sqrt(d2) < rho * rm) ok = 0;
+        }
+        if (ok) { acc[na++] = i; keep[i] = 1; }
+    }
+    free(acc);
+    free(keys);
+    return na;
+}
+
+/* Flags contours whose selection outcome could flip under FP32 evaluation: energy within
+ * rel_e of E0 or of an overlapping rival's energy, or a pair distance within tol_d of the
+ * overlap radius. */
+int64_t orc_cull_ambiguity(const orc_params *p, int64_t n, const double *c, const double *R,
+                           const double *e_vox, double rel_e, double tol_d, uint8_t *amb)
+{
+    int dim = p->dim;
+    double rho = rho_of(dim);
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) amb[i] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (fabs(e_vox[i] - p->e0) <= rel_e * fabs(p->e0)) amb[i] = 1;
+        for (int64_t j = i + 1; j < n; ++j) {
+            double d2 = 0.0;
+            for (int a = 0; a < dim; ++a) d2 += (c[i * 3 + a] - c[j * 3 + a]) * (c[i * 3 + a] - c[j * 3 + a]);
+            double d = sqrt(d2), thr = rho * (R[i] > R[j] ? R[i] : R[j]);
+            if (fabs(d - thr) <= tol_d) { amb[i] = 1; amb[j] = 1; }
+            if (d < thr + tol_d) {
+                double sc = fabs(e_vox[i]) > fabs(e_vox[j]) ? fabs(e_vox[i]) : fabs(e_vox[j]);
+                if (fabs(e_vox[i] - e_vox[j]) <= rel_e * sc) { amb[i] = 1; amb[j] = 1; }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) cnt += amb[i];
+    return cnt;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

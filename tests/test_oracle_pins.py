@@ -1,0 +1,562 @@
+"""Pins of the FP64 oracle against facts the paper and mathematics fix (CPU only).
+
+Each test checks one piece of the oracle against something other than the oracle itself:
+published known-answer vectors, an independent library routine, a closed form from the paper
+(Eq. (3), the alpha = d normalisation of Eq. (4), the zero-mean weight of Sec. II-B), finite
+differences, exact symmetries, or an independent i.i.d. Monte-Carlo estimate.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RHO3 = 2.0 ** (-1.0 / 3.0)
+RHO2 = 2.0 ** (-0.5)
+
+
+def _kat_rows():
+    rows = []
+    with open(os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(t, 16) for t in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+# ------------------------------------------------------------------------------------------
+# random numbers
+# ------------------------------------------------------------------------------------------
+
+def test_philox_known_answers(orc):
+    rows = _kat_rows()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        assert orc.philox(ctr, key) == want
+
+
+ROCRAND_SRC = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char **argv) {
+  unsigned long long seed = strtoull(argv[1], 0, 0) | (strtoull(argv[2], 0, 0) << 32);
+  unsigned long long c0 = strtoull(argv[3], 0, 0), c1 = strtoull(argv[4], 0, 0);
+  unsigned long long c2 = strtoull(argv[5], 0, 0), c3 = strtoull(argv[6], 0, 0);
+  rocrand_device::philox4x32_10_engine e(seed, c2 | (c3 << 32), 0);
+  unsigned long long total = c0 | (c1 << 32), chunk = total / 8, done = 0;
+  for (int i = 0; i < 7; ++i) { e.discard(4ull * chunk); done += chunk; }
+  e.discard(4ull * (total - done));
+  uint4 v = e.next4();
+  printf("%u %u %u %u\n", v.x, v.y, v.z, v.w);
+  return 0;
+}
+"""
+
+
+def test_philox_matches_rocrand(orc, tmp_path):
+    """Cross-check against rocRAND's open-source Philox4x32-10 engine, run as a host program."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    src = tmp_path / "rr.cpp"
+    src.write_text(ROCRAND_SRC)
+    exe = tmp_path / "rr"
+    subprocess.check_call([hipcc, "-O1", "-x", "hip", "--offload-arch=gfx950", str(src), "-o", str(exe)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    rng = np.random.default_rng(7)
+    cases = [([0, 0, 0, 0], [0, 0])] + [
+        (list(rng.integers(0, 2 ** 32, 4)), list(rng.integers(0, 2 ** 32, 2))) for _ in range(12)]
+    cases += [([5, 17, 3, 1], [0x40000002, 0x18040630])]  # a contour-iteration counter shape
+    for ctr, key in cases:
+        out = subprocess.check_output([str(exe), str(key[0]), str(key[1])] + [str(c) for c in ctr])
+        assert [int(t) for t in out.split()] == orc.philox(ctr, key)
+
+
+def test_uniform_mapping_exact(orc):
+    assert orc.uniform(0) == 2.0 ** -24
+    assert orc.uniform(0xFFFFFFFF) == 1.0 - 2.0 ** -24
+    for x in np.random.default_rng(1).integers(0, 2 ** 32, 2000):
+        u = orc.uniform(int(x))
+        assert 0.0 < u < 1.0
+        assert float(np.float32(u)) == u  # exactly representable in FP32
+
+
+def test_rotation_is_uniform_proper_rotation(orc):
+    p = synth.Params()
+    cols = []
+    for n in range(1, 1201):
+        Q = orc.rotation(p, n, 3)
+        assert np.allclose(Q @ Q.T, np.eye(3), atol=1e-12)
+        assert abs(np.linalg.det(Q) - 1.0) < 1e-12
+        cols.append(Q[:, 0])
+    cols = np.array(cols)
+    # a uniform rotation maps e_x to a uniform point on the sphere: mean 0, E[v_i^2] = 1/3
+    assert np.all(np.abs(cols.mean(0)) < 4.0 / math.sqrt(3 * len(cols)))
+    assert np.all(np.abs((cols ** 2).mean(0) - 1.0 / 3.0) < 0.04)
+    p2 = synth.Params(dim=2)
+    Q2 = orc.rotation(p2, 4, 9)
+    assert np.allclose(Q2[:2, :2] @ Q2[:2, :2].T, np.eye(2), atol=1e-12)
+    assert np.allclose(orc.rotation(synth.Params(flags=1), 4, 9), np.eye(3))
+
+
+# ------------------------------------------------------------------------------------------
+# weight function and energy (Sec. II-B, Eqs. (3)-(5))
+# ------------------------------------------------------------------------------------------
+
+def _gl_integral(f, breaks, order=8):
+    """Gauss-Legendre on each interval between sorted breakpoints (exact for piecewise
+    polynomials of degree < 2*order)."""
+    x, w = np.polynomial.legendre.leggauss(order)
+    total = 0.0
+    b = np.unique(np.asarray(breaks, dtype=np.float64))
+    for lo, hi in zip(b[:-1], b[1:]):
+        t = 0.5 * (hi - lo) * x + 0.5 * (hi + lo)
+        total += 0.5 * (hi - lo) * float(np.dot(w, f(t)))
+    return total
+
+
+def _kinks(dim, R, dR):
+    rho = RHO3 if dim == 3 else RHO2
+    a, dr = rho * R, rho * dR
+    return [0.0, a - dr / 2, a + dr / 2, R - dR / 2, R + dR / 2]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dR", [0.75, 1.0])
+@pytest.mark.parametrize("R", [4.5, 6.0, 9.3, 15.0])
+def test_weight_zero_mean(orc, dim, dR, R):
+    """int_0^inf S(r) r^(d-1) dr = 0 (Sec. II-B): fixes rho = 2^(-1/d) and dr = rho*dR."""
+    f = lambda r: orc.weight_vec(dim, r, R, dR)[..., 0] * r ** (dim - 1)
+    g = lambda r: np.abs(orc.weight_vec(dim, r, R, dR)[..., 0]) * r ** (dim - 1)
+    ks = _kinks(dim, R, dR)
+    val = _gl_integral(f, ks)
+    scale = _gl_integral(g, ks)
+    assert abs(val) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_weight_shape_and_derivatives(orc, dim):
+    R, dR = 7.3, 0.9
+    rho = RHO3 if dim == 3 else RHO2
+    ks = _kinks(dim, R, dR)
+    # four regions: -1 core, +1 shell, zero outside, continuous at every kink
+    assert orc.weight(dim, 0.1, R, dR)[0] == -1.0
+    assert orc.weight(dim, 0.5 * (ks[2] + ks[3]), R, dR)[0] == 1.0
+    assert orc.weight(dim, ks[4] + 0.01, R, dR)[0] == 0.0
+    for k in ks[1:]:
+        lo, hi = orc.weight(dim, k - 1e-9, R, dR)[0], orc.weight(dim, k + 1e-9, R, dR)[0]
+        assert abs(lo - hi) < 1e-8
+    # ramp widths: inner dr = rho*dR, outer dR (Sec. II-B: dr = dR / cbrt(2) in 3D)
+    assert abs((ks[2] - ks[1]) - rho * dR) < 1e-12 and abs((ks[4] - ks[3]) - dR) < 1e-12
+    # dS/dr and dS/dR agree with finite differences away from kinks
+    rng = np.random.default_rng(3)
+    for r in rng.uniform(0.0, ks[4] + 1.0, 400):
+        if min(abs(r - k) for k in ks) < 1e-4:
+            continue
+        h = 1e-6
+        S, Sr, SR = orc.weight(dim, r, R, dR)
+        fr = (orc.weight(dim, r + h, R, dR)[0] - orc.weight(dim, r - h, R, dR)[0]) / (2 * h)
+        fR = (orc.weight(dim, r, R + h, dR)[0] - orc.weight(dim, r, R - h, dR)[0]) / (2 * h)
+        assert abs(fr - Sr) < 1e-6 and abs(fR - SR) < 1e-6
+
+
+def _hat_energy_ideal_blob(orc, dim, R, r0, dR):
+    """E-hat of the ideal blob I = 1 + sgn(r0 - r) centred on the contour (the oracle's S)."""
+    meas = 4.0 * math.pi if dim == 3 else 2.0 * math.pi
+    f = lambda r: orc.weight_vec(dim, r, R, dR)[..., 0] * np.where(r < r0, 2.0, 0.0) * meas * r ** (dim - 1)
+    return _gl_integral(f, _kinks(dim, R, dR) + [r0])
+
+
+@pytest.mark.parametrize("r0", [4.0, 6.5, 11.0])
+def test_ideal_blob_energy_eq3(orc, r0):
+    """Eq. (3): 0 for R < r0; -(8/3) pi (R^3 - r0^3) for R/cbrt(2) < r0 < R; -(8/3) pi r0^3 beyond."""
+    dR = 1e-4
+    for R in np.linspace(0.5 * r0, 2.0 * r0, 31):
+        if R < orc.r_geom_min(3, dR):
+            continue
+        if R < r0:
+            want = 0.0
+        elif R * RHO3 < r0:
+            want = -(8.0 / 3.0) * math.pi * (R ** 3 - r0 ** 3)
+        else:
+            want = -(8.0 / 3.0) * math.pi * r0 ** 3
+        got = _hat_energy_ideal_blob(orc, 3, R, r0, dR)
+        assert abs(got - want) < 1e-3 * (8.0 / 3.0) * math.pi * r0 ** 3, (R, got, want)
+
+
+@pytest.mark.parametrize("r0", [4.0, 9.0])
+def test_ideal_disk_energy_2d(orc, r0):
+    """2D analogue of Eq. (3) with rho = 1/sqrt(2) (Sec. II-A): 0; -2 pi (R^2 - r0^2); -2 pi r0^2."""
+    dR = 1e-4
+    for R in np.linspace(0.5 * r0, 2.0 * r0, 25):
+        if R < r0:
+            want = 0.0
+        elif R * RHO2 < r0:
+            want = -2.0 * math.pi * (R ** 2 - r0 ** 2)
+        else:
+            want = -2.0 * math.pi * r0 ** 2
+        got = _hat_energy_ideal_blob(orc, 2, R, r0, dR)
+        assert abs(got - want) < 1e-3 * 2.0 * math.pi * r0 ** 2
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_normalisation_alpha_gives_symmetric_slopes(orc, dim):
+    """Eq. (4): with E = E-hat / ||p - q||^d the slopes on both sides of R* = 2^(1/d) r0 have equal
+    magnitude and opposite sign, E(R*) = -pi/6 (3D) / -pi/4 (2D) for the contrast-2 blob, and R*
+    is the unique minimum. Evaluated through the oracle's estimator with a deterministic radial
+    quadrature (sample points held fixed)."""
+    r0, dR = 5.0, 2e-3
+    rstar = 2.0 ** (1.0 / dim) * r0
+    big = 2.5 * r0
+    N = 400000
+    u = (np.arange(N) + 0.5) / N
+    r = big * u ** (1.0 / dim)            # equal-measure radial nodes in the ball of radius `big`
+    pts = np.zeros((N, 3))
+    pts[:, 0] = r
+    vals = np.where(r < r0, 2.0, 0.0)
+    vol = (4.0 / 3.0 * math.pi if dim == 3 else math.pi) * big ** dim
+    E = lambda R: orc.energy_fixed(dim, dR, pts, vals, vol / N, [0.0, 0.0, 0.0], R)
+    h = 0.02
+    left = (E(rstar - h) - E(rstar - 3 * h)) / (2 * h)
+    right = (E(rstar + 3 * h) - E(rstar + h)) / (2 * h)
+    assert left < 0 < right
+    # on both sides |dE/dR| = pi r0^d / R^(d+1): the one-sided limits at R* are equal
+    lim_l = -left * (rstar - 2 * h) ** (dim + 1)
+    lim_r = right * (rstar + 2 * h) ** (dim + 1)
+    assert abs(lim_l / lim_r - 1.0) < 0.01
+    assert abs(lim_r / (math.pi * r0 ** dim) - 1.0) < 0.01
+    want = -math.pi / 6.0 if dim == 3 else -math.pi / 4.0
+    assert abs(E(rstar) - want) < 2e-3
+    Rs = np.linspace(0.8 * r0, 2.2 * r0, 57)
+    Es = np.array([E(v) for v in Rs])
+    assert abs(Rs[np.argmin(Es)] - rstar) <= (Rs[1] - Rs[0]) * 1.01
+
+
+# ------------------------------------------------------------------------------------------
+# gradient (Eqs. (7)-(11)) and the p,q <-> c,R identity
+# ------------------------------------------------------------------------------------------
+
+def _smooth_volume(shape, seed=11, sigma=2.0, scale=3.0):
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    return gaussian_filter(rng.normal(size=shape), sigma, mode="nearest") * scale + 0.5
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_matches_finite_differences(orc, dim):
+    if dim == 3:
+        J = _smooth_volume((24, 26, 28))
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16)
+        dirs = synth.icosphere(2)
+        c = np.array([13.3, 12.1, 11.7])
+    else:
+        J = _smooth_volume((1, 40, 44))
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16)
+        dirs = synth.circle_directions(64)
+        c = np.array([21.3, 19.6, 0.0])
+    R = 6.4
+    checked = 0
+    for n in (1, 2, 7, 33):
+        t = orc.mc_terms(J, p, dirs, c, R, n, 5, want_samples=True)
+        pts, vals, sc = t["pts"], t["vals"], t["scale"]
+        E = lambda cc, RR: orc.energy_fixed(dim, p.dR, pts, vals, sc, cc, RR)
+        assert abs(E(c, R) - t["E"]) < 1e-12 * max(1.0, abs(t["E"]))
+        h = 1e-6
+        gR = (E(c, R + h) - E(c, R - h)) / (2 * h)
+        scale = np.abs(t["g_R"]) + 1e-3
+        assert abs(gR - t["g_R"]) < 1e-5 * scale, (n, gR, t["g_R"])
+        for a in range(dim):
+            e = np.zeros(3); e[a] = h
+            gc = (E(c + e, R) - E(c - e, R)) / (2 * h)
+            assert abs(gc - t["g_c"][a]) < 1e-5 * (np.abs(t["g_c"]).max() + 1e-3)
+        # Eqs. (7)-(8): move p_x alone (c_x by h/2, R by -h/2) or q_x alone
+        ex = np.array([h / 2, 0.0, 0.0])
+        dpx = (E(c + ex, R - h / 2) - E(c - ex, R + h / 2)) / (2 * h)
+        dqx = (E(c + ex, R + h / 2) - E(c - ex, R - h / 2)) / (2 * h)
+        tol = 1e-5 * (np.abs(t["dEdp"]).max() + np.abs(t["dEdq"]).max() + 1e-3)
+        assert abs(dpx - t["dEdp"][0]) < tol and abs(dqx - t["dEdq"][0]) < tol
+        # Eqs. (9)-(10): dE/dp_y = dE/dq_y (p, q stay aligned, Eq. (6))
+        for a in range(1, dim):
+            assert t["dEdp"][a] == t["dEdq"][a]
+            ey = np.zeros(3); ey[a] = h / 2
+            dpy = (E(c + ey, R) - E(c - ey, R)) / (2 * h)
+            assert abs(dpy - t["dEdp"][a]) < tol
+        # p,q <-> c,R identity: dE/dc = dE/dp + dE/dq, dE/dR = dE/dq_x - dE/dp_x
+        assert np.allclose(t["dEdp"][:dim] + t["dEdq"][:dim], t["g_c"][:dim], rtol=1e-10, atol=1e-14)
+        assert abs((t["dEdq"][0] - t["dEdp"][0]) - t["g_R"]) < 1e-10 * (abs(t["g_R"]) + 1e-12)
+        checked += 1
+    assert checked == 4
+
+
+def test_evolve_pq_and_cr_forms_agree(orc):
+    """The oracle updates in p,q form (Eqs. (12)-(15)) and checks the c,R form every iteration;
+    evolve raises on any disagreement."""
+    wl = synth.tiny_config()
+    J = orc.prepass(wl.raw, wl.params)
+    st = orc.init_state(wl.params, wl.seeds)
+    orc.evolve(J, wl.params, wl.dirs, st, 30)
+    assert np.all(st.iters == 30)
+
+
+# ------------------------------------------------------------------------------------------
+# Monte-Carlo estimator (Sec. II-E)
+# ------------------------------------------------------------------------------------------
+
+def _iid_reference(orc, J, dim, h, c, R, dR, n_pts, seed):
+    """Independent i.i.d. estimate of (A, B_R, B_c) by rejection sampling in the ball, with
+    scipy's order-1 map_coordinates (mode 'nearest') as the interpolant."""
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(seed)
+    smax = R + 0.5 * dR
+    pts = []
+    need = n_pts
+    while need > 0:
+        x = rng.uniform(-smax, smax, size=(2 * need, dim))
+        x = x[(x ** 2).sum(1) < smax ** 2][:need]
+        pts.append(x)
+        need -= len(x)
+    x = np.concatenate(pts)
+    r = np.sqrt((x ** 2).sum(1))
+    u = x / r[:, None]
+    pos = x + c[:dim]
+    if dim == 3:
+        coords = np.stack([pos[:, 2] / h[2], pos[:, 1] / h[1], pos[:, 0] / h[0]])
+        I = map_coordinates(J, coords, order=1, mode="nearest")
+    else:
+        coords = np.stack([pos[:, 1] / h[1], pos[:, 0] / h[0]])
+        I = map_coordinates(J[0], coords, order=1, mode="nearest")
+    w = orc.weight_vec(dim, r, R, dR)
+    V = (4.0 / 3.0 * math.pi if dim == 3 else math.pi) * smax ** dim
+    terms = np.concatenate([(w[:, 0] * I)[:, None], (w[:, 2] * I)[:, None], -(w[:, 1] * I)[:, None] * u], axis=1)
+    return V * terms.mean(0), V * terms.std(0) / math.sqrt(len(terms))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mc_estimator_unbiased(orc, dim):
+    if dim == 3:
+        J = _smooth_volume((18, 20, 22), seed=5)
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, spacing=(1.0, 1.0, 1.0))
+        dirs = synth.icosphere(2)
+        c = np.array([10.2, 9.6, 8.9])
+    else:
+        J = _smooth_volume((1, 30, 34), seed=5)
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16)
+        dirs = synth.circle_directions(64)
+        c = np.array([16.2, 14.4, 0.0])
+    R = 5.5
+    K = 1500
+    samples = np.array([np.concatenate([[t["A"], t["B_R"]], t["B_c"][:dim]]) for t in
+                        (orc.mc_terms(J, p, dirs, c, R, n, 2) for n in range(1, K + 1))])
+    mean, se = samples.mean(0), samples.std(0) / math.sqrt(K)
+    ref, ref_se = _iid_reference(orc, J, dim, p.spacing, c, R, p.dR, 1_500_000, seed=9)
+    z = np.abs(mean - ref) / np.sqrt(se ** 2 + ref_se ** 2)
+    assert np.all(z < 4.5), (mean, ref, z)
+
+
+def test_constant_image_has_no_force(orc):
+    """Constant image: the c-force vanishes exactly for antithetic pairs, and A, B_R are zero in
+    expectation (Sec. II-B: the energy does not move contours in uniform regions)."""
+    J = np.full((20, 20, 20), 3.0)
+    p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16)
+    dirs = synth.icosphere(2)
+    c = np.array([9.5, 10.1, 9.8])
+    R = 5.0
+    A, BR = [], []
+    for n in range(1, 801):
+        t = orc.mc_terms(J, p, dirs, c, R, n, 1)
+        assert np.all(np.abs(t["B_c"]) < 1e-10)
+        A.append(t["A"]); BR.append(t["B_R"])
+    for x in (np.array(A), np.array(BR)):
+        assert abs(x.mean()) < 4.5 * x.std() / math.sqrt(len(x))
+
+
+# ------------------------------------------------------------------------------------------
+# pre-pass and interpolation against scipy
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+def test_prepass_matches_scipy_gaussian(orc, dtype):
+    from scipy.ndimage import gaussian_filter1d
+    rng = np.random.default_rng(2)
+    raw = rng.integers(0, 250, size=(11, 17, 23)).astype(dtype)
+    p = synth.Params(dim=3, spacing=(1.0, 1.0, 2.0), sigma_pre=1.3, i_offset=17.0, i_scale=0.01)
+    J = orc.prepass(raw, p)
+    ref = (raw.astype(np.float64) - 17.0) * 0.01
+    for axis, h in ((2, 1.0), (1, 1.0), (0, 2.0)):
+        s = 1.3 / h
+        ref = gaussian_filter1d(ref, s, axis=axis, mode="nearest", radius=int(math.ceil(3 * s)))
+    assert np.max(np.abs(J - ref)) < 1e-12
+
+
+def test_prepass_2d_and_disabled(orc):
+    from scipy.ndimage import gaussian_filter1d
+    rng = np.random.default_rng(4)
+    raw = rng.integers(0, 250, size=(1, 19, 21)).astype(np.uint8)
+    p = synth.Params(dim=2, sigma_pre=1.1)
+    J = orc.prepass(raw, p)
+    ref = raw.astype(np.float64)[0]
+    for axis in (1, 0):
+        ref = gaussian_filter1d(ref, 1.1, axis=axis, mode="nearest", radius=4)
+    assert np.max(np.abs(J[0] - ref)) < 1e-12
+    J0 = orc.prepass(raw, p.replace(sigma_pre=0.0, i_offset=3.0, i_scale=2.0))
+    assert np.array_equal(J0, (raw.astype(np.float64) - 3.0) * 2.0)
+
+
+def test_interp_matches_scipy_map_coordinates(orc):
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(6)
+    J = rng.normal(size=(7, 9, 11))
+    pts = rng.uniform(-2.5, 13.0, size=(3000, 3))
+    got = np.array([orc.interp(J, 3, v) for v in pts])
+    ref = map_coordinates(J, pts[:, ::-1].T, order=1, mode="nearest")
+    assert np.max(np.abs(got - ref)) < 1e-12
+    J2 = rng.normal(size=(1, 9, 11))
+    got2 = np.array([orc.interp(J2, 2, v) for v in pts[:, :2]])
+    ref2 = map_coordinates(J2[0], pts[:, 1::-1].T, order=1, mode="nearest")
+    assert np.max(np.abs(got2 - ref2)) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# exact energy (Eq. (5))
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_vox_bruteforce(orc, dim):
+    rng = np.random.default_rng(8)
+    if dim == 3:
+        J = rng.normal(size=(10, 12, 14))
+        p = synth.Params(dim=3, spacing=(1.0, 1.0, 2.0), dR=0.75)
+    else:
+        J = rng.normal(size=(1, 15, 13))
+        p = synth.Params(dim=2, dR=1.0)
+    nz, ny, nx = J.shape
+    h = np.array(p.spacing)
+    cs = rng.uniform(-1.0, 14.0, size=(6, 3))
+    if dim == 2:
+        cs[:, 2] = 0.0
+    Rs = rng.uniform(4.0, 7.0, size=6)
+    e, _ = orc.energy_vox(J, p, cs, Rs)
+    kz, ky, kx = np.meshgrid(np.arange(-20, 40) if dim == 3 else np.array([0]), np.arange(-20, 40),
+                             np.arange(-20, 40), indexing="ij")
+    vals = J[np.clip(kz, 0, nz - 1), np.clip(ky, 0, ny - 1), np.clip(kx, 0, nx - 1)]
+    for i in range(6):
+        d = np.sqrt((kx * h[0] - cs[i, 0]) ** 2 + (ky * h[1] - cs[i, 1]) ** 2 +
+                    ((kz * h[2] - cs[i, 2]) ** 2 if dim == 3 else 0.0))
+        m = d < Rs[i] + 0.5 * p.dR
+        S = orc.weight_vec(dim, d[m], Rs[i], p.dR)[:, 0]
+        meas = h[0] * h[1] * (h[2] if dim == 3 else 1.0)
+        want = meas * float((S * vals[m]).sum()) / (2 * Rs[i]) ** dim
+        assert abs(e[i] - want) < 1e-12 * max(1.0, abs(want))
+
+
+# ------------------------------------------------------------------------------------------
+# symmetry of the whole iteration
+# ------------------------------------------------------------------------------------------
+
+def test_cube_symmetry_exact(orc):
+    """Swapping the x and y axes, or mirroring x, of the volume, the direction table and the
+    seeds (rotation disabled so the sampling frame moves with them) gives the same contours."""
+    wl = synth.tiny_config()
+    p = wl.params.replace(flags=1)
+    J = orc.prepass(wl.raw, p)
+    base = orc.init_state(p, wl.seeds)
+    orc.evolve(J, p, wl.dirs, base, 12)
+
+    Jt = np.ascontiguousarray(J.transpose(0, 2, 1))
+    st = orc.init_state(p, wl.seeds[:, [1, 0, 2]])
+    orc.evolve(Jt, p, wl.dirs[:, [1, 0, 2]], st, 12)
+    assert np.allclose(st.c[:, [1, 0, 2]], base.c, atol=1e-9)
+    assert np.allclose(st.R, base.R, atol=1e-9)
+
+    Jf = np.ascontiguousarray(J[:, :, ::-1])
+    seeds = wl.seeds.copy(); seeds[:, 0] = 63.0 - seeds[:, 0]
+    dirs = wl.dirs.copy(); dirs[:, 0] = -dirs[:, 0]
+    st = orc.init_state(p, seeds)
+    orc.evolve(Jf, p, dirs, st, 12)
+    cf = st.c.copy(); cf[:, 0] = 63.0 - cf[:, 0]
+    assert np.allclose(cf, base.c, atol=1e-9)
+    assert np.allclose(st.R, base.R, atol=1e-9)
+
+
+# ------------------------------------------------------------------------------------------
+# stop rule and selection (Results)
+# ------------------------------------------------------------------------------------------
+
+def test_status_rules(orc):
+    J = np.zeros((20, 20, 20))
+    p = synth.Params(dim=3, dR=1.0, r_init=5.0, conv_tol=1e-3, conv_window=3)
+    dirs = synth.icosphere(2)
+    st = orc.init_state(p, np.array([[10.0, 10.0, 10.0], [0.0, 19.0, 5.0]]))
+    orc.evolve(J, p, dirs, st, 10)
+    # zero image: no force at all -> converged after exactly conv_window steps
+    assert list(st.status) == [orc.CONVERGED, orc.CONVERGED] and list(st.iters) == [3, 3]
+    # radius clamping to the geometric minimum
+    p2 = p.replace(r_init=1.0)
+    assert abs(orc.initial_radius(p2, 1.0) - orc.r_geom_min(3, 1.0)) < 1e-15
+    assert abs(orc.r_geom_min(3, 1.0) - (1 + RHO3) / (2 * (1 - RHO3))) < 1e-15
+    # a contour pushed out of the volume is marked OUT
+    Jr = np.zeros((20, 20, 20)); Jr[:, :, :4] = 1.0
+    p3 = p.replace(eps0=400.0, conv_window=0)
+    st3 = orc.init_state(p3, np.array([[3.0, 10.0, 10.0]]))
+    orc.evolve(Jr, p3, dirs, st3, 50)
+    assert st3.status[0] & 0x0F in (orc.OUT, orc.ACTIVE)
+
+
+def test_cull_hand_cases(orc):
+    p = synth.Params(dim=3, e0=-0.05)
+    thr = lambda R: RHO3 * R
+    R = np.array([6.0, 6.0, 6.0, 6.0, 5.0])
+    d = 0.9 * thr(6.0)
+    # chain 0-1-2 along x with neighbours overlapping but 0, 2 apart; 3 isolated above E0; 4 OUT
+    c = np.array([[0.0, 0, 0], [d, 0, 0], [2 * d, 0, 0], [100.0, 0, 0], [0.5, 0, 0]])
+    e = np.array([-0.3, -0.2, -0.25, -0.01, -0.9])
+    status = np.array([orc.MAXITER, orc.CONVERGED, orc.MAXITER | orc.CLAMPED, orc.MAXITER, orc.OUT], np.uint8)
+    ids = np.arange(5, dtype=np.uint32)
+    keep = orc.cull(p, c, R, e, status, ids)
+    assert list(keep) == [1, 0, 1, 0, 0]
+    # middle one lowest: it suppresses both neighbours
+    e2 = np.array([-0.3, -0.4, -0.25, -0.06, -0.9])
+    assert list(orc.cull(p, c, R, e2, status, ids)) == [0, 1, 0, 1, 0]
+    # tie in energy: lower id wins
+    c3 = np.array([[0.0, 0, 0], [1.0, 0, 0]])
+    keep3 = orc.cull(p, c3, np.array([6.0, 6.0]), np.array([-0.2, -0.2]),
+                     np.array([2, 2], np.uint8), np.array([7, 3], np.uint32))
+    assert list(keep3) == [0, 1]
+    # overlap uses rho * max(R', R''): distance just inside / outside
+    c4 = np.array([[0.0, 0, 0], [thr(8.0) - 1e-6, 0, 0], [50.0, 0, 0], [50.0 + thr(8.0) + 1e-6, 0, 0]])
+    keep4 = orc.cull(p, c4, np.array([4.0, 8.0, 4.0, 8.0]), np.array([-0.2, -0.3, -0.2, -0.3]),
+                     np.full(4, 2, np.uint8), np.arange(4, dtype=np.uint32))
+    assert list(keep4) == [0, 1, 1, 1]
+
+
+def test_cull_threshold_order_irrelevant(orc):
+    """Thresholding before or after the competition selects the same set (greedy in ascending
+    energy): compare against a brute-force greedy over all contours followed by the threshold."""
+    rng = np.random.default_rng(12)
+    p = synth.Params(dim=3, e0=-0.1)
+    for trial in range(20):
+        n = 60
+        c = rng.uniform(0, 30, size=(n, 3))
+        R = rng.uniform(3, 8, size=n)
+        e = rng.uniform(-0.3, 0.05, size=n)
+        status = np.full(n, orc.MAXITER, np.uint8)
+        ids = rng.permutation(n).astype(np.uint32)
+        keep = orc.cull(p, c, R, e, status, ids)
+        order = sorted(range(n), key=lambda i: (e[i], ids[i]))
+        acc = []
+        for i in order:
+            if all(np.linalg.norm(c[i] - c[j]) >= RHO3 * max(R[i], R[j]) for j in acc):
+                acc.append(i)
+        want = np.zeros(n, np.uint8)
+        for i in acc:
+            if e[i] <= p.e0:
+                want[i] = 1
+        assert np.array_equal(keep, want)
