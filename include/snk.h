@@ -1,0 +1,205 @@
+/*
+ * snk.h -- C ABI of the MI355X (gfx950) snakuscule evolution library, libsnk.so.
+ *
+ * The library evolves many independent 3D (or 2D) snakuscules on one GPU, as in arXiv
+ * 1804.06304 ("Three-Dimensional GPU-Accelerated Active Contours for Automated Localization of
+ * Cells in Large Images"): load a volume and seed points, set the energy parameters, evolve N
+ * gradient-descent iterations with Monte-Carlo integration, then read back radii, centres and
+ * energies together with the detected set.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns snk_status; 0 is success. No C++ exception crosses this boundary.
+ *     On failure snk_last_error() returns a message; the context stays usable unless the error
+ *     is SNK_EDEVICE (a HIP runtime error, whose text is included).
+ *   - A context belongs to one host thread at a time.
+ *   - Work is enqueued asynchronously on the context's HIP stream. Calls that return data to the
+ *     host (snk_read, snk_get_state, snk_trace_step, snk_read_volume with on_device = 0,
+ *     snk_get_timing) and snk_sync synchronise that stream before returning.
+ *   - Volumes are [z][y][x] with x fastest. Physical coordinates have their origin at the centre
+ *     of voxel (0,0,0); voxel (i,j,k) sits at (i*h_x, j*h_y, k*h_z). 2D images are volumes with
+ *     nz = 1 and dim = 2; their z coordinate is 0.
+ *   - Per-contour arrays are in seed order. Centres cross the ABI as double (n x 3) so that
+ *     large images keep sub-voxel precision; the device holds each centre as an integer voxel
+ *     anchor plus an FP32 offset.
+ *   - Host buffers passed in are read before the call returns; the library keeps no pointer to
+ *     them. A device buffer passed with on_device = 1 is borrowed: it must stay valid until the
+ *     next snk_sync (or any synchronising call) on that context.
+ *   - Device memory for the smoothed volume, contour state and scratch is allocated by the
+ *     library (hipMalloc) and freed by snk_destroy.
+ */
+#ifndef SNK_H
+#define SNK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t snk_status;
+#define SNK_OK 0
+#define SNK_EINVAL (-1)   /* bad argument or parameter                                    */
+#define SNK_ENOMEM (-2)   /* device allocation failed                                      */
+#define SNK_EDEVICE (-3)  /* HIP runtime error (text in snk_last_error)                    */
+#define SNK_ESTATE (-4)   /* call out of order (e.g. evolve before a volume is loaded)      */
+#define SNK_EBUSY (-5)    /* admission refused (engine: HBM budget or slots exhausted)      */
+#define SNK_ERANGE (-6)   /* output capacity too small; *n_out holds the required count     */
+
+typedef enum { SNK_U8 = 0, SNK_U16 = 1, SNK_F32 = 2 } snk_dtype;
+
+/* Per-contour status byte: low nibble is the state, bit 0x10 is set once R was clamped. */
+#define SNK_ACTIVE 0       /* still evolving                                              */
+#define SNK_CONVERGED 1    /* froze after conv_window small steps (Results: "they converge") */
+#define SNK_MAXITER 2      /* stopped on the iteration limit (set by snk_finalize)          */
+#define SNK_OUT 3          /* centre left the volume                                        */
+#define SNK_NONFINITE 4    /* state became NaN/Inf                                          */
+#define SNK_CLAMPED 0x10
+
+/* Parameters of one run. Physical units are x-voxel units.
+ *   dim          2 or 3.
+ *   spacing      physical step per voxel along x, y, z (anisotropic stacks; Results: voxels are
+ *                made isotropic -- here samples live in physical space and map through h).
+ *   sigma_pre    low-pass sigma of the pre-pass, physical units; 0 disables it (Sec. II-E).
+ *   i_offset, i_scale   image I = (raw - i_offset) * i_scale before the low-pass.
+ *   dR           outer ramp width Delta R; the inner ramp is rho*dR (Sec. II-B, Eq. (5)).
+ *   eps0         step constant: eps_n = eps0 / sqrt(n) (Eqs. (12)-(15)).
+ *   r_min, r_max bounds on R; the lower bound is raised to dR(1+rho)/(2(1-rho)), the smallest
+ *                radius at which the four regions of the weight do not overlap.
+ *   r_init       initial radius R0 of every seed when snk_load_seeds gets no per-seed radii.
+ *   n_dirs       D, rows of the direction table.
+ *   n_rays       M, rays per contour-iteration; even (antithetic pairs).
+ *   n_radial     L, radial points per ray; a contour-iteration draws M*L points uniform in the
+ *                ball of radius R + dR/2 (Sec. II-E).
+ *   seed         Philox4x32-10 key (low word, high word).
+ *   conv_tol, conv_window   freeze a contour after conv_window consecutive steps with
+ *                max(|dR|, |dc|) < conv_tol; conv_window = 0 runs to the iteration limit.
+ *   e0           energy threshold of the selection (Results: contours above E0 are removed).
+ *   flags        bit 0: do not rotate the direction table (test mode; biased sampling).
+ */
+typedef struct snk_params {
+    int32_t dim;
+    double spacing[3];
+    double sigma_pre;
+    double i_offset, i_scale;
+    double dR;
+    double eps0;
+    double r_min, r_max, r_init;
+    int32_t n_dirs, n_rays, n_radial;
+    uint64_t seed;
+    double conv_tol;
+    int32_t conv_window;
+    double e0;
+    int32_t flags;
+} snk_params;
+
+/* Width of one contour's row written by snk_trace_step. Layout:
+ *  0 A = (V/N) sum S*I          1 B_R = (V/N) sum dS/dR * I
+ *  2..4 B_c = -(V/N) sum dS/dr * I * u  (x, y, z; z = 0 in 2D)
+ *  5 E_mc = A / (2R)^d          6 dR step = -(eps/2) (B_R - (d/R) A) / (2R)^d  (before clamping)
+ *  7..9 dc step = -(eps/2) B_c / (2R)^d                                             (physical)
+ *  10 n (iteration number)      11 R before the step       12 eps
+ *  13..15 reserved (0). */
+#define SNK_TRACE_W 16
+
+typedef struct snk_ctx snk_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream` (a hipStream_t; NULL means
+ * the device's null stream). The stream must outlive the context. */
+snk_status snk_create(snk_ctx **out, int device, void *hip_stream);
+
+/* Free the context and every device buffer it owns (synchronises its stream first). */
+snk_status snk_destroy(snk_ctx *ctx);
+
+/* Validate and store the parameters (copied). Must precede snk_load_seeds. Changing sigma_pre,
+ * i_offset, i_scale or spacing after a volume is loaded re-runs the pre-pass at the next evolve. */
+snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
+
+/* Launch shape of the evolution kernel: wave64s per contour (workgroup size 64 * waves);
+ * 0 = automatic (4, fewer when a contour-iteration has under two points per thread), 1, 2, 4 or
+ * 8. Results do not depend on it beyond FP32 summation order. */
+snk_status snk_set_launch(snk_ctx *ctx, int32_t waves_per_contour);
+
+/* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288 (the
+ * table is staged in LDS). D must equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per
+ * contour-iteration, carry the Monte-Carlo rays. */
+snk_status snk_set_directions(snk_ctx *ctx, const float *dirs, int32_t D);
+
+/* Load a raw volume nx*ny*nz of `dtype` (host pointer copied, or device pointer borrowed when
+ * on_device = 1). The pre-pass (Sec. II-E low-pass) runs at the next snk_prepass / snk_evolve.
+ * nx*ny*nz must be below 2^31; for dim = 3 every axis needs >= 2 voxels. */
+snk_status snk_load_volume(snk_ctx *ctx, const void *data, snk_dtype dtype, int64_t nx, int64_t ny,
+                           int64_t nz, int on_device);
+
+/* Run the pre-pass now: J = Gaussian_{sigma_pre/h}((raw - i_offset) * i_scale), separable,
+ * taps |k| <= ceil(3 sigma), clamp-to-edge. Enqueued on the stream. */
+snk_status snk_prepass(snk_ctx *ctx);
+
+/* Seed n contours (host pointers): centres n x 3 physical (double), optional per-seed initial
+ * radii r0 (NULL: params.r_init), optional 32-bit ids (NULL: 0..n-1) that key the Philox
+ * streams, so a contour's samples do not depend on its position in the list. Radii are clamped
+ * into the bounds; seeds outside the volume start as SNK_OUT. Resets iteration counters. */
+snk_status snk_load_seeds(snk_ctx *ctx, const double *centers, const float *r0, const uint32_t *ids,
+                          int64_t n);
+
+/* Run up to n_iter further iterations of every SNK_ACTIVE contour (Eqs. (7)-(15) with
+ * Monte-Carlo sums, Sec. II-E); each contour continues its own iteration counter, so
+ * evolve(a) then evolve(b) equals evolve(a + b). Runs the pre-pass first if needed. */
+snk_status snk_evolve(snk_ctx *ctx, int32_t n_iter);
+
+/* End of evolution (Results): contours still ACTIVE become SNK_MAXITER; compute the exact
+ * Eq. (5) energy E_vox of every contour (sum over the lattice points within R + dR/2, times the
+ * voxel measure, clamp-to-edge outside the volume); then select: candidates are CONVERGED or
+ * MAXITER with E_vox <= e0, and overlapping candidates (|c' - c''| < rho*max(R', R'')) compete,
+ * the lower (E_vox, id) surviving -- identical to sequential greedy in ascending order. */
+snk_status snk_finalize(snk_ctx *ctx);
+
+/* Read back (synchronises). Any output pointer may be NULL. radii, e_mc (last Monte-Carlo
+ * energy), e_vox (exact energy, valid after snk_finalize), iters, status, keep (1 = detected
+ * cell) are n-long; centers is n x 3 physical (double). If cap < n nothing is written,
+ * *n_out = n and SNK_ERANGE is returned. */
+snk_status snk_read(snk_ctx *ctx, float *radii, double *centers, float *e_mc, float *e_vox,
+                    int32_t *iters, uint8_t *status, uint8_t *keep, int64_t cap, int64_t *n_out);
+
+/* Checkpoint: the full evolving state (centre, radius, iteration counter, status, convergence
+ * streak). Same capacity rule as snk_read. */
+snk_status snk_get_state(snk_ctx *ctx, double *centers, float *radii, int32_t *iters,
+                         uint8_t *status, uint8_t *streak, int64_t cap, int64_t *n_out);
+
+/* Resume / teacher forcing: overwrite the state of the n loaded contours (n must equal the
+ * seeded count). streak may be NULL (zeros). */
+snk_status snk_set_state(snk_ctx *ctx, const double *centers, const float *radii, const int32_t *iters,
+                         const uint8_t *status, const uint8_t *streak, int64_t n);
+
+/* Parity aid: run exactly one iteration of every ACTIVE contour and write its terms
+ * (n x SNK_TRACE_W floats, host pointer; rows of inactive contours are zero). Synchronises. */
+snk_status snk_trace_step(snk_ctx *ctx, float *terms);
+
+/* Copy the smoothed FP32 volume J (nx*ny*nz) to `out` (host, or device when on_device = 1). */
+snk_status snk_read_volume(snk_ctx *ctx, float *out, int on_device);
+
+/* Kernel timings of the last calls, from HIP events recorded around each launch on the
+ * context's stream (synchronises). evolved = contour-iterations run by the last snk_evolve;
+ * vertex-updates = evolved * n_rays. */
+typedef struct snk_timing {
+    double prepass_ms;
+    double evolve_ms;
+    double finalize_ms;
+    int64_t evolved;
+    int64_t evolve_launches;
+} snk_timing;
+snk_status snk_get_timing(snk_ctx *ctx, snk_timing *t);
+
+/* Wait for all work enqueued on the context's stream. */
+snk_status snk_sync(snk_ctx *ctx);
+
+/* Message of the last failed call on this context ("" if none). NULL ctx: last create error. */
+const char *snk_last_error(const snk_ctx *ctx);
+
+/* Library version string. */
+const char *snk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNK_H */

@@ -209,7 +209,9 @@ class State:
                        ("c", "R", "iters", "status", "streak", "e_mc", "ids")))
 
 
-def init_state(p, seeds, r0=None, ids=None) -> State:
+def init_state(p, seeds, r0=None, ids=None, shape_zyx=None) -> State:
+    """Contours at the seeds with R = clamp(R0); with the volume shape given, seeds outside the
+    volume start OUT."""
     seeds = np.asarray(seeds, dtype=np.float64)
     n = len(seeds)
     c = np.zeros((n, 3))
@@ -220,8 +222,13 @@ def init_state(p, seeds, r0=None, ids=None) -> State:
         r0 = np.full(n, float(p.r_init))
     R = np.array([initial_radius(p, float(v)) for v in np.broadcast_to(r0, (n,))])
     ids = np.arange(n, dtype=np.uint32) if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
-    return State(c, R, np.zeros(n, np.int32), np.zeros(n, np.uint8), np.zeros(n, np.uint8),
-                 np.zeros(n), ids)
+    status = np.zeros(n, np.uint8)
+    if shape_zyx is not None:
+        nz, ny, nx = shape_zyx
+        ext = (np.array([nx, ny, nz]) - 1) * np.asarray(p.spacing, dtype=np.float64)
+        for a in range(p.dim):
+            status[(c[:, a] < 0.0) | (c[:, a] > ext[a])] = OUT
+    return State(c, R, np.zeros(n, np.int32), status, np.zeros(n, np.uint8), np.zeros(n), ids)
 
 
 def evolve(J, p, dirs, st: State, n_iter: int, trace: bool = False):
@@ -287,7 +294,7 @@ def cull_ambiguity(p, c, R, e_vox, rel_e=1e-4, tol_d=1e-3):
 def run(raw, p, dirs, seeds, n_iter, r0=None, ids=None):
     """Whole path: pre-pass, init, evolve n_iter, stop status, exact energy, selection."""
     J = prepass(raw, p)
-    st = init_state(p, seeds, r0, ids)
+    st = init_state(p, seeds, r0, ids, shape_zyx=raw.shape)
     _, done = evolve(J, p, dirs, st, n_iter)
     finalize_status(st)
     e_vox, e_abs = energy_vox(J, p, st.c, st.R)

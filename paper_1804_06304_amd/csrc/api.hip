@@ -1,0 +1,645 @@
+// Host side of the C ABI declared in include/snk.h: context, device buffers, parameter
+// validation, kernel launches on the caller's stream, readback and event timing.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "snk_internal.h"
+
+using snk::DevContour;
+
+struct snk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    snk_params P{};
+    bool have_params = false;
+    int waves = 0;  // 0: automatic
+
+    std::vector<float> dirs_host;
+    float *d_dirs = nullptr;
+    size_t dirs_cap = 0;
+    int D = 0;
+
+    int64_t nx = 0, ny = 0, nz = 0;
+    snk_dtype dtype = SNK_U8;
+    const void *raw = nullptr;      // borrowed or owned
+    void *raw_owned = nullptr;
+    size_t raw_owned_cap = 0;
+    float *J = nullptr;
+    size_t J_cap = 0;
+    bool have_volume = false;
+    bool J_dirty = true;
+
+    int64_t n = 0;
+    DevContour *d_st = nullptr;
+    double *d_evox = nullptr;
+    size_t n_cap = 0, evox_cap = 0;
+    float *d_trace = nullptr;
+    size_t trace_cap = 0;
+
+    int *d_cell_start = nullptr, *d_cell_fill = nullptr, *d_items = nullptr, *d_cell_of = nullptr,
+        *d_dec = nullptr;
+    size_t grid_cap = 0, sel_cap = 0;
+
+    unsigned long long *d_counters = nullptr;  // [0] evolved, [1] kept
+
+    hipEvent_t ev[6] = {};
+    bool ev_pre = false, ev_evo = false, ev_fin = false;
+    int64_t evolve_launches = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+snk_status fail(snk_ctx *c, snk_status code, const std::string &msg) {
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return code;
+}
+
+snk_status hip_fail(snk_ctx *c, hipError_t e, const char *what) {
+    return fail(c, SNK_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPTRY(c, call)                                      \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
+    } while (0)
+
+template <typename T>
+snk_status ensure(snk_ctx *c, T **p, size_t *cap, size_t count) {
+    if (*cap >= count && *p) return SNK_OK;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+        if (e != hipSuccess) return hip_fail(c, e, "hipFree");
+    }
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return fail(c, SNK_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    *p = static_cast<T *>(q);
+    *cap = count;
+    return SNK_OK;
+}
+
+double rho_of(int dim) { return dim == 3 ? pow(2.0, -1.0 / 3.0) : sqrt(0.5); }
+
+double r_low(const snk_params &p) {
+    const double rho = rho_of(p.dim);
+    const double geo = p.dR * (1.0 + rho) / (2.0 * (1.0 - rho));
+    return std::max(p.r_min, geo);
+}
+
+snk_status check_params(snk_ctx *c, const snk_params &p) {
+    if (p.dim != 2 && p.dim != 3) return fail(c, SNK_EINVAL, "dim must be 2 or 3");
+    for (int i = 0; i < 3; ++i)
+        if (!(p.spacing[i] > 0.0) || !isfinite(p.spacing[i])) return fail(c, SNK_EINVAL, "spacing must be > 0");
+    if (!(p.sigma_pre >= 0.0)) return fail(c, SNK_EINVAL, "sigma_pre must be >= 0");
+    if (!isfinite(p.i_offset) || !isfinite(p.i_scale)) return fail(c, SNK_EINVAL, "i_offset/i_scale not finite");
+    if (!(p.dR > 0.0)) return fail(c, SNK_EINVAL, "dR must be > 0");
+    if (!(p.eps0 >= 0.0) || !isfinite(p.eps0)) return fail(c, SNK_EINVAL, "eps0 must be finite and >= 0");
+    if (!(p.r_max >= r_low(p))) return fail(c, SNK_EINVAL, "r_max below the smallest admissible radius");
+    if (p.n_dirs <= 0) return fail(c, SNK_EINVAL, "n_dirs must be > 0");
+    if (p.n_rays <= 0 || (p.n_rays & 1)) return fail(c, SNK_EINVAL, "n_rays must be even and > 0");
+    if (p.n_radial <= 0) return fail(c, SNK_EINVAL, "n_radial must be > 0");
+    if ((int64_t)p.n_rays * p.n_radial > (1 << 20)) return fail(c, SNK_EINVAL, "n_rays*n_radial too large");
+    if (!(p.conv_tol >= 0.0) || p.conv_window < 0 || p.conv_window > 255)
+        return fail(c, SNK_EINVAL, "conv_tol >= 0 and 0 <= conv_window <= 255 required");
+    if (!isfinite(p.e0)) return fail(c, SNK_EINVAL, "e0 not finite");
+    return SNK_OK;
+}
+
+bool same_prepass(const snk_params &a, const snk_params &b) {
+    return a.dim == b.dim && a.sigma_pre == b.sigma_pre && a.i_offset == b.i_offset && a.i_scale == b.i_scale &&
+           a.spacing[0] == b.spacing[0] && a.spacing[1] == b.spacing[1] && a.spacing[2] == b.spacing[2];
+}
+
+snk::Geometry geometry(const snk_ctx *c) {
+    snk::Geometry g;
+    g.J = c->J;
+    g.nx = (int)c->nx;
+    g.ny = (int)c->ny;
+    g.nz = (int)c->nz;
+    for (int i = 0; i < 3; ++i) {
+        g.h[i] = (float)c->P.spacing[i];
+        g.inv_h[i] = (float)(1.0 / c->P.spacing[i]);
+    }
+    return g;
+}
+
+// centre (physical, double) -> anchor + offset (voxel units)
+void to_anchor(const snk_ctx *c, const double *cen, DevContour &s) {
+    for (int i = 0; i < 3; ++i) {
+        if (i >= c->P.dim) {
+            s.anc[i] = 0;
+            s.off[i] = 0.0f;
+            continue;
+        }
+        const double v = cen[i] / c->P.spacing[i];
+        const double a = floor(v + 0.5);
+        s.anc[i] = (int32_t)std::max(std::min(a, 2.0e9), -2.0e9);
+        s.off[i] = (float)(v - (double)s.anc[i]);
+    }
+}
+
+bool inside(const snk_ctx *c, const DevContour &s) {
+    const int64_t nn[3] = {c->nx, c->ny, c->nz};
+    for (int i = 0; i < c->P.dim; ++i) {
+        const double v = (double)s.anc[i] + (double)s.off[i];
+        if (!(v >= 0.0) || v > (double)(nn[i] - 1)) return false;
+    }
+    return true;
+}
+
+snk_status need(snk_ctx *c, bool vol, bool seeds) {
+    if (!c->have_params) return fail(c, SNK_ESTATE, "parameters not set");
+    if (vol && !c->have_volume) return fail(c, SNK_ESTATE, "no volume loaded");
+    if (seeds && c->n <= 0) return fail(c, SNK_ESTATE, "no seeds loaded");
+    return SNK_OK;
+}
+
+snk_status run_prepass(snk_ctx *c) {
+    snk::PrepassArgs a{};
+    a.raw = c->raw;
+    a.dtype = (int)c->dtype;
+    a.J = c->J;
+    a.nx = (int)c->nx;
+    a.ny = (int)c->ny;
+    a.nz = (int)c->nz;
+    a.i_offset = (float)c->P.i_offset;
+    a.i_scale = (float)c->P.i_scale;
+    int *rad[3] = {&a.rx, &a.ry, &a.rz};
+    float *tap[3] = {a.gx, a.gy, a.gz};
+    const int64_t nn[3] = {c->nx, c->ny, c->nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        const double s = c->P.sigma_pre / c->P.spacing[ax];
+        const bool use = s > 0.0 && ax < c->P.dim && nn[ax] > 1;
+        const int r = use ? (int)ceil(3.0 * s) : 0;
+        if (r > snk::kPrepassMaxR) return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass (radius > 16)");
+        *rad[ax] = r;
+        std::vector<double> g(2 * r + 1);
+        double sum = 0.0;
+        for (int k = -r; k <= r; ++k) {
+            g[k + r] = r ? exp(-(double)k * k / (2.0 * s * s)) : 1.0;
+            sum += g[k + r];
+        }
+        for (int k = 0; k <= 2 * r; ++k) tap[ax][k] = (float)(g[k] / sum);
+    }
+    const size_t lds = sizeof(float) * ((size_t)(snk::kPrepassTY + 2 * a.ry) * (snk::kPrepassTX + 2 * a.rx) +
+                                        (size_t)(snk::kPrepassTY + 2 * a.ry) * snk::kPrepassTX +
+                                        (size_t)(2 * a.rz + 1) * snk::kPrepassTY * snk::kPrepassTX);
+    if (lds > 65536) return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
+    HIPTRY(c, hipEventRecord(c->ev[0], c->stream));
+    HIPTRY(c, snk::launch_prepass(a, c->stream));
+    HIPTRY(c, hipEventRecord(c->ev[1], c->stream));
+    c->ev_pre = true;
+    c->J_dirty = false;
+    return SNK_OK;
+}
+
+int pick_waves(const snk_ctx *c) {
+    if (c->waves > 0) return c->waves;
+    const int npts = c->P.n_rays * c->P.n_radial;
+    int w = 4;
+    while (w > 1 && npts < 64 * w * 2) w >>= 1;   // at least two points per thread
+    return w;
+}
+
+snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
+    if (c->D != c->P.n_dirs) return fail(c, SNK_ESTATE, "direction table size != params.n_dirs");
+    if (c->J_dirty) {
+        snk_status st = run_prepass(c);
+        if (st != SNK_OK) return st;
+    }
+    snk::EvolveArgs a{};
+    a.g = geometry(c);
+    a.dirs = c->d_dirs;
+    a.st = c->d_st;
+    a.n = (int)c->n;
+    a.n_iter = n_iter;
+    a.D = c->D;
+    a.M = c->P.n_rays;
+    a.L = c->P.n_radial;
+    a.key0 = (uint32_t)(c->P.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->P.seed >> 32);
+    a.flags = c->P.flags;
+    a.dR = (float)c->P.dR;
+    a.eps0 = (float)c->P.eps0;
+    a.r_lo = (float)r_low(c->P);
+    a.r_hi = (float)c->P.r_max;
+    a.conv_tol = (float)c->P.conv_tol;
+    a.conv_window = c->P.conv_window;
+    a.trace = trace ? c->d_trace : nullptr;
+    a.counter = c->d_counters;
+    HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
+    HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
+    HIPTRY(c, snk::launch_evolve(a, c->P.dim, pick_waves(c), trace, c->stream));
+    HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
+    c->ev_evo = true;
+    c->evolve_launches += 1;
+    return SNK_OK;
+}
+
+snk_status unpack(snk_ctx *c, std::vector<DevContour> &h) {
+    h.resize((size_t)c->n);
+    if (c->n > 0)
+        HIPTRY(c, hipMemcpyAsync(h.data(), c->d_st, sizeof(DevContour) * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SNK_OK;
+}
+
+void centre_of(const snk_ctx *c, const DevContour &s, double *out) {
+    for (int i = 0; i < 3; ++i)
+        out[i] = i < c->P.dim ? ((double)s.anc[i] + (double)s.off[i]) * c->P.spacing[i] : 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *snk_version(void) { return "snk 0.1 (gfx950)"; }
+
+const char *snk_last_error(const snk_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+snk_status snk_create(snk_ctx **out, int device, void *hip_stream) {
+    if (!out) return fail(nullptr, SNK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(nullptr, SNK_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(nullptr, SNK_EINVAL, "device index out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, SNK_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    snk_ctx *c = new (std::nothrow) snk_ctx();
+    if (!c) return fail(nullptr, SNK_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    for (auto &ev : c->ev) {
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            snk_destroy(c);
+            return fail(nullptr, SNK_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+        }
+    }
+    e = hipMalloc(&c->d_counters, 4 * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        snk_destroy(c);
+        return fail(nullptr, SNK_ENOMEM, "hipMalloc counters");
+    }
+    *out = c;
+    return SNK_OK;
+}
+
+snk_status snk_destroy(snk_ctx *c) {
+    if (!c) return SNK_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
+                    c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (auto &ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    delete c;
+    return SNK_OK;
+}
+
+snk_status snk_set_params(snk_ctx *c, const snk_params *p) {
+    if (!c || !p) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = check_params(c, *p);
+    if (st != SNK_OK) return st;
+    if (c->have_params && !same_prepass(c->P, *p)) c->J_dirty = true;
+    if (c->have_volume && p->dim == 3 && (c->nx < 2 || c->ny < 2 || c->nz < 2))
+        return fail(c, SNK_EINVAL, "dim 3 needs >= 2 voxels on every axis");
+    c->P = *p;
+    c->have_params = true;
+    return SNK_OK;
+}
+
+snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (waves_per_contour != 0 && waves_per_contour != 1 && waves_per_contour != 2 && waves_per_contour != 4 &&
+        waves_per_contour != 8)
+        return fail(c, SNK_EINVAL, "waves_per_contour must be 0 (auto), 1, 2, 4 or 8");
+    c->waves = waves_per_contour;
+    return SNK_OK;
+}
+
+snk_status snk_set_directions(snk_ctx *c, const float *dirs, int32_t D) {
+    if (!c || !dirs || D <= 0) return fail(c, SNK_EINVAL, "bad direction table");
+    snk_status st = need(c, false, false);
+    if (st != SNK_OK) return st;
+    const int dim = c->P.dim;
+    if ((int64_t)D * dim > 12288) return fail(c, SNK_EINVAL, "direction table too large (D * dim > 12288)");
+    for (int32_t k = 0; k < D; ++k) {
+        double n2 = 0.0;
+        for (int i = 0; i < dim; ++i) n2 += (double)dirs[k * dim + i] * dirs[k * dim + i];
+        if (!(fabs(n2 - 1.0) < 1e-5)) return fail(c, SNK_EINVAL, "direction table rows must be unit vectors");
+    }
+    (void)hipSetDevice(c->device);
+    st = ensure(c, &c->d_dirs, &c->dirs_cap, (size_t)D * dim);
+    if (st != SNK_OK) return st;
+    c->dirs_host.assign(dirs, dirs + (size_t)D * dim);
+    HIPTRY(c, hipMemcpyAsync(c->d_dirs, c->dirs_host.data(), sizeof(float) * D * dim, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    c->D = D;
+    return SNK_OK;
+}
+
+snk_status snk_load_volume(snk_ctx *c, const void *data, snk_dtype dtype, int64_t nx, int64_t ny, int64_t nz,
+                           int on_device) {
+    if (!c || !data) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = need(c, false, false);
+    if (st != SNK_OK) return st;
+    if (dtype != SNK_U8 && dtype != SNK_U16 && dtype != SNK_F32) return fail(c, SNK_EINVAL, "bad dtype");
+    if (nx < 2 || ny < 2 || nz < 1) return fail(c, SNK_EINVAL, "volume needs nx, ny >= 2 and nz >= 1");
+    if (c->P.dim == 3 && nz < 2) return fail(c, SNK_EINVAL, "dim 3 needs nz >= 2");
+    if (c->P.dim == 2 && nz != 1) return fail(c, SNK_EINVAL, "dim 2 needs nz == 1");
+    if (nx * ny * nz >= (int64_t)1 << 31) return fail(c, SNK_EINVAL, "volume too large (>= 2^31 voxels)");
+    (void)hipSetDevice(c->device);
+    const size_t vox = (size_t)(nx * ny * nz);
+    const size_t esz = dtype == SNK_U8 ? 1 : (dtype == SNK_U16 ? 2 : 4);
+    if (on_device) {
+        c->raw = data;
+    } else {
+        st = ensure(c, reinterpret_cast<uint8_t **>(&c->raw_owned), &c->raw_owned_cap, vox * esz);
+        if (st != SNK_OK) return st;
+        HIPTRY(c, hipMemcpyAsync(c->raw_owned, data, vox * esz, hipMemcpyHostToDevice, c->stream));
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        c->raw = c->raw_owned;
+    }
+    st = ensure(c, &c->J, &c->J_cap, vox);
+    if (st != SNK_OK) return st;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->dtype = dtype;
+    c->have_volume = true;
+    c->J_dirty = true;
+    c->n = 0;  // seeds refer to a volume
+    return SNK_OK;
+}
+
+snk_status snk_prepass(snk_ctx *c) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    (void)hipSetDevice(c->device);
+    return run_prepass(c);
+}
+
+snk_status snk_load_seeds(snk_ctx *c, const double *centers, const float *r0, const uint32_t *ids, int64_t n) {
+    if (!c || (n > 0 && !centers) || n < 0) return fail(c, SNK_EINVAL, "bad seed arguments");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    if (n >= (int64_t)1 << 31) return fail(c, SNK_EINVAL, "too many seeds");
+    (void)hipSetDevice(c->device);
+    std::vector<DevContour> h((size_t)n);
+    const double lo = r_low(c->P), hi = c->P.r_max;
+    for (int64_t i = 0; i < n; ++i) {
+        DevContour &s = h[i];
+        memset(&s, 0, sizeof(s));
+        to_anchor(c, &centers[i * 3], s);
+        double R = r0 ? (double)r0[i] : c->P.r_init;
+        if (!isfinite(R)) return fail(c, SNK_EINVAL, "initial radius not finite");
+        R = std::min(std::max(R, lo), hi);
+        s.R = (float)R;
+        s.e_mc = 0.0f;
+        s.e_vox = 0.0f;
+        s.iters = 0;
+        s.id = ids ? ids[i] : (uint32_t)i;
+        s.status = inside(c, s) ? SNK_ACTIVE : SNK_OUT;
+        s.streak = 0;
+        s.keep = 0;
+    }
+    st = ensure(c, &c->d_st, &c->n_cap, (size_t)n);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_evox, &c->evox_cap, (size_t)n);
+    if (st != SNK_OK) return st;
+    if (n > 0)
+        HIPTRY(c, hipMemcpyAsync(c->d_st, h.data(), sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    c->n = n;
+    return SNK_OK;
+}
+
+snk_status snk_evolve(snk_ctx *c, int32_t n_iter) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (n_iter < 0) return fail(c, SNK_EINVAL, "n_iter must be >= 0");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    if (c->n == 0 || n_iter == 0) return SNK_OK;
+    (void)hipSetDevice(c->device);
+    return run_evolve(c, n_iter, false);
+}
+
+snk_status snk_trace_step(snk_ctx *c, float *terms) {
+    if (!c || !terms) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = need(c, true, true);
+    if (st != SNK_OK) return st;
+    (void)hipSetDevice(c->device);
+    st = ensure(c, &c->d_trace, &c->trace_cap, (size_t)c->n * SNK_TRACE_W);
+    if (st != SNK_OK) return st;
+    HIPTRY(c, hipMemsetAsync(c->d_trace, 0, sizeof(float) * c->n * SNK_TRACE_W, c->stream));
+    st = run_evolve(c, 1, true);
+    if (st != SNK_OK) return st;
+    HIPTRY(c, hipMemcpyAsync(terms, c->d_trace, sizeof(float) * c->n * SNK_TRACE_W, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SNK_OK;
+}
+
+snk_status snk_finalize(snk_ctx *c) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    if (c->n == 0) return SNK_OK;
+    (void)hipSetDevice(c->device);
+    if (c->J_dirty) {
+        st = run_prepass(c);
+        if (st != SNK_OK) return st;
+    }
+    snk::FinalizeArgs a{};
+    a.g = geometry(c);
+    a.st = c->d_st;
+    a.e_vox = c->d_evox;
+    a.n = (int)c->n;
+    a.dR = (float)c->P.dR;
+    a.e0 = (float)c->P.e0;
+    a.r_hi = (float)c->P.r_max;
+    const double rho = rho_of(c->P.dim);
+    double cell = rho * c->P.r_max * 1.01 + 0.01;
+    const int64_t nn[3] = {c->nx, c->ny, c->nz};
+    int64_t G = 1;
+    for (int iter = 0; iter < 64; ++iter) {
+        G = 1;
+        for (int i = 0; i < 3; ++i) {
+            const int64_t gi = i < c->P.dim ? (int64_t)floor((double)(nn[i] - 1) * c->P.spacing[i] / cell) + 1 : 1;
+            a.G[i] = (int)gi;
+            G *= gi;
+        }
+        if (G <= ((int64_t)1 << 22)) break;
+        cell *= 1.5;
+    }
+    a.cell = (float)cell;
+    st = ensure(c, &c->d_cell_start, &c->grid_cap, (size_t)G + 1);
+    if (st != SNK_OK) return st;
+    size_t cap2 = 0;
+    if (c->d_cell_fill) (void)hipFree(c->d_cell_fill);
+    c->d_cell_fill = nullptr;
+    st = ensure(c, &c->d_cell_fill, &cap2, (size_t)G + 1);
+    if (st != SNK_OK) return st;
+    if (c->sel_cap < (size_t)c->n) {
+        for (int **p : {&c->d_items, &c->d_cell_of, &c->d_dec}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        size_t k1 = 0, k2 = 0, k3 = 0;
+        if ((st = ensure(c, &c->d_items, &k1, (size_t)c->n)) != SNK_OK) return st;
+        if ((st = ensure(c, &c->d_cell_of, &k2, (size_t)c->n)) != SNK_OK) return st;
+        if ((st = ensure(c, &c->d_dec, &k3, (size_t)c->n)) != SNK_OK) return st;
+        c->sel_cap = (size_t)c->n;
+    }
+    a.cell_start = c->d_cell_start;
+    a.cell_fill = c->d_cell_fill;
+    a.items = c->d_items;
+    a.cell_of = c->d_cell_of;
+    a.dec = c->d_dec;
+    a.counter = c->d_counters + 1;
+    HIPTRY(c, hipMemsetAsync(c->d_counters + 1, 0, sizeof(unsigned long long), c->stream));
+    HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
+    HIPTRY(c, snk::launch_energy_vox(a, c->P.dim, c->stream));
+    HIPTRY(c, snk::launch_select(a, c->P.dim, c->stream));
+    HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
+    c->ev_fin = true;
+    return SNK_OK;
+}
+
+snk_status snk_read(snk_ctx *c, float *radii, double *centers, float *e_mc, float *e_vox, int32_t *iters,
+                    uint8_t *status, uint8_t *keep, int64_t cap, int64_t *n_out) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (n_out) *n_out = c->n;
+    if (cap < c->n) return fail(c, SNK_ERANGE, "capacity smaller than the number of contours");
+    (void)hipSetDevice(c->device);
+    std::vector<DevContour> h;
+    snk_status st = unpack(c, h);
+    if (st != SNK_OK) return st;
+    for (int64_t i = 0; i < c->n; ++i) {
+        const DevContour &s = h[i];
+        if (radii) radii[i] = s.R;
+        if (centers) centre_of(c, s, &centers[i * 3]);
+        if (e_mc) e_mc[i] = s.e_mc;
+        if (e_vox) e_vox[i] = s.e_vox;
+        if (iters) iters[i] = s.iters;
+        if (status) status[i] = s.status;
+        if (keep) keep[i] = s.keep;
+    }
+    return SNK_OK;
+}
+
+snk_status snk_get_state(snk_ctx *c, double *centers, float *radii, int32_t *iters, uint8_t *status,
+                         uint8_t *streak, int64_t cap, int64_t *n_out) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (n_out) *n_out = c->n;
+    if (cap < c->n) return fail(c, SNK_ERANGE, "capacity smaller than the number of contours");
+    (void)hipSetDevice(c->device);
+    std::vector<DevContour> h;
+    snk_status st = unpack(c, h);
+    if (st != SNK_OK) return st;
+    for (int64_t i = 0; i < c->n; ++i) {
+        if (centers) centre_of(c, h[i], &centers[i * 3]);
+        if (radii) radii[i] = h[i].R;
+        if (iters) iters[i] = h[i].iters;
+        if (status) status[i] = h[i].status;
+        if (streak) streak[i] = h[i].streak;
+    }
+    return SNK_OK;
+}
+
+snk_status snk_set_state(snk_ctx *c, const double *centers, const float *radii, const int32_t *iters,
+                         const uint8_t *status, const uint8_t *streak, int64_t n) {
+    if (!c || !centers || !radii || !iters || !status) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = need(c, true, true);
+    if (st != SNK_OK) return st;
+    if (n != c->n) return fail(c, SNK_EINVAL, "n must equal the number of seeded contours");
+    (void)hipSetDevice(c->device);
+    std::vector<DevContour> h;
+    st = unpack(c, h);
+    if (st != SNK_OK) return st;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(radii[i] > 0.0f) || !(radii[i] <= (float)c->P.r_max) || iters[i] < 0)
+            return fail(c, SNK_EINVAL, "state radius outside (0, r_max] or negative iteration count");
+        if ((status[i] & 0x0f) > SNK_NONFINITE) return fail(c, SNK_EINVAL, "bad status value");
+        to_anchor(c, &centers[i * 3], h[i]);
+        h[i].R = radii[i];
+        h[i].iters = iters[i];
+        h[i].status = status[i];
+        h[i].streak = streak ? streak[i] : 0;
+        h[i].keep = 0;
+    }
+    if (n > 0)
+        HIPTRY(c, hipMemcpyAsync(c->d_st, h.data(), sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SNK_OK;
+}
+
+snk_status snk_read_volume(snk_ctx *c, float *out, int on_device) {
+    if (!c || !out) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    (void)hipSetDevice(c->device);
+    if (c->J_dirty) {
+        st = run_prepass(c);
+        if (st != SNK_OK) return st;
+    }
+    const size_t bytes = sizeof(float) * (size_t)(c->nx * c->ny * c->nz);
+    HIPTRY(c, hipMemcpyAsync(out, c->J, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    if (!on_device) HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SNK_OK;
+}
+
+snk_status snk_get_timing(snk_ctx *c, snk_timing *t) {
+    if (!c || !t) return fail(c, SNK_EINVAL, "NULL argument");
+    (void)hipSetDevice(c->device);
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    float ms = 0.0f;
+    t->prepass_ms = t->evolve_ms = t->finalize_ms = 0.0;
+    if (c->ev_pre) {
+        HIPTRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        t->prepass_ms = ms;
+    }
+    if (c->ev_evo) {
+        HIPTRY(c, hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+        t->evolve_ms = ms;
+    }
+    if (c->ev_fin) {
+        HIPTRY(c, hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+        t->finalize_ms = ms;
+    }
+    unsigned long long cnt = 0;
+    HIPTRY(c, hipMemcpy(&cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    t->evolved = (int64_t)cnt;
+    t->evolve_launches = c->evolve_launches;
+    return SNK_OK;
+}
+
+snk_status snk_sync(snk_ctx *c) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    (void)hipSetDevice(c->device);
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SNK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+// End of evolution (Results of the paper): exact energy and selection.
+//
+// energy_vox_kernel: one workgroup per contour evaluates Eq. (5) literally over the lattice points
+// within R + dR/2 of the centre (clamp-to-edge values outside the volume), times the voxel measure,
+// divided by (2R)^d. FP32 terms, FP64 accumulation, fixed-order reduction. Contours still ACTIVE
+// become MAXITER here.
+//
+// select_kernel: one workgroup. Candidates (CONVERGED or MAXITER, E_vox <= E0) are binned on a
+// uniform grid with cell >= rho * r_max, so every overlapping pair (|c' - c''| < rho max(R', R''))
+// lies in neighbouring cells. Rounds of "accept a candidate whose (E_vox, id) is the smallest among
+// its undecided overlapping neighbours and that has no accepted overlapping neighbour; reject a
+// candidate with an accepted overlapping neighbour" run until nothing is undecided. An accepted
+// neighbour always has the smaller key, and the undecided candidate with the globally smallest key
+// is decided in every round, so the result equals the sequential greedy of the paper's competition
+// (lower energy survives) taken in ascending (E_vox, id) order.
+#include <math.h>
+
+#include "snk_internal.h"
+
+namespace snk {
+
+namespace {
+
+constexpr int EV_T = 256;
+constexpr int SEL_T = 1024;
+
+template <int DIM>
+__device__ __forceinline__ float weight_S(float r, float R, float dR) {
+    constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
+    const float ain = RHO * R, dr = RHO * dR;
+    if (r < ain - 0.5f * dr) return -1.0f;
+    if (r < ain + 0.5f * dr) return (r - ain) * (2.0f / dr);
+    if (r < R - 0.5f * dR) return 1.0f;
+    if (r < R + 0.5f * dR) return 0.5f - (r - R) * (1.0f / dR);
+    return 0.0f;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(EV_T) void energy_vox_kernel(FinalizeArgs a) {
+    __shared__ double part[EV_T / 64];
+    const int cid = blockIdx.x;
+    const int t = threadIdx.x;
+    DevContour s = a.st[cid];
+    const Geometry g = a.g;
+    const float R = s.R;
+    if (!isfinite(R) || !(R > 0.0f) || !(R <= a.r_hi) || (s.status & 0x0f) == SNK_NONFINITE) {
+        if (t == 0) {
+            a.e_vox[cid] = NAN;
+            a.st[cid].e_vox = NAN;
+        }
+        return;
+    }
+    const float smax = R + 0.5f * a.dR;
+    int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const float ext = smax * g.inv_h[i];
+        lo[i] = (int)floorf(s.off[i] - ext) - 1;
+        cnt[i] = (int)ceilf(s.off[i] + ext) + 1 - lo[i] + 1;
+    }
+    const int nn[3] = {g.nx, g.ny, g.nz};
+    const long total = (long)cnt[0] * cnt[1] * cnt[2];
+    double acc = 0.0;
+    for (long idx = t; idx < total; idx += EV_T) {
+        const int rx = (int)(idx % cnt[0]);
+        const int ry = (int)((idx / cnt[0]) % cnt[1]);
+        const int rz = (int)(idx / ((long)cnt[0] * cnt[1]));
+        const int rel[3] = {lo[0] + rx, lo[1] + ry, lo[2] + rz};
+        float d2 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            const float d = ((float)rel[i] - s.off[i]) * g.h[i];
+            d2 = fmaf(d, d, d2);
+        }
+        const float r = sqrtf(d2);
+        if (!(r < smax)) continue;
+        int k[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) k[i] = min(max(s.anc[i] + rel[i], 0), nn[i] - 1);
+        const float v = g.J[((long)k[2] * g.ny + k[1]) * g.nx + k[0]];
+        acc += (double)(weight_S<DIM>(r, R, a.dR) * v);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((t & 63) == 0) part[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < EV_T / 64; ++w) tot += part[w];
+        double meas = (double)g.h[0] * g.h[1] * (DIM == 3 ? g.h[2] : 1.0f);
+        double norm = 1.0;
+        for (int i = 0; i < DIM; ++i) norm *= 2.0 * (double)R;
+        const double e = tot * meas / norm;
+        a.e_vox[cid] = e;
+        DevContour o = s;
+        o.e_vox = (float)e;
+        if ((o.status & 0x0f) == SNK_ACTIVE) o.status = (uint8_t)((o.status & SNK_CLAMPED) | SNK_MAXITER);
+        a.st[cid] = o;
+    }
+}
+
+enum : int { DEC_NONE = 0, DEC_UNDECIDED = 1, DEC_ACCEPT = 2, DEC_REJECT = 3 };
+
+template <int DIM>
+__device__ __forceinline__ bool overlaps(const DevContour &x, const DevContour &y, const float h[3]) {
+    constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
+    float d2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const float d = ((float)(x.anc[i] - y.anc[i]) + (x.off[i] - y.off[i])) * h[i];
+        d2 = fmaf(d, d, d2);
+    }
+    const float thr = RHO * fmaxf(x.R, y.R);
+    return sqrtf(d2) < thr;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
+    const int t = threadIdx.x;
+    const int n = a.n;
+    const int G = a.G[0] * a.G[1] * a.G[2];
+    const Geometry g = a.g;
+    volatile int *dec = a.dec;
+
+    for (int c = t; c <= G; c += SEL_T) a.cell_start[c] = 0;
+    for (int c = t; c < G; c += SEL_T) a.cell_fill[c] = 0;
+    __syncthreads();
+    for (int i = t; i < n; i += SEL_T) {
+        const DevContour s = a.st[i];
+        const int st = s.status & 0x0f;
+        const double e = a.e_vox[i];
+        const bool cand = (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0;
+        dec[i] = cand ? DEC_UNDECIDED : DEC_NONE;
+        int cell = -1;
+        if (cand) {
+            int gi[3] = {0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const float p = ((float)s.anc[k] + s.off[k]) * g.h[k];
+                gi[k] = min(max((int)floorf(p / a.cell), 0), a.G[k] - 1);
+            }
+            cell = (gi[2] * a.G[1] + gi[1]) * a.G[0] + gi[0];
+            atomicAdd(&a.cell_start[cell + 1], 1);
+        }
+        a.cell_of[i] = cell;
+    }
+    __syncthreads();
+    // inclusive scan of cell_start[1..G] in place -> cell_start[c] = first slot of cell c
+    {
+        __shared__ int chunk_sum[SEL_T];
+        const int per = (G + SEL_T - 1) / SEL_T;
+        const int b = 1 + t * per, e = min(G + 1, b + per);
+        int run = 0;
+        for (int c = b; c < e; ++c) {
+            run += a.cell_start[c];
+            a.cell_start[c] = run;
+        }
+        chunk_sum[t] = run;
+        __syncthreads();
+        if (t == 0) {
+            int acc = 0;
+            for (int k = 0; k < SEL_T; ++k) {
+                const int v = chunk_sum[k];
+                chunk_sum[k] = acc;
+                acc += v;
+            }
+        }
+        __syncthreads();
+        const int add = chunk_sum[t];
+        for (int c = b; c < e; ++c) a.cell_start[c] += add;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += SEL_T) {
+        const int cell = a.cell_of[i];
+        if (cell >= 0) {
+            const int pos = atomicAdd(&a.cell_fill[cell], 1);
+            a.items[a.cell_start[cell] + pos] = i;
+        }
+    }
+    __syncthreads();
+
+    bool any = true;
+    int rounds = 0;
+    while (any) {
+        int local = 0;
+        for (int i = t; i < n; i += SEL_T) {
+            if (dec[i] != DEC_UNDECIDED) continue;
+            const DevContour si = a.st[i];
+            const double ei = a.e_vox[i];
+            const int cell = a.cell_of[i];
+            int gi[3] = {cell % a.G[0], (cell / a.G[0]) % a.G[1], cell / (a.G[0] * a.G[1])};
+            bool accepted_nb = false, minimal = true;
+            for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0) && !accepted_nb; ++dz)
+                for (int dy = -1; dy <= 1 && !accepted_nb; ++dy)
+                    for (int dx = -1; dx <= 1 && !accepted_nb; ++dx) {
+                        const int cx = gi[0] + dx, cy = gi[1] + dy, cz = gi[2] + dz;
+                        if (cx < 0 || cy < 0 || cz < 0 || cx >= a.G[0] || cy >= a.G[1] || cz >= a.G[2]) continue;
+                        const int c = (cz * a.G[1] + cy) * a.G[0] + cx;
+                        for (int q = a.cell_start[c]; q < a.cell_start[c + 1]; ++q) {
+                            const int j = a.items[q];
+                            if (j == i) continue;
+                            const int dj = dec[j];
+                            if (dj == DEC_REJECT) continue;
+                            const DevContour sj = a.st[j];
+                            if (!overlaps<DIM>(si, sj, g.h)) continue;
+                            if (dj == DEC_ACCEPT) {
+                                accepted_nb = true;
+                                break;
+                            }
+                            const double ej = a.e_vox[j];
+                            if (ej < ei || (ej == ei && sj.id < si.id)) minimal = false;
+                        }
+                    }
+            if (accepted_nb) dec[i] = DEC_REJECT;
+            else if (minimal) dec[i] = DEC_ACCEPT;
+            else local = 1;
+        }
+        __threadfence_block();
+        any = __syncthreads_or(local) != 0;
+        ++rounds;
+    }
+    unsigned long long kept = 0;
+    for (int i = t; i < n; i += SEL_T) {
+        const uint8_t k = dec[i] == DEC_ACCEPT ? 1 : 0;
+        a.st[i].keep = k;
+        kept += k;
+    }
+    if (kept) atomicAdd(a.counter, kept);
+}
+
+}  // namespace
+
+hipError_t launch_energy_vox(const FinalizeArgs &a, int dim, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(a.n), dim3(EV_T), 0, s, a);
+    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(a.n), dim3(EV_T), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const FinalizeArgs &a, int dim, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, a);
+    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace snk

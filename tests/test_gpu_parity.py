@@ -1,0 +1,334 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Bars (stated per test):
+  * pre-pass: |J_gpu - J_ref| <= 2e-6 * max|I| (FP32 sums of positive weights);
+  * one step (teacher forced from the oracle's state rounded to FP32): for every term X in
+    {A, B_R, B_c, E_mc, dR, dc}, |X_gpu - X_ref| <= 1e-5 * max(|X_ref|, X_abs) + slack, where X_abs
+    is X with every summand replaced by its magnitude and slack is the oracle's bound on what a
+    sample lying within 4e-6 s_max of a kink of S can change when FP32 places it on the other side;
+  * free run: |R_gpu - R_ref| <= 0.05, |c_gpu - c_ref| <= 0.5 voxel, identical iteration counts;
+  * exact energy: |E_gpu - E_ref| <= 1e-5 * E_abs; selection: identical keep sets apart from
+    decisions the oracle flags as within 1e-4 (energy) or 1e-3 voxel (overlap) of a threshold.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def snk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1804_06304_amd import snk as mod
+    mod.load()
+    return mod
+
+
+@pytest.fixture(scope="module")
+def stream():
+    import torch
+    return torch.cuda.current_stream()
+
+
+def make_ctx(snk, stream, wl, waves=0, on_device=True):
+    import torch
+    ctx = snk.Context(0, stream)
+    ctx.set_params(wl.params)
+    ctx.set_launch(waves)
+    ctx.set_directions(wl.dirs)
+    if on_device:
+        raw = torch.from_numpy(np.ascontiguousarray(wl.raw)).to("cuda:0")
+        ctx.load_volume(raw)
+        ctx._raw = raw  # keep the borrowed buffer alive
+    else:
+        ctx.load_volume(wl.raw)
+    return ctx
+
+
+def extra_seeds(wl, n, rng):
+    """Seeds spread over the whole volume (background, blob edges, near and on the faces)."""
+    nx, ny, nz = wl.shape_xyz
+    h = np.array(wl.params.spacing)
+    ext = (np.array([nx, ny, nz]) - 1) * h
+    s = rng.uniform(0.0, 1.0, size=(n, 3)) * ext
+    s[: n // 8, 0] = rng.uniform(0.0, 1.5, size=n // 8)            # near the x = 0 face
+    s[n // 8: n // 4, 1] = ext[1] - rng.uniform(0.0, 1.5, size=n // 4 - n // 8)
+    if wl.params.dim == 2:
+        s[:, 2] = 0.0
+    return s
+
+
+def tol_check(name, got, ref, ref_abs, slack, rel=1e-5):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    tol = rel * np.maximum(np.abs(ref), ref_abs) + slack + 1e-30
+    err = np.abs(got - ref)
+    bad = np.where(err > tol)[0]
+    assert len(bad) == 0, (f"{name}: {len(bad)} of {len(ref)} outside tolerance; worst "
+                           f"idx {bad[:5]} got {got[bad[:5]]} ref {ref[bad[:5]]} tol {tol[bad[:5]]}")
+    return float(np.max(err / tol)) if len(ref) else 0.0
+
+
+def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0):
+    p = wl.params
+    rng = np.random.default_rng(seed)
+    seeds = np.concatenate([wl.seeds, extra_seeds(wl, n_extra, rng)]) if n_extra else wl.seeds
+    ids = np.arange(len(seeds), dtype=np.uint32) * 7 + 3
+    r0 = rng.uniform(oracle.r_geom_min(p.dim, p.dR), p.r_max, size=len(seeds))
+    r0[: len(wl.seeds)] = p.r_init
+    J = oracle.prepass(wl.raw, p)
+    st = oracle.init_state(p, seeds, r0=r0, ids=ids, shape_zyx=wl.raw.shape)
+    ctx = make_ctx(snk, stream, wl, waves=waves)
+    ctx.load_seeds(seeds, r0=r0.astype(np.float32), ids=ids)
+    worst = {}
+    kinked = 0
+    steps = 0
+    done = 0
+    for target in prerun_iters:
+        if target > done:
+            oracle.evolve(J, p, wl.dirs, st, target - done)
+            done = target
+        # teacher forcing: both sides start from the oracle state rounded to FP32
+        c32 = st.c.astype(np.float32).astype(np.float64)
+        R32 = st.R.astype(np.float32)
+        ref = st.copy()
+        ref.c[:] = c32
+        ref.R[:] = R32.astype(np.float64)
+        active = (ref.status & 0x0F) == oracle.ACTIVE
+        tr, _ = oracle.evolve(J, p, wl.dirs, ref, 1, trace=True)
+        ctx.set_state(c32, R32, st.iters, st.status, st.streak)
+        say(f"  one-step parity {wl.name}: after {target} iterations, {int(active.sum())} active")
+        g = ctx.trace_step()
+        a = np.where(active)[0]
+        assert np.all(g[a, 10] == tr[a, 29])  # same iteration number n
+        d = p.dim
+        checks = [("A", g[a, 0], tr[a, 0], tr[a, 5], 0.0), ("B_R", g[a, 1], tr[a, 1], tr[a, 6], tr[a, 20]),
+                  ("E_mc", g[a, 5], tr[a, 10], tr[a, 11], 0.0), ("dR", g[a, 6], tr[a, 12], tr[a, 13], tr[a, 24])]
+        for k in range(d):
+            checks.append((f"B_c{k}", g[a, 2 + k], tr[a, 2 + k], tr[a, 7 + k], tr[a, 21 + k]))
+            checks.append((f"dc{k}", g[a, 7 + k], tr[a, 14 + k], tr[a, 17 + k], tr[a, 25 + k]))
+        for name, gv, rv, ra, sl in checks:
+            worst[name] = max(worst.get(name, 0.0), tol_check(f"{name} at n={target}", gv, rv, ra, sl))
+        kinked += int((tr[a, 28] > 0).sum())
+        steps += len(a)
+        # the state after the step matches too
+        gs = ctx.get_state()
+        assert np.all(gs["iters"][a] == ref.iters[a])
+        assert np.max(np.abs(gs["radii"][a] - ref.R[a])) < 1e-4
+        assert np.max(np.linalg.norm(gs["centers"][a] - ref.c[a], axis=1)) < 1e-4
+    ctx.close()
+    say(f"  worst err/tol: " + ", ".join(f"{k} {v:.3f}" for k, v in worst.items()) +
+        f"; contour-steps with a near-kink sample: {kinked}/{steps}")
+    assert kinked <= 0.2 * steps
+    return worst
+
+
+# ------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["tiny-u8", "aniso-u16", "plane-u8", "f32"])
+def test_prepass_parity(snk, stream, which):
+    rng = np.random.default_rng(1)
+    if which == "tiny-u8":
+        wl = synth.tiny_config()
+    elif which == "aniso-u16":
+        wl = synth.slab_config(n_target=60, shape_xyz=(100, 77, 23), n_iter=10)
+    elif which == "plane-u8":
+        wl = synth.plane_config(n_target=300, size=300, n_iter=10)
+    else:
+        wl = synth.tiny_config()
+        wl.raw = rng.normal(50.0, 20.0, size=(19, 70, 131)).astype(np.float32)
+        wl.params = wl.params.replace(sigma_pre=1.7, spacing=(1.0, 1.3, 0.8))
+    say(f"prepass parity: {which} {wl.raw.shape} {wl.raw.dtype}")
+    for on_device in (True, False):
+        ctx = make_ctx(snk, stream, wl, on_device=on_device)
+        ctx.prepass()
+        got = ctx.read_volume(wl.raw.shape)
+        ctx.close()
+        ref = oracle.prepass(wl.raw, wl.params)
+        I = (wl.raw.astype(np.float64) - wl.params.i_offset) * wl.params.i_scale
+        err = np.max(np.abs(got - ref))
+        assert err <= 2e-6 * np.max(np.abs(I)), (which, err)
+
+
+def test_one_step_parity_tiny(snk, stream):
+    say("one-step parity tiny (64^3 u8, D 162, M 32)")
+    one_step_parity(snk, stream, synth.tiny_config(), [0, 1, 7, 40, 99])
+
+
+def test_one_step_parity_aniso_u16(snk, stream):
+    wl = synth.slab_config(n_target=40, shape_xyz=(96, 80, 40), n_iter=50)
+    say("one-step parity anisotropic u16 (h = 1,1,2; D 642, M 64)")
+    one_step_parity(snk, stream, wl, [0, 3, 30])
+
+
+def test_one_step_parity_2d(snk, stream):
+    wl = synth.plane_config(n_target=120, size=256, n_iter=50)
+    say("one-step parity 2D (256^2 u8, D 64, M 16)")
+    one_step_parity(snk, stream, wl, [0, 2, 25], n_extra=40)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 8])
+def test_one_step_parity_launch_shapes(snk, stream, waves):
+    say(f"one-step parity tiny, {waves} waves per contour")
+    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, waves=waves)
+
+
+def test_one_step_parity_unrotated_and_odd_sizes(snk, stream):
+    wl = synth.tiny_config()
+    wl.params = wl.params.replace(flags=1, n_rays=6, n_radial=5)
+    say("one-step parity: rotation off, M = 6, L = 5 (ragged thread mapping)")
+    one_step_parity(snk, stream, wl, [0, 4], n_extra=16)
+
+
+def free_run(snk, stream, wl, seeds=None, ids=None, waves=0, chunks=None):
+    seeds = wl.seeds if seeds is None else seeds
+    ctx = make_ctx(snk, stream, wl, waves=waves)
+    ctx.load_seeds(seeds, ids=ids)
+    for k in (chunks or [wl.n_iter]):
+        ctx.evolve(k)
+    ctx.finalize()
+    out = ctx.read()
+    out["timing"] = ctx.get_timing()
+    ctx.close()
+    return out
+
+
+def test_free_run_tiny(snk, stream):
+    wl = synth.tiny_config()
+    say("free run tiny: 100 iterations, then exact energy and selection")
+    got = free_run(snk, stream, wl)
+    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    st = ref["state"]
+    assert np.array_equal(got["iters"], st.iters)
+    assert np.array_equal(got["status"], st.status)
+    assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+    assert got["timing"]["evolved"] == ref["evolved"]
+    # exact energy at the GPU's own final state
+    e_ref, e_abs = oracle.energy_vox(ref["J"], wl.params, got["centers"], got["radii"].astype(np.float64))
+    tol_check("E_vox", got["e_vox"], e_ref, e_abs, 0.0, rel=2e-5)
+    amb = oracle.cull_ambiguity(wl.params, got["centers"], got["radii"], e_ref)
+    keep_ref = oracle.cull(wl.params, got["centers"], got["radii"], got["e_vox"].astype(np.float64),
+                           got["status"], wl.ids)
+    ok = amb == 0
+    assert np.array_equal(got["keep"][ok], keep_ref[ok])
+    assert np.array_equal(got["keep"][ok], ref["keep"][ok])
+    say(f"  kept {int(got['keep'].sum())}/{len(got['keep'])}, ambiguous {int(amb.sum())}")
+
+
+def test_free_run_2d(snk, stream):
+    wl = synth.plane_config(n_target=200, size=320, n_iter=60)
+    say("free run 2D: 320^2, 60 iterations")
+    got = free_run(snk, stream, wl)
+    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    st = ref["state"]
+    same = got["iters"] == st.iters
+    assert same.mean() >= 0.98
+    assert np.max(np.abs(got["radii"] - st.R)[same]) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[same]) <= 0.5
+
+
+def test_selection_matches_greedy_dense(snk, stream):
+    """Dense random contours (many overlapping chains): the GPU's parallel rounds equal the
+    oracle's sequential greedy on the GPU's own energies."""
+    wl = synth.tiny_config()
+    p = wl.params.replace(e0=-0.01)
+    wl.params = p
+    rng = np.random.default_rng(5)
+    n = 1500
+    seeds = rng.uniform(2.0, 61.0, size=(n, 3))
+    R = rng.uniform(5.0, 9.0, size=n).astype(np.float32)
+    ctx = make_ctx(snk, stream, wl)
+    ctx.load_seeds(seeds, r0=R)
+    st = np.full(n, oracle.MAXITER, np.uint8)
+    st[::17] = oracle.OUT
+    st[::23] = oracle.CONVERGED | oracle.CLAMPED
+    ctx.set_state(seeds, R, np.full(n, 5, np.int32), st)
+    say(f"selection parity: {n} dense contours")
+    ctx.finalize()
+    got = ctx.read()
+    ctx.close()
+    keep_ref = oracle.cull(p, got["centers"], got["radii"], got["e_vox"].astype(np.float64), st,
+                           np.arange(n, dtype=np.uint32))
+    amb = oracle.cull_ambiguity(p, got["centers"], got["radii"], got["e_vox"].astype(np.float64))
+    ok = amb == 0
+    assert got["keep"].sum() > 20
+    assert np.array_equal(got["keep"][ok], keep_ref[ok]), (np.where(got["keep"] != keep_ref)[0][:10])
+    J = oracle.prepass(wl.raw, p)
+    e_ref, e_abs = oracle.energy_vox(J, p, got["centers"], got["radii"].astype(np.float64))
+    tol_check("E_vox dense", got["e_vox"], e_ref, e_abs, 0.0, rel=2e-5)
+
+
+def test_determinism_split_and_order(snk, stream):
+    """Bit-identical reruns; evolve(30)+evolve(70) == evolve(100); per-id results do not depend
+    on the seed order."""
+    wl = synth.tiny_config()
+    say("determinism / split / order")
+    a = free_run(snk, stream, wl)
+    b = free_run(snk, stream, wl)
+    c = free_run(snk, stream, wl, chunks=[30, 70])
+    for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+    perm = np.random.default_rng(3).permutation(len(wl.seeds))
+    d = free_run(snk, stream, wl, seeds=wl.seeds[perm], ids=wl.ids[perm])
+    for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
+        assert np.array_equal(a[k][perm], d[k]), k
+
+
+def test_edge_cases(snk, stream):
+    wl = synth.tiny_config()
+    p = wl.params
+    say("edge cases: empty seed set, seeds outside, radius clamps, 1 iteration")
+    ctx = make_ctx(snk, stream, wl)
+    ctx.load_seeds(np.zeros((0, 3)))
+    ctx.evolve(5)
+    ctx.finalize()
+    assert len(ctx.read()["radii"]) == 0
+    seeds = np.array([[-3.0, 10.0, 10.0], [70.0, 5.0, 5.0], [0.0, 0.0, 0.0], [63.0, 63.0, 63.0], [30.0, 31.0, 29.0]])
+    r0 = np.array([5.0, 5.0, 0.1, 1e3, 7.0], np.float32)
+    ctx.load_seeds(seeds, r0=r0)
+    s = ctx.get_state()
+    assert list(s["status"][:2]) == [oracle.OUT, oracle.OUT]
+    lo = oracle.r_geom_min(3, p.dR)
+    assert abs(s["radii"][2] - lo) < 1e-5 and abs(s["radii"][3] - p.r_max) < 1e-4
+    ctx.evolve(1)
+    g = ctx.get_state()
+    assert list(g["iters"]) == [0, 0, 1, 1, 1]
+    J = oracle.prepass(wl.raw, p)
+    st = oracle.init_state(p, seeds, r0=r0, shape_zyx=wl.raw.shape)
+    oracle.evolve(J, p, wl.dirs, st, 1)
+    assert np.max(np.abs(g["radii"] - st.R)) < 1e-4
+    with pytest.raises(snk.SnkError):
+        ctx.set_state(seeds[:2], r0[:2], np.zeros(2, np.int32), np.zeros(2, np.uint8))
+    bad = p.replace(n_rays=7)
+    with pytest.raises(snk.SnkError):
+        ctx.set_params(bad)
+    ctx.close()
+
+
+def test_full_size_slab_sampled(snk, stream):
+    """The benchmark workload at full size (512x512x128 u16, ~2,000 nuclei, D 642, M 64) in the
+    benchmark's launch configuration: one-step parity of every contour from the seeds and after
+    20 iterations, and a 20-iteration free run of all contours."""
+    wl = synth.slab_config()
+    say(f"full-size slab: {wl.name}")
+    worst = one_step_parity(snk, stream, wl, [0, 20], n_extra=0)
+    assert worst
+    got = free_run(snk, stream, wl, chunks=[20])
+    J = oracle.prepass(wl.raw, wl.params)
+    st = oracle.init_state(wl.params, wl.seeds, ids=wl.ids)
+    oracle.evolve(J, wl.params, wl.dirs, st, 20)
+    assert np.array_equal(got["iters"], st.iters)
+    assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
