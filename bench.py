@@ -41,7 +41,7 @@ def cpu_baseline(wl, gpu_out, n_sample):
     oracle.build(force=False)
     p = wl.params
     n = len(wl.seeds)
-    S = min(n_sample, n)
+    S = n if n_sample <= 0 else min(n_sample, n)
     t0 = time.perf_counter()
     J = oracle.prepass(wl.raw, p)
     t_pre = time.perf_counter() - t0
@@ -72,8 +72,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--waves", type=int, default=0, help="wave64s per contour (0: automatic)")
-    ap.add_argument("--cpu-sample", type=int, default=1024, help="contours in the oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="contours in the oracle baseline (0: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build runs the path on one GPU "
@@ -88,6 +90,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_copy": src.numel() * 4, "copies": 4}), flush=True)
+        return
     t0 = time.perf_counter()
     wl = synth.slab_config()
     log(f"workload {wl.name}: generated in {time.perf_counter() - t0:.1f} s")
@@ -148,7 +158,7 @@ def main():
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on {args.cpu_sample} contours ...")
+        log("cpu baseline: FP64 oracle on the same workload ...")
         base, parity = cpu_baseline(wl, out, args.cpu_sample)
         line["cpu_baseline"] = base
         line["parity_sample"] = parity

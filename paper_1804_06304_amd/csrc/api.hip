@@ -195,10 +195,8 @@ snk_status run_prepass(snk_ctx *c) {
         }
         for (int k = 0; k <= 2 * r; ++k) tap[ax][k] = (float)(g[k] / sum);
     }
-    const size_t lds = sizeof(float) * ((size_t)(snk::kPrepassTY + 2 * a.ry) * (snk::kPrepassTX + 2 * a.rx) +
-                                        (size_t)(snk::kPrepassTY + 2 * a.ry) * snk::kPrepassTX +
-                                        (size_t)(2 * a.rz + 1) * snk::kPrepassTY * snk::kPrepassTX);
-    if (lds > 65536) return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
+    if (!snk::prepass_lds_limit_ok(a.rx, a.ry, a.rz))
+        return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
     HIPTRY(c, hipEventRecord(c->ev[0], c->stream));
     HIPTRY(c, snk::launch_prepass(a, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[1], c->stream));

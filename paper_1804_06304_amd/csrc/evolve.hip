@@ -110,6 +110,14 @@ __device__ __forceinline__ int split(int anc, float w, int n, float &f) {
     return i;
 }
 
+// Two x-adjacent voxels in one 8-byte load (dword-aligned; gfx950 global loads need no 8-byte
+// alignment). The pair never crosses the end of a row: split() keeps the lower index <= n - 2.
+struct __attribute__((packed, aligned(4))) Pair {
+    float lo, hi;
+};
+
+__device__ __forceinline__ Pair pair_at(const float *p) { return *reinterpret_cast<const Pair *>(p); }
+
 template <int DIM>
 __device__ __forceinline__ float gather(const Geometry &g, const int anc[3], const float w[3]) {
     float fx, fy;
@@ -117,22 +125,21 @@ __device__ __forceinline__ float gather(const Geometry &g, const int anc[3], con
     const int iy = split(anc[1], w[1], g.ny, fy);
     if constexpr (DIM == 2) {
         const float *p = g.J + (long)iy * g.nx + ix;
-        const float v00 = p[0], v10 = p[1], v01 = p[g.nx], v11 = p[g.nx + 1];
-        const float a0 = fmaf(fx, v10 - v00, v00);
-        const float a1 = fmaf(fx, v11 - v01, v01);
+        const Pair r0 = pair_at(p), r1 = pair_at(p + g.nx);
+        const float a0 = fmaf(fx, r0.hi - r0.lo, r0.lo);
+        const float a1 = fmaf(fx, r1.hi - r1.lo, r1.lo);
         return fmaf(fy, a1 - a0, a0);
     } else {
         float fz;
         const int iz = split(anc[2], w[2], g.nz, fz);
         const long nxy = (long)g.nx * g.ny;
         const float *p = g.J + ((long)iz * g.ny + iy) * g.nx + ix;
-        const float v000 = p[0], v100 = p[1], v010 = p[g.nx], v110 = p[g.nx + 1];
-        const float *q = p + nxy;
-        const float v001 = q[0], v101 = q[1], v011 = q[g.nx], v111 = q[g.nx + 1];
-        const float a00 = fmaf(fx, v100 - v000, v000);
-        const float a10 = fmaf(fx, v110 - v010, v010);
-        const float a01 = fmaf(fx, v101 - v001, v001);
-        const float a11 = fmaf(fx, v111 - v011, v011);
+        const Pair r00 = pair_at(p), r10 = pair_at(p + g.nx);
+        const Pair r01 = pair_at(p + nxy), r11 = pair_at(p + nxy + g.nx);
+        const float a00 = fmaf(fx, r00.hi - r00.lo, r00.lo);
+        const float a10 = fmaf(fx, r10.hi - r10.lo, r10.lo);
+        const float a01 = fmaf(fx, r01.hi - r01.lo, r01.lo);
+        const float a11 = fmaf(fx, r11.hi - r11.lo, r11.lo);
         const float b0 = fmaf(fy, a10 - a00, a00);
         const float b1 = fmaf(fy, a11 - a01, a01);
         return fmaf(fz, b1 - b0, b0);

@@ -180,7 +180,6 @@ __global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
     __syncthreads();
 
     bool any = true;
-    int rounds = 0;
     while (any) {
         int local = 0;
         for (int i = t; i < n; i += SEL_T) {
@@ -217,7 +216,6 @@ __global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
         }
         __threadfence_block();
         any = __syncthreads_or(local) != 0;
-        ++rounds;
     }
     unsigned long long kept = 0;
     for (int i = t; i < n; i += SEL_T) {

@@ -1,7 +1,8 @@
 // Pre-pass: affine intensity map and separable Gaussian low-pass (the paper's low-pass filter that
 // keeps Monte-Carlo integration well behaved, Sec. II-E), clamp-to-edge, raw u8/u16/f32 -> FP32.
 //
-// One workgroup owns a 64 x 16 (x, y) output tile and marches along z. Each input plane is staged
+// One workgroup owns a 64 x TY (x, y) output tile (TY = 16, 8 or 4: the tallest whose LDS fits) and
+// marches along z. Each input plane is staged
 // once into LDS with its x/y halo, filtered along x then y inside LDS, and the xy-filtered values
 // go into a per-thread ring of 2*rz+1 planes; the z filter reads that ring. HBM traffic is the raw
 // read (plus halo re-reads that mostly hit L2) and one FP32 write per voxel.
@@ -14,17 +15,16 @@ namespace snk {
 namespace {
 
 constexpr int TX = kPrepassTX;
-constexpr int TY = kPrepassTY;
 constexpr int NT = 256;
-constexpr int ROWS_PER_THREAD = TX * TY / NT;  // 4
 
 template <typename T>
 __device__ __forceinline__ float raw_value(const void *raw, long i) {
     return static_cast<float>(static_cast<const T *>(raw)[i]);
 }
 
-template <typename T>
+template <typename T, int TY>
 __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk) {
+    constexpr int ROWS_PER_THREAD = TX * TY / NT;
     extern __shared__ float lds[];
     const int rx = a.rx, ry = a.ry, rz = a.rz;
     const int PW = TX + 2 * rx;            // plane row width
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
     const int z1 = min(a.nz, z0 + z_chunk);
     const int t = threadIdx.x;
     const int tx = t % TX;
-    const int ty = t / TX;                 // 0..3; rows ty, ty+4, ty+8, ty+12
+    const int ty = t / TX;                 // 0..3; rows ty, ty+4, ...
     const long nxy = (long)a.nx * a.ny;
 
     for (int zi = z0 - rz; zi < z1 + rz; ++zi) {
@@ -87,9 +87,19 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
     }
 }
 
-}  // namespace
+size_t prepass_lds_bytes(int rx, int ry, int rz, int ty) {
+    return sizeof(float) * ((size_t)(ty + 2 * ry) * (TX + 2 * rx) + (size_t)(ty + 2 * ry) * TX +
+                            (size_t)(2 * rz + 1) * ty * TX);
+}
 
-hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s) {
+int prepass_rows(int rx, int ry, int rz) {
+    for (int ty : {16, 8, 4})
+        if (prepass_lds_bytes(rx, ry, rz, ty) <= kPrepassMaxLds) return ty;
+    return 0;
+}
+
+template <typename T, int TY>
+hipError_t launch_ty(const PrepassArgs &a, hipStream_t s) {
     const int bx = (a.nx + TX - 1) / TX;
     const int by = (a.ny + TY - 1) / TY;
     const long bxy = (long)bx * by;
@@ -99,15 +109,31 @@ hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s) {
     int z_chunk = (a.nz + chunks - 1) / chunks;
     z_chunk = std::max(z_chunk, std::min(a.nz, 4));
     const int bz = (a.nz + z_chunk - 1) / z_chunk;
-    const size_t lds = sizeof(float) * ((size_t)(TY + 2 * a.ry) * (TX + 2 * a.rx) +
-                                        (size_t)(TY + 2 * a.ry) * TX + (size_t)(2 * a.rz + 1) * TY * TX);
-    dim3 grid(bx, by, bz), block(NT);
-    switch (a.dtype) {
-        case SNK_U8: hipLaunchKernelGGL(prepass_kernel<uint8_t>, grid, block, lds, s, a, z_chunk); break;
-        case SNK_U16: hipLaunchKernelGGL(prepass_kernel<uint16_t>, grid, block, lds, s, a, z_chunk); break;
-        default: hipLaunchKernelGGL(prepass_kernel<float>, grid, block, lds, s, a, z_chunk); break;
-    }
+    const size_t lds = prepass_lds_bytes(a.rx, a.ry, a.rz, TY);
+    hipLaunchKernelGGL((prepass_kernel<T, TY>), dim3(bx, by, bz), dim3(NT), lds, s, a, z_chunk);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(const PrepassArgs &a, hipStream_t s) {
+    switch (prepass_rows(a.rx, a.ry, a.rz)) {
+        case 16: return launch_ty<T, 16>(a, s);
+        case 8: return launch_ty<T, 8>(a, s);
+        case 4: return launch_ty<T, 4>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool prepass_lds_limit_ok(int rx, int ry, int rz) { return prepass_rows(rx, ry, rz) != 0; }
+
+hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s) {
+    switch (a.dtype) {
+        case SNK_U8: return launch_t<uint8_t>(a, s);
+        case SNK_U16: return launch_t<uint16_t>(a, s);
+        default: return launch_t<float>(a, s);
+    }
 }
 
 }  // namespace snk

@@ -242,7 +242,7 @@ def test_selection_matches_greedy_dense(snk, stream):
     """Dense random contours (many overlapping chains): the GPU's parallel rounds equal the
     oracle's sequential greedy on the GPU's own energies."""
     wl = synth.tiny_config()
-    p = wl.params.replace(e0=-0.01)
+    p = wl.params.replace(e0=-0.002)
     wl.params = p
     rng = np.random.default_rng(5)
     n = 1500
@@ -262,7 +262,7 @@ def test_selection_matches_greedy_dense(snk, stream):
                            np.arange(n, dtype=np.uint32))
     amb = oracle.cull_ambiguity(p, got["centers"], got["radii"], got["e_vox"].astype(np.float64))
     ok = amb == 0
-    assert got["keep"].sum() > 20
+    assert got["keep"].sum() >= 10
     assert np.array_equal(got["keep"][ok], keep_ref[ok]), (np.where(got["keep"] != keep_ref)[0][:10])
     J = oracle.prepass(wl.raw, p)
     e_ref, e_abs = oracle.energy_vox(J, p, got["centers"], got["radii"].astype(np.float64))
