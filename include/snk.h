@@ -114,10 +114,10 @@ snk_status snk_destroy(snk_ctx *ctx);
  * i_offset, i_scale or spacing after a volume is loaded re-runs the pre-pass at the next evolve. */
 snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
 
-/* Launch shape of the evolution kernel: wave64s per contour (workgroup size 64 * waves);
- * 0 = automatic (4, fewer when a contour-iteration has under two points per thread), 1, 2, 4 or
- * 8. Results do not depend on it beyond FP32 summation order. */
-snk_status snk_set_launch(snk_ctx *ctx, int32_t waves_per_contour);
+/* Launch shape of the evolution kernel: wave64s per contour (workgroup size 64 * waves; 0 =
+ * automatic, 1, 2, 4 or 8) and sample points whose gathers one thread issues before consuming
+ * them (0 = automatic, 1, 2 or 4). Results do not depend on either beyond FP32 summation order. */
+snk_status snk_set_launch(snk_ctx *ctx, int32_t waves_per_contour, int32_t gathers_in_flight);
 
 /* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288 (the
  * table is staged in LDS). D must equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per

@@ -20,7 +20,8 @@ struct snk_ctx {
 
     snk_params P{};
     bool have_params = false;
-    int waves = 0;  // 0: automatic
+    int waves = 0;   // 0: automatic
+    int unroll = 0;  // 0: automatic
 
     std::vector<float> dirs_host;
     float *d_dirs = nullptr;
@@ -241,7 +242,7 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
     a.counter = c->d_counters;
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIPTRY(c, snk::launch_evolve(a, c->P.dim, pick_waves(c), trace, c->stream));
+    HIPTRY(c, snk::launch_evolve(a, c->P.dim, pick_waves(c), c->unroll, trace, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
     c->ev_evo = true;
     c->evolve_launches += 1;
@@ -324,12 +325,15 @@ snk_status snk_set_params(snk_ctx *c, const snk_params *p) {
     return SNK_OK;
 }
 
-snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour) {
+snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour, int32_t gathers_in_flight) {
     if (!c) return fail(c, SNK_EINVAL, "NULL context");
     if (waves_per_contour != 0 && waves_per_contour != 1 && waves_per_contour != 2 && waves_per_contour != 4 &&
         waves_per_contour != 8)
         return fail(c, SNK_EINVAL, "waves_per_contour must be 0 (auto), 1, 2, 4 or 8");
+    if (gathers_in_flight != 0 && gathers_in_flight != 1 && gathers_in_flight != 2 && gathers_in_flight != 4)
+        return fail(c, SNK_EINVAL, "gathers_in_flight must be 0 (auto), 1, 2 or 4");
     c->waves = waves_per_contour;
+    c->unroll = gathers_in_flight;
     return SNK_OK;
 }
 

@@ -118,31 +118,48 @@ struct __attribute__((packed, aligned(4))) Pair {
 
 __device__ __forceinline__ Pair pair_at(const float *p) { return *reinterpret_cast<const Pair *>(p); }
 
+// The loaded corners of one trilinear (bilinear) gather, split from the arithmetic so that a thread
+// can issue the loads of several points before it consumes any of them.
 template <int DIM>
-__device__ __forceinline__ float gather(const Geometry &g, const int anc[3], const float w[3]) {
-    float fx, fy;
-    const int ix = split(anc[0], w[0], g.nx, fx);
-    const int iy = split(anc[1], w[1], g.ny, fy);
+struct Tap {
+    Pair r[DIM == 3 ? 4 : 2];
+    float fx, fy, fz;
+};
+
+template <int DIM>
+__device__ __forceinline__ Tap<DIM> tap_load(const Geometry &g, const int anc[3], const float w[3]) {
+    Tap<DIM> tp;
+    const int ix = split(anc[0], w[0], g.nx, tp.fx);
+    const int iy = split(anc[1], w[1], g.ny, tp.fy);
     if constexpr (DIM == 2) {
+        tp.fz = 0.0f;
         const float *p = g.J + (long)iy * g.nx + ix;
-        const Pair r0 = pair_at(p), r1 = pair_at(p + g.nx);
-        const float a0 = fmaf(fx, r0.hi - r0.lo, r0.lo);
-        const float a1 = fmaf(fx, r1.hi - r1.lo, r1.lo);
-        return fmaf(fy, a1 - a0, a0);
+        tp.r[0] = pair_at(p);
+        tp.r[1] = pair_at(p + g.nx);
     } else {
-        float fz;
-        const int iz = split(anc[2], w[2], g.nz, fz);
+        const int iz = split(anc[2], w[2], g.nz, tp.fz);
         const long nxy = (long)g.nx * g.ny;
         const float *p = g.J + ((long)iz * g.ny + iy) * g.nx + ix;
-        const Pair r00 = pair_at(p), r10 = pair_at(p + g.nx);
-        const Pair r01 = pair_at(p + nxy), r11 = pair_at(p + nxy + g.nx);
-        const float a00 = fmaf(fx, r00.hi - r00.lo, r00.lo);
-        const float a10 = fmaf(fx, r10.hi - r10.lo, r10.lo);
-        const float a01 = fmaf(fx, r01.hi - r01.lo, r01.lo);
-        const float a11 = fmaf(fx, r11.hi - r11.lo, r11.lo);
-        const float b0 = fmaf(fy, a10 - a00, a00);
-        const float b1 = fmaf(fy, a11 - a01, a01);
-        return fmaf(fz, b1 - b0, b0);
+        tp.r[0] = pair_at(p);
+        tp.r[1] = pair_at(p + g.nx);
+        tp.r[2] = pair_at(p + nxy);
+        tp.r[3] = pair_at(p + nxy + g.nx);
+    }
+    return tp;
+}
+
+template <int DIM>
+__device__ __forceinline__ float tap_value(const Tap<DIM> &tp) {
+    const float a0 = fmaf(tp.fx, tp.r[0].hi - tp.r[0].lo, tp.r[0].lo);
+    const float a1 = fmaf(tp.fx, tp.r[1].hi - tp.r[1].lo, tp.r[1].lo);
+    const float b0 = fmaf(tp.fy, a1 - a0, a0);
+    if constexpr (DIM == 2) {
+        return b0;
+    } else {
+        const float a2 = fmaf(tp.fx, tp.r[2].hi - tp.r[2].lo, tp.r[2].lo);
+        const float a3 = fmaf(tp.fx, tp.r[3].hi - tp.r[3].lo, tp.r[3].lo);
+        const float b1 = fmaf(tp.fy, a3 - a2, a2);
+        return fmaf(tp.fz, b1 - b0, b0);
     }
 }
 
@@ -152,11 +169,160 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-template <int DIM, int WAVES, bool TRACE>
+// Geometry of the weight S(r; R) for the current R (Sec. II-B, Eq. (5)): inner core -1 up to
+// rho R - dr/2, ramp of width dr = rho dR, shell +1 up to R - dR/2, outer ramp of width dR down to 0
+// at R + dR/2. Half-open intervals.
+template <int DIM>
+struct Weight {
+    static constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
+    float ain, R, k0, k1, k2, k3, in_slope, out_slope;
+    __device__ __forceinline__ Weight(float R_, float dR) {
+        const float dr = RHO * dR;
+        R = R_;
+        ain = RHO * R_;
+        k0 = ain - 0.5f * dr;
+        k1 = ain + 0.5f * dr;
+        k2 = R_ - 0.5f * dR;
+        k3 = R_ + 0.5f * dR;
+        in_slope = 2.0f / dr;
+        out_slope = 1.0f / dR;
+    }
+    // S, dS/dr, dS/dR at radius r
+    __device__ __forceinline__ void eval(float r, float &S, float &Sr, float &SR) const {
+        if (r < k0) {
+            S = -1.0f; Sr = 0.0f; SR = 0.0f;
+        } else if (r < k1) {
+            S = (r - ain) * in_slope; Sr = in_slope; SR = -RHO * in_slope;
+        } else if (r < k2) {
+            S = 1.0f; Sr = 0.0f; SR = 0.0f;
+        } else if (r < k3) {
+            S = 0.5f - (r - R) * out_slope; Sr = -out_slope; SR = out_slope;
+        } else {
+            S = 0.0f; Sr = 0.0f; SR = 0.0f;
+        }
+    }
+};
+
+// Direction and radial jitter of ray `ray` (0..M-1) at iteration n: pair m = ray mod M/2 draws
+// Philox at (m, n, id, 1); rays m and m + M/2 point along +u and -u.
+template <int DIM>
+__device__ __forceinline__ void draw_ray(int ray, int half, uint32_t n, uint32_t id, uint32_t k0, uint32_t k1,
+                                         int D, const float *tdir, const Rot<DIM> &Q, float u[DIM], float &xi) {
+    const int m = ray % half;
+    uint32_t x[4];
+    philox10((uint32_t)m, n, id, 1u, k0, k1, x);
+    const int k = (int)__umulhi(x[0], (uint32_t)D);
+    xi = unit_open(x[1]);
+    const float sgn = ray < half ? 1.0f : -1.0f;
+    float tk[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) tk[i] = tdir[k * DIM + i];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) acc = fmaf(Q.q[i][jj], tk[jj], acc);
+        u[i] = sgn * acc;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ float radial(float smax, int l, float xi, float invL) {
+    const float tau = ((float)l + xi) * invL;
+    return smax * (DIM == 3 ? cbrtf(tau) : sqrtf(tau));
+}
+
+// Sums of one thread for one iteration. Fast mapping (M divides T or T divides M): a thread owns
+// whole rays and walks their radial points U at a time, issuing all U gathers before using them.
+// Otherwise points are taken round-robin.
+template <int DIM, int T, int U>
+__device__ __forceinline__ void thread_sums(const Geometry &g, const int anc[3], const float off[3],
+                                            const Weight<DIM> &wt, float smax, const Rot<DIM> &Q, int M, int L,
+                                            uint32_t n, uint32_t id, uint32_t key0, uint32_t key1, int D,
+                                            const float *tdir, int t, float &accA, float &accBR,
+                                            float accB[DIM]) {
+    const int half = M / 2;
+    const float invL = 1.0f / (float)L;
+    if (M <= T ? (T % M == 0) : (M % T == 0)) {
+        const int ray0 = M <= T ? t % M : t;
+        const int rstep = M <= T ? M : T;
+        const int l0 = M <= T ? t / M : 0;
+        const int ls = M <= T ? T / M : 1;
+        if (l0 >= L) return;
+        for (int ray = ray0; ray < M; ray += rstep) {
+            float u[DIM], xi;
+            draw_ray<DIM>(ray, half, n, id, key0, key1, D, tdir, Q, u, xi);
+            float du[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) du[i] = u[i] * g.inv_h[i];
+            float q = 0.0f;
+            for (int l = l0; l < L; l += ls * U) {
+                Tap<DIM> tp[U];
+                float rad[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int ll = l + ls * k;
+                    rad[k] = radial<DIM>(smax, ll < L ? ll : l, xi, invL);
+                    float w[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) w[i] = fmaf(rad[k], du[i], off[i]);
+                    tp[k] = tap_load<DIM>(g, anc, w);
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    if (l + ls * k < L) {
+                        const float I = tap_value<DIM>(tp[k]);
+                        float S, Sr, SR;
+                        wt.eval(rad[k], S, Sr, SR);
+                        accA = fmaf(S, I, accA);
+                        accBR = fmaf(SR, I, accBR);
+                        q = fmaf(Sr, I, q);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) accB[i] = fmaf(-q, u[i], accB[i]);
+        }
+        return;
+    }
+    // general mapping
+    int cur_ray = -1;
+    float u[DIM], xi = 0.0f, q = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) u[i] = 0.0f;
+    for (int j = t; j < M * L; j += T) {
+        const int ray = j % M;
+        const int l = j / M;
+        if (ray != cur_ray) {
+            if (cur_ray >= 0) {
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) accB[i] = fmaf(-q, u[i], accB[i]);
+                q = 0.0f;
+            }
+            cur_ray = ray;
+            draw_ray<DIM>(ray, half, n, id, key0, key1, D, tdir, Q, u, xi);
+        }
+        const float rad = radial<DIM>(smax, l, xi, invL);
+        float w[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) w[i] = fmaf(rad * u[i], g.inv_h[i], off[i]);
+        const float I = tap_value<DIM>(tap_load<DIM>(g, anc, w));
+        float S, Sr, SR;
+        wt.eval(rad, S, Sr, SR);
+        accA = fmaf(S, I, accA);
+        accBR = fmaf(SR, I, accBR);
+        q = fmaf(Sr, I, q);
+    }
+    if (cur_ray >= 0) {
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) accB[i] = fmaf(-q, u[i], accB[i]);
+    }
+}
+
+template <int DIM, int WAVES, bool TRACE, int U>
 __global__ __launch_bounds__(64 * WAVES) void evolve_kernel(EvolveArgs a) {
     constexpr int T = 64 * WAVES;
     constexpr int NR = 2 + DIM;  // A, B_R, B_c[DIM]
-    constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
     constexpr float BALL = DIM == 3 ? 4.18879020478639098462f : 3.14159265358979323846f;
     extern __shared__ float lds[];
     float *tdir = lds;                     // D x DIM direction table
@@ -180,85 +346,21 @@ __global__ __launch_bounds__(64 * WAVES) void evolve_kernel(EvolveArgs a) {
     int streak = s.streak;
     float e_mc = s.e_mc;
     const uint32_t id = s.id;
-    const int M = a.M, L = a.L, half = a.M / 2;
-    const int NPTS = M * L;
-    const float invL = 1.0f / (float)L;
+    const int NPTS = a.M * a.L;
     const float dR = a.dR;
-    const float dr = RHO * dR;
     int ran = 0;
 
     for (int it = 0; it < a.n_iter; ++it) {
         n += 1;
         const float smax = R + 0.5f * dR;
-        const float ain = RHO * R;
-        const float k0 = ain - 0.5f * dr, k1 = ain + 0.5f * dr;
-        const float k2 = R - 0.5f * dR, k3 = R + 0.5f * dR;
-        const float in_slope = 2.0f / dr;
-        const float out_slope = 1.0f / dR;
+        const Weight<DIM> wt(R, dR);
         const Rot<DIM> Q = draw_rotation<DIM>((uint32_t)n, id, a.key0, a.key1, (a.flags & 1) != 0);
 
         float accA = 0.0f, accBR = 0.0f, accB[DIM];
 #pragma unroll
         for (int i = 0; i < DIM; ++i) accB[i] = 0.0f;
-        int cur_ray = -1;
-        float u[DIM];
-        float xi = 0.0f, accQ = 0.0f;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) u[i] = 0.0f;
-
-        for (int j = t; j < NPTS; j += T) {
-            const int ray = j % M;
-            const int l = j / M;
-            if (ray != cur_ray) {
-                if (cur_ray >= 0) {
-#pragma unroll
-                    for (int i = 0; i < DIM; ++i) accB[i] = fmaf(-accQ, u[i], accB[i]);
-                    accQ = 0.0f;
-                }
-                cur_ray = ray;
-                const int m = ray % half;
-                uint32_t x[4];
-                philox10((uint32_t)m, (uint32_t)n, id, 1u, a.key0, a.key1, x);
-                const int k = (int)__umulhi(x[0], (uint32_t)a.D);
-                xi = unit_open(x[1]);
-                const float sgn = ray < half ? 1.0f : -1.0f;
-                float tk[DIM];
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) tk[i] = tdir[k * DIM + i];
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) {
-                    float acc = 0.0f;
-#pragma unroll
-                    for (int jj = 0; jj < DIM; ++jj) acc = fmaf(Q.q[i][jj], tk[jj], acc);
-                    u[i] = sgn * acc;
-                }
-            }
-            const float tau = ((float)l + xi) * invL;
-            const float rad = smax * (DIM == 3 ? cbrtf(tau) : sqrtf(tau));
-            float w[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) w[i] = fmaf(rad * u[i], g.inv_h[i], off[i]);
-            const float I = gather<DIM>(g, anc, w);
-            float S, Sr, SR;
-            if (rad < k0) {
-                S = -1.0f; Sr = 0.0f; SR = 0.0f;
-            } else if (rad < k1) {
-                S = (rad - ain) * in_slope; Sr = in_slope; SR = -RHO * in_slope;
-            } else if (rad < k2) {
-                S = 1.0f; Sr = 0.0f; SR = 0.0f;
-            } else if (rad < k3) {
-                S = 0.5f - (rad - R) * out_slope; Sr = -out_slope; SR = out_slope;
-            } else {
-                S = 0.0f; Sr = 0.0f; SR = 0.0f;
-            }
-            accA = fmaf(S, I, accA);
-            accBR = fmaf(SR, I, accBR);
-            accQ = fmaf(Sr, I, accQ);
-        }
-        if (cur_ray >= 0) {
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) accB[i] = fmaf(-accQ, u[i], accB[i]);
-        }
+        thread_sums<DIM, T, U>(g, anc, off, wt, smax, Q, a.M, a.L, (uint32_t)n, id, a.key0, a.key1, a.D, tdir, t,
+                               accA, accBR, accB);
 
         float tot[NR];
         tot[0] = wave_sum(accA);
@@ -369,29 +471,43 @@ __global__ __launch_bounds__(64 * WAVES) void evolve_kernel(EvolveArgs a) {
     }
 }
 
-template <int DIM, int WAVES, bool TRACE>
+template <int DIM, int WAVES, bool TRACE, int U>
 hipError_t launch_t(const EvolveArgs &a, hipStream_t s) {
     const size_t lds = sizeof(float) * ((size_t)a.D * DIM + 2 * WAVES * (2 + DIM));
-    hipLaunchKernelGGL((evolve_kernel<DIM, WAVES, TRACE>), dim3(a.n), dim3(64 * WAVES), lds, s, a);
+    hipLaunchKernelGGL((evolve_kernel<DIM, WAVES, TRACE, U>), dim3(a.n), dim3(64 * WAVES), lds, s, a);
     return hipGetLastError();
 }
 
+// Gathers in flight per thread: `unroll` points at a time (0: as many as the thread has, up to 4).
+template <int DIM, int WAVES, bool TRACE>
+hipError_t launch_u(const EvolveArgs &a, int unroll, hipStream_t s) {
+    constexpr int T = 64 * WAVES;
+    int u = unroll;
+    if (u <= 0) {
+        const int per = a.M <= T ? (a.L + T / a.M - 1) / (T / a.M) : a.L;
+        u = per >= 4 ? 4 : (per >= 2 ? 2 : 1);
+    }
+    if (u >= 4) return launch_t<DIM, WAVES, TRACE, 4>(a, s);
+    if (u >= 2) return launch_t<DIM, WAVES, TRACE, 2>(a, s);
+    return launch_t<DIM, WAVES, TRACE, 1>(a, s);
+}
+
 template <int DIM, bool TRACE>
-hipError_t launch_w(const EvolveArgs &a, int waves, hipStream_t s) {
+hipError_t launch_w(const EvolveArgs &a, int waves, int unroll, hipStream_t s) {
     switch (waves) {
-        case 1: return launch_t<DIM, 1, TRACE>(a, s);
-        case 2: return launch_t<DIM, 2, TRACE>(a, s);
-        case 8: return launch_t<DIM, 8, TRACE>(a, s);
-        default: return launch_t<DIM, 4, TRACE>(a, s);
+        case 1: return launch_u<DIM, 1, TRACE>(a, unroll, s);
+        case 2: return launch_u<DIM, 2, TRACE>(a, unroll, s);
+        case 8: return launch_u<DIM, 8, TRACE>(a, unroll, s);
+        default: return launch_u<DIM, 4, TRACE>(a, unroll, s);
     }
 }
 
 }  // namespace
 
-hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, bool trace, hipStream_t s) {
+hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, int unroll, bool trace, hipStream_t s) {
     if (a.n <= 0 || a.n_iter <= 0) return hipSuccess;
-    if (dim == 2) return trace ? launch_w<2, true>(a, waves, s) : launch_w<2, false>(a, waves, s);
-    return trace ? launch_w<3, true>(a, waves, s) : launch_w<3, false>(a, waves, s);
+    if (dim == 2) return trace ? launch_w<2, true>(a, waves, unroll, s) : launch_w<2, false>(a, waves, unroll, s);
+    return trace ? launch_w<3, true>(a, waves, unroll, s) : launch_w<3, false>(a, waves, unroll, s);
 }
 
 }  // namespace snk

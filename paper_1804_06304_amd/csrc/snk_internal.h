@@ -83,7 +83,7 @@ constexpr size_t kPrepassMaxLds = 65536;
 
 hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s);
 bool prepass_lds_limit_ok(int rx, int ry, int rz);
-hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, bool trace, hipStream_t s);
+hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, int unroll, bool trace, hipStream_t s);
 hipError_t launch_energy_vox(const FinalizeArgs &a, int dim, hipStream_t s);
 hipError_t launch_select(const FinalizeArgs &a, int dim, hipStream_t s);
 

@@ -66,7 +66,7 @@ def load(path: str = LIB_PATH):
         "snk_create": [C.POINTER(C.c_void_p), C.c_int, vp],
         "snk_destroy": [vp],
         "snk_set_params": [vp, C.POINTER(snk_params)],
-        "snk_set_launch": [vp, i32],
+        "snk_set_launch": [vp, i32, i32],
         "snk_set_directions": [vp, vp, i32],
         "snk_load_volume": [vp, vp, C.c_int, i64, i64, i64, C.c_int],
         "snk_prepass": [vp],
@@ -151,8 +151,8 @@ def snk_set_params(h, params) -> None:
     _check(h, load().snk_set_params(h, C.byref(s)))
 
 
-def snk_set_launch(h, waves_per_contour: int) -> None:
-    _check(h, load().snk_set_launch(h, int(waves_per_contour)))
+def snk_set_launch(h, waves_per_contour: int = 0, gathers_in_flight: int = 0) -> None:
+    _check(h, load().snk_set_launch(h, int(waves_per_contour), int(gathers_in_flight)))
 
 
 def snk_set_directions(h, dirs) -> None:

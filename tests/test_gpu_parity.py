@@ -41,11 +41,11 @@ def stream():
     return torch.cuda.current_stream()
 
 
-def make_ctx(snk, stream, wl, waves=0, on_device=True):
+def make_ctx(snk, stream, wl, waves=0, on_device=True, unroll=0):
     import torch
     ctx = snk.Context(0, stream)
     ctx.set_params(wl.params)
-    ctx.set_launch(waves)
+    ctx.set_launch(waves, unroll)
     ctx.set_directions(wl.dirs)
     if on_device:
         raw = torch.from_numpy(np.ascontiguousarray(wl.raw)).to("cuda:0")
@@ -79,7 +79,7 @@ def tol_check(name, got, ref, ref_abs, slack, rel=1e-5):
     return float(np.max(err / tol)) if len(ref) else 0.0
 
 
-def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0):
+def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0, unroll=0):
     p = wl.params
     rng = np.random.default_rng(seed)
     seeds = np.concatenate([wl.seeds, extra_seeds(wl, n_extra, rng)]) if n_extra else wl.seeds
@@ -88,7 +88,7 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0):
     r0[: len(wl.seeds)] = p.r_init
     J = oracle.prepass(wl.raw, p)
     st = oracle.init_state(p, seeds, r0=r0, ids=ids, shape_zyx=wl.raw.shape)
-    ctx = make_ctx(snk, stream, wl, waves=waves)
+    ctx = make_ctx(snk, stream, wl, waves=waves, unroll=unroll)
     ctx.load_seeds(seeds, r0=r0.astype(np.float32), ids=ids)
     worst = {}
     kinked = 0
@@ -177,10 +177,18 @@ def test_one_step_parity_2d(snk, stream):
     one_step_parity(snk, stream, wl, [0, 2, 25], n_extra=40)
 
 
-@pytest.mark.parametrize("waves", [1, 2, 8])
-def test_one_step_parity_launch_shapes(snk, stream, waves):
-    say(f"one-step parity tiny, {waves} waves per contour")
-    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, waves=waves)
+@pytest.mark.parametrize("waves,unroll", [(1, 1), (1, 4), (2, 2), (8, 1), (8, 4)])
+def test_one_step_parity_launch_shapes(snk, stream, waves, unroll):
+    say(f"one-step parity tiny, {waves} waves per contour, {unroll} gathers in flight")
+    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, waves=waves, unroll=unroll)
+
+
+def test_one_step_parity_many_rays(snk, stream):
+    """More rays than threads (M = 128 on one wave): each thread walks several rays."""
+    wl = synth.tiny_config()
+    wl.params = wl.params.replace(n_rays=128, n_radial=8)
+    say("one-step parity tiny, M = 128, L = 8, 1 wave")
+    one_step_parity(snk, stream, wl, [0, 5], n_extra=16, waves=1, unroll=4)
 
 
 def test_one_step_parity_unrotated_and_odd_sizes(snk, stream):
