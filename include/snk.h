@@ -189,6 +189,71 @@ typedef struct snk_timing {
 } snk_timing;
 snk_status snk_get_timing(snk_ctx *ctx, snk_timing *t);
 
+/* ------------------------------------------------------------------------------------------
+ * Engine: many volumes in one launch (batched) and a request loop (served).
+ *
+ * A job is one volume with its seeds, parameters, direction table and iteration target. Jobs are
+ * queued by snk_engine_submit and admitted in FIFO order while their device footprint (raw copy,
+ * FP32 volume, contour state, scratch) fits the HBM budget given at creation. Every job of one
+ * engine has the same dim; engine volumes must be below 2 GiB as FP32. Contours evolve exactly as
+ * in snk_evolve (Sec. II-D: independent contours), so a job's results do not depend on which other
+ * jobs share its launches.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct snk_engine snk_engine;
+
+typedef struct snk_engine_stats {
+    int64_t submitted, admitted, completed, pending, running;
+    uint64_t bytes_in_use, budget;
+    double last_ms;           /* snk_engine_run: the captured graph's duration (HIP events)      */
+    double last_evolve_ms;    /* snk_engine_step: the evolve launches of the step (HIP events)   */
+    int64_t last_evolved;     /* contour-iterations run by the last run / step                   */
+    int32_t waves, gathers_in_flight, persistent;   /* launch shape of the last evolve launch    */
+    int32_t graph_replays;
+} snk_engine_stats;
+
+/* Create an engine on `device` enqueuing on `hip_stream` (NULL: a private stream). */
+snk_status snk_engine_create(snk_engine **out, int device, void *hip_stream, uint64_t hbm_budget_bytes);
+snk_status snk_engine_destroy(snk_engine *e);
+const char *snk_engine_last_error(const snk_engine *e);
+
+/* Force the evolve launch shape (waves 1/2/4/8, gathers in flight 1/2/4, persistent 0/1), or
+ * waves = 0 to pick per launch class (dim, D, M, L) by timing short trials of every shape. */
+snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent);
+
+/* Queue a job (arguments as in snk_set_params / snk_set_directions / snk_load_volume /
+ * snk_load_seeds; host data is copied, a device volume with on_device = 1 is borrowed until the job
+ * completes). n_iter is the job's iteration target. SNK_EBUSY if the job alone exceeds the budget. */
+snk_status snk_engine_submit(snk_engine *e, const snk_params *params, const float *dirs, int32_t D,
+                             const void *vol, snk_dtype dtype, int64_t nx, int64_t ny, int64_t nz, int on_device,
+                             const double *centers, const float *r0, const uint32_t *ids, int64_t n,
+                             int32_t n_iter, uint64_t *job);
+
+/* Batched: admit what fits, then evolve every admitted job from its seeds to its target and
+ * finalise it (exact energy + selection) in one captured hipGraph, replayed while the job set is
+ * unchanged. Synchronises; results are then readable with snk_engine_read. */
+snk_status snk_engine_run(snk_engine *e);
+
+/* Served: admit what fits (pre-pass on admission), advance every running contour by up to `chunk`
+ * iterations in one launch per launch class, then finalise the jobs whose contours have all stopped,
+ * copy their results to the host and return their device memory to the budget. Synchronises.
+ * *n_finished (may be NULL) receives the number of jobs completed by this step. */
+snk_status snk_engine_step(snk_engine *e, int32_t chunk, int32_t *n_finished);
+
+/* Ids of jobs completed since the last poll (up to cap). */
+snk_status snk_engine_poll(snk_engine *e, uint64_t *done, int64_t cap, int64_t *n_done);
+
+/* Results of a completed job (same outputs and capacity rule as snk_read). */
+snk_status snk_engine_read(snk_engine *e, uint64_t job, float *radii, double *centers, float *e_mc, float *e_vox,
+                           int32_t *iters, uint8_t *status, uint8_t *keep, int64_t cap, int64_t *n_out);
+
+/* Host timestamps (milliseconds, steady clock) of a job's submission and completion. */
+snk_status snk_engine_job_times(snk_engine *e, uint64_t job, double *submit_ms, double *done_ms);
+
+/* Forget a job (frees its device memory if still held). */
+snk_status snk_engine_release(snk_engine *e, uint64_t job);
+
+snk_status snk_engine_get_stats(snk_engine *e, snk_engine_stats *s);
+
 /* Wait for all work enqueued on the context's stream. */
 snk_status snk_sync(snk_ctx *ctx);
 

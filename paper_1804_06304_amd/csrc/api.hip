@@ -47,7 +47,7 @@ struct snk_ctx {
 
     int *d_cell_start = nullptr, *d_cell_fill = nullptr, *d_items = nullptr, *d_cell_of = nullptr,
         *d_dec = nullptr;
-    size_t grid_cap = 0, sel_cap = 0;
+    size_t grid_cap = 0, grid_fill_cap = 0, sel_cap = 0;
 
     unsigned long long *d_counters = nullptr;  // [0] evolved, [1] kept
 
@@ -124,6 +124,31 @@ bool same_prepass(const snk_params &a, const snk_params &b) {
     return a.dim == b.dim && a.sigma_pre == b.sigma_pre && a.i_offset == b.i_offset && a.i_scale == b.i_scale &&
            a.spacing[0] == b.spacing[0] && a.spacing[1] == b.spacing[1] && a.spacing[2] == b.spacing[2];
 }
+
+}  // namespace
+
+// Uniform grid for the selection: cell >= rho * r_max (plus a rounding margin), so overlapping
+// pairs sit in neighbouring cells; grown if the grid would exceed 2^22 cells.
+int64_t snk_grid_for(const snk_params &P, int64_t nx, int64_t ny, int64_t nz, int G[3], double *cell_out) {
+    const double rho = P.dim == 3 ? pow(2.0, -1.0 / 3.0) : sqrt(0.5);
+    double cell = rho * P.r_max * 1.01 + 0.01;
+    const int64_t nn[3] = {nx, ny, nz};
+    int64_t total = 1;
+    for (int iter = 0; iter < 64; ++iter) {
+        total = 1;
+        for (int i = 0; i < 3; ++i) {
+            const int64_t gi = i < P.dim ? (int64_t)floor((double)(nn[i] - 1) * P.spacing[i] / cell) + 1 : 1;
+            G[i] = (int)gi;
+            total *= gi;
+        }
+        if (total <= ((int64_t)1 << 22)) break;
+        cell *= 1.5;
+    }
+    *cell_out = cell;
+    return total;
+}
+
+namespace {
 
 snk::Geometry geometry(const snk_ctx *c) {
     snk::Geometry g;
@@ -214,6 +239,28 @@ int pick_waves(const snk_ctx *c) {
     return w;
 }
 
+snk::JobParams job_params(const snk_ctx *c) {
+    snk::JobParams p{};
+    p.g = geometry(c);
+    p.dirs = c->d_dirs;
+    p.D = c->D;
+    p.M = c->P.n_rays;
+    p.L = c->P.n_radial;
+    p.key0 = (uint32_t)(c->P.seed & 0xffffffffu);
+    p.key1 = (uint32_t)(c->P.seed >> 32);
+    p.flags = c->P.flags;
+    p.dR = (float)c->P.dR;
+    p.eps0 = (float)c->P.eps0;
+    p.r_lo = (float)r_low(c->P);
+    p.r_hi = (float)c->P.r_max;
+    p.conv_tol = (float)c->P.conv_tol;
+    p.conv_window = c->P.conv_window;
+    p.in_slope = (float)(2.0 / (rho_of(c->P.dim) * c->P.dR));
+    p.out_slope = (float)(1.0 / c->P.dR);
+    p.buffer_ok = (c->nx * c->ny * c->nz * 4) < ((int64_t)1 << 31) ? 1 : 0;
+    return p;
+}
+
 snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
     if (c->D != c->P.n_dirs) return fail(c, SNK_ESTATE, "direction table size != params.n_dirs");
     if (c->J_dirty) {
@@ -221,23 +268,10 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
         if (st != SNK_OK) return st;
     }
     snk::EvolveArgs a{};
-    a.g = geometry(c);
-    a.dirs = c->d_dirs;
+    a.p = job_params(c);
     a.st = c->d_st;
     a.n = (int)c->n;
     a.n_iter = n_iter;
-    a.D = c->D;
-    a.M = c->P.n_rays;
-    a.L = c->P.n_radial;
-    a.key0 = (uint32_t)(c->P.seed & 0xffffffffu);
-    a.key1 = (uint32_t)(c->P.seed >> 32);
-    a.flags = c->P.flags;
-    a.dR = (float)c->P.dR;
-    a.eps0 = (float)c->P.eps0;
-    a.r_lo = (float)r_low(c->P);
-    a.r_hi = (float)c->P.r_max;
-    a.conv_tol = (float)c->P.conv_tol;
-    a.conv_window = c->P.conv_window;
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
@@ -472,35 +506,21 @@ snk_status snk_finalize(snk_ctx *c) {
         st = run_prepass(c);
         if (st != SNK_OK) return st;
     }
-    snk::FinalizeArgs a{};
-    a.g = geometry(c);
+    snk::JobDev a{};
+    a.p = job_params(c);
     a.st = c->d_st;
     a.e_vox = c->d_evox;
     a.n = (int)c->n;
-    a.dR = (float)c->P.dR;
+    a.target = 0;
     a.e0 = (float)c->P.e0;
-    a.r_hi = (float)c->P.r_max;
-    const double rho = rho_of(c->P.dim);
-    double cell = rho * c->P.r_max * 1.01 + 0.01;
-    const int64_t nn[3] = {c->nx, c->ny, c->nz};
-    int64_t G = 1;
-    for (int iter = 0; iter < 64; ++iter) {
-        G = 1;
-        for (int i = 0; i < 3; ++i) {
-            const int64_t gi = i < c->P.dim ? (int64_t)floor((double)(nn[i] - 1) * c->P.spacing[i] / cell) + 1 : 1;
-            a.G[i] = (int)gi;
-            G *= gi;
-        }
-        if (G <= ((int64_t)1 << 22)) break;
-        cell *= 1.5;
-    }
+    int G3[3];
+    double cell = 0.0;
+    const int64_t G = snk_grid_for(c->P, c->nx, c->ny, c->nz, G3, &cell);
+    for (int i = 0; i < 3; ++i) a.G[i] = G3[i];
     a.cell = (float)cell;
     st = ensure(c, &c->d_cell_start, &c->grid_cap, (size_t)G + 1);
     if (st != SNK_OK) return st;
-    size_t cap2 = 0;
-    if (c->d_cell_fill) (void)hipFree(c->d_cell_fill);
-    c->d_cell_fill = nullptr;
-    st = ensure(c, &c->d_cell_fill, &cap2, (size_t)G + 1);
+    st = ensure(c, &c->d_cell_fill, &c->grid_fill_cap, (size_t)G + 1);
     if (st != SNK_OK) return st;
     if (c->sel_cap < (size_t)c->n) {
         for (int **p : {&c->d_items, &c->d_cell_of, &c->d_dec}) {
@@ -518,10 +538,10 @@ snk_status snk_finalize(snk_ctx *c) {
     a.items = c->d_items;
     a.cell_of = c->d_cell_of;
     a.dec = c->d_dec;
-    a.counter = c->d_counters + 1;
+    a.kept = c->d_counters + 1;
     HIPTRY(c, hipMemsetAsync(c->d_counters + 1, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
-    HIPTRY(c, snk::launch_energy_vox(a, c->P.dim, c->stream));
+    HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, c->stream));
     HIPTRY(c, snk::launch_select(a, c->P.dim, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
     c->ev_fin = true;

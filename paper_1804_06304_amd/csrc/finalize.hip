@@ -1,11 +1,11 @@
 // End of evolution (Results of the paper): exact energy and selection.
 //
-// energy_vox_kernel: one workgroup per contour evaluates Eq. (5) literally over the lattice points
-// within R + dR/2 of the centre (clamp-to-edge values outside the volume), times the voxel measure,
+// Exact energy: one workgroup per contour evaluates Eq. (5) literally over the lattice points within
+// R + dR/2 of the centre (clamp-to-edge values outside the volume), times the voxel measure,
 // divided by (2R)^d. FP32 terms, FP64 accumulation, fixed-order reduction. Contours still ACTIVE
 // become MAXITER here.
 //
-// select_kernel: one workgroup. Candidates (CONVERGED or MAXITER, E_vox <= E0) are binned on a
+// Selection: one workgroup per job. Candidates (CONVERGED or MAXITER, E_vox <= E0) are binned on a
 // uniform grid with cell >= rho * r_max, so every overlapping pair (|c' - c''| < rho max(R', R''))
 // lies in neighbouring cells. Rounds of "accept a candidate whose (E_vox, id) is the smallest among
 // its undecided overlapping neighbours and that has no accepted overlapping neighbour; reject a
@@ -36,21 +36,20 @@ __device__ __forceinline__ float weight_S(float r, float R, float dR) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(EV_T) void energy_vox_kernel(FinalizeArgs a) {
+__device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) {
     __shared__ double part[EV_T / 64];
-    const int cid = blockIdx.x;
     const int t = threadIdx.x;
-    DevContour s = a.st[cid];
-    const Geometry g = a.g;
+    const DevContour s = *slot;
+    const Geometry &g = p.g;
     const float R = s.R;
-    if (!isfinite(R) || !(R > 0.0f) || !(R <= a.r_hi) || (s.status & 0x0f) == SNK_NONFINITE) {
+    if (!isfinite(R) || !(R > 0.0f) || !(R <= p.r_hi) || (s.status & 0x0f) == SNK_NONFINITE) {
         if (t == 0) {
-            a.e_vox[cid] = NAN;
-            a.st[cid].e_vox = NAN;
+            *e_out = NAN;
+            slot->e_vox = NAN;
         }
         return;
     }
-    const float smax = R + 0.5f * a.dR;
+    const float smax = R + 0.5f * p.dR;
     int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
 #pragma unroll
     for (int i = 0; i < DIM; ++i) {
@@ -78,7 +77,7 @@ __global__ __launch_bounds__(EV_T) void energy_vox_kernel(FinalizeArgs a) {
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = min(max(s.anc[i] + rel[i], 0), nn[i] - 1);
         const float v = g.J[((long)k[2] * g.ny + k[1]) * g.nx + k[0]];
-        acc += (double)(weight_S<DIM>(r, R, a.dR) * v);
+        acc += (double)(weight_S<DIM>(r, R, p.dR) * v);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -87,16 +86,32 @@ __global__ __launch_bounds__(EV_T) void energy_vox_kernel(FinalizeArgs a) {
     if (t == 0) {
         double tot = 0.0;
         for (int w = 0; w < EV_T / 64; ++w) tot += part[w];
-        double meas = (double)g.h[0] * g.h[1] * (DIM == 3 ? g.h[2] : 1.0f);
+        const double meas = (double)g.h[0] * g.h[1] * (DIM == 3 ? g.h[2] : 1.0f);
         double norm = 1.0;
         for (int i = 0; i < DIM; ++i) norm *= 2.0 * (double)R;
         const double e = tot * meas / norm;
-        a.e_vox[cid] = e;
+        *e_out = e;
         DevContour o = s;
         o.e_vox = (float)e;
         if ((o.status & 0x0f) == SNK_ACTIVE) o.status = (uint8_t)((o.status & SNK_CLAMPED) | SNK_MAXITER);
-        a.st[cid] = o;
+        *slot = o;
     }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(EV_T) void energy_vox_kernel(JobParams p, DevContour *st, double *e_vox, int n) {
+    const int cid = blockIdx.x;
+    if (cid < n) energy_one<DIM>(p, st + cid, e_vox + cid);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(EV_T) void energy_vox_batch_kernel(const JobDev *jobs, const int2 *items, int n_items) {
+    const int item = blockIdx.x;
+    if (item >= n_items) return;
+    const int job = __builtin_amdgcn_readfirstlane(items[item].x);
+    const int cid = __builtin_amdgcn_readfirstlane(items[item].y);
+    const JobDev &j = jobs[job];
+    energy_one<DIM>(j.p, j.st + cid, j.e_vox + cid);
 }
 
 enum : int { DEC_NONE = 0, DEC_UNDECIDED = 1, DEC_ACCEPT = 2, DEC_REJECT = 3 };
@@ -115,11 +130,12 @@ __device__ __forceinline__ bool overlaps(const DevContour &x, const DevContour &
 }
 
 template <int DIM>
-__global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
+__device__ void select_job(const JobDev &a) {
+    __shared__ int chunk_sum[SEL_T];
     const int t = threadIdx.x;
     const int n = a.n;
     const int G = a.G[0] * a.G[1] * a.G[2];
-    const Geometry g = a.g;
+    const Geometry &g = a.p.g;
     volatile int *dec = a.dec;
 
     for (int c = t; c <= G; c += SEL_T) a.cell_start[c] = 0;
@@ -136,8 +152,8 @@ __global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
             int gi[3] = {0, 0, 0};
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                const float p = ((float)s.anc[k] + s.off[k]) * g.h[k];
-                gi[k] = min(max((int)floorf(p / a.cell), 0), a.G[k] - 1);
+                const float pk = ((float)s.anc[k] + s.off[k]) * g.h[k];
+                gi[k] = min(max((int)floorf(pk / a.cell), 0), a.G[k] - 1);
             }
             cell = (gi[2] * a.G[1] + gi[1]) * a.G[0] + gi[0];
             atomicAdd(&a.cell_start[cell + 1], 1);
@@ -147,7 +163,6 @@ __global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
     __syncthreads();
     // inclusive scan of cell_start[1..G] in place -> cell_start[c] = first slot of cell c
     {
-        __shared__ int chunk_sum[SEL_T];
         const int per = (G + SEL_T - 1) / SEL_T;
         const int b = 1 + t * per, e = min(G + 1, b + per);
         int run = 0;
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
             const DevContour si = a.st[i];
             const double ei = a.e_vox[i];
             const int cell = a.cell_of[i];
-            int gi[3] = {cell % a.G[0], (cell / a.G[0]) % a.G[1], cell / (a.G[0] * a.G[1])};
+            const int gi[3] = {cell % a.G[0], (cell / a.G[0]) % a.G[1], cell / (a.G[0] * a.G[1])};
             bool accepted_nb = false, minimal = true;
             for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0) && !accepted_nb; ++dz)
                 for (int dy = -1; dy <= 1 && !accepted_nb; ++dy)
@@ -223,22 +238,48 @@ __global__ __launch_bounds__(SEL_T) void select_kernel(FinalizeArgs a) {
         a.st[i].keep = k;
         kept += k;
     }
-    if (kept) atomicAdd(a.counter, kept);
+    if (kept) atomicAdd(a.kept, kept);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(SEL_T) void select_kernel(JobDev j) {
+    if (j.n > 0) select_job<DIM>(j);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(SEL_T) void select_batch_kernel(const JobDev *jobs, const int *job_list, int n_jobs) {
+    if ((int)blockIdx.x >= n_jobs) return;
+    const JobDev &j = jobs[__builtin_amdgcn_readfirstlane(job_list[blockIdx.x])];
+    if (j.n > 0) select_job<DIM>(j);
 }
 
 }  // namespace
 
-hipError_t launch_energy_vox(const FinalizeArgs &a, int dim, hipStream_t s) {
-    if (a.n <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(a.n), dim3(EV_T), 0, s, a);
-    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(a.n), dim3(EV_T), 0, s, a);
+hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(n), dim3(EV_T), 0, s, p, st, e_vox, n);
+    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(n), dim3(EV_T), 0, s, p, st, e_vox, n);
     return hipGetLastError();
 }
 
-hipError_t launch_select(const FinalizeArgs &a, int dim, hipStream_t s) {
-    if (a.n <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, a);
-    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, a);
+hipError_t launch_select(const JobDev &j, int dim, hipStream_t s) {
+    if (j.n <= 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, j);
+    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(energy_vox_batch_kernel<2>, dim3(n_items), dim3(EV_T), 0, s, jobs, items, n_items);
+    else hipLaunchKernelGGL(energy_vox_batch_kernel<3>, dim3(n_items), dim3(EV_T), 0, s, jobs, items, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_batch(const JobDev *jobs, const int *job_list, int n_jobs, int dim, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    if (dim == 2) hipLaunchKernelGGL(select_batch_kernel<2>, dim3(n_jobs), dim3(SEL_T), 0, s, jobs, job_list, n_jobs);
+    else hipLaunchKernelGGL(select_batch_kernel<3>, dim3(n_jobs), dim3(SEL_T), 0, s, jobs, job_list, n_jobs);
     return hipGetLastError();
 }
 

@@ -33,19 +33,50 @@ struct Geometry {
     float inv_h[3];
 };
 
-struct EvolveArgs {
+// Per-job constants of the evolution (one volume, one parameter set).
+struct JobParams {
     Geometry g;
     const float *dirs;           // D x dim
-    DevContour *st;
-    int n;                       // contours
-    int n_iter;
     int D, M, L;
     uint32_t key0, key1;
     int flags;
     float dR, eps0, r_lo, r_hi, conv_tol;
     int conv_window;
+    float in_slope, out_slope;   // 2 / (rho dR) and 1 / dR
+    int buffer_ok;               // volume fits a 32-bit buffer descriptor
+};
+
+struct EvolveArgs {
+    JobParams p;
+    DevContour *st;
+    int n;                       // contours
+    int n_iter;
     float *trace;                // n x SNK_TRACE_W or null
     unsigned long long *counter; // contour-iterations evolved
+};
+
+// One job of a batch, resident in device memory.
+struct JobDev {
+    JobParams p;
+    DevContour *st;
+    double *e_vox;
+    int n;
+    int target;                  // iteration count every contour evolves to
+    float e0;
+    int *cell_start, *cell_fill, *items, *cell_of, *dec;   // selection scratch
+    int G[3];
+    float cell;
+    unsigned long long *kept;
+};
+
+struct BatchArgs {
+    const JobDev *jobs;
+    const int2 *items;           // (job, contour)
+    int n_items;
+    int *queue;                  // work-queue head (persistent launch)
+    int chunk;                   // iterations per contour in this launch
+    unsigned long long *counter;
+    int max_D, max_M;
 };
 
 struct PrepassArgs {
@@ -58,25 +89,6 @@ struct PrepassArgs {
     float gx[33], gy[33], gz[33];
 };
 
-struct FinalizeArgs {
-    Geometry g;
-    DevContour *st;
-    double *e_vox;
-    int n;
-    float dR;
-    float e0;
-    float r_hi;
-    // selection scratch (single-workgroup kernel)
-    int *cell_start;     // G + 1
-    int *cell_fill;      // G
-    int *items;          // n
-    int *cell_of;        // n
-    int *dec;            // n
-    int G[3];
-    float cell;          // physical cell size
-    unsigned long long *counter;  // survivors
-};
-
 constexpr int kPrepassTX = 64;
 constexpr int kPrepassMaxR = 16;
 constexpr size_t kPrepassMaxLds = 65536;
@@ -84,7 +96,21 @@ constexpr size_t kPrepassMaxLds = 65536;
 hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s);
 bool prepass_lds_limit_ok(int rx, int ry, int rz);
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, int unroll, bool trace, hipStream_t s);
-hipError_t launch_energy_vox(const FinalizeArgs &a, int dim, hipStream_t s);
-hipError_t launch_select(const FinalizeArgs &a, int dim, hipStream_t s);
+hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int waves, int unroll, bool persistent, int grid,
+                               hipStream_t s);
+int evolve_batch_max_blocks(int dim, int waves, int unroll, int max_D, int max_M);
+
+// Engine helpers (engine_kernels.hip).
+hipError_t launch_reset_items(const JobDev *jobs, const int2 *items, int n_items, const DevContour *const *init,
+                              hipStream_t s);
+hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_count_unfinished(const JobDev *jobs, const int2 *items, int n_items, int *unfinished, hipStream_t s);
+hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, hipStream_t s);
+hipError_t launch_select(const JobDev &j, int dim, hipStream_t s);
+hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s);
+hipError_t launch_select_batch(const JobDev *jobs, const int *job_list, int n_jobs, int dim, hipStream_t s);
 
 }  // namespace snk
+
+// Uniform selection grid for one volume (defined in api.hip).
+int64_t snk_grid_for(const snk_params &P, int64_t nx, int64_t ny, int64_t nz, int G[3], double *cell_out);

@@ -27,6 +27,9 @@ EXPORTS = [
     "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
     "snk_sync", "snk_last_error", "snk_version",
+    "snk_engine_create", "snk_engine_destroy", "snk_engine_last_error", "snk_engine_set_launch",
+    "snk_engine_submit", "snk_engine_run", "snk_engine_step", "snk_engine_poll", "snk_engine_read",
+    "snk_engine_job_times", "snk_engine_release", "snk_engine_get_stats",
 ]
 
 
@@ -48,6 +51,14 @@ class snk_params(C.Structure):
 class snk_timing(C.Structure):
     _fields_ = [("prepass_ms", C.c_double), ("evolve_ms", C.c_double), ("finalize_ms", C.c_double),
                 ("evolved", C.c_int64), ("evolve_launches", C.c_int64)]
+
+
+class snk_engine_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("pending", C.c_int64), ("running", C.c_int64), ("bytes_in_use", C.c_uint64),
+                ("budget", C.c_uint64), ("last_ms", C.c_double), ("last_evolve_ms", C.c_double),
+                ("last_evolved", C.c_int64), ("waves", C.c_int32), ("gathers_in_flight", C.c_int32),
+                ("persistent", C.c_int32), ("graph_replays", C.c_int32)]
 
 
 _lib = None
@@ -82,11 +93,24 @@ def load(path: str = LIB_PATH):
         "snk_sync": [vp],
         "snk_last_error": [vp],
         "snk_version": [],
+        "snk_engine_create": [C.POINTER(C.c_void_p), C.c_int, vp, C.c_uint64],
+        "snk_engine_destroy": [vp],
+        "snk_engine_last_error": [vp],
+        "snk_engine_set_launch": [vp, i32, i32, i32],
+        "snk_engine_submit": [vp, C.POINTER(snk_params), vp, i32, vp, C.c_int, i64, i64, i64, C.c_int, vp, vp, vp,
+                              i64, i32, C.POINTER(C.c_uint64)],
+        "snk_engine_run": [vp],
+        "snk_engine_step": [vp, i32, C.POINTER(i32)],
+        "snk_engine_poll": [vp, vp, i64, C.POINTER(i64)],
+        "snk_engine_read": [vp, C.c_uint64, vp, vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64)],
+        "snk_engine_job_times": [vp, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "snk_engine_release": [vp, C.c_uint64],
+        "snk_engine_get_stats": [vp, C.POINTER(snk_engine_stats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
-        f.restype = C.c_char_p if name in ("snk_last_error", "snk_version") else C.c_int32
+        f.restype = C.c_char_p if name in ("snk_last_error", "snk_version", "snk_engine_last_error") else C.c_int32
     _lib = L
     return L
 
@@ -265,6 +289,134 @@ def snk_sync(h) -> None:
 
 def snk_last_error(h) -> str:
     return load().snk_last_error(h).decode()
+
+
+# ------------------------------------------------------------------------------------------------
+# engine (batched + served)
+# ------------------------------------------------------------------------------------------------
+
+def _echeck(e, code):
+    if code != SNK_OK:
+        raise SnkError(code, load().snk_engine_last_error(e).decode())
+
+
+def snk_engine_create(device: int = 0, stream=None, hbm_budget_bytes: int = 64 << 30):
+    e = C.c_void_p()
+    code = load().snk_engine_create(C.byref(e), int(device), _stream_handle(stream), int(hbm_budget_bytes))
+    if code != SNK_OK:
+        raise SnkError(code, "snk_engine_create failed")
+    return e
+
+
+def snk_engine_destroy(e) -> None:
+    _echeck(e, load().snk_engine_destroy(e))
+
+
+def snk_engine_last_error(e) -> str:
+    return load().snk_engine_last_error(e).decode()
+
+
+def snk_engine_set_launch(e, waves: int = 0, gathers_in_flight: int = 0, persistent: int = 1) -> None:
+    _echeck(e, load().snk_engine_set_launch(e, int(waves), int(gathers_in_flight), int(persistent)))
+
+
+def snk_engine_submit(e, params, dirs, vol, centers, r0=None, ids=None, n_iter: int = 100,
+                      on_device: bool | None = None) -> int:
+    s = params if isinstance(params, snk_params) else to_params(params)
+    d = np.ascontiguousarray(dirs, dtype=np.float32)
+    if on_device is None:
+        on_device = hasattr(vol, "data_ptr") and getattr(vol, "is_cuda", False)
+    if not hasattr(vol, "data_ptr"):
+        vol = np.ascontiguousarray(vol)
+    nz, ny, nx = vol.shape
+    c = np.zeros((len(centers), 3), dtype=np.float64)
+    cc = np.asarray(centers, dtype=np.float64)
+    if len(cc):
+        c[:, : cc.shape[1]] = cc
+    r = None if r0 is None else np.ascontiguousarray(r0, dtype=np.float32)
+    i = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
+    job = C.c_uint64(0)
+    _echeck(e, load().snk_engine_submit(e, C.byref(s), _ptr(d), int(d.shape[0]), _ptr(vol), _dtype_code(vol), nx, ny,
+                                        nz, int(bool(on_device)), _ptr(c), _ptr(r), _ptr(i), len(c), int(n_iter),
+                                        C.byref(job)))
+    return int(job.value)
+
+
+def snk_engine_run(e) -> None:
+    _echeck(e, load().snk_engine_run(e))
+
+
+def snk_engine_step(e, chunk: int) -> int:
+    k = C.c_int32(0)
+    _echeck(e, load().snk_engine_step(e, int(chunk), C.byref(k)))
+    return int(k.value)
+
+
+def snk_engine_poll(e, cap: int = 1 << 16) -> list:
+    buf = np.zeros(cap, np.uint64)
+    n = C.c_int64(0)
+    _echeck(e, load().snk_engine_poll(e, _ptr(buf), cap, C.byref(n)))
+    return [int(v) for v in buf[: n.value]]
+
+
+def snk_engine_read(e, job: int) -> dict:
+    n = C.c_int64(0)
+    load().snk_engine_read(e, int(job), None, None, None, None, None, None, None, 0, C.byref(n))
+    n = int(n.value)
+    out = {"radii": np.zeros(n, np.float32), "centers": np.zeros((n, 3), np.float64),
+           "e_mc": np.zeros(n, np.float32), "e_vox": np.zeros(n, np.float32),
+           "iters": np.zeros(n, np.int32), "status": np.zeros(n, np.uint8), "keep": np.zeros(n, np.uint8)}
+    got = C.c_int64(0)
+    _echeck(e, load().snk_engine_read(e, int(job), _ptr(out["radii"]), _ptr(out["centers"]), _ptr(out["e_mc"]),
+                                      _ptr(out["e_vox"]), _ptr(out["iters"]), _ptr(out["status"]),
+                                      _ptr(out["keep"]), n, C.byref(got)))
+    return out
+
+
+def snk_engine_job_times(e, job: int):
+    a, b = C.c_double(0), C.c_double(0)
+    _echeck(e, load().snk_engine_job_times(e, int(job), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def snk_engine_release(e, job: int) -> None:
+    _echeck(e, load().snk_engine_release(e, int(job)))
+
+
+def snk_engine_get_stats(e) -> dict:
+    s = snk_engine_stats()
+    _echeck(e, load().snk_engine_get_stats(e, C.byref(s)))
+    return {f: getattr(s, f) for f, _ in snk_engine_stats._fields_}
+
+
+class Engine:
+    """Owns one snk_engine handle; methods forward to the snk_engine_* entry points."""
+
+    def __init__(self, device: int = 0, stream=None, hbm_budget_bytes: int = 64 << 30):
+        self.e = snk_engine_create(device, stream, hbm_budget_bytes)
+
+    def close(self):
+        if self.e is not None:
+            snk_engine_destroy(self.e)
+            self.e = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __getattr__(self, name):
+        f = globals().get("snk_engine_" + name)
+        if f is None:
+            raise AttributeError(name)
+        return lambda *a, **k: f(self.e, *a, **k)
 
 
 class Context:

@@ -59,16 +59,19 @@ def test_params_struct_layout_matches_header(lib, tmp_path):
     from paper_1804_06304_amd import snk
     fields = [f for f, _ in snk.snk_params._fields_]
     tfields = [f for f, _ in snk.snk_timing._fields_]
+    efields = [f for f, _ in snk.snk_engine_stats._fields_]
     src = tmp_path / "layout.c"
     body = "".join(f'printf("%zu ", offsetof(snk_params, {f}));' for f in fields)
     body += "".join(f'printf("%zu ", offsetof(snk_timing, {f}));' for f in tfields)
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "snk.h"\nint main(void){'
-                   + body + 'printf("%zu %zu", sizeof(snk_params), sizeof(snk_timing)); return 0;}')
+    body += "".join(f'printf("%zu ", offsetof(snk_engine_stats, {f}));' for f in efields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "snk.h"\nint main(void){' + body +
+                   'printf("%zu %zu %zu", sizeof(snk_params), sizeof(snk_timing), sizeof(snk_engine_stats)); return 0;}')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)], text=True).split()]
     want = [getattr(snk.snk_params, f).offset for f in fields] + [getattr(snk.snk_timing, f).offset for f in tfields]
-    want += [ctypes.sizeof(snk.snk_params), ctypes.sizeof(snk.snk_timing)]
+    want += [getattr(snk.snk_engine_stats, f).offset for f in efields]
+    want += [ctypes.sizeof(snk.snk_params), ctypes.sizeof(snk.snk_timing), ctypes.sizeof(snk.snk_engine_stats)]
     assert vals == want
 
 
