@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--waves", type=int, default=0, help="wave64s per contour (0: automatic)")
     ap.add_argument("--unroll", type=int, default=0, help="gathers in flight per thread (0: automatic)")
+    ap.add_argument("--box", type=int, default=0, help="LDS footprint floats per contour (0: automatic, -1: off)")
     ap.add_argument("--cpu-sample", type=int, default=0, help="contours in the oracle baseline (0: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
@@ -109,21 +110,23 @@ def main():
     raw = torch.from_numpy(wl.raw).to("cuda:0")
     ctx = snk.Context(0, stream)
     ctx.set_params(p)
-    ctx.set_launch(args.waves, args.unroll)
+    ctx.set_launch(args.waves, args.unroll, args.box)
     ctx.set_directions(wl.dirs)
     ctx.load_volume(raw)
     torch.cuda.synchronize()
 
     if args.sweep:
-        for w in (1, 2, 4, 8):
-            for u in (1, 2, 4):
-                ctx.set_launch(w, u)
-                ms = []
-                for _ in range(3):
-                    ctx.load_seeds(wl.seeds, ids=wl.ids)
-                    ctx.evolve(wl.n_iter)
-                    ms.append(ctx.get_timing()["evolve_ms"])
-                log(f"sweep waves={w} gathers_in_flight={u}: evolve {min(ms):.3f} ms (min of 3; {ms})")
+        for box in (0, -1):
+            for w in (1, 2, 4, 8):
+                for u in (1, 2, 4):
+                    ctx.set_launch(w, u, box)
+                    ms = []
+                    for _ in range(3):
+                        ctx.load_seeds(wl.seeds, ids=wl.ids)
+                        ctx.evolve(wl.n_iter)
+                        ms.append(ctx.get_timing()["evolve_ms"])
+                    log(f"sweep box={box} waves={w} gathers_in_flight={u}: evolve {min(ms):.3f} ms "
+                        f"(min of 3; {[round(v, 3) for v in ms]})")
         ctx.close()
         return
 
@@ -165,7 +168,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "volume": "512x512x128 u16, h=(1,1,2)", "contours": len(wl.seeds),
                    "n_iter": wl.n_iter, "n_dirs": p.n_dirs, "n_rays": M, "n_radial": L,
-                   "waves_per_contour": args.waves or "auto", "gathers_in_flight": args.unroll or "auto"},
+                   "waves_per_contour": args.waves or "auto", "gathers_in_flight": args.unroll or "auto",
+                   "lds_box_floats": args.box or "auto"},
         "kernels_ms": {"prepass": float(np.mean(prepass_ms)), "evolve": ev_ms,
                        "finalize": float(np.mean(finalize_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

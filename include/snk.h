@@ -115,9 +115,11 @@ snk_status snk_destroy(snk_ctx *ctx);
 snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
 
 /* Launch shape of the evolution kernel: wave64s per contour (workgroup size 64 * waves; 0 =
- * automatic, 1, 2, 4 or 8) and sample points whose gathers one thread issues before consuming
- * them (0 = automatic, 1, 2 or 4). Results do not depend on either beyond FP32 summation order. */
-snk_status snk_set_launch(snk_ctx *ctx, int32_t waves_per_contour, int32_t gathers_in_flight);
+ * automatic, 1, 2, 4 or 8), sample points whose gathers one thread issues before consuming them
+ * (0 = automatic, 1, 2 or 4), and the LDS capacity (floats) for staging each contour's footprint box
+ * (0 = automatic, < 0 = off: every gather goes to memory). A contour whose box does not fit gathers
+ * from memory. Results do not depend on any of these beyond FP32 summation order. */
+snk_status snk_set_launch(snk_ctx *ctx, int32_t waves_per_contour, int32_t gathers_in_flight, int32_t lds_box_floats);
 
 /* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288 (the
  * table is staged in LDS). D must equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per
@@ -216,9 +218,11 @@ snk_status snk_engine_create(snk_engine **out, int device, void *hip_stream, uin
 snk_status snk_engine_destroy(snk_engine *e);
 const char *snk_engine_last_error(const snk_engine *e);
 
-/* Force the evolve launch shape (waves 1/2/4/8, gathers in flight 1/2/4, persistent 0/1), or
- * waves = 0 to pick per launch class (dim, D, M, L) by timing short trials of every shape. */
-snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent);
+/* Force the evolve launch shape (waves 1/2/4/8, gathers in flight 1/2/4, persistent 0/1, LDS box
+ * floats as in snk_set_launch), or waves = 0 to pick it per launch class (dim, D, M, L) by timing
+ * short trials of every shape. */
+snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent,
+                                 int32_t lds_box_floats);
 
 /* Queue a job (arguments as in snk_set_params / snk_set_directions / snk_load_volume /
  * snk_load_seeds; host data is copied, a device volume with on_device = 1 is borrowed until the job

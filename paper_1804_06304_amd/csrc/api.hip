@@ -22,6 +22,7 @@ struct snk_ctx {
     bool have_params = false;
     int waves = 0;   // 0: automatic
     int unroll = 0;  // 0: automatic
+    int box = 0;     // LDS footprint floats: 0 automatic, < 0 off
 
     std::vector<float> dirs_host;
     float *d_dirs = nullptr;
@@ -274,9 +275,11 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
     a.n_iter = n_iter;
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
+    const int waves = pick_waves(c);
+    a.box_cap = snk::evolve_box_cap(c->box, c->P.dim, waves, a.p.D, a.p.M, c->P);
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIPTRY(c, snk::launch_evolve(a, c->P.dim, pick_waves(c), c->unroll, trace, c->stream));
+    HIPTRY(c, snk::launch_evolve(a, c->P.dim, waves, c->unroll, trace, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
     c->ev_evo = true;
     c->evolve_launches += 1;
@@ -359,7 +362,7 @@ snk_status snk_set_params(snk_ctx *c, const snk_params *p) {
     return SNK_OK;
 }
 
-snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour, int32_t gathers_in_flight) {
+snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour, int32_t gathers_in_flight, int32_t lds_box_floats) {
     if (!c) return fail(c, SNK_EINVAL, "NULL context");
     if (waves_per_contour != 0 && waves_per_contour != 1 && waves_per_contour != 2 && waves_per_contour != 4 &&
         waves_per_contour != 8)
@@ -368,6 +371,7 @@ snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour, int32_t gathers
         return fail(c, SNK_EINVAL, "gathers_in_flight must be 0 (auto), 1, 2 or 4");
     c->waves = waves_per_contour;
     c->unroll = gathers_in_flight;
+    c->box = lds_box_floats;
     return SNK_OK;
 }
 

@@ -80,7 +80,9 @@ struct ClassKey {
 
 struct Launch {
     int waves = 4, unroll = 2, persistent = 1;
+    int box = 0;    // LDS footprint request (0 automatic, < 0 off)
     int grid = 1;   // workgroups of a persistent launch
+    int box_cap = 0;
 };
 
 constexpr int kMaxClasses = 64;            // launch classes per run (one queue head each)
@@ -364,6 +366,7 @@ snk_status prepass_job(snk_engine *e, const EJob &j) {
 struct ItemPlan {
     std::vector<int2> items;
     std::vector<std::pair<ClassKey, std::pair<int, int>>> classes;   // key -> [begin, end)
+    std::vector<snk_params> params;                                   // one job's parameters per class
     std::vector<int> joblist;
 };
 
@@ -380,6 +383,7 @@ ItemPlan plan_items(const std::vector<EJob *> &js) {
         for (const EJob *j : kv.second)
             for (int c = 0; c < j->n; ++c) pl.items.push_back(make_int2(j->slot, c));
         pl.classes.push_back({kv.first, {b, (int)pl.items.size()}});
+        pl.params.push_back(kv.second.front()->P);
     }
     return pl;
 }
@@ -399,7 +403,7 @@ snk_status upload_plan(snk_engine *e, const ItemPlan &pl) {
     return SNK_OK;
 }
 
-snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int cls, int chunk) {
+snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int cls, int chunk, int box_cap) {
     snk::BatchArgs a{};
     a.jobs = e->d_jobs;
     a.items = e->d_items + b;
@@ -409,12 +413,18 @@ snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int 
     a.counter = e->d_counters;
     a.max_D = k.D;
     a.max_M = k.M;
+    a.box_cap = box_cap;
     return a;
 }
 
 int grid_for(snk_engine *e, const ClassKey &k, const Launch &L, int n_items) {
-    const int per_cu = snk::evolve_batch_max_blocks(k.dim, L.waves, L.unroll, k.D, k.M);
+    const int per_cu = snk::evolve_batch_max_blocks(k.dim, L.waves, L.unroll, k.D, k.M, L.box_cap);
     return std::max(1, std::min(n_items, per_cu * e->cus));
+}
+
+// Box capacity of a launch shape for a class (uses the parameters of one job of the class).
+void resolve_box(Launch &L, const ClassKey &k, const snk_params &P) {
+    L.box_cap = snk::evolve_box_cap(L.box, k.dim, L.waves, k.D, k.M, P);
 }
 
 // Evolve launches of every class of the plan (queue heads must be zero).
@@ -423,7 +433,7 @@ snk_status launch_classes(snk_engine *e, const ItemPlan &pl, int chunk, const st
         const ClassKey &k = pl.classes[c].first;
         const int b = pl.classes[c].second.first, end = pl.classes[c].second.second;
         const Launch &L = shapes[c];
-        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk);
+        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk, L.box_cap);
         EHIP(e, snk::launch_evolve_batch(a, k.dim, L.waves, L.unroll, L.persistent != 0, L.grid, e->stream));
         e->last_launch = L;
     }
@@ -437,6 +447,7 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
         const ClassKey &k = pl.classes[c].first;
         const int b = pl.classes[c].second.first, end = pl.classes[c].second.second;
         const int n_items = end - b;
+        const snk_params &P = pl.params[c];
         Launch L{};
         auto it = e->tuned.find(k);
         if (e->force) {
@@ -446,24 +457,28 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
         } else if (allow_trials) {
             const int trial_iters = 6;
             float best_ms = 1e30f;
-            for (int w : {1, 2, 4}) {
+            for (int w : {1, 2, 4, 8}) {
                 for (int u : {1, 2, 4}) {
                     for (int pers : {0, 1}) {
-                        Launch T{w, u, pers, 1};
-                        T.grid = grid_for(e, k, T, n_items);
-                        EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs, e->stream));
-                        EHIP(e, snk::launch_zero(reinterpret_cast<unsigned long long *>(e->d_queues), kQueueWords,
-                                                 e->stream));
-                        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, trial_iters);
-                        EHIP(e, hipEventRecord(e->ev0, e->stream));
-                        EHIP(e, snk::launch_evolve_batch(a, k.dim, w, u, pers != 0, T.grid, e->stream));
-                        EHIP(e, hipEventRecord(e->ev1, e->stream));
-                        EHIP(e, hipEventSynchronize(e->ev1));
-                        float ms = 0.0f;
-                        EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            L = T;
+                        for (int bx : {0, -1}) {
+                            Launch T{w, u, pers, bx, 1, 0};
+                            resolve_box(T, k, P);
+                            T.grid = grid_for(e, k, T, n_items);
+                            EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs,
+                                                            e->stream));
+                            EHIP(e, snk::launch_zero(reinterpret_cast<unsigned long long *>(e->d_queues), kQueueWords,
+                                                     e->stream));
+                            snk::BatchArgs a = batch_args(e, k, b, end, (int)c, trial_iters, T.box_cap);
+                            EHIP(e, hipEventRecord(e->ev0, e->stream));
+                            EHIP(e, snk::launch_evolve_batch(a, k.dim, w, u, pers != 0, T.grid, e->stream));
+                            EHIP(e, hipEventRecord(e->ev1, e->stream));
+                            EHIP(e, hipEventSynchronize(e->ev1));
+                            float ms = 0.0f;
+                            EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                L = T;
+                            }
                         }
                     }
                 }
@@ -472,6 +487,7 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
             EHIP(e, hipStreamSynchronize(e->stream));
             e->tuned[k] = L;
         }
+        resolve_box(L, k, P);
         L.grid = grid_for(e, k, L, n_items);
         out.push_back(L);
     }
@@ -567,7 +583,8 @@ snk_status snk_engine_destroy(snk_engine *e) {
 
 const char *snk_engine_last_error(const snk_engine *e) { return e ? e->err.c_str() : ""; }
 
-snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent) {
+snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent,
+                                 int32_t lds_box_floats) {
     if (!e) return SNK_EINVAL;
     if (waves == 0) {
         e->force = false;
@@ -578,7 +595,7 @@ snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_i
         (persistent != 0 && persistent != 1))
         return efail(e, SNK_EINVAL, "waves in {0,1,2,4,8}, gathers_in_flight in {1,2,4}, persistent in {0,1}");
     e->force = true;
-    e->forced = Launch{waves, gathers_in_flight, persistent};
+    e->forced = Launch{waves, gathers_in_flight, persistent, lds_box_floats, 1, 0};
     drop_graph(e);
     return SNK_OK;
 }

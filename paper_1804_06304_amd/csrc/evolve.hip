@@ -103,6 +103,7 @@ struct Smem {
     int *rk;       // [2][MH] table row of each antithetic pair
     float *rxi;    // [2][MH] radial jitter of each pair
     float *red;    // [2][WAVES][NR] per-wave partial sums
+    float *box;    // staged footprint of the contour (box_cap floats)
     int MH;
     __device__ __forceinline__ Smem(float *base, int D, int MH_) {
         MH = MH_;
@@ -111,8 +112,11 @@ struct Smem {
         rk = reinterpret_cast<int *>(rot + 18);
         rxi = reinterpret_cast<float *>(rk + 2 * MH);
         red = rxi + 2 * MH;
+        box = red + 2 * WAVES * NR;
     }
-    static size_t bytes(int D, int MH) { return sizeof(float) * ((size_t)D * DIM + 18 + 4 * MH + 2 * WAVES * NR); }
+    static size_t bytes(int D, int MH, int box_cap) {
+        return sizeof(float) * ((size_t)D * DIM + 18 + 4 * MH + 2 * WAVES * NR + (size_t)box_cap);
+    }
 };
 
 // Wave 0 writes Q(n) into slot `par`; wave 1 (wave 0 when alone) writes the pair draws of n.
@@ -211,7 +215,7 @@ __device__ __forceinline__ int split(int anc, float w, int n, float &f) {
 }
 
 template <int DIM, bool BUF, bool CLAMP>
-__device__ __forceinline__ Tap<DIM> tap_load(const Vol<DIM, BUF> &v, const int anc[3], const float w[3]) {
+__device__ __forceinline__ Tap<DIM> vol_tap_load(const Vol<DIM, BUF> &v, const int anc[3], const float w[3]) {
     Tap<DIM> tp;
     const int ix = split<CLAMP>(anc[0], w[0], v.nx, tp.fx);
     const int iy = split<CLAMP>(anc[1], w[1], v.ny, tp.fy);
@@ -227,6 +231,43 @@ __device__ __forceinline__ Tap<DIM> tap_load(const Vol<DIM, BUF> &v, const int a
         tp.r[1] = v.template load<1>(idx);
         tp.r[2] = v.template load<2>(idx);
         tp.r[3] = v.template load<3>(idx);
+    }
+    return tp;
+}
+
+template <int DIM, bool CLAMP, bool BUF>
+__device__ __forceinline__ Tap<DIM> tap_load(const Vol<DIM, BUF> &v, const int anc[3], const float w[3]) {
+    return vol_tap_load<DIM, BUF, CLAMP>(v, anc, w);
+}
+
+// The contour's footprint staged in LDS: voxels [lo, lo + n) of the volume, x fastest. Holds exact
+// copies of the smoothed volume, so gathers from it equal gathers from memory.
+template <int DIM>
+struct Box {
+    const float *data;
+    int lo[3];
+    int bx, bxy;
+    int n[3];   // volume dimensions (clamp-to-edge happens in volume coordinates)
+};
+
+template <int DIM, bool CLAMP>
+__device__ __forceinline__ Tap<DIM> tap_load(const Box<DIM> &b, const int anc[3], const float w[3]) {
+    Tap<DIM> tp;
+    const int ix = split<CLAMP>(anc[0], w[0], b.n[0], tp.fx) - b.lo[0];
+    const int iy = split<CLAMP>(anc[1], w[1], b.n[1], tp.fy) - b.lo[1];
+    int idx = iy * b.bx + ix;
+    if constexpr (DIM == 2) {
+        tp.fz = 0.0f;
+    } else {
+        const int iz = split<CLAMP>(anc[2], w[2], b.n[2], tp.fz) - b.lo[2];
+        idx += iz * b.bxy;
+    }
+    const float *p = b.data + idx;
+    tp.r[0] = Pair{p[0], p[1]};
+    tp.r[1] = Pair{p[b.bx], p[b.bx + 1]};
+    if constexpr (DIM == 3) {
+        tp.r[2] = Pair{p[b.bxy], p[b.bxy + 1]};
+        tp.r[3] = Pair{p[b.bxy + b.bx], p[b.bxy + b.bx + 1]};
     }
     return tp;
 }
@@ -294,8 +335,8 @@ __device__ __forceinline__ float cube_or_square_root(float tau) {
 // Sums of one thread for one iteration. Fast mapping (M divides T or T divides M): a thread owns
 // whole rays and walks their radial points U at a time, issuing all U gathers before using them.
 // Otherwise points are taken round-robin, one at a time.
-template <int DIM, int T, int U, bool BUF, bool CLAMP>
-__device__ __forceinline__ void thread_sums(const Vol<DIM, BUF> &vol, const float inv_h[3], const int anc[3],
+template <int DIM, int T, int U, bool CLAMP, typename Src>
+__device__ __forceinline__ void thread_sums(const Src &vol, const float inv_h[3], const int anc[3],
                                             const float off[3], const Weight<DIM> &wt, float smax, const float Q[9],
                                             const float *tdir, const int *rk, const float *rxi, int M, int L, int t,
                                             float &accA, float &accBR, float accB[DIM]) {
@@ -352,7 +393,7 @@ __device__ __forceinline__ void thread_sums(const Vol<DIM, BUF> &vol, const floa
                     float w[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) w[i] = fmaf(rad[k], du[i], off[i]);
-                    tp[k] = tap_load<DIM, BUF, CLAMP>(vol, anc, w);
+                    tp[k] = tap_load<DIM, CLAMP>(vol, anc, w);
                 }
 #pragma unroll
                 for (int k = 0; k < U; ++k)
@@ -379,7 +420,7 @@ __device__ __forceinline__ void thread_sums(const Vol<DIM, BUF> &vol, const floa
         float w[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < DIM; ++i) w[i] = fmaf(rad * u[i], inv_h[i], off[i]);
-        point(rad, tap_load<DIM, BUF, CLAMP>(vol, anc, w), q1, q2);
+        point(rad, tap_load<DIM, CLAMP>(vol, anc, w), q1, q2);
     }
     if (cur_ray >= 0) flush(u, q1, q2);
 }
@@ -388,7 +429,7 @@ __device__ __forceinline__ void thread_sums(const Vol<DIM, BUF> &vol, const floa
 // leaves SNK_ACTIVE. Every thread of the workgroup calls this with the same arguments.
 template <int DIM, int WAVES, bool TRACE, int U, bool BUF>
 __device__ void run_contour(const JobParams &p, DevContour *slot, int n_iter, int target, float *trace_row,
-                            float *lds, unsigned long long *counter) {
+                            float *lds, int box_cap, unsigned long long *counter) {
     constexpr int T = 64 * WAVES;
     constexpr int NR = Smem<DIM, WAVES>::NR;
     constexpr float BALL = DIM == 3 ? 4.18879020478639098462f : 3.14159265358979323846f;
@@ -418,6 +459,20 @@ __device__ void run_contour(const JobParams &p, DevContour *slot, int n_iter, in
     const float inv_npts = 1.0f / (float)(p.M * p.L);
     const float tol2 = p.conv_tol * p.conv_tol;
     int ran = 0;
+    // staged footprint: voxels [b.lo, b.lo + bn) of the volume, valid when `staged`
+    Box<DIM> box;
+    box.data = sm.box;
+    int bn[3] = {1, 1, 1};
+    bool staged = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        box.lo[i] = 0;
+        box.n[i] = nn[i];
+    }
+    box.bx = box.bxy = 1;
+    int margin[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) margin[i] = max(1, (int)ceilf(1.5f * inv_h[i]));
 
     for (int it = 0; it < budget; ++it) {
         n += 1;
@@ -434,17 +489,70 @@ __device__ void run_contour(const JobParams &p, DevContour *slot, int n_iter, in
             const float ext = fmaf(smax * inv_h[i], 1.0001f, 1e-3f);
             interior = interior && (off[i] - ext > (float)(-anc[i])) && (off[i] + ext < (float)(nn[i] - 1 - anc[i]));
         }
+        // voxel range this iteration's gathers touch (corner pairs included), clamped to the volume
+        bool use_box = false;
+        if (box_cap > 0) {
+            int need_lo[3] = {0, 0, 0}, need_hi[3] = {0, 0, 0};
+            bool inside = staged;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                const float ext = fmaf(smax * inv_h[i], 1.0001f, 1e-3f);
+                // clamped gathers use index pairs within [0, n-2] + 1, so keep at least one such pair
+                need_lo[i] = max(0, min(nn[i] - 2, anc[i] + (int)floorf(off[i] - ext)));
+                need_hi[i] = min(nn[i] - 1, max(1, anc[i] + (int)floorf(off[i] + ext) + 1));
+                inside = inside && need_lo[i] >= box.lo[i] && need_hi[i] < box.lo[i] + bn[i];
+            }
+            if (!inside) {
+                int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+                long size = 1;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    lo[i] = max(0, need_lo[i] - margin[i]);
+                    cnt[i] = min(nn[i] - 1, need_hi[i] + margin[i]) - lo[i] + 1;
+                    size *= cnt[i];
+                }
+                staged = size <= box_cap;
+                if (staged) {
+                    // every wave finished reading the old box before the previous iteration's barrier
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        box.lo[i] = lo[i];
+                        bn[i] = cnt[i];
+                    }
+                    box.bx = cnt[0];
+                    box.bxy = cnt[0] * cnt[1];
+                    const int rows = cnt[1] * cnt[2];
+                    for (int row = wave; row < rows; row += WAVES) {
+                        const int y = row % cnt[1], z = row / cnt[1];
+                        const float *src = p.g.J + ((long)(lo[2] + z) * nn[1] + (lo[1] + y)) * nn[0] + lo[0];
+                        float *dst = sm.box + row * cnt[0];
+                        for (int x = lane; x < cnt[0]; x += 64) dst[x] = src[x];
+                    }
+                    __syncthreads();
+                }
+            }
+            use_box = staged;
+        }
         float accA = 0.0f, accBR = 0.0f, accB[DIM];
 #pragma unroll
         for (int i = 0; i < DIM; ++i) accB[i] = 0.0f;
         const int *rk = sm.rk + par * sm.MH;
         const float *rxi = sm.rxi + par * sm.MH;
-        if (interior)
-            thread_sums<DIM, T, U, BUF, false>(vol, inv_h, anc, off, wt, smax, Q, sm.tdir, rk, rxi, p.M, p.L, t,
-                                               accA, accBR, accB);
-        else
-            thread_sums<DIM, T, U, BUF, true>(vol, inv_h, anc, off, wt, smax, Q, sm.tdir, rk, rxi, p.M, p.L, t,
-                                              accA, accBR, accB);
+        if (use_box) {
+            if (interior)
+                thread_sums<DIM, T, U, false>(box, inv_h, anc, off, wt, smax, Q, sm.tdir, rk, rxi, p.M, p.L, t, accA,
+                                              accBR, accB);
+            else
+                thread_sums<DIM, T, U, true>(box, inv_h, anc, off, wt, smax, Q, sm.tdir, rk, rxi, p.M, p.L, t, accA,
+                                             accBR, accB);
+        } else {
+            if (interior)
+                thread_sums<DIM, T, U, false>(vol, inv_h, anc, off, wt, smax, Q, sm.tdir, rk, rxi, p.M, p.L, t, accA,
+                                              accBR, accB);
+            else
+                thread_sums<DIM, T, U, true>(vol, inv_h, anc, off, wt, smax, Q, sm.tdir, rk, rxi, p.M, p.L, t, accA,
+                                             accBR, accB);
+        }
         // draws of the next iteration, published by the barrier below
         if (it + 1 < budget) produce<DIM, WAVES>(sm, 1 - par, (uint32_t)(n + 1), id, p, wave, lane);
 
@@ -563,7 +671,8 @@ __global__ __launch_bounds__(64 * WAVES) void evolve_kernel(EvolveArgs a) {
     extern __shared__ float lds[];
     const int cid = blockIdx.x;
     run_contour<DIM, WAVES, TRACE, U, BUF>(a.p, a.st + cid, a.n_iter, 0x7fffffff,
-                                           TRACE ? a.trace + (long)cid * SNK_TRACE_W : nullptr, lds, a.counter);
+                                           TRACE ? a.trace + (long)cid * SNK_TRACE_W : nullptr, lds, a.box_cap,
+                                           a.counter);
 }
 
 // Copy of a record that every lane reads at the same address, forced into scalar registers (the
@@ -598,7 +707,7 @@ __global__ __launch_bounds__(64 * WAVES) void evolve_batch_kernel(BatchArgs a) {
             const JobParams p = uniform_copy(&a.jobs[job].p);
             DevContour *st = uniform_copy(&a.jobs[job].st);
             const int target = __builtin_amdgcn_readfirstlane(a.jobs[job].target);
-            run_contour<DIM, WAVES, false, U, BUF>(p, st + cid, a.chunk, target, nullptr, lds, a.counter);
+            run_contour<DIM, WAVES, false, U, BUF>(p, st + cid, a.chunk, target, nullptr, lds, a.box_cap, a.counter);
             __syncthreads();
         }
     } else {
@@ -609,18 +718,18 @@ __global__ __launch_bounds__(64 * WAVES) void evolve_batch_kernel(BatchArgs a) {
         const JobParams p = uniform_copy(&a.jobs[job].p);
         DevContour *st = uniform_copy(&a.jobs[job].st);
         const int target = __builtin_amdgcn_readfirstlane(a.jobs[job].target);
-        run_contour<DIM, WAVES, false, U, BUF>(p, st + cid, a.chunk, target, nullptr, lds, a.counter);
+        run_contour<DIM, WAVES, false, U, BUF>(p, st + cid, a.chunk, target, nullptr, lds, a.box_cap, a.counter);
     }
 }
 
 template <int DIM, int WAVES>
-size_t smem_bytes(int D, int M) {
-    return Smem<DIM, WAVES>::bytes(D, M / 2);
+size_t smem_bytes(int D, int M, int box_cap) {
+    return Smem<DIM, WAVES>::bytes(D, M / 2, box_cap);
 }
 
 template <int DIM, int WAVES, bool TRACE, int U>
 hipError_t launch_t(const EvolveArgs &a, hipStream_t s) {
-    const size_t lds = smem_bytes<DIM, WAVES>(a.p.D, a.p.M);
+    const size_t lds = smem_bytes<DIM, WAVES>(a.p.D, a.p.M, a.box_cap);
     if (a.p.buffer_ok)
         hipLaunchKernelGGL((evolve_kernel<DIM, WAVES, TRACE, U, true>), dim3(a.n), dim3(64 * WAVES), lds, s, a);
     else
@@ -655,7 +764,7 @@ hipError_t launch_w(const EvolveArgs &a, int waves, int unroll, hipStream_t s) {
 
 template <int DIM, int WAVES, int U, bool PERSISTENT>
 hipError_t batch_t(const BatchArgs &a, int grid, hipStream_t s) {
-    const size_t lds = smem_bytes<DIM, WAVES>(a.max_D, a.max_M);
+    const size_t lds = smem_bytes<DIM, WAVES>(a.max_D, a.max_M, a.box_cap);
     const int g = PERSISTENT ? grid : a.n_items;
     if (g <= 0) return hipSuccess;
     hipLaunchKernelGGL((evolve_batch_kernel<DIM, WAVES, U, true, PERSISTENT>), dim3(g), dim3(64 * WAVES), lds, s, a);
@@ -687,9 +796,9 @@ hipError_t batch_w(const BatchArgs &a, int waves, int unroll, bool persistent, i
 }
 
 template <int DIM, int WAVES, int U>
-int max_blocks_t(int max_D, int max_M) {
+int max_blocks_t(int max_D, int max_M, int box_cap) {
     int blocks = 0;
-    const size_t lds = smem_bytes<DIM, WAVES>(max_D, max_M);
+    const size_t lds = smem_bytes<DIM, WAVES>(max_D, max_M, box_cap);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, evolve_batch_kernel<DIM, WAVES, U, true, true>,
                                                      64 * WAVES, lds) != hipSuccess)
         return 1;
@@ -697,21 +806,21 @@ int max_blocks_t(int max_D, int max_M) {
 }
 
 template <int DIM, int WAVES>
-int max_blocks_u(int unroll, int max_D, int max_M) {
+int max_blocks_u(int unroll, int max_D, int max_M, int box_cap) {
     switch (unroll >= 4 ? 4 : (unroll >= 2 ? 2 : 1)) {
-        case 4: return max_blocks_t<DIM, WAVES, 4>(max_D, max_M);
-        case 2: return max_blocks_t<DIM, WAVES, 2>(max_D, max_M);
-        default: return max_blocks_t<DIM, WAVES, 1>(max_D, max_M);
+        case 4: return max_blocks_t<DIM, WAVES, 4>(max_D, max_M, box_cap);
+        case 2: return max_blocks_t<DIM, WAVES, 2>(max_D, max_M, box_cap);
+        default: return max_blocks_t<DIM, WAVES, 1>(max_D, max_M, box_cap);
     }
 }
 
 template <int DIM>
-int max_blocks_w(int waves, int unroll, int max_D, int max_M) {
+int max_blocks_w(int waves, int unroll, int max_D, int max_M, int box_cap) {
     switch (waves) {
-        case 1: return max_blocks_u<DIM, 1>(unroll, max_D, max_M);
-        case 2: return max_blocks_u<DIM, 2>(unroll, max_D, max_M);
-        case 8: return max_blocks_u<DIM, 8>(unroll, max_D, max_M);
-        default: return max_blocks_u<DIM, 4>(unroll, max_D, max_M);
+        case 1: return max_blocks_u<DIM, 1>(unroll, max_D, max_M, box_cap);
+        case 2: return max_blocks_u<DIM, 2>(unroll, max_D, max_M, box_cap);
+        case 8: return max_blocks_u<DIM, 8>(unroll, max_D, max_M, box_cap);
+        default: return max_blocks_u<DIM, 4>(unroll, max_D, max_M, box_cap);
     }
 }
 
@@ -731,8 +840,33 @@ hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int waves, int unrol
     return batch_w<3>(a, waves, unroll, persistent, grid, s);
 }
 
-int evolve_batch_max_blocks(int dim, int waves, int unroll, int max_D, int max_M) {
-    return dim == 2 ? max_blocks_w<2>(waves, unroll, max_D, max_M) : max_blocks_w<3>(waves, unroll, max_D, max_M);
+int evolve_batch_max_blocks(int dim, int waves, int unroll, int max_D, int max_M, int box_cap) {
+    return dim == 2 ? max_blocks_w<2>(waves, unroll, max_D, max_M, box_cap)
+                    : max_blocks_w<3>(waves, unroll, max_D, max_M, box_cap);
+}
+
+size_t evolve_lds_bytes(int dim, int waves, int D, int M, int box_cap) {
+    const int w = waves == 1 || waves == 2 || waves == 8 ? waves : 4;
+    const int nr = 2 + dim;
+    return sizeof(float) * ((size_t)D * dim + 18 + 4 * (M / 2) + 2 * w * nr + (size_t)box_cap);
+}
+
+int evolve_box_cap(int requested, int dim, int waves, int D, int M, const snk_params &P) {
+    if (requested < 0) return 0;
+    const size_t limit = 65536;  // dynamic LDS of one workgroup
+    const size_t base = evolve_lds_bytes(dim, waves, D, M, 0);
+    if (base + 4096 >= limit) return 0;
+    const int maxcap = (int)((limit - base) / 4);
+    if (requested > 0) return requested < maxcap ? requested : maxcap;
+    const double R = P.r_max < 1.5 * P.r_init ? P.r_max : 1.5 * P.r_init;
+    const double smax = R + 0.5 * P.dR;
+    long size = 1;
+    for (int a = 0; a < dim; ++a) {
+        const double inv_h = 1.0 / P.spacing[a];
+        const int margin = (int)ceil(1.5 * inv_h) > 1 ? (int)ceil(1.5 * inv_h) : 1;
+        size *= 2 * (long)ceil(smax * inv_h) + 3 + 2 * margin;
+    }
+    return size < maxcap ? (int)size : maxcap;
 }
 
 }  // namespace snk

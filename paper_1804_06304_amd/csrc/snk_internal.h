@@ -53,6 +53,7 @@ struct EvolveArgs {
     int n_iter;
     float *trace;                // n x SNK_TRACE_W or null
     unsigned long long *counter; // contour-iterations evolved
+    int box_cap;                 // LDS floats for the staged footprint (0: gather from memory)
 };
 
 // One job of a batch, resident in device memory.
@@ -77,6 +78,7 @@ struct BatchArgs {
     int chunk;                   // iterations per contour in this launch
     unsigned long long *counter;
     int max_D, max_M;
+    int box_cap;                 // LDS floats for the staged footprint (0: gather from memory)
 };
 
 struct PrepassArgs {
@@ -98,7 +100,11 @@ bool prepass_lds_limit_ok(int rx, int ry, int rz);
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, int unroll, bool trace, hipStream_t s);
 hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int waves, int unroll, bool persistent, int grid,
                                hipStream_t s);
-int evolve_batch_max_blocks(int dim, int waves, int unroll, int max_D, int max_M);
+int evolve_batch_max_blocks(int dim, int waves, int unroll, int max_D, int max_M, int box_cap);
+size_t evolve_lds_bytes(int dim, int waves, int D, int M, int box_cap);
+// LDS floats for the staged footprint: `requested` > 0 as given, 0 = automatic (the box of a contour
+// of radius about 1.5 r_init, bounded by what fits the workgroup's LDS), < 0 = off.
+int evolve_box_cap(int requested, int dim, int waves, int D, int M, const snk_params &P);
 
 // Engine helpers (engine_kernels.hip).
 hipError_t launch_reset_items(const JobDev *jobs, const int2 *items, int n_items, const DevContour *const *init,

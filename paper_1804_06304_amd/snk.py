@@ -77,7 +77,7 @@ def load(path: str = LIB_PATH):
         "snk_create": [C.POINTER(C.c_void_p), C.c_int, vp],
         "snk_destroy": [vp],
         "snk_set_params": [vp, C.POINTER(snk_params)],
-        "snk_set_launch": [vp, i32, i32],
+        "snk_set_launch": [vp, i32, i32, i32],
         "snk_set_directions": [vp, vp, i32],
         "snk_load_volume": [vp, vp, C.c_int, i64, i64, i64, C.c_int],
         "snk_prepass": [vp],
@@ -96,7 +96,7 @@ def load(path: str = LIB_PATH):
         "snk_engine_create": [C.POINTER(C.c_void_p), C.c_int, vp, C.c_uint64],
         "snk_engine_destroy": [vp],
         "snk_engine_last_error": [vp],
-        "snk_engine_set_launch": [vp, i32, i32, i32],
+        "snk_engine_set_launch": [vp, i32, i32, i32, i32],
         "snk_engine_submit": [vp, C.POINTER(snk_params), vp, i32, vp, C.c_int, i64, i64, i64, C.c_int, vp, vp, vp,
                               i64, i32, C.POINTER(C.c_uint64)],
         "snk_engine_run": [vp],
@@ -175,8 +175,8 @@ def snk_set_params(h, params) -> None:
     _check(h, load().snk_set_params(h, C.byref(s)))
 
 
-def snk_set_launch(h, waves_per_contour: int = 0, gathers_in_flight: int = 0) -> None:
-    _check(h, load().snk_set_launch(h, int(waves_per_contour), int(gathers_in_flight)))
+def snk_set_launch(h, waves_per_contour: int = 0, gathers_in_flight: int = 0, lds_box_floats: int = 0) -> None:
+    _check(h, load().snk_set_launch(h, int(waves_per_contour), int(gathers_in_flight), int(lds_box_floats)))
 
 
 def snk_set_directions(h, dirs) -> None:
@@ -316,8 +316,10 @@ def snk_engine_last_error(e) -> str:
     return load().snk_engine_last_error(e).decode()
 
 
-def snk_engine_set_launch(e, waves: int = 0, gathers_in_flight: int = 0, persistent: int = 1) -> None:
-    _echeck(e, load().snk_engine_set_launch(e, int(waves), int(gathers_in_flight), int(persistent)))
+def snk_engine_set_launch(e, waves: int = 0, gathers_in_flight: int = 0, persistent: int = 1,
+                          lds_box_floats: int = 0) -> None:
+    _echeck(e, load().snk_engine_set_launch(e, int(waves), int(gathers_in_flight), int(persistent),
+                                            int(lds_box_floats)))
 
 
 def snk_engine_submit(e, params, dirs, vol, centers, r0=None, ids=None, n_iter: int = 100,

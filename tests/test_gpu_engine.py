@@ -42,7 +42,7 @@ def plain(snk, wl, waves, unroll):
     import torch
     ctx = snk.Context(0, torch.cuda.current_stream())
     ctx.set_params(wl.params)
-    ctx.set_launch(waves, unroll)
+    ctx.set_launch(waves, unroll, 0)
     ctx.set_directions(wl.dirs)
     ctx.load_volume(wl.raw)
     ctx.load_seeds(wl.seeds, ids=wl.ids)

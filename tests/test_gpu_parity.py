@@ -41,11 +41,11 @@ def stream():
     return torch.cuda.current_stream()
 
 
-def make_ctx(snk, stream, wl, waves=0, on_device=True, unroll=0):
+def make_ctx(snk, stream, wl, waves=0, on_device=True, unroll=0, box=0):
     import torch
     ctx = snk.Context(0, stream)
     ctx.set_params(wl.params)
-    ctx.set_launch(waves, unroll)
+    ctx.set_launch(waves, unroll, box)
     ctx.set_directions(wl.dirs)
     if on_device:
         raw = torch.from_numpy(np.ascontiguousarray(wl.raw)).to("cuda:0")
@@ -79,7 +79,7 @@ def tol_check(name, got, ref, ref_abs, slack, rel=1e-5):
     return float(np.max(err / tol)) if len(ref) else 0.0
 
 
-def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0, unroll=0):
+def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0, unroll=0, box=0):
     p = wl.params
     rng = np.random.default_rng(seed)
     seeds = np.concatenate([wl.seeds, extra_seeds(wl, n_extra, rng)]) if n_extra else wl.seeds
@@ -88,7 +88,7 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0, 
     r0[: len(wl.seeds)] = p.r_init
     J = oracle.prepass(wl.raw, p)
     st = oracle.init_state(p, seeds, r0=r0, ids=ids, shape_zyx=wl.raw.shape)
-    ctx = make_ctx(snk, stream, wl, waves=waves, unroll=unroll)
+    ctx = make_ctx(snk, stream, wl, waves=waves, unroll=unroll, box=box)
     ctx.load_seeds(seeds, r0=r0.astype(np.float32), ids=ids)
     worst = {}
     kinked = 0
@@ -177,10 +177,30 @@ def test_one_step_parity_2d(snk, stream):
     one_step_parity(snk, stream, wl, [0, 2, 25], n_extra=40)
 
 
-@pytest.mark.parametrize("waves,unroll", [(1, 1), (1, 4), (2, 2), (8, 1), (8, 4)])
-def test_one_step_parity_launch_shapes(snk, stream, waves, unroll):
-    say(f"one-step parity tiny, {waves} waves per contour, {unroll} gathers in flight")
-    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, waves=waves, unroll=unroll)
+@pytest.mark.parametrize("waves,unroll,box", [(1, 1, 0), (1, 4, 0), (2, 2, -1), (8, 1, 0), (8, 4, 512), (4, 2, 3000)])
+def test_one_step_parity_launch_shapes(snk, stream, waves, unroll, box):
+    """Launch shapes, including memory gathers only (box -1) and LDS boxes too small for some
+    contours (512 / 3000 floats), so that staged and unstaged contours share a launch."""
+    say(f"one-step parity tiny, {waves} waves per contour, {unroll} gathers in flight, box {box}")
+    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, waves=waves, unroll=unroll, box=box)
+
+
+def test_staged_equals_unstaged_bitwise(snk, stream):
+    """The LDS footprint holds exact copies of the volume: a free run with and without staging is
+    bit-identical (same launch shape otherwise)."""
+    wl = synth.tiny_config()
+    say("free run tiny: LDS-staged vs memory gathers")
+    outs = []
+    for box in (0, -1, 700):
+        ctx = make_ctx(snk, stream, wl, waves=4, unroll=2, box=box)
+        ctx.load_seeds(wl.seeds, ids=wl.ids)
+        ctx.evolve(wl.n_iter)
+        ctx.finalize()
+        outs.append(ctx.read())
+        ctx.close()
+    for o in outs[1:]:
+        for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
+            assert np.array_equal(outs[0][k], o[k]), k
 
 
 def test_one_step_parity_many_rays(snk, stream):
