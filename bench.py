@@ -78,6 +78,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="only time the evolve kernel for every (waves, gathers-in-flight) launch shape")
+    ap.add_argument("--workload", default="slab", choices=["slab", "batched", "served"],
+                    help="slab: the plain path on the slab volume (default); batched: 256 uneven subvolumes "
+                         "through the engine vs the plain per-volume loop; served: Poisson tile requests")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="served: arrival window (s)")
+    ap.add_argument("--rate", type=float, default=200.0, help="served: mean arrivals per second")
+    ap.add_argument("--chunk", type=int, default=25, help="served: iterations per engine step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -102,6 +108,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read_per_copy": src.numel() * 4, "copies": 4}), flush=True)
         return
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
     t0 = time.perf_counter()
     wl = synth.slab_config()
     log(f"workload {wl.name}: generated in {time.perf_counter() - t0:.1f} s")
@@ -182,6 +192,172 @@ def main():
         base, parity = cpu_baseline(wl, out, args.cpu_sample)
         line["cpu_baseline"] = base
         line["parity_sample"] = parity
+    print(json.dumps(line), flush=True)
+
+
+def plain_pass(snk, ctx, wl, raw_dev):
+    """One volume through the plain per-volume path (a context reused across volumes)."""
+    ctx.set_params(wl.params)
+    ctx.set_directions(wl.dirs)
+    ctx.load_volume(raw_dev)
+    ctx.load_seeds(wl.seeds, ids=wl.ids)
+    ctx.prepass()
+    ctx.evolve(wl.n_iter)
+    ctx.finalize()
+    return ctx.read()
+
+
+def bench_batched(args):
+    """256 cubic u16 subvolumes (edge 32..160, 10..800 nuclei, D 162 or 642): the engine's captured
+    batched run against the plain per-volume loop on the same resident inputs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1804_06304_amd import snk
+
+    t0 = time.perf_counter()
+    jobs = synth.subvolume_batch()
+    log(f"batched workload: {len(jobs)} subvolumes, {sum(len(w.seeds) for w in jobs)} contours, "
+        f"{sum(w.raw.size for w in jobs) / 1e6:.0f} M voxels, generated in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    raws = [torch.from_numpy(w.raw).to("cuda:0") for w in jobs]
+    torch.cuda.synchronize()
+    vu_of = lambda outs: sum(int(o["iters"].sum()) * w.params.n_rays for w, o in zip(jobs, outs))
+
+    ctx = snk.Context(0, stream)
+    outs = [plain_pass(snk, ctx, w, r) for w, r in zip(jobs[:8], raws[:8])]   # warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_outs = [plain_pass(snk, ctx, w, r) for w, r in zip(jobs, raws)]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    ctx.close()
+    plain_vu = vu_of(plain_outs)
+    log(f"plain per-volume loop: {plain_s * 1e3:.1f} ms, {plain_vu / plain_s:.4g} vertex-updates/s")
+
+    eng = snk.Engine(0, stream, 64 << 30)
+    ids = [eng.submit(w.params, w.dirs, r, w.seeds, ids=w.ids, n_iter=w.n_iter) for w, r in zip(jobs, raws)]
+    t0 = time.perf_counter()
+    eng.run()   # autotune per launch class + capture
+    log(f"engine first run (autotune + capture): {(time.perf_counter() - t0) * 1e3:.1f} ms")
+    for _ in range(args.warmup):
+        eng.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eng.run()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    outs = [eng.read(j) for j in ids]
+    st = eng.get_stats()
+    eng.close()
+    vu = vu_of(outs) * args.steps
+    same = all(np.array_equal(a["iters"], b["iters"]) for a, b in zip(outs, plain_outs))
+    drift = max(float(np.max(np.abs(a["radii"] - b["radii"]), initial=0.0)) for a, b in zip(outs, plain_outs))
+    line = {
+        "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched-256-subvolumes-u16", "volumes": len(jobs),
+                   "contours": sum(len(w.seeds) for w in jobs), "n_iter": jobs[0].n_iter,
+                   "launch": {"waves": st["waves"], "gathers_in_flight": st["gathers_in_flight"],
+                              "persistent": st["persistent"]}},
+        "graph_ms": st["last_ms"],
+        "plain_loop": {"value": plain_vu / plain_s, "ms": plain_s * 1e3},
+        "speedup_vs_plain_loop": (vu / secs) / (plain_vu / plain_s),
+        "parity_vs_plain": {"same_iters": same, "max_abs_dR": drift},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_served(args):
+    """Poisson stream of tile requests (cubic u16 tiles 96^3..288^3 from a pool generated once and
+    resident on the device; every request has its own contour ids, so its samples differ) through
+    the engine's continuous batching; reports p50/p99 latency (arrival to results on the host) and
+    throughput, against serving the same requests one at a time through the plain path."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1804_06304_amd import snk
+
+    t0 = time.perf_counter()
+    pool = synth.served_tiles()
+    log(f"served workload: pool of {len(pool)} tiles ({min(w.raw.shape[0] for w in pool)}^3.."
+        f"{max(w.raw.shape[0] for w in pool)}^3), generated in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    raws = [torch.from_numpy(w.raw).to("cuda:0") for w in pool]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0x5E)
+    arrivals, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t > args.serve_seconds:
+            break
+        arrivals.append((t, int(rng.integers(len(pool)))))
+    log(f"{len(arrivals)} requests over {args.serve_seconds:.0f} s (rate {args.rate}/s)")
+
+    eng = snk.Engine(0, stream, 64 << 30)
+    # warm-up: tune the launch class on a few pool tiles, then forget them
+    warm = [eng.submit(w.params, w.dirs, r, w.seeds, ids=w.ids, n_iter=w.n_iter) for w, r in zip(pool[:4], raws[:4])]
+    eng.run()
+    for j in warm:
+        eng.release(j)
+    eng.poll()
+
+    req_job, job_req, lat, vu = {}, {}, [], 0
+    nxt = 0
+    t0 = time.perf_counter()
+    while nxt < len(arrivals) or job_req:
+        now = time.perf_counter() - t0
+        while nxt < len(arrivals) and arrivals[nxt][0] <= now:
+            w = pool[arrivals[nxt][1]]
+            ids = (np.uint32(nxt) << np.uint32(16)) + np.arange(len(w.seeds), dtype=np.uint32)
+            j = eng.submit(w.params, w.dirs, raws[arrivals[nxt][1]], w.seeds, ids=ids, n_iter=w.n_iter)
+            job_req[j] = nxt
+            nxt += 1
+        st = eng.get_stats()
+        if st["running"] or st["pending"]:
+            eng.step(args.chunk)
+        elif nxt < len(arrivals):
+            time.sleep(max(0.0, arrivals[nxt][0] - (time.perf_counter() - t0)))
+        for j in eng.poll():
+            r = job_req.pop(j)
+            done = time.perf_counter() - t0
+            lat.append(done - arrivals[r][0])
+            out = eng.read(j)
+            vu += int(out["iters"].sum()) * pool[arrivals[r][1]].params.n_rays
+            eng.release(j)
+    secs = time.perf_counter() - t0
+    eng.close()
+    lat_ms = np.array(lat) * 1e3
+
+    # the same kind of request served one at a time through the plain path
+    ctx = snk.Context(0, stream)
+    plain_pass(snk, ctx, pool[0], raws[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pvu, plat = 0, []
+    for i in range(min(48, len(arrivals))):
+        k = arrivals[i][1]
+        s0 = time.perf_counter()
+        o = plain_pass(snk, ctx, pool[k], raws[k])
+        plat.append(time.perf_counter() - s0)
+        pvu += int(o["iters"].sum()) * pool[k].params.n_rays
+    plain_s = time.perf_counter() - t1
+    ctx.close()
+    line = {
+        "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": len(arrivals),
+        "warmup": 4, "ms_per_step": secs / max(len(arrivals), 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served-poisson-tiles-u16", "rate_per_s": args.rate, "window_s": args.serve_seconds,
+                   "tiles_in_pool": len(pool), "n_iter": pool[0].n_iter, "chunk": args.chunk},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "max": float(lat_ms.max())},
+        "requests": len(arrivals), "wall_s": secs,
+        "plain_one_at_a_time": {"value": pvu / plain_s, "latency_ms_p50": float(np.median(plat) * 1e3)},
+    }
     print(json.dumps(line), flush=True)
 
 

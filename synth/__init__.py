@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "Params", "Workload", "icosphere", "circle_directions", "render_ellipsoids", "blurred_ball",
-    "tiny_config", "slab_config", "plane_config", "subvolume_batch", "served_source",
+    "tiny_config", "slab_config", "plane_config", "subvolume_batch", "served_tiles",
     "CONFIG_SEED_BASE",
 ]
 
@@ -416,5 +416,35 @@ def subvolume_batch(seed: int = CONFIG_SEED_BASE + 4, n_vol: int = 256, edge_lo:
     return out
 
 
-def served_source(*args, **kw):  # pragma: no cover - filled in with the serving engine
-    raise NotImplementedError("served tile source is generated by the serving harness")
+def served_tiles(seed: int = CONFIG_SEED_BASE + 5, n_tiles: int = 24, edge_lo: int = 64, edge_hi: int = 256,
+                 halo: int = 16, max_edge: int = 288, n_iter: int = 200):
+    """Pool of tile-segmentation requests: cubic uint16 tiles (core edge U{edge_lo..edge_hi} plus a
+    halo, capped at max_edge), nucleus density U[20, 400] per 128^3 block, smooth multiplicative gain
+    0.7-1.0 and Poisson counts, spacing (1, 1, 2); seeds are the true centres in the tile core.
+    D 162, M 32, L 16."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(n_tiles):
+        core = int(rng.integers(edge_lo, edge_hi + 1))
+        e = min(core + 2 * halo, max_edge)
+        density = rng.uniform(20.0, 400.0)
+        n_target = max(1, int(density * (e ** 3) / 128.0 ** 3))
+        wl = slab_config(seed=int(rng.integers(1 << 62)), n_target=n_target, shape_xyz=(e, e, e), n_iter=n_iter)
+        # smooth gain field 0.7..1.0 along a random direction
+        g = rng.normal(size=3)
+        g /= np.linalg.norm(g)
+        zz, yy, xx = np.meshgrid(*(np.linspace(0.0, 1.0, e),) * 3, indexing="ij")
+        ramp = (g[0] * xx + g[1] * yy + g[2] * zz)
+        ramp = (ramp - ramp.min()) / max(ramp.max() - ramp.min(), 1e-9)
+        gain = (0.7 + 0.3 * ramp).astype(np.float32)
+        wl.raw = np.clip(np.rint(wl.raw.astype(np.float32) * gain), 0, 65535).astype(np.uint16)
+        h = np.asarray(wl.params.spacing)
+        lo, hi = halo * h, (e - 1 - halo) * h
+        core_mask = np.all((wl.truth["centers"] >= lo) & (wl.truth["centers"] <= hi), axis=1)
+        wl.seeds = wl.truth["centers"][core_mask].copy()
+        wl.ids = np.arange(len(wl.seeds), dtype=np.uint32)
+        wl.params = wl.params.replace(n_dirs=162, n_rays=32)
+        wl.dirs = icosphere(2)
+        wl.name = "tile%02d-%d^3-%d" % (t, e, len(wl.seeds))
+        out.append(wl)
+    return out
