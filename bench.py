@@ -71,13 +71,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--waves", type=int, default=0, help="wave64s per contour (0: automatic)")
-    ap.add_argument("--unroll", type=int, default=0, help="gathers in flight per thread (0: automatic)")
-    ap.add_argument("--box", type=int, default=0, help="LDS footprint floats per contour (0: automatic, -1: off)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per contour: 16..256 (0: automatic)")
+    ap.add_argument("--unroll", type=int, default=0, help="pair-points in flight per lane (0: automatic)")
+    ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad")
     ap.add_argument("--cpu-sample", type=int, default=0, help="contours in the oracle baseline (0: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
-                    help="only time the evolve kernel for every (waves, gathers-in-flight) launch shape")
+                    help="only time the evolve kernel for every (lanes, pair-points in flight, layout) shape")
     ap.add_argument("--workload", default="slab", choices=["slab", "batched", "served"],
                     help="slab: the plain path on the slab volume (default); batched: 256 uneven subvolumes "
                          "through the engine vs the plain per-volume loop; served: Poisson tile requests")
@@ -120,22 +120,22 @@ def main():
     raw = torch.from_numpy(wl.raw).to("cuda:0")
     ctx = snk.Context(0, stream)
     ctx.set_params(p)
-    ctx.set_launch(args.waves, args.unroll, args.box)
+    ctx.set_launch(args.lanes, args.unroll, args.layout)
     ctx.set_directions(wl.dirs)
     ctx.load_volume(raw)
     torch.cuda.synchronize()
 
     if args.sweep:
-        for box in (0, -1):
-            for w in (1, 2, 4, 8):
-                for u in (1, 2, 4):
-                    ctx.set_launch(w, u, box)
+        for layout in (2, 1):
+            for g in (16, 32, 64, 128, 256):
+                for u in (1, 2):
+                    ctx.set_launch(g, u, layout)
                     ms = []
                     for _ in range(3):
                         ctx.load_seeds(wl.seeds, ids=wl.ids)
                         ctx.evolve(wl.n_iter)
                         ms.append(ctx.get_timing()["evolve_ms"])
-                    log(f"sweep box={box} waves={w} gathers_in_flight={u}: evolve {min(ms):.3f} ms "
+                    log(f"sweep layout={layout} lanes={g} pairs_in_flight={u}: evolve {min(ms):.3f} ms "
                         f"(min of 3; {[round(v, 3) for v in ms]})")
         ctx.close()
         return
@@ -178,8 +178,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "volume": "512x512x128 u16, h=(1,1,2)", "contours": len(wl.seeds),
                    "n_iter": wl.n_iter, "n_dirs": p.n_dirs, "n_rays": M, "n_radial": L,
-                   "waves_per_contour": args.waves or "auto", "gathers_in_flight": args.unroll or "auto",
-                   "lds_box_floats": args.box or "auto"},
+                   "lanes_per_contour": args.lanes or "auto", "pairs_in_flight": args.unroll or "auto",
+                   "layout": {0: "auto", 1: "plain", 2: "quad"}[args.layout]},
         "kernels_ms": {"prepass": float(np.mean(prepass_ms)), "evolve": ev_ms,
                        "finalize": float(np.mean(finalize_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -261,8 +261,9 @@ def bench_batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched-256-subvolumes-u16", "volumes": len(jobs),
                    "contours": sum(len(w.seeds) for w in jobs), "n_iter": jobs[0].n_iter,
-                   "launch": {"waves": st["waves"], "gathers_in_flight": st["gathers_in_flight"],
-                              "persistent": st["persistent"]}},
+                   "launch": {"lanes_per_contour": st["lanes_per_contour"],
+                              "pairs_in_flight": st["pairs_in_flight"], "persistent": st["persistent"],
+                              "layout": st["layout"]}},
         "graph_ms": st["last_ms"],
         "plain_loop": {"value": plain_vu / plain_s, "ms": plain_s * 1e3},
         "speedup_vs_plain_loop": (vu / secs) / (plain_vu / plain_s),

@@ -114,15 +114,19 @@ snk_status snk_destroy(snk_ctx *ctx);
  * i_offset, i_scale or spacing after a volume is loaded re-runs the pre-pass at the next evolve. */
 snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
 
-/* Launch shape of the evolution kernel: wave64s per contour (workgroup size 64 * waves; 0 =
- * automatic, 1, 2, 4 or 8), sample points whose gathers one thread issues before consuming them
- * (0 = automatic, 1, 2 or 4), and the LDS capacity (floats) for staging each contour's footprint box
- * (0 = automatic, < 0 = off: every gather goes to memory). A contour whose box does not fit gathers
- * from memory. Results do not depend on any of these beyond FP32 summation order. */
-snk_status snk_set_launch(snk_ctx *ctx, int32_t waves_per_contour, int32_t gathers_in_flight, int32_t lds_box_floats);
+/* Launch shape of the evolution kernel: lanes per contour (0 = automatic; 16 or 32: several
+ * contours share one wave64; 64: one wave; 128 or 256: a workgroup of 2 or 4 waves), antithetic
+ * pair-points whose gathers one lane issues before consuming them (0 = automatic, 1 or 2), and the
+ * layout the kernel reads the smoothed volume from (0 = automatic: quad when it fits, 1 = plain FP32,
+ * 2 = quad: one 16-byte record per voxel with its +x, +y, +xy neighbours, 4x the FP32 volume; needs
+ * 16 * nx*ny*nz below 2 GiB and ny, nz <= 65535, else SNK_EINVAL at the next evolve; 3 = plain FP32
+ * with 64-bit addressing, the path of volumes beyond 2 GiB). Layouts change only how voxels are
+ * fetched: results are bit-identical across layouts, and depend on the other two knobs only through
+ * FP32 summation order. */
+snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs_in_flight, int32_t layout);
 
-/* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288 (the
- * table is staged in LDS). D must equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per
+/* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288. D must
+ * equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per
  * contour-iteration, carry the Monte-Carlo rays. */
 snk_status snk_set_directions(snk_ctx *ctx, const float *dirs, int32_t D);
 
@@ -196,8 +200,9 @@ snk_status snk_get_timing(snk_ctx *ctx, snk_timing *t);
  *
  * A job is one volume with its seeds, parameters, direction table and iteration target. Jobs are
  * queued by snk_engine_submit and admitted in FIFO order while their device footprint (raw copy,
- * FP32 volume, contour state, scratch) fits the HBM budget given at creation. Every job of one
- * engine has the same dim; engine volumes must be below 2 GiB as FP32. Contours evolve exactly as
+ * FP32 volume and its quad copy, contour state, scratch) fits the HBM budget given at creation. Every job of one
+ * engine has the same dim; every engine volume must fit the quad layout (16 * nx*ny*nz below 2 GiB,
+ * ny, nz <= 65535). Contours evolve exactly as
  * in snk_evolve (Sec. II-D: independent contours), so a job's results do not depend on which other
  * jobs share its launches.
  * ------------------------------------------------------------------------------------------ */
@@ -209,7 +214,7 @@ typedef struct snk_engine_stats {
     double last_ms;           /* snk_engine_run: the captured graph's duration (HIP events)      */
     double last_evolve_ms;    /* snk_engine_step: the evolve launches of the step (HIP events)   */
     int64_t last_evolved;     /* contour-iterations run by the last run / step                   */
-    int32_t waves, gathers_in_flight, persistent;   /* launch shape of the last evolve launch    */
+    int32_t lanes_per_contour, pairs_in_flight, persistent, layout;   /* last evolve launch's shape */
     int32_t graph_replays;
 } snk_engine_stats;
 
@@ -218,11 +223,11 @@ snk_status snk_engine_create(snk_engine **out, int device, void *hip_stream, uin
 snk_status snk_engine_destroy(snk_engine *e);
 const char *snk_engine_last_error(const snk_engine *e);
 
-/* Force the evolve launch shape (waves 1/2/4/8, gathers in flight 1/2/4, persistent 0/1, LDS box
- * floats as in snk_set_launch), or waves = 0 to pick it per launch class (dim, D, M, L) by timing
- * short trials of every shape. */
-snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent,
-                                 int32_t lds_box_floats);
+/* Force the evolve launch shape (lanes per contour 64/128/256, pair-points in flight 1/2,
+ * persistent 0/1, layout 0 = quad / 1 = plain / 2 = quad), or lanes = 0 to pick lanes, pair-points
+ * and persistence per launch class (dim, D, M, L) by timing short trials of every shape. */
+snk_status snk_engine_set_launch(snk_engine *e, int32_t lanes_per_contour, int32_t pairs_in_flight,
+                                 int32_t persistent, int32_t layout);
 
 /* Queue a job (arguments as in snk_set_params / snk_set_directions / snk_load_volume /
  * snk_load_seeds; host data is copied, a device volume with on_device = 1 is borrowed until the job

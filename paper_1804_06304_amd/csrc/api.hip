@@ -20,9 +20,10 @@ struct snk_ctx {
 
     snk_params P{};
     bool have_params = false;
-    int waves = 0;   // 0: automatic
-    int unroll = 0;  // 0: automatic
-    int box = 0;     // LDS footprint floats: 0 automatic, < 0 off
+    int lanes = 0;   // lanes per contour (0: automatic)
+    int unroll = 0;  // pair-points in flight (0: automatic)
+    int layout_req = 0;  // volume layout: 0 automatic, 1 plain, 2 quad
+    int layout = snk::kGlobalPlain;  // layout of the current pre-pass output
 
     std::vector<float> dirs_host;
     float *d_dirs = nullptr;
@@ -36,6 +37,8 @@ struct snk_ctx {
     size_t raw_owned_cap = 0;
     float *J = nullptr;
     size_t J_cap = 0;
+    float4 *Jq = nullptr;   // quad layout copy of J (when the layout is quad)
+    size_t Jq_cap = 0;
     bool have_volume = false;
     bool J_dirty = true;
 
@@ -154,6 +157,7 @@ namespace {
 snk::Geometry geometry(const snk_ctx *c) {
     snk::Geometry g;
     g.J = c->J;
+    g.Jq = c->layout == snk::kBufferQuad ? c->Jq : nullptr;
     g.nx = (int)c->nx;
     g.ny = (int)c->ny;
     g.nz = (int)c->nz;
@@ -224,20 +228,32 @@ snk_status run_prepass(snk_ctx *c) {
     }
     if (!snk::prepass_lds_limit_ok(a.rx, a.ry, a.rz))
         return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
+    const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
+    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the quad layout");
+    if (layout == snk::kBufferQuad) {
+        snk_status st = ensure(c, &c->Jq, &c->Jq_cap, (size_t)(c->nx * c->ny * c->nz));
+        if (st != SNK_OK) return st;
+    }
     HIPTRY(c, hipEventRecord(c->ev[0], c->stream));
     HIPTRY(c, snk::launch_prepass(a, c->stream));
+    if (layout == snk::kBufferQuad)
+        HIPTRY(c, snk::launch_pack_quad(c->J, c->Jq, (int)c->nx, (int)c->ny, (int)c->nz, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[1], c->stream));
+    c->layout = layout;
     c->ev_pre = true;
     c->J_dirty = false;
     return SNK_OK;
 }
 
-int pick_waves(const snk_ctx *c) {
-    if (c->waves > 0) return c->waves;
-    const int npts = c->P.n_rays * c->P.n_radial;
-    int w = 4;
-    while (w > 1 && npts < 64 * w * 2) w >>= 1;   // at least two points per thread
-    return w;
+// Lanes per contour: at least two pair-points per lane, and narrower groups while the contours
+// alone fill the GPU (more than 8192 waves).
+int pick_lanes(const snk_ctx *c) {
+    if (c->lanes > 0) return c->lanes;
+    const int64_t pairs = (int64_t)(c->P.n_rays / 2) * c->P.n_radial;
+    int g = 256;
+    while (g > 16 && 2 * g > pairs) g >>= 1;
+    while (g > 16 && c->n * g > (int64_t)8192 * 64) g >>= 1;
+    return g;
 }
 
 snk::JobParams job_params(const snk_ctx *c) {
@@ -258,8 +274,21 @@ snk::JobParams job_params(const snk_ctx *c) {
     p.conv_window = c->P.conv_window;
     p.in_slope = (float)(2.0 / (rho_of(c->P.dim) * c->P.dR));
     p.out_slope = (float)(1.0 / c->P.dR);
-    p.buffer_ok = (c->nx * c->ny * c->nz * 4) < ((int64_t)1 << 31) ? 1 : 0;
     return p;
+}
+
+// Re-packs the current J when the requested layout changed after the pre-pass.
+snk_status ensure_layout(snk_ctx *c) {
+    const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
+    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the quad layout");
+    if (layout == c->layout) return SNK_OK;
+    if (layout == snk::kBufferQuad) {
+        snk_status st = ensure(c, &c->Jq, &c->Jq_cap, (size_t)(c->nx * c->ny * c->nz));
+        if (st != SNK_OK) return st;
+        HIPTRY(c, snk::launch_pack_quad(c->J, c->Jq, (int)c->nx, (int)c->ny, (int)c->nz, c->stream));
+    }
+    c->layout = layout;
+    return SNK_OK;
 }
 
 snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
@@ -268,6 +297,8 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
         snk_status st = run_prepass(c);
         if (st != SNK_OK) return st;
     }
+    snk_status lst = ensure_layout(c);
+    if (lst != SNK_OK) return lst;
     snk::EvolveArgs a{};
     a.p = job_params(c);
     a.st = c->d_st;
@@ -275,11 +306,14 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
     a.n_iter = n_iter;
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
-    const int waves = pick_waves(c);
-    a.box_cap = snk::evolve_box_cap(c->box, c->P.dim, waves, a.p.D, a.p.M, c->P);
+    const int lanes = pick_lanes(c);
+    if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M) > 65536)
+        return fail(c, SNK_EINVAL, "n_rays too large for the evolve kernel's LDS (64 KiB per workgroup)");
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
-    HIPTRY(c, snk::launch_evolve(a, c->P.dim, waves, c->unroll, trace, c->stream));
+    // two pair-points in flight pay off once a contour spans whole waves
+    const int unroll = c->unroll > 0 ? c->unroll : (lanes >= 64 ? 2 : 1);
+    HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, c->layout, trace, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
     c->ev_evo = true;
     c->evolve_launches += 1;
@@ -340,7 +374,7 @@ snk_status snk_destroy(snk_ctx *c) {
     if (!c) return SNK_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
+    void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->Jq, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
                     c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -362,16 +396,18 @@ snk_status snk_set_params(snk_ctx *c, const snk_params *p) {
     return SNK_OK;
 }
 
-snk_status snk_set_launch(snk_ctx *c, int32_t waves_per_contour, int32_t gathers_in_flight, int32_t lds_box_floats) {
+snk_status snk_set_launch(snk_ctx *c, int32_t lanes_per_contour, int32_t pairs_in_flight, int32_t layout) {
     if (!c) return fail(c, SNK_EINVAL, "NULL context");
-    if (waves_per_contour != 0 && waves_per_contour != 1 && waves_per_contour != 2 && waves_per_contour != 4 &&
-        waves_per_contour != 8)
-        return fail(c, SNK_EINVAL, "waves_per_contour must be 0 (auto), 1, 2, 4 or 8");
-    if (gathers_in_flight != 0 && gathers_in_flight != 1 && gathers_in_flight != 2 && gathers_in_flight != 4)
-        return fail(c, SNK_EINVAL, "gathers_in_flight must be 0 (auto), 1, 2 or 4");
-    c->waves = waves_per_contour;
-    c->unroll = gathers_in_flight;
-    c->box = lds_box_floats;
+    if (lanes_per_contour != 0 && lanes_per_contour != 16 && lanes_per_contour != 32 && lanes_per_contour != 64 &&
+        lanes_per_contour != 128 && lanes_per_contour != 256)
+        return fail(c, SNK_EINVAL, "lanes_per_contour must be 0 (auto), 16, 32, 64, 128 or 256");
+    if (pairs_in_flight < 0 || pairs_in_flight > 2)
+        return fail(c, SNK_EINVAL, "pairs_in_flight must be 0 (auto), 1 or 2");
+    if (layout < 0 || layout > 3)
+        return fail(c, SNK_EINVAL, "layout must be 0 (auto), 1 (plain), 2 (quad) or 3 (plain, 64-bit addressing)");
+    c->lanes = lanes_per_contour;
+    c->unroll = pairs_in_flight;
+    c->layout_req = layout;
     return SNK_OK;
 }
 

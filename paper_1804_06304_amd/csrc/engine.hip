@@ -9,8 +9,9 @@
 //    and finalised in one captured hipGraph: state reset -> pre-pass per volume -> one evolve launch
 //    per launch class (dim, D, M, L) -> exact energy over all items -> selection, one workgroup per
 //    job. The graph is replayed while the job set is unchanged. The launch shape of each class
-//    (waves per contour, gathers in flight, persistent work queue or one workgroup per item) is
-//    picked once by timing short trials of every candidate.
+//    (lanes per contour, pair-points in flight, persistent work queue or one workgroup per item) is
+//    picked once by timing short trials of every candidate. Every job keeps its volume in the quad
+//    layout next to the FP32 one; launches read the quad copy unless the plain layout is forced.
 //  - snk_engine_step (served): continuous batching. Newly admitted jobs get their pre-pass and join
 //    the running set; every running contour advances by at most `chunk` iterations in one launch
 //    per class; jobs whose contours have all stopped are finalised, copied to the host and their
@@ -61,6 +62,7 @@ struct EJob {
     void *block = nullptr;
     const void *d_raw = nullptr;
     float *d_J = nullptr;
+    float4 *d_Jq = nullptr;
     float *d_dirs = nullptr;
     DevContour *d_st = nullptr, *d_init = nullptr;
     double *d_evox = nullptr;
@@ -79,10 +81,8 @@ struct ClassKey {
 };
 
 struct Launch {
-    int waves = 4, unroll = 2, persistent = 1;
-    int box = 0;    // LDS footprint request (0 automatic, < 0 off)
+    int lanes = 256, unroll = 1, persistent = 1;
     int grid = 1;   // workgroups of a persistent launch
-    int box_cap = 0;
 };
 
 constexpr int kMaxClasses = 64;            // launch classes per run (one queue head each)
@@ -132,6 +132,7 @@ struct snk_engine {
     // launch shapes
     Launch forced;
     bool force = false;
+    int layout = snk::kBufferQuad;             // volume layout of every evolve launch
     std::map<ClassKey, Launch> tuned;
 
     // captured batched run
@@ -211,6 +212,7 @@ size_t footprint(const EJob &j, int64_t grid_cells) {
     size_t b = 0;
     if (!j.borrowed) b += align256(j.raw_bytes);
     b += align256(vox * 4);                                    // J
+    b += align256(vox * 16);                                   // quad copy of J
     b += align256(j.dirs.size() * 4);
     b += 2 * align256((size_t)std::max(j.n, 1) * sizeof(DevContour));
     b += align256((size_t)std::max(j.n, 1) * 8);               // e_vox
@@ -221,6 +223,7 @@ size_t footprint(const EJob &j, int64_t grid_cells) {
 snk::JobParams params_of(const EJob &j) {
     snk::JobParams p{};
     p.g.J = j.d_J;
+    p.g.Jq = j.d_Jq;
     p.g.nx = (int)j.nx;
     p.g.ny = (int)j.ny;
     p.g.nz = (int)j.nz;
@@ -243,7 +246,6 @@ snk::JobParams params_of(const EJob &j) {
     p.conv_window = j.P.conv_window;
     p.in_slope = (float)(2.0 / (rho_of(j.P.dim) * j.P.dR));
     p.out_slope = (float)(1.0 / j.P.dR);
-    p.buffer_ok = 1;
     return p;
 }
 
@@ -257,6 +259,7 @@ snk_status admit(snk_engine *e, EJob &j) {
     size_t off = 0;
     const size_t o_raw = off; if (!j.borrowed) off += align256(j.raw_bytes);
     const size_t o_J = off; off += align256(vox * 4);
+    const size_t o_Jq = off; off += align256(vox * 16);
     const size_t o_dirs = off; off += align256(j.dirs.size() * 4);
     const size_t o_st = off; off += align256(n * sizeof(DevContour));
     const size_t o_init = off; off += align256(n * sizeof(DevContour));
@@ -266,6 +269,7 @@ snk_status admit(snk_engine *e, EJob &j) {
     char *b = static_cast<char *>(j.block);
     j.d_raw = j.borrowed ? j.borrowed : (const void *)(b + o_raw);
     j.d_J = reinterpret_cast<float *>(b + o_J);
+    j.d_Jq = reinterpret_cast<float4 *>(b + o_Jq);
     j.d_dirs = reinterpret_cast<float *>(b + o_dirs);
     j.d_st = reinterpret_cast<DevContour *>(b + o_st);
     j.d_init = reinterpret_cast<DevContour *>(b + o_init);
@@ -359,6 +363,7 @@ snk_status prepass_job(snk_engine *e, const EJob &j) {
         for (int k = 0; k <= 2 * r; ++k) tap[ax][k] = (float)(g[k] / sum);
     }
     EHIP(e, snk::launch_prepass(a, e->stream));
+    EHIP(e, snk::launch_pack_quad(j.d_J, j.d_Jq, (int)j.nx, (int)j.ny, (int)j.nz, e->stream));
     return SNK_OK;
 }
 
@@ -403,7 +408,7 @@ snk_status upload_plan(snk_engine *e, const ItemPlan &pl) {
     return SNK_OK;
 }
 
-snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int cls, int chunk, int box_cap) {
+snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int cls, int chunk) {
     snk::BatchArgs a{};
     a.jobs = e->d_jobs;
     a.items = e->d_items + b;
@@ -413,18 +418,12 @@ snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int 
     a.counter = e->d_counters;
     a.max_D = k.D;
     a.max_M = k.M;
-    a.box_cap = box_cap;
     return a;
 }
 
 int grid_for(snk_engine *e, const ClassKey &k, const Launch &L, int n_items) {
-    const int per_cu = snk::evolve_batch_max_blocks(k.dim, L.waves, L.unroll, k.D, k.M, L.box_cap);
+    const int per_cu = snk::evolve_batch_max_blocks(k.dim, L.lanes, L.unroll, e->layout, k.M);
     return std::max(1, std::min(n_items, per_cu * e->cus));
-}
-
-// Box capacity of a launch shape for a class (uses the parameters of one job of the class).
-void resolve_box(Launch &L, const ClassKey &k, const snk_params &P) {
-    L.box_cap = snk::evolve_box_cap(L.box, k.dim, L.waves, k.D, k.M, P);
 }
 
 // Evolve launches of every class of the plan (queue heads must be zero).
@@ -433,8 +432,11 @@ snk_status launch_classes(snk_engine *e, const ItemPlan &pl, int chunk, const st
         const ClassKey &k = pl.classes[c].first;
         const int b = pl.classes[c].second.first, end = pl.classes[c].second.second;
         const Launch &L = shapes[c];
-        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk, L.box_cap);
-        EHIP(e, snk::launch_evolve_batch(a, k.dim, L.waves, L.unroll, L.persistent != 0, L.grid, e->stream));
+        if (snk::evolve_lds_bytes(k.dim, L.lanes, k.M) > 65536)
+            return efail(e, SNK_EINVAL, "n_rays too large for this launch shape's LDS");
+        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk);
+        EHIP(e, snk::launch_evolve_batch(a, k.dim, L.lanes, L.unroll, e->layout, L.persistent != 0, L.grid,
+                                         e->stream));
         e->last_launch = L;
     }
     return SNK_OK;
@@ -447,7 +449,6 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
         const ClassKey &k = pl.classes[c].first;
         const int b = pl.classes[c].second.first, end = pl.classes[c].second.second;
         const int n_items = end - b;
-        const snk_params &P = pl.params[c];
         Launch L{};
         auto it = e->tuned.find(k);
         if (e->force) {
@@ -457,28 +458,26 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
         } else if (allow_trials) {
             const int trial_iters = 6;
             float best_ms = 1e30f;
-            for (int w : {1, 2, 4, 8}) {
-                for (int u : {1, 2, 4}) {
+            for (int g : {64, 128, 256}) {
+                if (snk::evolve_lds_bytes(k.dim, g, k.M) > 65536) continue;
+                for (int u : {1, 2}) {
                     for (int pers : {0, 1}) {
-                        for (int bx : {0, -1}) {
-                            Launch T{w, u, pers, bx, 1, 0};
-                            resolve_box(T, k, P);
-                            T.grid = grid_for(e, k, T, n_items);
-                            EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs,
-                                                            e->stream));
-                            EHIP(e, snk::launch_zero(reinterpret_cast<unsigned long long *>(e->d_queues), kQueueWords,
-                                                     e->stream));
-                            snk::BatchArgs a = batch_args(e, k, b, end, (int)c, trial_iters, T.box_cap);
-                            EHIP(e, hipEventRecord(e->ev0, e->stream));
-                            EHIP(e, snk::launch_evolve_batch(a, k.dim, w, u, pers != 0, T.grid, e->stream));
-                            EHIP(e, hipEventRecord(e->ev1, e->stream));
-                            EHIP(e, hipEventSynchronize(e->ev1));
-                            float ms = 0.0f;
-                            EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
-                            if (ms < best_ms) {
-                                best_ms = ms;
-                                L = T;
-                            }
+                        Launch T{g, u, pers, 1};
+                        T.grid = grid_for(e, k, T, n_items);
+                        EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs,
+                                                        e->stream));
+                        EHIP(e, snk::launch_zero(reinterpret_cast<unsigned long long *>(e->d_queues), kQueueWords,
+                                                 e->stream));
+                        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, trial_iters);
+                        EHIP(e, hipEventRecord(e->ev0, e->stream));
+                        EHIP(e, snk::launch_evolve_batch(a, k.dim, g, u, e->layout, pers != 0, T.grid, e->stream));
+                        EHIP(e, hipEventRecord(e->ev1, e->stream));
+                        EHIP(e, hipEventSynchronize(e->ev1));
+                        float ms = 0.0f;
+                        EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            L = T;
                         }
                     }
                 }
@@ -487,7 +486,6 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
             EHIP(e, hipStreamSynchronize(e->stream));
             e->tuned[k] = L;
         }
-        resolve_box(L, k, P);
         L.grid = grid_for(e, k, L, n_items);
         out.push_back(L);
     }
@@ -583,19 +581,25 @@ snk_status snk_engine_destroy(snk_engine *e) {
 
 const char *snk_engine_last_error(const snk_engine *e) { return e ? e->err.c_str() : ""; }
 
-snk_status snk_engine_set_launch(snk_engine *e, int32_t waves, int32_t gathers_in_flight, int32_t persistent,
-                                 int32_t lds_box_floats) {
+snk_status snk_engine_set_launch(snk_engine *e, int32_t lanes_per_contour, int32_t pairs_in_flight,
+                                 int32_t persistent, int32_t layout) {
     if (!e) return SNK_EINVAL;
-    if (waves == 0) {
+    if (layout < 0 || layout > 2) return efail(e, SNK_EINVAL, "layout in {0,1,2}");
+    const int lay = layout == 1 ? snk::kBufferPlain : snk::kBufferQuad;
+    if (lay != e->layout) {
+        e->layout = lay;
+        e->tuned.clear();
+        drop_graph(e);
+    }
+    if (lanes_per_contour == 0) {
         e->force = false;
         return SNK_OK;
     }
-    if ((waves != 1 && waves != 2 && waves != 4 && waves != 8) ||
-        (gathers_in_flight != 1 && gathers_in_flight != 2 && gathers_in_flight != 4) ||
-        (persistent != 0 && persistent != 1))
-        return efail(e, SNK_EINVAL, "waves in {0,1,2,4,8}, gathers_in_flight in {1,2,4}, persistent in {0,1}");
+    if ((lanes_per_contour != 64 && lanes_per_contour != 128 && lanes_per_contour != 256) ||
+        (pairs_in_flight != 1 && pairs_in_flight != 2) || (persistent != 0 && persistent != 1))
+        return efail(e, SNK_EINVAL, "lanes in {0,64,128,256}, pairs_in_flight in {1,2}, persistent in {0,1}");
     e->force = true;
-    e->forced = Launch{waves, gathers_in_flight, persistent, lds_box_floats, 1, 0};
+    e->forced = Launch{lanes_per_contour, pairs_in_flight, persistent, 1};
     drop_graph(e);
     return SNK_OK;
 }
@@ -612,13 +616,14 @@ snk_status snk_engine_submit(snk_engine *e, const snk_params *p, const float *di
     for (int i = 0; i < 3; ++i)
         if (!(P.spacing[i] > 0.0)) return efail(e, SNK_EINVAL, "spacing must be > 0");
     if (!(P.dR > 0.0) || !(P.r_max >= r_low(P)) || P.n_rays <= 0 || (P.n_rays & 1) || P.n_radial <= 0 ||
-        P.n_rays / 2 > 1024 || !(P.eps0 >= 0.0) || !(P.sigma_pre >= 0.0) || P.conv_window < 0 || P.conv_window > 255)
+        P.n_rays / 2 > 768 || !(P.eps0 >= 0.0) || !(P.sigma_pre >= 0.0) || P.conv_window < 0 || P.conv_window > 255)
         return efail(e, SNK_EINVAL, "invalid parameters");
     if (D <= 0 || D != P.n_dirs || (int64_t)D * P.dim > 12288) return efail(e, SNK_EINVAL, "direction table size");
     if (e->dim != 0 && P.dim != e->dim) return efail(e, SNK_EINVAL, "all jobs of an engine must have the same dim");
     if (nx < 2 || ny < 2 || nz < 1 || (P.dim == 3 && nz < 2) || (P.dim == 2 && nz != 1))
         return efail(e, SNK_EINVAL, "volume shape");
-    if (nx * ny * nz * 4 >= ((int64_t)1 << 31)) return efail(e, SNK_EINVAL, "engine volumes must be below 2 GiB as FP32");
+    if (snk::volume_layout(P.dim, nx, ny, nz, 2) != snk::kBufferQuad)
+        return efail(e, SNK_EINVAL, "engine volumes must fit the quad layout (16 B per voxel below 2 GiB)");
     if (n >= ((int64_t)1 << 30)) return efail(e, SNK_EINVAL, "too many seeds");
     for (int ax = 0; ax < 3; ++ax) {
         const double s = P.sigma_pre / P.spacing[ax];
@@ -888,9 +893,10 @@ snk_status snk_engine_get_stats(snk_engine *e, snk_engine_stats *s) {
     s->last_ms = e->last_ms;
     s->last_evolve_ms = e->last_evolve_ms;
     s->last_evolved = e->last_evolved;
-    s->waves = e->last_launch.waves;
-    s->gathers_in_flight = e->last_launch.unroll;
+    s->lanes_per_contour = e->last_launch.lanes;
+    s->pairs_in_flight = e->last_launch.unroll;
     s->persistent = e->last_launch.persistent;
+    s->layout = e->layout == snk::kBufferPlain ? 1 : 2;
     s->graph_replays = e->graph_replays;
     return SNK_OK;
 }

@@ -124,7 +124,28 @@ hipError_t launch_t(const PrepassArgs &a, hipStream_t s) {
     }
 }
 
+// Quad records of one row segment: J(x,y), J(x+1,y), J(x,y+1), J(x+1,y+1) of plane z, the
+// neighbours clamped to the last column / row (only cells with x <= nx-2, y <= ny-2 are gathered).
+__global__ __launch_bounds__(256) void pack_quad_kernel(const float *__restrict__ J, float4 *__restrict__ Jq,
+                                                       int nx, int ny, int nz) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    const int z = blockIdx.z;
+    if (x >= nx) return;
+    const long row = ((long)z * ny + y) * nx;
+    const long row1 = ((long)z * ny + min(y + 1, ny - 1)) * nx;
+    const int x1 = min(x + 1, nx - 1);
+    Jq[row + x] = make_float4(J[row + x], J[row + x1], J[row1 + x], J[row1 + x1]);
+}
+
 }  // namespace
+
+hipError_t launch_pack_quad(const float *J, float4 *Jq, int nx, int ny, int nz, hipStream_t s) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
+    if (ny > 65535 || nz > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pack_quad_kernel, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, s, J, Jq, nx, ny, nz);
+    return hipGetLastError();
+}
 
 bool prepass_lds_limit_ok(int rx, int ry, int rz) { return prepass_rows(rx, ry, rz) != 0; }
 

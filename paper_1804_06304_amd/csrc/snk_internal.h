@@ -28,6 +28,7 @@ static_assert(sizeof(DevContour) == 48, "DevContour layout");
 
 struct Geometry {
     const float *J;    // smoothed volume [z][y][x]
+    const float4 *Jq;  // the same in the quad layout (J(x,y), J(x+1,y), J(x,y+1), J(x+1,y+1)), or null
     int nx, ny, nz;
     float h[3];
     float inv_h[3];
@@ -43,8 +44,27 @@ struct JobParams {
     float dR, eps0, r_lo, r_hi, conv_tol;
     int conv_window;
     float in_slope, out_slope;   // 2 / (rho dR) and 1 / dR
-    int buffer_ok;               // volume fits a 32-bit buffer descriptor
 };
+
+// How the evolve kernels read the smoothed volume.
+enum VolumeLayout {
+    kGlobalPlain = 0,  // FP32 [z][y][x], 64-bit addressing (any size)
+    kBufferPlain = 1,  // FP32 [z][y][x] through a buffer descriptor (< 2 GiB, 24-bit strides)
+    kBufferQuad = 2,   // quad records through a buffer descriptor (< 2 GiB, 24-bit strides)
+};
+
+// Layout for a volume: `requested` 0 = automatic (quad when it fits), 1 = plain, 2 = quad, 3 = plain
+// with 64-bit addressing. Returns the layout, or -1 if the request cannot be met.
+inline int volume_layout(int dim, int64_t nx, int64_t ny, int64_t nz, int requested) {
+    const int64_t vox = nx * ny * nz;
+    const bool strides = nx < (1 << 23) && (dim == 2 || nx * ny < (1 << 23));
+    const bool plain_ok = strides && vox * 4 < ((int64_t)1 << 31);
+    const bool quad_ok = strides && vox * 16 < ((int64_t)1 << 31) && ny <= 65535 && nz <= 65535;
+    if (requested == 3) return kGlobalPlain;
+    if (requested == 2) return quad_ok ? kBufferQuad : -1;
+    if (requested == 1) return plain_ok ? kBufferPlain : kGlobalPlain;
+    return quad_ok ? kBufferQuad : (plain_ok ? kBufferPlain : kGlobalPlain);
+}
 
 struct EvolveArgs {
     JobParams p;
@@ -53,7 +73,6 @@ struct EvolveArgs {
     int n_iter;
     float *trace;                // n x SNK_TRACE_W or null
     unsigned long long *counter; // contour-iterations evolved
-    int box_cap;                 // LDS floats for the staged footprint (0: gather from memory)
 };
 
 // One job of a batch, resident in device memory.
@@ -78,7 +97,6 @@ struct BatchArgs {
     int chunk;                   // iterations per contour in this launch
     unsigned long long *counter;
     int max_D, max_M;
-    int box_cap;                 // LDS floats for the staged footprint (0: gather from memory)
 };
 
 struct PrepassArgs {
@@ -97,14 +115,16 @@ constexpr size_t kPrepassMaxLds = 65536;
 
 hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s);
 bool prepass_lds_limit_ok(int rx, int ry, int rz);
-hipError_t launch_evolve(const EvolveArgs &a, int dim, int waves, int unroll, bool trace, hipStream_t s);
-hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int waves, int unroll, bool persistent, int grid,
-                               hipStream_t s);
-int evolve_batch_max_blocks(int dim, int waves, int unroll, int max_D, int max_M, int box_cap);
-size_t evolve_lds_bytes(int dim, int waves, int D, int M, int box_cap);
-// LDS floats for the staged footprint: `requested` > 0 as given, 0 = automatic (the box of a contour
-// of radius about 1.5 r_init, bounded by what fits the workgroup's LDS), < 0 = off.
-int evolve_box_cap(int requested, int dim, int waves, int D, int M, const snk_params &P);
+// Pack J into the quad layout (one record per voxel, neighbours clamped at the upper edges).
+hipError_t launch_pack_quad(const float *J, float4 *Jq, int nx, int ny, int nz, hipStream_t s);
+// lanes: contour group size 16, 32, 64, 128 or 256; unroll: pair-points in flight (1 or 2);
+// layout: a VolumeLayout (batched launches: buffer layouts only).
+hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, int layout, bool trace,
+                         hipStream_t s);
+hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unroll, int layout, bool persistent,
+                               int grid, hipStream_t s);
+int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M);
+size_t evolve_lds_bytes(int dim, int lanes, int M);
 
 // Engine helpers (engine_kernels.hip).
 hipError_t launch_reset_items(const JobDev *jobs, const int2 *items, int n_items, const DevContour *const *init,

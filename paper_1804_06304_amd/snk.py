@@ -57,8 +57,8 @@ class snk_engine_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("pending", C.c_int64), ("running", C.c_int64), ("bytes_in_use", C.c_uint64),
                 ("budget", C.c_uint64), ("last_ms", C.c_double), ("last_evolve_ms", C.c_double),
-                ("last_evolved", C.c_int64), ("waves", C.c_int32), ("gathers_in_flight", C.c_int32),
-                ("persistent", C.c_int32), ("graph_replays", C.c_int32)]
+                ("last_evolved", C.c_int64), ("lanes_per_contour", C.c_int32), ("pairs_in_flight", C.c_int32),
+                ("persistent", C.c_int32), ("layout", C.c_int32), ("graph_replays", C.c_int32)]
 
 
 _lib = None
@@ -175,8 +175,8 @@ def snk_set_params(h, params) -> None:
     _check(h, load().snk_set_params(h, C.byref(s)))
 
 
-def snk_set_launch(h, waves_per_contour: int = 0, gathers_in_flight: int = 0, lds_box_floats: int = 0) -> None:
-    _check(h, load().snk_set_launch(h, int(waves_per_contour), int(gathers_in_flight), int(lds_box_floats)))
+def snk_set_launch(h, lanes_per_contour: int = 0, pairs_in_flight: int = 0, layout: int = 0) -> None:
+    _check(h, load().snk_set_launch(h, int(lanes_per_contour), int(pairs_in_flight), int(layout)))
 
 
 def snk_set_directions(h, dirs) -> None:
@@ -316,10 +316,10 @@ def snk_engine_last_error(e) -> str:
     return load().snk_engine_last_error(e).decode()
 
 
-def snk_engine_set_launch(e, waves: int = 0, gathers_in_flight: int = 0, persistent: int = 1,
-                          lds_box_floats: int = 0) -> None:
-    _echeck(e, load().snk_engine_set_launch(e, int(waves), int(gathers_in_flight), int(persistent),
-                                            int(lds_box_floats)))
+def snk_engine_set_launch(e, lanes_per_contour: int = 0, pairs_in_flight: int = 1, persistent: int = 1,
+                          layout: int = 0) -> None:
+    _echeck(e, load().snk_engine_set_launch(e, int(lanes_per_contour), int(pairs_in_flight), int(persistent),
+                                            int(layout)))
 
 
 def snk_engine_submit(e, params, dirs, vol, centers, r0=None, ids=None, n_iter: int = 100,

@@ -38,11 +38,11 @@ def jobs():
     return synth.subvolume_batch(n_vol=6, edge_lo=32, edge_hi=72, n_iter=40)
 
 
-def plain(snk, wl, waves, unroll):
+def plain(snk, wl, lanes, unroll):
     import torch
     ctx = snk.Context(0, torch.cuda.current_stream())
     ctx.set_params(wl.params)
-    ctx.set_launch(waves, unroll, 0)
+    ctx.set_launch(lanes, unroll, 0)
     ctx.set_directions(wl.dirs)
     ctx.load_volume(wl.raw)
     ctx.load_seeds(wl.seeds, ids=wl.ids)
@@ -56,14 +56,14 @@ def plain(snk, wl, waves, unroll):
 def test_batched_equals_plain_and_oracle(snk, jobs):
     say("engine batched: " + ", ".join(w.name for w in jobs))
     eng = snk.Engine(0, None, 8 << 30)
-    eng.set_launch(4, 2, 1)
+    eng.set_launch(256, 2, 1)
     ids = [eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter) for w in jobs]
     eng.run()
     stats = eng.get_stats()
     assert stats["completed"] == len(jobs) and stats["graph_replays"] == 1
     for w, j in zip(jobs, ids):
         got = eng.read(j)
-        ref = plain(snk, w, 4, 2)
+        ref = plain(snk, w, 256, 2)
         for k in KEYS:
             assert np.array_equal(got[k], ref[k]), (w.name, k)
         orc = oracle.run(w.raw, w.params, w.dirs, w.seeds, w.n_iter, ids=w.ids)
@@ -88,11 +88,11 @@ def test_autotuned_batched_within_tolerance(snk, jobs):
     ids = [eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter) for w in jobs]
     eng.run()
     s = eng.get_stats()
-    say(f"  tuned shape of the last class: waves {s['waves']}, gathers {s['gathers_in_flight']}, "
-        f"persistent {s['persistent']}")
+    say(f"  tuned shape of the last class: lanes {s['lanes_per_contour']}, pair-points in flight "
+        f"{s['pairs_in_flight']}, persistent {s['persistent']}, layout {s['layout']}")
     for w, j in zip(jobs, ids):
         got = eng.read(j)
-        ref = plain(snk, w, 4, 2)
+        ref = plain(snk, w, 256, 2)
         assert np.array_equal(got["iters"], ref["iters"])
         assert np.max(np.abs(got["radii"] - ref["radii"]), initial=0.0) <= 0.05
     eng.close()
@@ -103,7 +103,7 @@ def test_served_alone_equals_mix(snk, jobs):
     runs (and it joins a running mix)."""
     say("engine served: alone vs mix")
     eng = snk.Engine(0, None, 8 << 30)
-    eng.set_launch(4, 2, 1)
+    eng.set_launch(128, 1, 1)
     target = jobs[2]
     j0 = eng.submit(target.params, target.dirs, target.raw, target.seeds, ids=target.ids, n_iter=target.n_iter)
     done = []
@@ -128,7 +128,7 @@ def test_served_alone_equals_mix(snk, jobs):
     mixed = eng.read(j1)
     for k in KEYS:
         assert np.array_equal(alone[k], mixed[k]), k
-    ref = plain(snk, target, 4, 2)
+    ref = plain(snk, target, 128, 1)
     for k in KEYS:
         assert np.array_equal(alone[k], ref[k]), k
     s = eng.get_stats()

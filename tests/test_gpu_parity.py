@@ -41,11 +41,11 @@ def stream():
     return torch.cuda.current_stream()
 
 
-def make_ctx(snk, stream, wl, waves=0, on_device=True, unroll=0, box=0):
+def make_ctx(snk, stream, wl, lanes=0, on_device=True, unroll=0, layout=0):
     import torch
     ctx = snk.Context(0, stream)
     ctx.set_params(wl.params)
-    ctx.set_launch(waves, unroll, box)
+    ctx.set_launch(lanes, unroll, layout)
     ctx.set_directions(wl.dirs)
     if on_device:
         raw = torch.from_numpy(np.ascontiguousarray(wl.raw)).to("cuda:0")
@@ -79,7 +79,7 @@ def tol_check(name, got, ref, ref_abs, slack, rel=1e-5):
     return float(np.max(err / tol)) if len(ref) else 0.0
 
 
-def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0, unroll=0, box=0):
+def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, unroll=0, layout=0):
     p = wl.params
     rng = np.random.default_rng(seed)
     seeds = np.concatenate([wl.seeds, extra_seeds(wl, n_extra, rng)]) if n_extra else wl.seeds
@@ -88,7 +88,7 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, waves=0, 
     r0[: len(wl.seeds)] = p.r_init
     J = oracle.prepass(wl.raw, p)
     st = oracle.init_state(p, seeds, r0=r0, ids=ids, shape_zyx=wl.raw.shape)
-    ctx = make_ctx(snk, stream, wl, waves=waves, unroll=unroll, box=box)
+    ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout)
     ctx.load_seeds(seeds, r0=r0.astype(np.float32), ids=ids)
     worst = {}
     kinked = 0
@@ -177,22 +177,24 @@ def test_one_step_parity_2d(snk, stream):
     one_step_parity(snk, stream, wl, [0, 2, 25], n_extra=40)
 
 
-@pytest.mark.parametrize("waves,unroll,box", [(1, 1, 0), (1, 4, 0), (2, 2, -1), (8, 1, 0), (8, 4, 512), (4, 2, 3000)])
-def test_one_step_parity_launch_shapes(snk, stream, waves, unroll, box):
-    """Launch shapes, including memory gathers only (box -1) and LDS boxes too small for some
-    contours (512 / 3000 floats), so that staged and unstaged contours share a launch."""
-    say(f"one-step parity tiny, {waves} waves per contour, {unroll} gathers in flight, box {box}")
-    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, waves=waves, unroll=unroll, box=box)
+@pytest.mark.parametrize("lanes,unroll,layout", [(16, 1, 0), (16, 2, 1), (32, 1, 2), (32, 2, 3), (64, 1, 1),
+                                                 (64, 2, 2), (128, 1, 3), (128, 2, 1), (256, 1, 2), (256, 2, 0)])
+def test_one_step_parity_launch_shapes(snk, stream, lanes, unroll, layout):
+    """Every contour group size (several contours per wave, one wave, 2 and 4 waves per contour),
+    one or two pair-points in flight, and every volume layout."""
+    say(f"one-step parity tiny, {lanes} lanes per contour, {unroll} pair-points in flight, layout {layout}")
+    one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, lanes=lanes, unroll=unroll,
+                    layout=layout)
 
 
-def test_staged_equals_unstaged_bitwise(snk, stream):
-    """The LDS footprint holds exact copies of the volume: a free run with and without staging is
-    bit-identical (same launch shape otherwise)."""
+def test_layouts_bitwise(snk, stream):
+    """The quad records hold exact copies of the volume and the arithmetic is the same, so a free
+    run reads identical results from every layout (same launch shape otherwise)."""
     wl = synth.tiny_config()
-    say("free run tiny: LDS-staged vs memory gathers")
+    say("free run tiny: plain vs quad vs 64-bit-addressed plain layout")
     outs = []
-    for box in (0, -1, 700):
-        ctx = make_ctx(snk, stream, wl, waves=4, unroll=2, box=box)
+    for layout in (1, 2, 3):
+        ctx = make_ctx(snk, stream, wl, lanes=128, unroll=1, layout=layout)
         ctx.load_seeds(wl.seeds, ids=wl.ids)
         ctx.evolve(wl.n_iter)
         ctx.finalize()
@@ -204,11 +206,11 @@ def test_staged_equals_unstaged_bitwise(snk, stream):
 
 
 def test_one_step_parity_many_rays(snk, stream):
-    """More rays than threads (M = 128 on one wave): each thread walks several rays."""
+    """More antithetic pairs than lanes (M = 128 on one wave): a block of draws takes two passes."""
     wl = synth.tiny_config()
     wl.params = wl.params.replace(n_rays=128, n_radial=8)
     say("one-step parity tiny, M = 128, L = 8, 1 wave")
-    one_step_parity(snk, stream, wl, [0, 5], n_extra=16, waves=1, unroll=4)
+    one_step_parity(snk, stream, wl, [0, 5], n_extra=16, lanes=64, unroll=2)
 
 
 def test_one_step_parity_unrotated_and_odd_sizes(snk, stream):
@@ -218,9 +220,9 @@ def test_one_step_parity_unrotated_and_odd_sizes(snk, stream):
     one_step_parity(snk, stream, wl, [0, 4], n_extra=16)
 
 
-def free_run(snk, stream, wl, seeds=None, ids=None, waves=0, chunks=None):
+def free_run(snk, stream, wl, seeds=None, ids=None, lanes=0, chunks=None):
     seeds = wl.seeds if seeds is None else seeds
-    ctx = make_ctx(snk, stream, wl, waves=waves)
+    ctx = make_ctx(snk, stream, wl, lanes=lanes)
     ctx.load_seeds(seeds, ids=ids)
     for k in (chunks or [wl.n_iter]):
         ctx.evolve(k)
