@@ -78,9 +78,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="only time the evolve kernel for every (lanes, pair-points in flight, layout) shape")
-    ap.add_argument("--workload", default="slab", choices=["slab", "batched", "served"],
-                    help="slab: the plain path on the slab volume (default); batched: 256 uneven subvolumes "
-                         "through the engine vs the plain per-volume loop; served: Poisson tile requests")
+    ap.add_argument("--workload", default="slab", choices=["slab", "plane", "batched", "served"],
+                    help="slab: the plain path on the slab volume (default); plane: the plain path on the "
+                         "8192^2 2D image; batched: 256 uneven subvolumes through the engine vs the plain "
+                         "per-volume loop; served: Poisson tile requests")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="served: arrival window (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: mean arrivals per second")
     ap.add_argument("--chunk", type=int, default=25, help="served: iterations per engine step")
@@ -113,7 +114,7 @@ def main():
     if args.workload == "served":
         return bench_served(args)
     t0 = time.perf_counter()
-    wl = synth.slab_config()
+    wl = synth.slab_config() if args.workload == "slab" else synth.plane_config()
     log(f"workload {wl.name}: generated in {time.perf_counter() - t0:.1f} s")
     p = wl.params
     stream = torch.cuda.current_stream()
@@ -176,7 +177,9 @@ def main():
         "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl.name, "volume": "512x512x128 u16, h=(1,1,2)", "contours": len(wl.seeds),
+        "config": {"workload": wl.name,
+                   "volume": "512x512x128 u16, h=(1,1,2)" if d == 3 else "8192x8192 u8 (2D)",
+                   "contours": len(wl.seeds),
                    "n_iter": wl.n_iter, "n_dirs": p.n_dirs, "n_rays": M, "n_radial": L,
                    "lanes_per_contour": args.lanes or "auto", "pairs_in_flight": args.unroll or "auto",
                    "layout": {0: "auto", 1: "plain", 2: "quad"}[args.layout]},
@@ -184,7 +187,7 @@ def main():
                        "finalize": float(np.mean(finalize_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "evolve_kernel<3,*,false>",
+                     "kernel": f"evolve_kernel<{d},*,false>",
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }
     if not args.no_cpu_baseline:

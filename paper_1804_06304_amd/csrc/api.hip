@@ -234,10 +234,9 @@ snk_status run_prepass(snk_ctx *c) {
         snk_status st = ensure(c, &c->Jq, &c->Jq_cap, (size_t)(c->nx * c->ny * c->nz));
         if (st != SNK_OK) return st;
     }
+    a.Jq = layout == snk::kBufferQuad ? c->Jq : nullptr;
     HIPTRY(c, hipEventRecord(c->ev[0], c->stream));
     HIPTRY(c, snk::launch_prepass(a, c->stream));
-    if (layout == snk::kBufferQuad)
-        HIPTRY(c, snk::launch_pack_quad(c->J, c->Jq, (int)c->nx, (int)c->ny, (int)c->nz, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[1], c->stream));
     c->layout = layout;
     c->ev_pre = true;
@@ -245,14 +244,14 @@ snk_status run_prepass(snk_ctx *c) {
     return SNK_OK;
 }
 
-// Lanes per contour: at least two pair-points per lane, and narrower groups while the contours
-// alone fill the GPU (more than 8192 waves).
+// Lanes per contour: whole waves with at least two pair-points per lane; sub-wave groups only
+// when a contour has fewer pair-points than a wave has lanes.
 int pick_lanes(const snk_ctx *c) {
     if (c->lanes > 0) return c->lanes;
     const int64_t pairs = (int64_t)(c->P.n_rays / 2) * c->P.n_radial;
     int g = 256;
-    while (g > 16 && 2 * g > pairs) g >>= 1;
-    while (g > 16 && c->n * g > (int64_t)8192 * 64) g >>= 1;
+    while (g > 64 && 2 * g > pairs) g >>= 1;
+    while (g > 16 && g > pairs) g >>= 1;
     return g;
 }
 

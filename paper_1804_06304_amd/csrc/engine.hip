@@ -342,6 +342,7 @@ snk_status prepass_job(snk_engine *e, const EJob &j) {
     a.raw = j.d_raw;
     a.dtype = (int)j.dtype;
     a.J = j.d_J;
+    a.Jq = j.d_Jq;
     a.nx = (int)j.nx;
     a.ny = (int)j.ny;
     a.nz = (int)j.nz;
@@ -363,7 +364,6 @@ snk_status prepass_job(snk_engine *e, const EJob &j) {
         for (int k = 0; k <= 2 * r; ++k) tap[ax][k] = (float)(g[k] / sum);
     }
     EHIP(e, snk::launch_prepass(a, e->stream));
-    EHIP(e, snk::launch_pack_quad(j.d_J, j.d_Jq, (int)j.nx, (int)j.ny, (int)j.nz, e->stream));
     return SNK_OK;
 }
 

@@ -53,8 +53,10 @@ enum VolumeLayout {
     kBufferQuad = 2,   // quad records through a buffer descriptor (< 2 GiB, 24-bit strides)
 };
 
-// Layout for a volume: `requested` 0 = automatic (quad when it fits), 1 = plain, 2 = quad, 3 = plain
-// with 64-bit addressing. Returns the layout, or -1 if the request cannot be met.
+// Layout for a volume: `requested` 0 = automatic (quad in 3D when it fits, where one load fetches two
+// of the four corner pairs; plain in 2D, where it saves only one load per point and its 4x footprint
+// falls out of the caches), 1 = plain, 2 = quad, 3 = plain with 64-bit addressing. Returns the
+// layout, or -1 if the request cannot be met.
 inline int volume_layout(int dim, int64_t nx, int64_t ny, int64_t nz, int requested) {
     const int64_t vox = nx * ny * nz;
     const bool strides = nx < (1 << 23) && (dim == 2 || nx * ny < (1 << 23));
@@ -62,7 +64,7 @@ inline int volume_layout(int dim, int64_t nx, int64_t ny, int64_t nz, int reques
     const bool quad_ok = strides && vox * 16 < ((int64_t)1 << 31) && ny <= 65535 && nz <= 65535;
     if (requested == 3) return kGlobalPlain;
     if (requested == 2) return quad_ok ? kBufferQuad : -1;
-    if (requested == 1) return plain_ok ? kBufferPlain : kGlobalPlain;
+    if (requested == 1 || dim == 2) return plain_ok ? kBufferPlain : kGlobalPlain;
     return quad_ok ? kBufferQuad : (plain_ok ? kBufferPlain : kGlobalPlain);
 }
 
@@ -103,6 +105,7 @@ struct PrepassArgs {
     const void *raw;
     int dtype;
     float *J;
+    float4 *Jq;                  // quad layout output, or null
     int nx, ny, nz;
     float i_offset, i_scale;
     int rx, ry, rz;              // tap radii per axis (0: axis not smoothed)

@@ -171,10 +171,11 @@ def test_one_step_parity_aniso_u16(snk, stream):
     one_step_parity(snk, stream, wl, [0, 3, 30])
 
 
-def test_one_step_parity_2d(snk, stream):
+@pytest.mark.parametrize("lanes,layout", [(0, 0), (64, 2), (16, 1), (32, 2)])
+def test_one_step_parity_2d(snk, stream, lanes, layout):
     wl = synth.plane_config(n_target=120, size=256, n_iter=50)
-    say("one-step parity 2D (256^2 u8, D 64, M 16)")
-    one_step_parity(snk, stream, wl, [0, 2, 25], n_extra=40)
+    say(f"one-step parity 2D (256^2 u8, D 64, M 16), lanes {lanes}, layout {layout}")
+    one_step_parity(snk, stream, wl, [0, 2, 25], n_extra=40, lanes=lanes, layout=layout)
 
 
 @pytest.mark.parametrize("lanes,unroll,layout", [(16, 1, 0), (16, 2, 1), (32, 1, 2), (32, 2, 3), (64, 1, 1),
