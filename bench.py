@@ -15,6 +15,7 @@ timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +26,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "evolve_slab_counters.json")
+
+
+def measured_traffic(workload, launch_auto):
+    """HBM bytes per evolve launch from the committed FETCH_SIZE / WRITE_SIZE counters (scaled by the
+    copy-kernel calibration), or None when they were taken on other evolve sources or shapes."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        h = hashlib.sha256()
+        root = os.path.dirname(os.path.abspath(__file__))
+        for name in c["source_files"]:
+            with open(os.path.join(root, name), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if h.hexdigest() != c["source_sha256"] or c["workload"] != workload or not launch_auto:
+        return None
+    return float(c["hbm_bytes_per_dispatch"])
 METRIC = "contour vertex-updates/s at fixed accuracy"
 
 
@@ -186,7 +206,8 @@ def main():
         "kernels_ms": {"prepass": float(np.mean(prepass_ms)), "evolve": ev_ms,
                        "finalize": float(np.mean(finalize_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(wl.name, args.lanes == 0 and args.unroll == 0 and args.layout == 0),
                      "kernel": f"evolve_kernel<{d},*,false>",
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }

@@ -489,7 +489,9 @@ __device__ __forceinline__ void lane_sums(const Vol<DIM, LAYOUT> &vol, const Fra
             const bool r2 = d2 >= -fr.hD && d2 < fr.hD;   // outer ramp
             const float sin_ = __builtin_amdgcn_fmed3f(d1 * fr.is, -1.0f, 1.0f);
             const float sout = __builtin_amdgcn_fmed3f(fmaf(-d2, fr.os, 0.5f), 0.0f, 1.0f);
-            const float S = d2 < -fr.hD ? sin_ : sout;
+            // the inner profile is +1 wherever the outer one is below 1 (R >= the geometric
+            // minimum keeps the regions disjoint), and vice versa
+            const float S = fminf(sin_, sout);
             const float cC = r1 ? fr.is : (r2 ? -fr.os : 0.0f);  // dS/dr on the ramps
             const float cR = r1 ? -fr.rho_is : -cC;               // dS/dR on the ramps
             const float Is = Ip + Im, Id = Ip - Im;
@@ -546,7 +548,8 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
     constexpr float BALL = DIM == 3 ? 4.18879020478639098462f : 3.14159265358979323846f;
     const int t = threadIdx.x;
     const int gl = G < 64 ? (t & (G - 1)) : t;
-    const int lane = t & 63, wave = t >> 6;
+    const int lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform (scalar branches)
 
     DevContour s{};
     s.status = SNK_OUT;
@@ -649,15 +652,19 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
-                float v = red[k * WAVES];
+                float v = 0.0f;
+                if (wave == 0) {
+                    v = red[k * WAVES];
 #pragma unroll
-                for (int w = 1; w < WAVES; ++w) v += red[k * WAVES + w];
+                    for (int w = 1; w < WAVES; ++w) v += red[k * WAVES + w];
+                }
                 tot[k] = v;
             }
         }
 
-        if (active) {
-            // descent step, identical in every lane of the group
+        // descent step, identical in every lane of the group (multi-wave groups: wave 0 only, the
+        // others take the new state from LDS below)
+        if (active && (G <= 64 || wave == 0)) {
             n += 1;
             const float smax = fr.smax;
             float smax_d = smax;
@@ -746,6 +753,29 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             }
             ++ran;
         }
+        if constexpr (G > 64) {
+            // broadcast of wave 0's new state: centre anchor / offset, R, status
+            float *bc = lds_red + 2 * NR * WAVES + (it & 1) * 8;
+            if (active && t == 0) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    bc[i] = off[i];
+                    bc[3 + i] = __int_as_float(anc[i]);
+                }
+                bc[6] = R;
+                bc[7] = __int_as_float((int)status);
+            }
+            __syncthreads();
+            if (active && wave != 0) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    off[i] = uni<G>(bc[i]);
+                    anc[i] = uni<G>(__float_as_int(bc[3 + i]));
+                }
+                R = uni<G>(bc[6]);
+                status = (uint8_t)uni<G>(__float_as_int(bc[7]));
+            }
+        }
         if constexpr (G <= 64) __syncthreads();  // orders this iteration's LDS draws before later reads
     }
 
@@ -770,11 +800,11 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
 template <int DIM, int G>
 __host__ __device__ __forceinline__ int lds_floats(int MH) {
     const int per = (draw_floats(G, MH) + 3) & ~3;
-    return Grp<G>::CPB * per + (G > 64 ? 2 * (2 + DIM) * Grp<G>::WAVES : 0);
+    return Grp<G>::CPB * per + (G > 64 ? 2 * (2 + DIM) * Grp<G>::WAVES + 16 : 0);
 }
 
-// One pair-point in flight fits 64 vector registers: ask for 8 waves per SIMD (a full CU of
-// 4-wave groups holds 8 contours).
+// Whole-wave groups with one pair-point in flight fit 64 vector registers: ask for 8 waves per SIMD
+// (a full CU of 4-wave groups holds 8 contours).
 template <int DIM, int G, int U, bool TRACE, int LAYOUT>
 __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolve_kernel(EvolveArgs a) {
     extern __shared__ float lds[];
@@ -947,7 +977,7 @@ size_t evolve_lds_bytes(int dim, int lanes, int M) {
     const int per = (draw_floats(G, MH) + 3) & ~3;
     const int cpb = G < 64 ? 64 / G : 1;
     const int waves = G > 64 ? G / 64 : 1;
-    return sizeof(float) * ((size_t)cpb * per + (G > 64 ? 2 * (2 + dim) * waves : 0));
+    return sizeof(float) * ((size_t)cpb * per + (G > 64 ? 2 * (2 + dim) * waves + 16 : 0));
 }
 
 }  // namespace snk

@@ -21,8 +21,14 @@ namespace snk {
 
 namespace {
 
-constexpr int EV_T = 256;
 constexpr int SEL_T = 1024;
+
+// Threads per contour of the exact energy: a 3D ball holds thousands of lattice points, a disk
+// hundreds.
+template <int DIM>
+constexpr int ev_threads() {
+    return DIM == 3 ? 256 : 64;
+}
 
 template <int DIM>
 __device__ __forceinline__ float weight_S(float r, float R, float dR) {
@@ -37,6 +43,7 @@ __device__ __forceinline__ float weight_S(float r, float R, float dR) {
 
 template <int DIM>
 __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) {
+    constexpr int EV_T = ev_threads<DIM>();
     __shared__ double part[EV_T / 64];
     const int t = threadIdx.x;
     const DevContour s = *slot;
@@ -58,13 +65,24 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) 
         cnt[i] = (int)ceilf(s.off[i] + ext) + 1 - lo[i] + 1;
     }
     const int nn[3] = {g.nx, g.ny, g.nz};
-    const long total = (long)cnt[0] * cnt[1] * cnt[2];
+    const int total = cnt[0] * cnt[1] * cnt[2];
+    // box coordinates of this thread's first point and the step of EV_T points (no division in
+    // the loop)
+    int rx = t % cnt[0], ry = (t / cnt[0]) % cnt[1], rz = t / (cnt[0] * cnt[1]);
+    const int sx = EV_T % cnt[0], sy = EV_T / cnt[0];
     double acc = 0.0;
-    for (long idx = t; idx < total; idx += EV_T) {
-        const int rx = (int)(idx % cnt[0]);
-        const int ry = (int)((idx / cnt[0]) % cnt[1]);
-        const int rz = (int)(idx / ((long)cnt[0] * cnt[1]));
+    for (int idx = t; idx < total; idx += EV_T) {
         const int rel[3] = {lo[0] + rx, lo[1] + ry, lo[2] + rz};
+        rx += sx;
+        if (rx >= cnt[0]) {
+            rx -= cnt[0];
+            ry += 1;
+        }
+        ry += sy;
+        while (ry >= cnt[1]) {
+            ry -= cnt[1];
+            rz += 1;
+        }
         float d2 = 0.0f;
 #pragma unroll
         for (int i = 0; i < DIM; ++i) {
@@ -72,7 +90,7 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) 
             d2 = fmaf(d, d, d2);
         }
         const float r = sqrtf(d2);
-        if (!(r < smax)) continue;
+        if (!(r < smax)) continue;  // (the step above already advanced the coordinates)
         int k[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = min(max(s.anc[i] + rel[i], 0), nn[i] - 1);
@@ -85,6 +103,7 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) 
     __syncthreads();
     if (t == 0) {
         double tot = 0.0;
+#pragma unroll
         for (int w = 0; w < EV_T / 64; ++w) tot += part[w];
         const double meas = (double)g.h[0] * g.h[1] * (DIM == 3 ? g.h[2] : 1.0f);
         double norm = 1.0;
@@ -99,13 +118,15 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) 
 }
 
 template <int DIM>
-__global__ __launch_bounds__(EV_T) void energy_vox_kernel(JobParams p, DevContour *st, double *e_vox, int n) {
+__global__ __launch_bounds__(ev_threads<DIM>()) void energy_vox_kernel(JobParams p, DevContour *st, double *e_vox,
+                                                                      int n) {
     const int cid = blockIdx.x;
     if (cid < n) energy_one<DIM>(p, st + cid, e_vox + cid);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(EV_T) void energy_vox_batch_kernel(const JobDev *jobs, const int2 *items, int n_items) {
+__global__ __launch_bounds__(ev_threads<DIM>()) void energy_vox_batch_kernel(const JobDev *jobs, const int2 *items,
+                                                                            int n_items) {
     const int item = blockIdx.x;
     if (item >= n_items) return;
     const int job = __builtin_amdgcn_readfirstlane(items[item].x);
@@ -257,8 +278,8 @@ __global__ __launch_bounds__(SEL_T) void select_batch_kernel(const JobDev *jobs,
 
 hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(n), dim3(EV_T), 0, s, p, st, e_vox, n);
-    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(n), dim3(EV_T), 0, s, p, st, e_vox, n);
+    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(n), dim3(ev_threads<2>()), 0, s, p, st, e_vox, n);
+    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(n), dim3(ev_threads<3>()), 0, s, p, st, e_vox, n);
     return hipGetLastError();
 }
 
@@ -271,8 +292,10 @@ hipError_t launch_select(const JobDev &j, int dim, hipStream_t s) {
 
 hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(energy_vox_batch_kernel<2>, dim3(n_items), dim3(EV_T), 0, s, jobs, items, n_items);
-    else hipLaunchKernelGGL(energy_vox_batch_kernel<3>, dim3(n_items), dim3(EV_T), 0, s, jobs, items, n_items);
+    if (dim == 2)
+        hipLaunchKernelGGL(energy_vox_batch_kernel<2>, dim3(n_items), dim3(ev_threads<2>()), 0, s, jobs, items, n_items);
+    else
+        hipLaunchKernelGGL(energy_vox_batch_kernel<3>, dim3(n_items), dim3(ev_threads<3>()), 0, s, jobs, items, n_items);
     return hipGetLastError();
 }
 
