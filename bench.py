@@ -323,7 +323,10 @@ def bench_served(args):
         arrivals.append((t, int(rng.integers(len(pool)))))
     log(f"{len(arrivals)} requests over {args.serve_seconds:.0f} s (rate {args.rate}/s)")
 
-    eng = snk.Engine(0, stream, 64 << 30)
+    free_b, total_b = torch.cuda.mem_get_info(0)
+    budget = min(64 << 30, free_b // 2)
+    log(f"device memory: {free_b / 2**30:.1f} GiB free of {total_b / 2**30:.1f} GiB; HBM budget {budget / 2**30:.1f} GiB")
+    eng = snk.Engine(0, stream, budget)
     # warm-up: tune the launch class on a few pool tiles, then forget them
     warm = [eng.submit(w.params, w.dirs, r, w.seeds, ids=w.ids, n_iter=w.n_iter) for w, r in zip(pool[:4], raws[:4])]
     eng.run()
@@ -376,7 +379,7 @@ def bench_served(args):
         "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": len(arrivals),
         "warmup": 4, "ms_per_step": secs / max(len(arrivals), 1) * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "served-poisson-tiles-u16", "rate_per_s": args.rate, "window_s": args.serve_seconds,
+        "config": {"workload": "served-poisson-tiles-u16", "hbm_budget_gib": round(budget / 2**30, 1), "rate_per_s": args.rate, "window_s": args.serve_seconds,
                    "tiles_in_pool": len(pool), "n_iter": pool[0].n_iter, "chunk": args.chunk},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},

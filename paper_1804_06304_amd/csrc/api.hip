@@ -53,7 +53,7 @@ struct snk_ctx {
         *d_dec = nullptr;
     size_t grid_cap = 0, grid_fill_cap = 0, sel_cap = 0;
 
-    unsigned long long *d_counters = nullptr;  // [0] evolved, [1] kept
+    unsigned long long *d_counters = nullptr;  // [0] evolved, [1] kept, [2..3] selection round counters
 
     hipEvent_t ev[6] = {};
     bool ev_pre = false, ev_evo = false, ev_fin = false;
@@ -581,7 +581,7 @@ snk_status snk_finalize(snk_ctx *c) {
     HIPTRY(c, hipMemsetAsync(c->d_counters + 1, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
     HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, c->stream));
-    HIPTRY(c, snk::launch_select(a, c->P.dim, c->stream));
+    HIPTRY(c, snk::launch_select(a, c->P.dim, reinterpret_cast<int *>(c->d_counters + 2), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
     c->ev_fin = true;
     return SNK_OK;

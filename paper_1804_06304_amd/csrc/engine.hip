@@ -265,7 +265,15 @@ snk_status admit(snk_engine *e, EJob &j) {
     const size_t o_init = off; off += align256(n * sizeof(DevContour));
     const size_t o_evox = off; off += align256(n * 8);
     const size_t o_sel = off; off += align256(((size_t)j.grid_cells + 1) * 2 * 4 + n * 3 * 4);
-    if (hipMalloc(&j.block, off) != hipSuccess) return efail(e, SNK_ENOMEM, "hipMalloc (job buffers)");
+    if (hipMalloc(&j.block, off) != hipSuccess) {
+        size_t free_b = 0, total_b = 0;
+        (void)hipGetLastError();
+        (void)hipMemGetInfo(&free_b, &total_b);
+        return efail(e, SNK_ENOMEM,
+                     "hipMalloc (job buffers): " + std::to_string(off) + " bytes requested, " +
+                         std::to_string(e->in_use) + " charged to the budget, " + std::to_string(free_b) +
+                         " of " + std::to_string(total_b) + " bytes free on the device");
+    }
     char *b = static_cast<char *>(j.block);
     j.d_raw = j.borrowed ? j.borrowed : (const void *)(b + o_raw);
     j.d_J = reinterpret_cast<float *>(b + o_J);

@@ -22,6 +22,8 @@ namespace snk {
 namespace {
 
 constexpr int SEL_T = 1024;
+constexpr int kSelectGridMin = 4096;   // contours above which the plain path bins and decides grid-wide
+constexpr int kSelectGridRounds = 6;   // grid-wide decision rounds before the single-workgroup finish
 
 // Threads per contour of the exact energy: a 3D ball holds thousands of lattice points, a disk
 // hundreds.
@@ -150,106 +152,127 @@ __device__ __forceinline__ bool overlaps(const DevContour &x, const DevContour &
     return sqrtf(d2) < thr;
 }
 
+// One decision step for contour i (no-op unless undecided): reject if an overlapping neighbour is
+// accepted, accept if it has the smallest (E_vox, id) among its undecided overlapping neighbours.
+// Decisions of other contours may change concurrently; every decision taken is final and
+// correct whatever the interleaving, since a contour is accepted only once every overlapping
+// contour with a smaller key has been rejected.
 template <int DIM>
-__device__ void select_job(const JobDev &a) {
+__device__ int decide(const JobDev &a, int i) {
+    volatile int *dec = a.dec;
+    if (dec[i] != DEC_UNDECIDED) return dec[i];
+    const Geometry &g = a.p.g;
+    const DevContour si = a.st[i];
+    const double ei = a.e_vox[i];
+    const int cell = a.cell_of[i];
+    const int gi[3] = {cell % a.G[0], (cell / a.G[0]) % a.G[1], cell / (a.G[0] * a.G[1])};
+    bool accepted_nb = false, minimal = true;
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0) && !accepted_nb; ++dz)
+        for (int dy = -1; dy <= 1 && !accepted_nb; ++dy)
+            for (int dx = -1; dx <= 1 && !accepted_nb; ++dx) {
+                const int cx = gi[0] + dx, cy = gi[1] + dy, cz = gi[2] + dz;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= a.G[0] || cy >= a.G[1] || cz >= a.G[2]) continue;
+                const int c = (cz * a.G[1] + cy) * a.G[0] + cx;
+                for (int q = a.cell_start[c]; q < a.cell_start[c + 1]; ++q) {
+                    const int j = a.items[q];
+                    if (j == i) continue;
+                    const int dj = dec[j];
+                    if (dj == DEC_REJECT) continue;
+                    const DevContour sj = a.st[j];
+                    if (!overlaps<DIM>(si, sj, g.h)) continue;
+                    if (dj == DEC_ACCEPT) {
+                        accepted_nb = true;
+                        break;
+                    }
+                    const double ej = a.e_vox[j];
+                    if (ej < ei || (ej == ei && sj.id < si.id)) minimal = false;
+                }
+            }
+    const int d = accepted_nb ? DEC_REJECT : (minimal ? DEC_ACCEPT : DEC_UNDECIDED);
+    if (d != DEC_UNDECIDED) dec[i] = d;
+    return d;
+}
+
+// Candidate flag and grid cell of contour i; counts the cell's members in cell_start[cell + 1].
+template <int DIM>
+__device__ __forceinline__ void bin_one(const JobDev &a, int i) {
+    const Geometry &g = a.p.g;
+    const DevContour s = a.st[i];
+    const int st = s.status & 0x0f;
+    const double e = a.e_vox[i];
+    const bool cand = (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0;
+    a.dec[i] = cand ? DEC_UNDECIDED : DEC_NONE;
+    int cell = -1;
+    if (cand) {
+        int gi[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const float pk = ((float)s.anc[k] + s.off[k]) * g.h[k];
+            gi[k] = min(max((int)floorf(pk / a.cell), 0), a.G[k] - 1);
+        }
+        cell = (gi[2] * a.G[1] + gi[1]) * a.G[0] + gi[0];
+        atomicAdd(&a.cell_start[cell + 1], 1);
+    }
+    a.cell_of[i] = cell;
+}
+
+// In-place inclusive scan of cell_start[1..G] by one workgroup: cell_start[c] = first slot of cell c.
+__device__ void scan_cells(const JobDev &a, int G, int *chunk_sum) {
+    const int t = threadIdx.x;
+    const int per = (G + SEL_T - 1) / SEL_T;
+    const int b = 1 + t * per, e = min(G + 1, b + per);
+    int run = 0;
+    for (int c = b; c < e; ++c) {
+        run += a.cell_start[c];
+        a.cell_start[c] = run;
+    }
+    chunk_sum[t] = run;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int k = 0; k < SEL_T; ++k) {
+            const int v = chunk_sum[k];
+            chunk_sum[k] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    const int add = chunk_sum[t];
+    for (int c = b; c < e; ++c) a.cell_start[c] += add;
+}
+
+__device__ __forceinline__ void scatter_one(const JobDev &a, int i) {
+    const int cell = a.cell_of[i];
+    if (cell >= 0) {
+        const int pos = atomicAdd(&a.cell_fill[cell], 1);
+        a.items[a.cell_start[cell] + pos] = i;
+    }
+}
+
+// Whole selection of one job by one workgroup. binned: the grid (cell_start, items, cell_of, dec)
+// was already built and some decisions may already be taken.
+template <int DIM>
+__device__ void select_job(const JobDev &a, bool binned) {
     __shared__ int chunk_sum[SEL_T];
     const int t = threadIdx.x;
     const int n = a.n;
     const int G = a.G[0] * a.G[1] * a.G[2];
-    const Geometry &g = a.p.g;
     volatile int *dec = a.dec;
-
-    for (int c = t; c <= G; c += SEL_T) a.cell_start[c] = 0;
-    for (int c = t; c < G; c += SEL_T) a.cell_fill[c] = 0;
-    __syncthreads();
-    for (int i = t; i < n; i += SEL_T) {
-        const DevContour s = a.st[i];
-        const int st = s.status & 0x0f;
-        const double e = a.e_vox[i];
-        const bool cand = (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0;
-        dec[i] = cand ? DEC_UNDECIDED : DEC_NONE;
-        int cell = -1;
-        if (cand) {
-            int gi[3] = {0, 0, 0};
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                const float pk = ((float)s.anc[k] + s.off[k]) * g.h[k];
-                gi[k] = min(max((int)floorf(pk / a.cell), 0), a.G[k] - 1);
-            }
-            cell = (gi[2] * a.G[1] + gi[1]) * a.G[0] + gi[0];
-            atomicAdd(&a.cell_start[cell + 1], 1);
-        }
-        a.cell_of[i] = cell;
-    }
-    __syncthreads();
-    // inclusive scan of cell_start[1..G] in place -> cell_start[c] = first slot of cell c
-    {
-        const int per = (G + SEL_T - 1) / SEL_T;
-        const int b = 1 + t * per, e = min(G + 1, b + per);
-        int run = 0;
-        for (int c = b; c < e; ++c) {
-            run += a.cell_start[c];
-            a.cell_start[c] = run;
-        }
-        chunk_sum[t] = run;
+    if (!binned) {
+        for (int c = t; c <= G; c += SEL_T) a.cell_start[c] = 0;
+        for (int c = t; c < G; c += SEL_T) a.cell_fill[c] = 0;
         __syncthreads();
-        if (t == 0) {
-            int acc = 0;
-            for (int k = 0; k < SEL_T; ++k) {
-                const int v = chunk_sum[k];
-                chunk_sum[k] = acc;
-                acc += v;
-            }
-        }
+        for (int i = t; i < n; i += SEL_T) bin_one<DIM>(a, i);
         __syncthreads();
-        const int add = chunk_sum[t];
-        for (int c = b; c < e; ++c) a.cell_start[c] += add;
+        scan_cells(a, G, chunk_sum);
+        __syncthreads();
+        for (int i = t; i < n; i += SEL_T) scatter_one(a, i);
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = t; i < n; i += SEL_T) {
-        const int cell = a.cell_of[i];
-        if (cell >= 0) {
-            const int pos = atomicAdd(&a.cell_fill[cell], 1);
-            a.items[a.cell_start[cell] + pos] = i;
-        }
-    }
-    __syncthreads();
-
     bool any = true;
     while (any) {
         int local = 0;
-        for (int i = t; i < n; i += SEL_T) {
-            if (dec[i] != DEC_UNDECIDED) continue;
-            const DevContour si = a.st[i];
-            const double ei = a.e_vox[i];
-            const int cell = a.cell_of[i];
-            const int gi[3] = {cell % a.G[0], (cell / a.G[0]) % a.G[1], cell / (a.G[0] * a.G[1])};
-            bool accepted_nb = false, minimal = true;
-            for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0) && !accepted_nb; ++dz)
-                for (int dy = -1; dy <= 1 && !accepted_nb; ++dy)
-                    for (int dx = -1; dx <= 1 && !accepted_nb; ++dx) {
-                        const int cx = gi[0] + dx, cy = gi[1] + dy, cz = gi[2] + dz;
-                        if (cx < 0 || cy < 0 || cz < 0 || cx >= a.G[0] || cy >= a.G[1] || cz >= a.G[2]) continue;
-                        const int c = (cz * a.G[1] + cy) * a.G[0] + cx;
-                        for (int q = a.cell_start[c]; q < a.cell_start[c + 1]; ++q) {
-                            const int j = a.items[q];
-                            if (j == i) continue;
-                            const int dj = dec[j];
-                            if (dj == DEC_REJECT) continue;
-                            const DevContour sj = a.st[j];
-                            if (!overlaps<DIM>(si, sj, g.h)) continue;
-                            if (dj == DEC_ACCEPT) {
-                                accepted_nb = true;
-                                break;
-                            }
-                            const double ej = a.e_vox[j];
-                            if (ej < ei || (ej == ei && sj.id < si.id)) minimal = false;
-                        }
-                    }
-            if (accepted_nb) dec[i] = DEC_REJECT;
-            else if (minimal) dec[i] = DEC_ACCEPT;
-            else local = 1;
-        }
+        for (int i = t; i < n; i += SEL_T) local |= decide<DIM>(a, i) == DEC_UNDECIDED ? 1 : 0;
         __threadfence_block();
         any = __syncthreads_or(local) != 0;
     }
@@ -263,15 +286,68 @@ __device__ void select_job(const JobDev &a) {
 }
 
 template <int DIM>
-__global__ __launch_bounds__(SEL_T) void select_kernel(JobDev j) {
-    if (j.n > 0) select_job<DIM>(j);
+__global__ __launch_bounds__(SEL_T) void select_kernel(JobDev j, int binned) {
+    if (j.n > 0) select_job<DIM>(j, binned != 0);
 }
 
 template <int DIM>
 __global__ __launch_bounds__(SEL_T) void select_batch_kernel(const JobDev *jobs, const int *job_list, int n_jobs) {
     if ((int)blockIdx.x >= n_jobs) return;
     const JobDev &j = jobs[__builtin_amdgcn_readfirstlane(job_list[blockIdx.x])];
-    if (j.n > 0) select_job<DIM>(j);
+    if (j.n > 0) select_job<DIM>(j, false);
+}
+
+// Grid-wide selection steps for one job with many contours (the single-workgroup loop above then
+// finishes whatever the rounds left undecided).
+constexpr int SG_T = 256;
+
+__global__ __launch_bounds__(SG_T) void sel_zero_kernel(JobDev a, int G, int *rounds) {
+    const int i = blockIdx.x * SG_T + threadIdx.x;
+    if (i <= G) a.cell_start[i] = 0;
+    if (i < G) a.cell_fill[i] = 0;
+    if (i < 3) rounds[i] = 0;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(SG_T) void sel_bin_kernel(JobDev a) {
+    const int i = blockIdx.x * SG_T + threadIdx.x;
+    if (i < a.n) bin_one<DIM>(a, i);
+}
+
+__global__ __launch_bounds__(SEL_T) void sel_scan_kernel(JobDev a, int G) {
+    __shared__ int chunk_sum[SEL_T];
+    scan_cells(a, G, chunk_sum);
+}
+
+__global__ __launch_bounds__(SG_T) void sel_scatter_kernel(JobDev a) {
+    const int i = blockIdx.x * SG_T + threadIdx.x;
+    if (i < a.n) scatter_one(a, i);
+}
+
+// Round r: skipped when round r-1 left nothing undecided; counts what it leaves undecided in
+// rounds[r % 3] and clears rounds[(r + 1) % 3] for the next round.
+template <int DIM>
+__global__ __launch_bounds__(SG_T) void sel_round_kernel(JobDev a, int r, int *rounds) {
+    if (r > 0 && *(volatile int *)&rounds[(r + 2) % 3] == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) rounds[(r + 1) % 3] = 0;
+    const int i = blockIdx.x * SG_T + threadIdx.x;
+    int left = 0;
+    if (i < a.n) left = decide<DIM>(a, i) == DEC_UNDECIDED ? 1 : 0;
+    if (__builtin_amdgcn_ballot_w64(left != 0) != 0 && (threadIdx.x & 63) == 0) atomicAdd(&rounds[r % 3], 1);
+}
+
+template <int DIM>
+hipError_t select_grid(const JobDev &j, int *rounds, hipStream_t s) {
+    const int G = j.G[0] * j.G[1] * j.G[2];
+    const int bn = (j.n + SG_T - 1) / SG_T;
+    hipLaunchKernelGGL(sel_zero_kernel, dim3((G + 1 + SG_T - 1) / SG_T), dim3(SG_T), 0, s, j, G, rounds);
+    hipLaunchKernelGGL(sel_bin_kernel<DIM>, dim3(bn), dim3(SG_T), 0, s, j);
+    hipLaunchKernelGGL(sel_scan_kernel, dim3(1), dim3(SEL_T), 0, s, j, G);
+    hipLaunchKernelGGL(sel_scatter_kernel, dim3(bn), dim3(SG_T), 0, s, j);
+    for (int r = 0; r < kSelectGridRounds; ++r)
+        hipLaunchKernelGGL(sel_round_kernel<DIM>, dim3(bn), dim3(SG_T), 0, s, j, r, rounds);
+    hipLaunchKernelGGL(select_kernel<DIM>, dim3(1), dim3(SEL_T), 0, s, j, 1);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -283,10 +359,11 @@ hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, 
     return hipGetLastError();
 }
 
-hipError_t launch_select(const JobDev &j, int dim, hipStream_t s) {
+hipError_t launch_select(const JobDev &j, int dim, int *rounds, hipStream_t s) {
     if (j.n <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, j);
-    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, j);
+    if (j.n > kSelectGridMin && rounds) return dim == 2 ? select_grid<2>(j, rounds, s) : select_grid<3>(j, rounds, s);
+    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, j, 0);
+    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, j, 0);
     return hipGetLastError();
 }
 

@@ -135,7 +135,8 @@ hipError_t launch_reset_items(const JobDev *jobs, const int2 *items, int n_items
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_count_unfinished(const JobDev *jobs, const int2 *items, int n_items, int *unfinished, hipStream_t s);
 hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, hipStream_t s);
-hipError_t launch_select(const JobDev &j, int dim, hipStream_t s);
+// rounds: 3 ints of device scratch for the grid-wide rounds (null: one workgroup does everything).
+hipError_t launch_select(const JobDev &j, int dim, int *rounds, hipStream_t s);
 hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s);
 hipError_t launch_select_batch(const JobDev *jobs, const int *job_list, int n_jobs, int dim, hipStream_t s);
 

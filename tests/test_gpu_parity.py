@@ -269,14 +269,15 @@ def test_free_run_2d(snk, stream):
     assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[same]) <= 0.5
 
 
-def test_selection_matches_greedy_dense(snk, stream):
-    """Dense random contours (many overlapping chains): the GPU's parallel rounds equal the
+@pytest.mark.parametrize("n", [1500, 9000])
+def test_selection_matches_greedy_dense(snk, stream, n):
+    """Dense random contours (many overlapping chains): the GPU's parallel rounds (one workgroup
+    at 1,500 contours; grid-wide rounds then the one-workgroup finish at 9,000) equal the
     oracle's sequential greedy on the GPU's own energies."""
     wl = synth.tiny_config()
     p = wl.params.replace(e0=-0.002)
     wl.params = p
     rng = np.random.default_rng(5)
-    n = 1500
     seeds = rng.uniform(2.0, 61.0, size=(n, 3))
     R = rng.uniform(5.0, 9.0, size=n).astype(np.float32)
     ctx = make_ctx(snk, stream, wl)
