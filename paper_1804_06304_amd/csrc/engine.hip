@@ -55,7 +55,8 @@ struct EJob {
     std::vector<DevContour> init;        // initial contour states
     int n = 0;
     int n_iter = 0;
-    size_t bytes = 0;                    // device footprint charged to the budget
+    size_t bytes = 0;                    // device footprint (admission estimate)
+    size_t charged = 0;                  // capacity of the block it holds, charged to the budget
     JobState state = PENDING;
     int slot = -1;                       // row in the device job table
     // device buffers (one allocation)
@@ -102,7 +103,10 @@ double r_low(const snk_params &p) {
 struct snk_engine {
     int device = 0;
     hipStream_t stream = nullptr;
-    uint64_t budget = 0, in_use = 0;
+    uint64_t budget = 0, in_use = 0;       // in_use: capacity of the blocks held by admitted jobs
+    std::multimap<size_t, void *> pool;    // blocks of released jobs, reused before allocating
+    uint64_t pooled = 0;
+    std::vector<EJob *> staged;            // admitted jobs whose host copies are freed at the next sync
     std::string err;
     uint64_t next_id = 1;
     std::map<uint64_t, EJob *> jobs;     // every job not yet released
@@ -148,6 +152,8 @@ struct snk_engine {
 };
 
 namespace {
+
+void unstage(snk_engine *e);
 
 snk_status efail(snk_engine *e, snk_status code, const std::string &m) {
     if (e) e->err = m;
@@ -204,6 +210,7 @@ snk_status ensure_table(snk_engine *e, int need) {
     EHIP(e, hipMemcpyAsync(e->d_init_ptrs, e->h_init_ptrs.data(), sizeof(DevContour *) * cap, hipMemcpyHostToDevice,
                            e->stream));
     EHIP(e, hipStreamSynchronize(e->stream));
+    unstage(e);
     return SNK_OK;
 }
 
@@ -249,7 +256,50 @@ snk::JobParams params_of(const EJob &j) {
     return p;
 }
 
-// Allocate, upload and enter a job into the device table.
+// A device block of at least `need` bytes for a job: a pooled block up to 25% larger when the budget
+// allows, else a new allocation (pooled blocks are freed first while budget or device memory run
+// short). Pooled and admitted blocks together stay within the budget.
+void *pool_get(snk_engine *e, size_t need, size_t *cap) {
+    auto it = e->pool.lower_bound(need);
+    if (it != e->pool.end() && it->first <= need + need / 4 && e->in_use + it->first <= e->budget) {
+        void *b = it->second;
+        *cap = it->first;
+        e->pooled -= it->first;
+        e->pool.erase(it);
+        return b;
+    }
+    while (!e->pool.empty() && e->in_use + e->pooled + need > e->budget) {
+        auto big = std::prev(e->pool.end());
+        (void)hipFree(big->second);
+        e->pooled -= big->first;
+        e->pool.erase(big);
+    }
+    void *b = nullptr;
+    while (hipMalloc(&b, need) != hipSuccess) {
+        (void)hipGetLastError();
+        if (e->pool.empty()) return nullptr;
+        auto big = std::prev(e->pool.end());
+        (void)hipFree(big->second);
+        e->pooled -= big->first;
+        e->pool.erase(big);
+    }
+    *cap = need;
+    return b;
+}
+
+void pool_put(snk_engine *e, void *b, size_t cap) {
+    e->pool.insert({cap, b});
+    e->pooled += cap;
+}
+
+void pool_drain(snk_engine *e) {
+    for (auto &kv : e->pool) (void)hipFree(kv.second);
+    e->pool.clear();
+    e->pooled = 0;
+}
+
+// Allocate, upload and enter a job into the device table (asynchronously: its host copies stay
+// alive until the next synchronisation of the engine's stream).
 snk_status admit(snk_engine *e, EJob &j) {
     snk_status st = ensure_table(e, (int)(e->jobs.size() + 1));
     if (st != SNK_OK) return st;
@@ -265,9 +315,10 @@ snk_status admit(snk_engine *e, EJob &j) {
     const size_t o_init = off; off += align256(n * sizeof(DevContour));
     const size_t o_evox = off; off += align256(n * 8);
     const size_t o_sel = off; off += align256(((size_t)j.grid_cells + 1) * 2 * 4 + n * 3 * 4);
-    if (hipMalloc(&j.block, off) != hipSuccess) {
+    size_t cap = 0;
+    j.block = pool_get(e, off, &cap);
+    if (!j.block) {
         size_t free_b = 0, total_b = 0;
-        (void)hipGetLastError();
         (void)hipMemGetInfo(&free_b, &total_b);
         return efail(e, SNK_ENOMEM,
                      "hipMalloc (job buffers): " + std::to_string(off) + " bytes requested, " +
@@ -313,30 +364,42 @@ snk_status admit(snk_engine *e, EJob &j) {
     EHIP(e, hipMemcpyAsync(e->d_jobs + j.slot, &e->h_jobs[j.slot], sizeof(JobDev), hipMemcpyHostToDevice, e->stream));
     EHIP(e, hipMemcpyAsync(e->d_init_ptrs + j.slot, &e->h_init_ptrs[j.slot], sizeof(DevContour *),
                            hipMemcpyHostToDevice, e->stream));
-    EHIP(e, hipStreamSynchronize(e->stream));
-    j.host_raw.clear();
-    j.host_raw.shrink_to_fit();
+    e->staged.push_back(&j);
     j.state = RUNNING;
-    e->in_use += j.bytes;
+    j.charged = cap;
+    e->in_use += cap;
     e->admitted += 1;
     return SNK_OK;
 }
 
+// After a synchronisation of the engine's stream: drop the host copies of uploaded volumes.
+void unstage(snk_engine *e) {
+    for (EJob *j : e->staged) {
+        j->host_raw.clear();
+        j->host_raw.shrink_to_fit();
+    }
+    e->staged.clear();
+}
+
+// Returns a job's device memory and table row; idempotent (a finished job is released when it
+// completes and again when the caller releases it), so the budget is credited exactly once.
 void release_device(snk_engine *e, EJob &j) {
-    if (j.block) (void)hipFree(j.block);
-    j.block = nullptr;
+    if (j.block) {
+        pool_put(e, j.block, j.charged);
+        j.block = nullptr;
+        e->in_use = e->in_use >= j.charged ? e->in_use - j.charged : 0;
+    }
     if (j.slot >= 0) {
         e->free_slots.push_back(j.slot);
         j.slot = -1;
     }
-    if (e->in_use >= j.bytes) e->in_use -= j.bytes;
 }
 
 // Admit pending jobs in FIFO order while they fit.
 snk_status admit_pending(snk_engine *e, std::vector<EJob *> &newly) {
     while (!e->pending.empty()) {
         EJob *j = e->jobs[e->pending.front()];
-        if (e->in_use + j->bytes > e->budget) break;
+        if (e->in_use + j->bytes > e->budget) break;  // pooled blocks are evicted as needed
         snk_status st = admit(e, *j);
         if (st != SNK_OK) return st;
         newly.push_back(j);
@@ -413,6 +476,7 @@ snk_status upload_plan(snk_engine *e, const ItemPlan &pl) {
         EHIP(e, hipMemcpyAsync(e->d_joblist, pl.joblist.data(), sizeof(int) * pl.joblist.size(),
                                hipMemcpyHostToDevice, e->stream));
     EHIP(e, hipStreamSynchronize(e->stream));
+    unstage(e);
     return SNK_OK;
 }
 
@@ -492,6 +556,7 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
             }
             EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs, e->stream));
             EHIP(e, hipStreamSynchronize(e->stream));
+            unstage(e);
             e->tuned[k] = L;
         }
         L.grid = grid_for(e, k, L, n_items);
@@ -512,6 +577,7 @@ snk_status collect(snk_engine *e, const std::vector<EJob *> &js) {
                                    e->stream));
     }
     EHIP(e, hipStreamSynchronize(e->stream));
+    unstage(e);
     const double t = now_ms();
     for (EJob *j : js) {
         j->state = DONE;
@@ -573,10 +639,12 @@ snk_status snk_engine_destroy(snk_engine *e) {
     (void)hipSetDevice(e->device);
     (void)hipStreamSynchronize(e->stream);
     drop_graph(e);
+    e->staged.clear();
     for (auto &kv : e->jobs) {
         release_device(e, *kv.second);
         delete kv.second;
     }
+    pool_drain(e);
     void *bufs[] = {e->d_jobs, e->d_init_ptrs, e->d_items, e->d_joblist, e->d_unfinished, e->d_counters, e->d_queues};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -807,6 +875,7 @@ snk_status snk_engine_step(snk_engine *e, int32_t chunk, int32_t *n_finished) {
     EHIP(e, hipMemcpyAsync(unfinished.data(), e->d_unfinished, sizeof(int) * e->table_cap, hipMemcpyDeviceToHost,
                            e->stream));
     EHIP(e, hipStreamSynchronize(e->stream));
+    unstage(e);
     float ms = 0.0f;
     EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
     e->last_evolve_ms = ms;

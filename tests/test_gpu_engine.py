@@ -164,3 +164,17 @@ def test_admission_by_budget(snk, jobs):
     for k in KEYS:
         assert np.array_equal(ra[k], rb[k])
     eng.close()
+    # releasing a finished job while another runs must not credit the budget a second time
+    eng = snk.Engine(0, None, int(one * 1.5))
+    a = eng.submit(small.params, small.dirs, small.raw, small.seeds, n_iter=10)
+    b = eng.submit(small.params, small.dirs, small.raw, small.seeds, n_iter=1000)
+    c = eng.submit(small.params, small.dirs, small.raw, small.seeds, n_iter=10)
+    eng.step(20)
+    assert eng.poll() == [a]
+    eng.step(20)                       # b admitted and running, c waits
+    eng.release(a)
+    assert eng.get_stats()["bytes_in_use"] == one
+    eng.step(20)
+    s = eng.get_stats()
+    assert s["running"] == 1 and s["pending"] == 1, s
+    eng.close()
