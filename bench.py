@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per contour: 16..256 (0: automatic)")
     ap.add_argument("--unroll", type=int, default=0, help="pair-points in flight per lane (0: automatic)")
     ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad")
+    ap.add_argument("--exact", action="store_true",
+                    help="exact lattice sums instead of Monte-Carlo samples (params flags bit 1); reports "
+                         "contour-iterations/s next to the Monte-Carlo path's")
     ap.add_argument("--cpu-sample", type=int, default=0, help="contours in the oracle baseline (0: all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
@@ -135,6 +138,8 @@ def main():
         return bench_served(args)
     t0 = time.perf_counter()
     wl = synth.slab_config() if args.workload == "slab" else synth.plane_config()
+    if args.exact:
+        wl.params = wl.params.replace(flags=wl.params.flags | 2)
     log(f"workload {wl.name}: generated in {time.perf_counter() - t0:.1f} s")
     p = wl.params
     stream = torch.cuda.current_stream()
@@ -211,6 +216,14 @@ def main():
                      "kernel": f"evolve_kernel<{d},*,false>",
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }
+    if args.exact:
+        # no rays are sampled: report contour-iterations/s (and its time per contour-iteration) to
+        # set beside the Monte-Carlo path's on the same workload
+        ci = evolved / args.steps
+        line.update({"metric": "contour-iterations/s, exact lattice sums", "value": ci * args.steps / secs,
+                     "unit": "contour-iterations/s",
+                     "evolve_ns_per_contour_iteration": ev_ms * 1e6 / ci, "roofline": None})
+        line["config"]["sums"] = "exact lattice (flags bit 1)"
     if not args.no_cpu_baseline:
         log("cpu baseline: FP64 oracle on the same workload ...")
         base, parity = cpu_baseline(wl, out, args.cpu_sample)

@@ -75,6 +75,12 @@ typedef enum { SNK_U8 = 0, SNK_U16 = 1, SNK_F32 = 2 } snk_dtype;
  *                max(|dR|, |dc|) < conv_tol; conv_window = 0 runs to the iteration limit.
  *   e0           energy threshold of the selection (Results: contours above E0 are removed).
  *   flags        bit 0: do not rotate the direction table (test mode; biased sampling).
+ *                bit 1: exact sums: every iteration takes A, B_R, B_c over all lattice points
+ *                within R + dR/2 of the centre (the point set of Eq. (5)), times the voxel
+ *                measure, instead of the Monte-Carlo estimate: the gradient of the exact discrete
+ *                energy, deterministic (no random numbers; n_dirs, n_rays, n_radial and seed are
+ *                not used). Plain context path only (snk_engine_submit rejects it).
+ *                Other bits must be zero.
  */
 typedef struct snk_params {
     int32_t dim;

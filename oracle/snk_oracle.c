@@ -20,6 +20,9 @@
  *   - the sums are Monte-Carlo estimates from points uniform in the ball of radius R + dR/2
  *     (Sec. II-E), drawn as randomly rotated table directions in antithetic pairs with
  *     r^d-stratified radial points (one reading of the unspecified sampling pattern);
+ *   - optionally (flags bit 1) the same sums taken exactly over every lattice point of the ball of
+ *     radius R + dR/2, i.e. the gradient of the discrete energy of Eq. (5) itself, the full
+ *     voxel-sum evolution the paper compares its Monte-Carlo estimate with (Sec. II-E);
  *   - stopping on maximum iterations or convergence, overlap competition with the lower energy
  *     surviving (||c' - c''|| < max(R', R'')*rho), and the energy threshold E0 (Results).
  *
@@ -50,6 +53,8 @@
 
 #define ORC_TRACE_W 32
 #define ORC_KINK_REL 4e-6
+#define ORC_FLAG_NOROT 1   /* flags bit 0: rotation Q = I */
+#define ORC_FLAG_EXACT 2   /* flags bit 1: exact lattice sums instead of Monte-Carlo samples */
 
 static const double ORC_PI = 3.14159265358979323846;
 
@@ -269,7 +274,7 @@ double orc_interp(const double *J, int64_t nx, int64_t ny, int64_t nz, int dim, 
 void orc_rotation(const orc_params *p, uint32_t n, uint32_t id, double Q[9])
 {
     for (int i = 0; i < 9; ++i) Q[i] = (i % 4 == 0) ? 1.0 : 0.0;
-    if (p->flags & 1) return;
+    if (p->flags & ORC_FLAG_NOROT) return;
     uint32_t x[4];
     philox_at(p, 0u, n, id, 0u, x);
     if (p->dim == 2) {
@@ -393,6 +398,95 @@ static void accumulate_samples(const orc_vol *vol, const double c[3], double R, 
     sm->n_samples = idx;
 }
 
+/* Adds one point's terms: weight, derivatives, p,q-form derivatives, magnitudes and kink slack.
+ * u: unit vector from the centre to the point (zero at the centre), r its distance. */
+static void add_point(const orc_params *p, double r, const double u[3], double I, double R, const double kinks[4],
+                      double smax, orc_sums *sm)
+{
+    int dim = p->dim;
+    double w[3];
+    orc_weight(dim, r, R, p->dR, w);
+    double S = w[0], Sr = w[1], SR = w[2];
+    sm->A += S * I;
+    sm->Aabs += fabs(S * I);
+    sm->BR += SR * I;
+    sm->BRabs += fabs(SR * I);
+    for (int i = 0; i < dim; ++i) {
+        sm->Bc[i] += -Sr * I * u[i];
+        sm->Bcabs[i] += fabs(Sr * I * u[i]);
+    }
+    for (int i = 0; i < dim; ++i) {
+        sm->Sp[i] += (-0.5 * Sr * u[i] - (i == 0 ? 0.5 * SR : 0.0)) * I;
+        sm->Sq[i] += (-0.5 * Sr * u[i] + (i == 0 ? 0.5 * SR : 0.0)) * I;
+    }
+    for (int kk = 0; kk < 4; ++kk) {
+        if (fabs(r - kinks[kk]) <= ORC_KINK_REL * smax) {
+            double wl[3], wr[3];
+            orc_weight(dim, kinks[kk] - 1e-9 * smax, R, p->dR, wl);
+            orc_weight(dim, kinks[kk] + 1e-9 * smax, R, p->dR, wr);
+            sm->slBR += fabs((wr[2] - wl[2]) * I);
+            for (int i = 0; i < dim; ++i) sm->slBc[i] += fabs((wr[1] - wl[1]) * I * u[i]);
+            sm->n_kink += 1;
+        }
+    }
+}
+
+/* Exact sums (flags bit 1): every lattice point k with |k h - c| < R + dR/2, the point set of
+ * Eq. (5), with I(k) = J(k) (clamp-to-edge outside the volume). Multiplied by the voxel measure
+ * they are the terms of the exact discrete energy's gradient (the lattice held fixed). */
+static void accumulate_lattice(const orc_vol *vol, const double c[3], double R, orc_sums *sm)
+{
+    const orc_params *p = vol->p;
+    int dim = p->dim;
+    double smax = R + 0.5 * p->dR;
+    double rho = rho_of(dim);
+    double a = rho * R, dr = rho * p->dR;
+    double kinks[4] = {a - 0.5 * dr, a + 0.5 * dr, R - 0.5 * p->dR, R + 0.5 * p->dR};
+    memset(sm, 0, sizeof(*sm));
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int i = 0; i < dim; ++i) {
+        lo[i] = (int64_t)ceil((c[i] - smax) / p->spacing[i]);
+        hi[i] = (int64_t)floor((c[i] + smax) / p->spacing[i]);
+    }
+    int count = 0;
+    for (int64_t kz = lo[2]; kz <= hi[2]; ++kz)
+        for (int64_t ky = lo[1]; ky <= hi[1]; ++ky)
+            for (int64_t kx = lo[0]; kx <= hi[0]; ++kx) {
+                double d[3] = {kx * p->spacing[0] - c[0], ky * p->spacing[1] - c[1],
+                               dim == 3 ? kz * p->spacing[2] - c[2] : 0.0};
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (!(r < smax)) continue;
+                double u[3] = {0.0, 0.0, 0.0};
+                if (r > 0.0)
+                    for (int i = 0; i < dim; ++i) u[i] = d[i] / r;
+                double I = vol->J[(clampi(kz, 0, vol->nz - 1) * vol->ny + clampi(ky, 0, vol->ny - 1)) * vol->nx +
+                                  clampi(kx, 0, vol->nx - 1)];
+                add_point(p, r, u, I, R, kinks, smax, sm);
+                ++count;
+            }
+    sm->n_samples = count;
+}
+
+static double voxel_measure(const orc_params *p)
+{
+    return p->spacing[0] * p->spacing[1] * (p->dim == 3 ? p->spacing[2] : 1.0);
+}
+
+/* Sums of one contour-iteration and their scale: exact lattice sums times the voxel measure, or
+ * Monte-Carlo sums times V/N. */
+static double contour_sums(const orc_vol *vol, const double c[3], double R, uint32_t n, uint32_t id, orc_sums *sm,
+                           double *pts, double *vals)
+{
+    const orc_params *p = vol->p;
+    if (p->flags & ORC_FLAG_EXACT) {
+        accumulate_lattice(vol, c, R, sm);
+        return voxel_measure(p);
+    }
+    accumulate_samples(vol, c, R, n, id, sm, pts, vals);
+    double smax = R + 0.5 * p->dR;
+    return ball_measure(p->dim) * pow(smax, p->dim) / (double)sm->n_samples;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* One gradient-descent iteration of one contour (Eqs. (7)-(15)).                               */
 /* ------------------------------------------------------------------------------------------ */
@@ -406,10 +500,7 @@ static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *ite
     uint32_t n = (uint32_t)(*iter + 1);
     *iter = (int32_t)n;
     orc_sums sm;
-    accumulate_samples(vol, c, Rc, n, id, &sm, NULL, NULL);
-    double smax = Rc + 0.5 * p->dR;
-    double V = ball_measure(dim) * pow(smax, dim);
-    double scale = V / (double)sm.n_samples;
+    double scale = contour_sums(vol, c, Rc, n, id, &sm, NULL, NULL);
     double twoR_d = pow(2.0 * Rc, dim);
     double eps = p->eps0 / sqrt((double)n);
 
@@ -536,7 +627,8 @@ int64_t orc_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, const or
     return mism;
 }
 
-/* Monte-Carlo terms of one contour at (c, R) for iteration n without updating it.
+/* Terms of one contour at (c, R) for iteration n without updating it (Monte-Carlo, or exact lattice
+ * sums when flags bit 1 is set; pts / vals are filled by the Monte-Carlo form only).
  * out: [A, B_R, Bc_x, Bc_y, Bc_z, scale=V/N, dE/dp (3), dE/dq (3), E, g_R, g_c (3)] (17 values).
  * pts (N x 3) / vals (N) receive the sample positions and interpolated values if non-NULL. */
 void orc_mc_terms(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
@@ -545,10 +637,8 @@ void orc_mc_terms(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc
 {
     orc_vol vol = {J, nx, ny, nz, p, dirs};
     orc_sums sm;
-    accumulate_samples(&vol, c, R, n, id, &sm, pts, vals);
+    double scale = contour_sums(&vol, c, R, n, id, &sm, pts, vals);
     int dim = p->dim;
-    double smax = R + 0.5 * p->dR;
-    double scale = ball_measure(dim) * pow(smax, dim) / (double)sm.n_samples;
     double twoR_d = pow(2.0 * R, dim);
     double A = scale * sm.A;
     out[0] = A;

@@ -121,6 +121,7 @@ snk_status check_params(snk_ctx *c, const snk_params &p) {
     if (!(p.conv_tol >= 0.0) || p.conv_window < 0 || p.conv_window > 255)
         return fail(c, SNK_EINVAL, "conv_tol >= 0 and 0 <= conv_window <= 255 required");
     if (!isfinite(p.e0)) return fail(c, SNK_EINVAL, "e0 not finite");
+    if (p.flags & ~(snk::kFlagNoRotation | snk::kFlagExact)) return fail(c, SNK_EINVAL, "unknown flag bits");
     return SNK_OK;
 }
 
@@ -305,14 +306,17 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
     a.n_iter = n_iter;
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
-    const int lanes = pick_lanes(c);
+    const bool exact = (c->P.flags & snk::kFlagExact) != 0;
+    const int lanes = exact ? (c->lanes > 0 ? c->lanes : 256) : pick_lanes(c);
     if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M) > 65536)
         return fail(c, SNK_EINVAL, "n_rays too large for the evolve kernel's LDS (64 KiB per workgroup)");
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     // two pair-points in flight pay off once a contour spans whole waves
     const int unroll = c->unroll > 0 ? c->unroll : (lanes >= 64 ? 2 : 1);
-    HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, c->layout, trace, c->stream));
+    // exact sums read single voxels from J (the plain layout)
+    const int layout = exact && c->layout == snk::kBufferQuad ? snk::kBufferPlain : c->layout;
+    HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
     c->ev_evo = true;
     c->evolve_launches += 1;

@@ -695,6 +695,8 @@ snk_status snk_engine_submit(snk_engine *e, const snk_params *p, const float *di
         P.n_rays / 2 > 768 || !(P.eps0 >= 0.0) || !(P.sigma_pre >= 0.0) || P.conv_window < 0 || P.conv_window > 255)
         return efail(e, SNK_EINVAL, "invalid parameters");
     if (D <= 0 || D != P.n_dirs || (int64_t)D * P.dim > 12288) return efail(e, SNK_EINVAL, "direction table size");
+    if (P.flags & ~snk::kFlagNoRotation)
+        return efail(e, SNK_EINVAL, "engine jobs evolve by Monte-Carlo sums (exact lattice sums: snk_evolve)");
     if (e->dim != 0 && P.dim != e->dim) return efail(e, SNK_EINVAL, "all jobs of an engine must have the same dim");
     if (nx < 2 || ny < 2 || nz < 1 || (P.dim == 3 && nz < 2) || (P.dim == 2 && nz != 1))
         return efail(e, SNK_EINVAL, "volume shape");

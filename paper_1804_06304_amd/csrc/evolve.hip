@@ -304,6 +304,14 @@ struct Vol {
                                                      (int)kBufferWord3);
         }
     }
+    // One voxel value (plain layouts).
+    __device__ __forceinline__ float load1(long idx) const {
+        if constexpr (LAYOUT == kBufferPlain) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)idx * 4, 0, 0));
+        } else {
+            return J[idx];
+        }
+    }
     // Loads the corners of the cell whose lower corner has linear voxel index `idx` (< 2^31 for
     // the buffer layouts).
     __device__ __forceinline__ void load(long idx, Corners<DIM> &c) const {
@@ -506,6 +514,88 @@ __device__ __forceinline__ void lane_sums(const Vol<DIM, LAYOUT> &vol, const Fra
     }
 }
 
+// Exact sums of one lane (flags bit 1): the lattice points of the box around the ball of radius
+// s_max, those inside the ball counted (the point set of Eq. (5)), I = J at the voxel itself
+// (clamp-to-edge outside the volume when CLAMP). Box points q = gl, gl + G, ..., x fastest; P
+// points are evaluated per pass with their loads issued first.
+template <int DIM, int G, bool CLAMP, int LAYOUT>
+__device__ __forceinline__ void lattice_sums(const Vol<DIM, LAYOUT> &vol, const Frame<DIM> &fr, const float hh[3],
+                                             const float inv_h[3], int gl, float acc[2 + DIM]) {
+    constexpr int P = 4;
+    int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float e = fr.smax * inv_h[a];
+        lo[a] = (int)ceilf(fr.off[a] - e);
+        cnt[a] = (int)floorf(fr.off[a] + e) - lo[a] + 1;
+    }
+    const int total = cnt[0] * cnt[1] * cnt[2];
+    int x = gl % cnt[0], y = (gl / cnt[0]) % cnt[1], z = gl / (cnt[0] * cnt[1]);
+    const int sx = G % cnt[0], sy = G / cnt[0];
+    const float smax2 = fr.smax * fr.smax;
+    for (int q0 = gl; q0 < total; q0 += G * P) {
+        float I[P], d[P][3], r2[P];
+        bool in[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int j[3] = {lo[0] + x, lo[1] + y, lo[2] + z};
+            x += sx;
+            if (x >= cnt[0]) {
+                x -= cnt[0];
+                y += 1;
+            }
+            y += sy;
+            while (y >= cnt[1]) {
+                y -= cnt[1];
+                z += 1;
+            }
+            r2[k] = 0.0f;
+            d[k][0] = d[k][1] = d[k][2] = 0.0f;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                d[k][a] = ((float)j[a] - fr.off[a]) * hh[a];
+                r2[k] = fmaf(d[k][a], d[k][a], r2[k]);
+            }
+            in[k] = q0 + k * G < total && r2[k] < smax2;
+            long idx;
+            if constexpr (CLAMP) {
+                idx = 0;
+                const long stride[3] = {1, vol.nx, vol.nxy};
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) idx += (long)min(max(fr.anc[a] + j[a], 0), vol.n[a] - 1) * stride[a];
+            } else if constexpr (LAYOUT != kGlobalPlain) {
+                int rel = __mul24(j[1], vol.nx) + j[0];
+                if constexpr (DIM == 3) rel += __mul24(j[2], vol.nxy);
+                idx = fr.base + rel;
+            } else {
+                long rel = (long)j[1] * vol.nx + j[0];
+                if constexpr (DIM == 3) rel += (long)j[2] * vol.nxy;
+                idx = fr.base + rel;
+            }
+            I[k] = in[k] ? vol.load1(idx) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (!in[k]) continue;
+            const float r = __builtin_amdgcn_sqrtf(r2[k]);
+            const float inv_r = r > 0.0f ? __builtin_amdgcn_rcpf(r) : 0.0f;
+            const float d1 = r - fr.ain, d2 = r - fr.R;
+            const bool r1 = d1 >= -fr.hd && d1 < fr.hd;   // inner ramp
+            const bool ro = d2 >= -fr.hD && d2 < fr.hD;   // outer ramp
+            const float sin_ = __builtin_amdgcn_fmed3f(d1 * fr.is, -1.0f, 1.0f);
+            const float sout = __builtin_amdgcn_fmed3f(fmaf(-d2, fr.os, 0.5f), 0.0f, 1.0f);
+            const float S = fminf(sin_, sout);
+            const float cC = r1 ? fr.is : (ro ? -fr.os : 0.0f);
+            const float cR = r1 ? -fr.rho_is : -cC;
+            acc[0] = fmaf(S, I[k], acc[0]);
+            acc[1] = fmaf(cR, I[k], acc[1]);
+            const float g = cC * I[k] * inv_r;   // dS/dr I / r; u = d / r
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) acc[2 + a] = fmaf(-g, d[k][a] * inv_h[a], acc[2 + a]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Per-contour iteration loop
 // ---------------------------------------------------------------------------------------------
@@ -539,7 +629,7 @@ __device__ __forceinline__ int uni(int v) {
 // Run up to n_iter iterations of the group's contour (slot == nullptr: no contour), stopping early at
 // iteration `target` or when it leaves SNK_ACTIVE. All lanes of the workgroup call this; the loop
 // and its barriers are workgroup-uniform.
-template <int DIM, int G, int U, bool TRACE, int LAYOUT>
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false>
 __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int target, float *trace_row,
                           float *lds_draws, float *lds_red, unsigned long long *counter) {
     constexpr int NR = 2 + DIM;
@@ -567,9 +657,9 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
     const float inv_h[3] = {p.g.inv_h[0], p.g.inv_h[1], p.g.inv_h[2]};
     const float hh[3] = {p.g.h[0], p.g.h[1], p.g.h[2]};
 
-    if (budget > 0) draws_phase1<DIM, G>(dr, 0, (uint32_t)(n0 + 1), id, p, gl);
+    if (!EXACT && budget > 0) draws_phase1<DIM, G>(dr, 0, (uint32_t)(n0 + 1), id, p, gl);
     __syncthreads();
-    if (budget > 0) draws_phase2<DIM, G>(dr, 0, p, gl);
+    if (!EXACT && budget > 0) draws_phase2<DIM, G>(dr, 0, p, gl);
     __syncthreads();
 
     // lane's first pair-point and its step
@@ -602,8 +692,9 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
         bool interior = true;
         if (active) {
             const int blk = it / dr.K, sl = it - blk * dr.K;
-            if (sl == 0) draws_phase1<DIM, G>(dr, (blk + 1) & 1, (uint32_t)(n0 + 1 + (blk + 1) * dr.K), id, p, gl);
-            if (sl == 1) draws_phase2<DIM, G>(dr, (blk + 1) & 1, p, gl);
+            if (!EXACT && sl == 0)
+                draws_phase1<DIM, G>(dr, (blk + 1) & 1, (uint32_t)(n0 + 1 + (blk + 1) * dr.K), id, p, gl);
+            if (!EXACT && sl == 1) draws_phase2<DIM, G>(dr, (blk + 1) & 1, p, gl);
 
             fr.smax = uni<G>(R + 0.5f * p.dR);
             fr.ain = uni<G>(RHO * R);
@@ -630,11 +721,18 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                            (off[a] + ext < (float)(vol.n[a] - 1 - anc[a]));
             }
             fr.base = base;
-            const float4 *pu = dr.pu + dr.slot(blk & 1, sl) * MH;
-            if (interior)
-                lane_sums<DIM, G, U, false, LAYOUT>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
-            else
-                lane_sums<DIM, G, U, true, LAYOUT>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+            if constexpr (EXACT) {
+                if (interior)
+                    lattice_sums<DIM, G, false, LAYOUT>(vol, fr, hh, inv_h, gl, acc);
+                else
+                    lattice_sums<DIM, G, true, LAYOUT>(vol, fr, hh, inv_h, gl, acc);
+            } else {
+                const float4 *pu = dr.pu + dr.slot(blk & 1, sl) * MH;
+                if (interior)
+                    lane_sums<DIM, G, U, false, LAYOUT>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                else
+                    lane_sums<DIM, G, U, true, LAYOUT>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+            }
         }
 
         // group totals
@@ -670,7 +768,8 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             float smax_d = smax;
 #pragma unroll
             for (int i = 1; i < DIM; ++i) smax_d *= smax;
-            const float scale = BALL * smax_d * inv_npts;
+            // Monte-Carlo: V/N; exact: the voxel measure
+            const float scale = EXACT ? hh[0] * hh[1] * (DIM == 3 ? hh[2] : 1.0f) : BALL * smax_d * inv_npts;
             const float A = scale * tot[0];
             const float BR = scale * tot[1];
             const float inv2R = __builtin_amdgcn_rcpf(2.0f * R);
@@ -805,7 +904,7 @@ __host__ __device__ __forceinline__ int lds_floats(int MH) {
 
 // Whole-wave groups with one pair-point in flight fit 64 vector registers: ask for 8 waves per SIMD
 // (a full CU of 4-wave groups holds 8 contours).
-template <int DIM, int G, int U, bool TRACE, int LAYOUT>
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT>
 __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolve_kernel(EvolveArgs a) {
     extern __shared__ float lds[];
     const int MH = a.p.M / 2;
@@ -813,9 +912,9 @@ __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolv
     const int sub = G < 64 ? (int)threadIdx.x / G : 0;
     const int cid = blockIdx.x * Grp<G>::CPB + sub;
     DevContour *slot = cid < a.n ? a.st + cid : nullptr;
-    run_group<DIM, G, U, TRACE, LAYOUT>(a.p, slot, a.n_iter, 0x7fffffff,
-                                        TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
-                                        lds + sub * per, lds + Grp<G>::CPB * per, a.counter);
+    run_group<DIM, G, U, TRACE, LAYOUT, EXACT>(a.p, slot, a.n_iter, 0x7fffffff,
+                                               TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
+                                               lds + sub * per, lds + Grp<G>::CPB * per, a.counter);
 }
 
 // Batched launch over (job, contour) items, one workgroup (G >= 64 lanes) per item. PERSISTENT: a
@@ -852,12 +951,30 @@ __global__ __launch_bounds__(G, U == 1 ? 8 : 1) void evolve_batch_kernel(BatchAr
 // Host launchers
 // ---------------------------------------------------------------------------------------------
 
-template <int DIM, int G, int U, bool TRACE, int LAYOUT>
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false>
 hipError_t launch_t(const EvolveArgs &a, hipStream_t s) {
     const size_t lds = sizeof(float) * (size_t)lds_floats<DIM, G>(a.p.M / 2);
     const int blocks = (a.n + Grp<G>::CPB - 1) / Grp<G>::CPB;
-    hipLaunchKernelGGL((evolve_kernel<DIM, G, U, TRACE, LAYOUT>), dim3(blocks), dim3(Grp<G>::NT), lds, s, a);
+    hipLaunchKernelGGL((evolve_kernel<DIM, G, U, TRACE, LAYOUT, EXACT>), dim3(blocks), dim3(Grp<G>::NT), lds, s, a);
     return hipGetLastError();
+}
+
+// Exact lattice sums read single voxels: plain layouts only.
+template <int DIM, int G, bool TRACE>
+hipError_t launch_exact_l(const EvolveArgs &a, int layout, hipStream_t s) {
+    return layout == kGlobalPlain ? launch_t<DIM, G, 1, TRACE, kGlobalPlain, true>(a, s)
+                                  : launch_t<DIM, G, 1, TRACE, kBufferPlain, true>(a, s);
+}
+
+template <int DIM, bool TRACE>
+hipError_t launch_exact_g(const EvolveArgs &a, int lanes, int layout, hipStream_t s) {
+    switch (lanes) {
+        case 16: return launch_exact_l<DIM, 16, TRACE>(a, layout, s);
+        case 32: return launch_exact_l<DIM, 32, TRACE>(a, layout, s);
+        case 64: return launch_exact_l<DIM, 64, TRACE>(a, layout, s);
+        case 128: return launch_exact_l<DIM, 128, TRACE>(a, layout, s);
+        default: return launch_exact_l<DIM, 256, TRACE>(a, layout, s);
+    }
 }
 
 template <int DIM, int G, int U, bool TRACE>
@@ -954,6 +1071,11 @@ int max_blocks_g(int lanes, int unroll, int layout, int max_M) {
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, int layout, bool trace,
                          hipStream_t s) {
     if (a.n <= 0 || a.n_iter <= 0) return hipSuccess;
+    if (a.p.flags & kFlagExact) {
+        if (layout == kBufferQuad) return hipErrorInvalidValue;
+        if (dim == 2) return trace ? launch_exact_g<2, true>(a, lanes, layout, s) : launch_exact_g<2, false>(a, lanes, layout, s);
+        return trace ? launch_exact_g<3, true>(a, lanes, layout, s) : launch_exact_g<3, false>(a, lanes, layout, s);
+    }
     if (dim == 2)
         return trace ? launch_g<2, true>(a, lanes, unroll, layout, s) : launch_g<2, false>(a, lanes, unroll, layout, s);
     return trace ? launch_g<3, true>(a, lanes, unroll, layout, s) : launch_g<3, false>(a, lanes, unroll, layout, s);

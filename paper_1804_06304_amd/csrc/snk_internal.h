@@ -46,6 +46,10 @@ struct JobParams {
     float in_slope, out_slope;   // 2 / (rho dR) and 1 / dR
 };
 
+// snk_params.flags bits.
+constexpr int kFlagNoRotation = 1;  // random rotation off (Q = I)
+constexpr int kFlagExact = 2;       // exact lattice sums over the ball instead of Monte-Carlo samples
+
 // How the evolve kernels read the smoothed volume.
 enum VolumeLayout {
     kGlobalPlain = 0,  // FP32 [z][y][x], 64-bit addressing (any size)

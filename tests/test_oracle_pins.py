@@ -250,6 +250,50 @@ def _smooth_volume(shape, seed=11, sigma=2.0, scale=3.0):
     return gaussian_filter(rng.normal(size=shape), sigma, mode="nearest") * scale + 0.5
 
 
+@pytest.mark.parametrize("dim,spacing", [(3, (1.0, 1.0, 1.0)), (3, (1.0, 1.0, 2.0)), (2, (1.0, 1.0, 1.0))])
+def test_exact_sums_are_gradient_of_exact_energy(orc, dim, spacing):
+    """Exact mode (flags bit 1): the lattice sums give E equal to the exact Eq. (5) energy, and
+    g_R, g_c equal its central differences in R and c (the lattice held fixed); p,q form too. Points
+    crossing a kink of S within the difference step are detected by one-sided differences and
+    skipped (at most a few of the cases)."""
+    if dim == 3:
+        J = _smooth_volume((24, 26, 28))
+        dirs = synth.icosphere(2)
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, spacing=spacing, flags=2)
+    else:
+        J = _smooth_volume((1, 40, 44))
+        dirs = synth.circle_directions(64)
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16, flags=2)
+    rng = np.random.default_rng(11)
+    h = 1e-6
+    smooth = 0
+    for trial in range(12):
+        c = np.array([rng.uniform(9, 15), rng.uniform(9, 15), rng.uniform(9, 13) if dim == 3 else 0.0])
+        R = rng.uniform(4.5, 7.5)
+        t = orc.mc_terms(J, p, dirs, c, R, 1 + trial, 3)
+        t2 = orc.mc_terms(J, p, dirs, c, R, 99, 77)   # no random numbers: n and id do not matter
+        assert t["g_R"] == t2["g_R"] and np.array_equal(t["g_c"], t2["g_c"])
+        E = lambda cc, RR: orc.energy_vox(J, p, np.array([cc]), np.array([RR]))[0][0]
+        assert abs(E(c, R) - t["E"]) < 1e-12 * max(1.0, abs(t["E"]))
+        e0 = E(c, R)
+        cases = [((c, R + h), (c, R - h), t["g_R"])]
+        for a in range(dim):
+            e = np.zeros(3)
+            e[a] = h
+            cases.append(((c + e, R), (c - e, R), t["g_c"][a]))
+        ex = np.array([h / 2, 0.0, 0.0])
+        cases.append(((c + ex, R - h / 2), (c - ex, R + h / 2), t["dEdp"][0]))   # p_x alone
+        cases.append(((c + ex, R + h / 2), (c - ex, R - h / 2), t["dEdq"][0]))   # q_x alone
+        for plus, minus, g in cases:
+            ep, em = E(*plus), E(*minus)
+            fwd, bwd = (ep - e0) / h, (e0 - em) / h
+            if abs(fwd - bwd) > 1e-4 * (abs(g) + 1e-3):
+                continue   # a lattice point crossed a kink of S within +-h
+            smooth += 1
+            assert abs((ep - em) / (2 * h) - g) < 1e-5 * (abs(g) + 1e-3), (trial, g, (ep - em) / (2 * h))
+    assert smooth >= 0.9 * 12 * (3 + dim)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_gradient_matches_finite_differences(orc, dim):
     if dim == 3:
