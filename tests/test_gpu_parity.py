@@ -125,8 +125,10 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, 
         # the state after the step matches too
         gs = ctx.get_state()
         assert np.all(gs["iters"][a] == ref.iters[a])
-        assert np.max(np.abs(gs["radii"][a] - ref.R[a])) < 1e-4
-        assert np.max(np.linalg.norm(gs["centers"][a] - ref.c[a], axis=1)) < 1e-4
+        # a sample on the other side of a kink moves the state by up to the step's slack
+        assert np.all(np.abs(gs["radii"][a] - ref.R[a]) < 1e-4 + tr[a, 24])
+        slack_c = np.linalg.norm(tr[a, 25:25 + d], axis=1)
+        assert np.all(np.linalg.norm(gs["centers"][a] - ref.c[a], axis=1) < 1e-4 + slack_c)
     ctx.close()
     say(f"  worst err/tol: " + ", ".join(f"{k} {v:.3f}" for k, v in worst.items()) +
         f"; contour-steps with a near-kink sample: {kinked}/{steps}")
@@ -395,3 +397,21 @@ def test_full_size_slab_sampled(snk, stream):
     assert np.array_equal(got["iters"], st.iters)
     assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
     assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+
+
+def test_full_size_plane_sampled(snk, stream):
+    """The 2D workload at full size (8192^2 u8, 40,000 cells, D 64, M 16) in the benchmark's launch
+    configuration: one-step parity of every contour from the seeds and after 20 iterations, and a
+    20-iteration free run of all contours."""
+    wl = synth.plane_config()
+    say(f"full-size plane: {wl.name}")
+    worst = one_step_parity(snk, stream, wl, [0, 20], n_extra=0)
+    assert worst
+    got = free_run(snk, stream, wl, chunks=[20])
+    J = oracle.prepass(wl.raw, wl.params)
+    st = oracle.init_state(wl.params, wl.seeds, ids=wl.ids, shape_zyx=wl.raw.shape)
+    oracle.evolve(J, wl.params, wl.dirs, st, 20)
+    same = got["iters"] == st.iters
+    assert same.mean() >= 0.999
+    assert np.max(np.abs(got["radii"] - st.R)[same]) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[same]) <= 0.5
