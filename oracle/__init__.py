@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "snk_oracle.c")
 _LIB = os.path.join(_HERE, "libsnk_oracle.so")
 
 TRACE_W = 32
-ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CLAMPED = 0, 1, 2, 3, 4, 0x10
+ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CULLED, CLAMPED = 0, 1, 2, 3, 4, 5, 0x10
 
 
 def build(force: bool = True) -> str:
@@ -76,6 +76,10 @@ def lib():
         L.orc_cull_ambiguity.argtypes = [P(_Params), i64, vp, vp, vp, d, d, vp]
         L.orc_cull_ambiguity.restype = i64
         L.orc_num_threads.restype = C.c_int
+        L.orc_lattice_seeds.argtypes = [P(_Params), i64, i64, i64, d, vp, i64]
+        L.orc_lattice_seeds.restype = i64
+        L.orc_cull_pass.argtypes = [vp, i64, i64, i64, P(_Params), i64, vp, vp, vp, vp, vp, i32, vp]
+        L.orc_cull_pass.restype = i64
         _lib = L
     return _lib
 
@@ -289,6 +293,42 @@ def cull_ambiguity(p, c, R, e_vox, rel_e=1e-4, tol_d=1e-3):
                              _ptr(np.ascontiguousarray(e_vox, dtype=np.float64)), float(rel_e), float(tol_d),
                              _ptr(amb))
     return amb
+
+
+def lattice_seeds(p, shape_zyx, pitch=None):
+    """Centres (n x 3, physical) of the initial lattice: pitch sqrt(1.5) * r_init unless given."""
+    nz, ny, nx = shape_zyx
+    pitch = float(np.sqrt(1.5) * p.r_init if pitch is None else pitch)
+    ps = params_struct(p)
+    n = lib().orc_lattice_seeds(C.byref(ps), nx, ny, nz, pitch, None, 0)
+    out = np.zeros((n, 3))
+    lib().orc_lattice_seeds(C.byref(ps), nx, ny, nz, pitch, _ptr(out), n)
+    return out
+
+
+def cull_pass(J, p, st: State, grace: int):
+    """One culling pass at the current state (in place); returns (E_vox of the live contours,
+    number retired)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    ps = params_struct(p)
+    e = np.zeros(len(st.R))
+    k = lib().orc_cull_pass(_ptr(J), nx, ny, nz, C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.iters),
+                            _ptr(st.status), _ptr(st.ids), int(grace), _ptr(e))
+    return e, int(k)
+
+
+def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int):
+    """Evolution in chunks of `every` iterations with a culling pass after each chunk; returns the
+    number of contour-iterations run."""
+    done, total = 0, 0
+    while done < n_iter:
+        k = min(every, n_iter - done)
+        _, ran = evolve(J, p, dirs, st, k)
+        total += ran
+        done += k
+        cull_pass(J, p, st, grace)
+    return total
 
 
 def run(raw, p, dirs, seeds, n_iter, r0=None, ids=None):

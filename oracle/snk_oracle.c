@@ -49,6 +49,7 @@
 #define ORC_MAXITER 2
 #define ORC_OUT 3
 #define ORC_NONFINITE 4
+#define ORC_CULLED 5       /* retired by a culling pass during evolution */
 #define ORC_CLAMPED 0x10
 
 #define ORC_TRACE_W 32
@@ -791,6 +792,96 @@ int64_t orc_cull_ambiguity(const orc_params *p, int64_t n, const double *c, cons
     }
     for (int64_t i = 0; i < n; ++i) cnt += amb[i];
     return cnt;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Unattended workflow: a lattice of initial contours (Sec. II-A / II-B figures: neighbours      */
+/* sqrt(1.5) R apart) and culling passes during evolution (the dynamic culling the Conclusion    */
+/* proposes).                                                                                   */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Centres of a cubic (square in 2D) lattice of pitch `pitch` (physical units) centred in the
+ * volume: k_a = max(1, floor(extent_a / pitch)) points per axis, extent_a = (n_a - 1) h_a, the first
+ * one at (extent_a - (k_a - 1) pitch) / 2. x fastest. Writes up to cap centres (n x 3) and returns
+ * the count. */
+int64_t orc_lattice_seeds(const orc_params *p, int64_t nx, int64_t ny, int64_t nz, double pitch, double *out,
+                          int64_t cap)
+{
+    int dim = p->dim;
+    int64_t nn[3] = {nx, ny, nz}, k[3] = {1, 1, 1};
+    double o[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a) {
+        double ext = (double)(nn[a] - 1) * p->spacing[a];
+        k[a] = (int64_t)floor(ext / pitch);
+        if (k[a] < 1) k[a] = 1;
+        o[a] = 0.5 * (ext - (double)(k[a] - 1) * pitch);
+    }
+    int64_t total = k[0] * k[1] * k[2], m = 0;
+    for (int64_t iz = 0; iz < k[2]; ++iz)
+        for (int64_t iy = 0; iy < k[1]; ++iy)
+            for (int64_t ix = 0; ix < k[0]; ++ix) {
+                if (m < cap) {
+                    out[m * 3 + 0] = o[0] + (double)ix * pitch;
+                    out[m * 3 + 1] = o[1] + (double)iy * pitch;
+                    out[m * 3 + 2] = dim == 3 ? o[2] + (double)iz * pitch : 0.0;
+                }
+                ++m;
+            }
+    return total;
+}
+
+/* One culling pass at the current state: the exact energy E_vox of every live contour (ACTIVE or
+ * CONVERGED); candidates are the live contours with a finite energy that either are younger than
+ * `grace` iterations or have E_vox <= E0; overlapping candidates compete as in the final selection
+ * (sequential greedy in ascending (E_vox, id)) and the losers are retired, as are the live contours
+ * that are not candidates. Retired contours keep their state with status CULLED (clamp flag kept).
+ * e_vox (n) receives the energies (NaN for contours that were not live). Returns the number
+ * retired. */
+int64_t orc_cull_pass(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p, int64_t n,
+                      const double *c, const double *R, const int32_t *iters, uint8_t *status,
+                      const uint32_t *ids, int32_t grace, double *e_vox)
+{
+    int dim = p->dim;
+    double rho = rho_of(dim);
+    orc_energy_vox(J, nx, ny, nz, p, n, c, R, e_vox, NULL);
+    orc_key *keys = (orc_key *)malloc(sizeof(orc_key) * (n > 0 ? n : 1));
+    int64_t nc = 0, retired = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int st = status[i] & 0x0f;
+        if (st != ORC_ACTIVE && st != ORC_CONVERGED) {
+            e_vox[i] = NAN;
+            continue;
+        }
+        if (isfinite(e_vox[i]) && (iters[i] < grace || e_vox[i] <= p->e0)) {
+            keys[nc].e = e_vox[i]; keys[nc].id = ids[i]; keys[nc].idx = i; ++nc;
+        } else {
+            status[i] = (uint8_t)((status[i] & ORC_CLAMPED) | ORC_CULLED);
+            ++retired;
+        }
+    }
+    qsort(keys, (size_t)nc, sizeof(orc_key), key_cmp);
+    int64_t *acc = (int64_t *)malloc(sizeof(int64_t) * (nc > 0 ? nc : 1));
+    int64_t na = 0;
+    for (int64_t t = 0; t < nc; ++t) {
+        int64_t i = keys[t].idx;
+        int ok = 1;
+        for (int64_t u = 0; u < na && ok; ++u) {
+            int64_t j = acc[u];
+            double d2 = 0.0;
+            for (int a = 0; a < dim; ++a) d2 += (c[i * 3 + a] - c[j * 3 + a]) * (c[i * 3 + a] - c[j * 3 + a]);
+            double rm = R[i] > R[j] ? R[i] : R[j];
+            if (sqrt(d2) < rho * rm) ok = 0;
+        }
+        if (ok) {
+            acc[na++] = i;
+        } else {
+            status[i] = (uint8_t)((status[i] & ORC_CLAMPED) | ORC_CULLED);
+            ++retired;
+        }
+    }
+    free(acc);
+    free(keys);
+    return retired;
 }
 
 int orc_num_threads(void)

@@ -604,3 +604,68 @@ def test_cull_threshold_order_irrelevant(orc):
             if e[i] <= p.e0:
                 want[i] = 1
         assert np.array_equal(keep, want)
+
+
+def test_lattice_seeds(orc):
+    """Initial lattice (figures of Sec. II-A / II-B): neighbours sqrt(1.5) R0 apart along each axis,
+    centred in the volume, every centre inside."""
+    p = synth.Params(dim=3, spacing=(1.0, 1.0, 2.0), r_init=6.0)
+    shape = (23, 61, 50)   # z, y, x
+    pts = orc.lattice_seeds(p, shape)
+    pitch = np.sqrt(1.5) * 6.0
+    ext = (np.array([50, 61, 23]) - 1) * np.array([1.0, 1.0, 2.0])
+    k = np.maximum(1, np.floor(ext / pitch)).astype(int)
+    assert len(pts) == k.prod()
+    for a in range(3):
+        u = np.unique(np.round(pts[:, a], 9))
+        assert len(u) == k[a]
+        assert np.allclose(np.diff(u), pitch)
+        assert abs((u[0] + u[-1]) / 2 - ext[a] / 2) < 1e-9     # centred
+        assert u[0] >= 0 and u[-1] <= ext[a]
+    p2 = synth.Params(dim=2, r_init=5.0)
+    pts2 = orc.lattice_seeds(p2, (1, 30, 40))
+    assert np.all(pts2[:, 2] == 0.0) and len(pts2) == int(29 // np.sqrt(37.5)) * int(39 // np.sqrt(37.5))
+
+
+def _greedy_cull(c, R, e, live, iters, ids, grace, e0, dim):
+    """Brute-force reference of one culling pass: which live contours survive."""
+    rho = 2.0 ** (-1.0 / dim)
+    cand = [i for i in range(len(R)) if live[i] and np.isfinite(e[i]) and (iters[i] < grace or e[i] <= e0)]
+    cand.sort(key=lambda i: (e[i], ids[i]))
+    acc = []
+    for i in cand:
+        if all(np.linalg.norm(c[i, :dim] - c[j, :dim]) >= rho * max(R[i], R[j]) for j in acc):
+            acc.append(i)
+    return set(acc)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cull_pass_matches_brute_force(orc, seed):
+    """A culling pass retires exactly the live contours that lose the greedy competition or are
+    past the grace period above E0; other statuses are untouched and keep their clamp flag."""
+    rng = np.random.default_rng(seed)
+    J = _smooth_volume((20, 32, 34))
+    p = synth.Params(dim=3, dR=1.0, e0=-0.01)
+    n = 120
+    c = np.column_stack([rng.uniform(2, 31, n), rng.uniform(2, 29, n), rng.uniform(2, 17, n)])
+    R = rng.uniform(4.4, 8.0, n)
+    status = rng.choice([orc.ACTIVE, orc.CONVERGED, orc.MAXITER, orc.OUT], size=n, p=[0.5, 0.3, 0.1, 0.1])
+    status = status.astype(np.uint8) | np.where(rng.random(n) < 0.2, orc.CLAMPED, 0).astype(np.uint8)
+    iters = rng.integers(0, 60, n).astype(np.int32)
+    ids = rng.permutation(n).astype(np.uint32)
+    st = orc.State(c=c.copy(), R=R.copy(), iters=iters.copy(), status=status.copy(),
+                   streak=np.zeros(n, np.uint8), e_mc=np.zeros(n), ids=ids)
+    e, k = orc.cull_pass(J, p, st, grace=30)
+    e_ref, _ = orc.energy_vox(J, p, c, R)
+    live = np.isin(status & 0x0F, [orc.ACTIVE, orc.CONVERGED])
+    assert np.allclose(e[live], e_ref[live], rtol=0, atol=0)
+    keep = _greedy_cull(c, R, e_ref, live, iters, ids, 30, p.e0, 3)
+    for i in range(n):
+        if not live[i]:
+            assert st.status[i] == status[i]
+        elif i in keep:
+            assert st.status[i] == status[i]
+        else:
+            assert st.status[i] == (status[i] & orc.CLAMPED) | orc.CULLED
+    assert k == int(live.sum()) - len(keep)
+    assert 0 < k < int(live.sum())
