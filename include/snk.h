@@ -53,6 +53,7 @@ typedef enum { SNK_U8 = 0, SNK_U16 = 1, SNK_F32 = 2 } snk_dtype;
 #define SNK_MAXITER 2      /* stopped on the iteration limit (set by snk_finalize)          */
 #define SNK_OUT 3          /* centre left the volume                                        */
 #define SNK_NONFINITE 4    /* state became NaN/Inf                                          */
+#define SNK_CULLED 5       /* retired by a culling pass during evolution (snk_evolve_cull)  */
 #define SNK_CLAMPED 0x10
 
 /* Parameters of one run. Physical units are x-voxel units.
@@ -164,6 +165,26 @@ snk_status snk_evolve(snk_ctx *ctx, int32_t n_iter);
  * MAXITER with E_vox <= e0, and overlapping candidates (|c' - c''| < rho*max(R', R'')) compete,
  * the lower (E_vox, id) surviving -- identical to sequential greedy in ascending order. */
 snk_status snk_finalize(snk_ctx *ctx);
+
+/* Unattended workflow (the initial configuration of Sec. II-A / II-B: contours placed on a lattice,
+ * neighbours sqrt(1.5) R apart; culling while evolving, the remedy the Conclusion proposes for the
+ * work spent on contours that are culled at the end).
+ *
+ * snk_seed_lattice replaces the seeds with the centres of a cubic (2D: square) lattice of pitch
+ * `pitch` (physical units; <= 0: sqrt(1.5) * params.r_init) centred in the volume: per axis
+ * k = max(1, floor((n - 1) h / pitch)) points, the first at ((n - 1) h - (k - 1) pitch) / 2, x fastest.
+ * Radii params.r_init, ids 0..n-1. *n_out (may be NULL) receives the contour count. */
+snk_status snk_seed_lattice(snk_ctx *ctx, double pitch, int64_t *n_out);
+
+/* snk_evolve with a culling pass after every `cull_every` (> 0) iterations and after the last one.
+ * A pass ranks the live contours (ACTIVE or CONVERGED) by the Monte-Carlo energy of their last
+ * iteration (e_mc of snk_read; the exact energy is left to snk_finalize): candidates are the live
+ * contours with a finite energy that are younger than `grace_iters` iterations or have
+ * e_mc <= params.e0; overlapping candidates compete as in snk_finalize (the lower (e_mc, id)
+ * survives); the losers and the live non-candidates become SNK_CULLED (clamp flag kept) and stop.
+ * n_iter = 0 runs one culling pass. Timing (snk_get_timing): evolve_ms covers the evolve launches
+ * and the passes; evolved counts every contour-iteration of the call. */
+snk_status snk_evolve_cull(snk_ctx *ctx, int32_t n_iter, int32_t cull_every, int32_t grace_iters);
 
 /* Read back (synchronises). Any output pointer may be NULL. radii, e_mc (last Monte-Carlo
  * energy), e_vox (exact energy, valid after snk_finalize), iters, status, keep (1 = detected

@@ -78,7 +78,7 @@ def lib():
         L.orc_num_threads.restype = C.c_int
         L.orc_lattice_seeds.argtypes = [P(_Params), i64, i64, i64, d, vp, i64]
         L.orc_lattice_seeds.restype = i64
-        L.orc_cull_pass.argtypes = [vp, i64, i64, i64, P(_Params), i64, vp, vp, vp, vp, vp, i32, vp]
+        L.orc_cull_pass.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, vp, i32]
         L.orc_cull_pass.restype = i64
         _lib = L
     return _lib
@@ -306,16 +306,12 @@ def lattice_seeds(p, shape_zyx, pitch=None):
     return out
 
 
-def cull_pass(J, p, st: State, grace: int):
-    """One culling pass at the current state (in place); returns (E_vox of the live contours,
-    number retired)."""
-    J = np.ascontiguousarray(J, dtype=np.float64)
-    nz, ny, nx = J.shape
+def cull_pass(p, st: State, grace: int) -> int:
+    """One culling pass at the current state (in place, ranking by E_mc); returns the number
+    retired."""
     ps = params_struct(p)
-    e = np.zeros(len(st.R))
-    k = lib().orc_cull_pass(_ptr(J), nx, ny, nz, C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.iters),
-                            _ptr(st.status), _ptr(st.ids), int(grace), _ptr(e))
-    return e, int(k)
+    return int(lib().orc_cull_pass(C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.iters), _ptr(st.e_mc),
+                                   _ptr(st.status), _ptr(st.ids), int(grace)))
 
 
 def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int):
@@ -327,7 +323,7 @@ def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int):
         _, ran = evolve(J, p, dirs, st, k)
         total += ran
         done += k
-        cull_pass(J, p, st, grace)
+        cull_pass(p, st, grace)
     return total
 
 

@@ -830,30 +830,25 @@ int64_t orc_lattice_seeds(const orc_params *p, int64_t nx, int64_t ny, int64_t n
     return total;
 }
 
-/* One culling pass at the current state: the exact energy E_vox of every live contour (ACTIVE or
- * CONVERGED); candidates are the live contours with a finite energy that either are younger than
- * `grace` iterations or have E_vox <= E0; overlapping candidates compete as in the final selection
- * (sequential greedy in ascending (E_vox, id)) and the losers are retired, as are the live contours
+/* One culling pass at the current state, ranking live contours (ACTIVE or CONVERGED) by the
+ * Monte-Carlo energy of their last iteration (the exact energy stays with the final selection):
+ * candidates are the live contours with a finite energy that either are younger than `grace`
+ * iterations or have E_mc <= E0; overlapping candidates compete as in the final selection
+ * (sequential greedy in ascending (E_mc, id)) and the losers are retired, as are the live contours
  * that are not candidates. Retired contours keep their state with status CULLED (clamp flag kept).
- * e_vox (n) receives the energies (NaN for contours that were not live). Returns the number
- * retired. */
-int64_t orc_cull_pass(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p, int64_t n,
-                      const double *c, const double *R, const int32_t *iters, uint8_t *status,
-                      const uint32_t *ids, int32_t grace, double *e_vox)
+ * Returns the number retired. */
+int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const double *R, const int32_t *iters,
+                      const double *e_mc, uint8_t *status, const uint32_t *ids, int32_t grace)
 {
     int dim = p->dim;
     double rho = rho_of(dim);
-    orc_energy_vox(J, nx, ny, nz, p, n, c, R, e_vox, NULL);
     orc_key *keys = (orc_key *)malloc(sizeof(orc_key) * (n > 0 ? n : 1));
     int64_t nc = 0, retired = 0;
     for (int64_t i = 0; i < n; ++i) {
         int st = status[i] & 0x0f;
-        if (st != ORC_ACTIVE && st != ORC_CONVERGED) {
-            e_vox[i] = NAN;
-            continue;
-        }
-        if (isfinite(e_vox[i]) && (iters[i] < grace || e_vox[i] <= p->e0)) {
-            keys[nc].e = e_vox[i]; keys[nc].id = ids[i]; keys[nc].idx = i; ++nc;
+        if (st != ORC_ACTIVE && st != ORC_CONVERGED) continue;
+        if (isfinite(e_mc[i]) && (iters[i] < grace || e_mc[i] <= p->e0)) {
+            keys[nc].e = e_mc[i]; keys[nc].id = ids[i]; keys[nc].idx = i; ++nc;
         } else {
             status[i] = (uint8_t)((status[i] & ORC_CLAMPED) | ORC_CULLED);
             ++retired;

@@ -291,7 +291,9 @@ snk_status ensure_layout(snk_ctx *c) {
     return SNK_OK;
 }
 
-snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
+// standalone: zero the contour-iteration counter and record the evolve events around the launch
+// (off for the chunks of snk_evolve_cull, which brackets the whole call).
+snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = true) {
     if (c->D != c->P.n_dirs) return fail(c, SNK_ESTATE, "direction table size != params.n_dirs");
     if (c->J_dirty) {
         snk_status st = run_prepass(c);
@@ -310,15 +312,19 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace) {
     const int lanes = exact ? (c->lanes > 0 ? c->lanes : 256) : pick_lanes(c);
     if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M) > 65536)
         return fail(c, SNK_EINVAL, "n_rays too large for the evolve kernel's LDS (64 KiB per workgroup)");
-    HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
-    HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
+    if (standalone) {
+        HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
+        HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
+    }
     // two pair-points in flight pay off once a contour spans whole waves
     const int unroll = c->unroll > 0 ? c->unroll : (lanes >= 64 ? 2 : 1);
     // exact sums read single voxels from J (the plain layout)
     const int layout = exact && c->layout == snk::kBufferQuad ? snk::kBufferPlain : c->layout;
     HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
-    HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
-    c->ev_evo = true;
+    if (standalone) {
+        HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
+        c->ev_evo = true;
+    }
     c->evolve_launches += 1;
     return SNK_OK;
 }
@@ -334,6 +340,51 @@ snk_status unpack(snk_ctx *c, std::vector<DevContour> &h) {
 void centre_of(const snk_ctx *c, const DevContour &s, double *out) {
     for (int i = 0; i < 3; ++i)
         out[i] = i < c->P.dim ? ((double)s.anc[i] + (double)s.off[i]) * c->P.spacing[i] : 0.0;
+}
+
+// Exact energies and the final selection (mode 0), or a culling pass (mode 1) over every contour.
+snk_status run_select(snk_ctx *c, int mode, int grace) {
+    snk_status st = SNK_OK;
+    snk::JobDev a{};
+    a.p = job_params(c);
+    a.st = c->d_st;
+    a.e_vox = c->d_evox;
+    a.n = (int)c->n;
+    a.target = 0;
+    a.e0 = (float)c->P.e0;
+    int G3[3];
+    double cell = 0.0;
+    const int64_t G = snk_grid_for(c->P, c->nx, c->ny, c->nz, G3, &cell);
+    for (int i = 0; i < 3; ++i) a.G[i] = G3[i];
+    a.cell = (float)cell;
+    st = ensure(c, &c->d_cell_start, &c->grid_cap, (size_t)G + 1);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_cell_fill, &c->grid_fill_cap, (size_t)G + 1);
+    if (st != SNK_OK) return st;
+    if (c->sel_cap < (size_t)c->n) {
+        for (int **p : {&c->d_items, &c->d_cell_of, &c->d_dec}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        size_t k1 = 0, k2 = 0, k3 = 0;
+        if ((st = ensure(c, &c->d_items, &k1, (size_t)c->n)) != SNK_OK) return st;
+        if ((st = ensure(c, &c->d_cell_of, &k2, (size_t)c->n)) != SNK_OK) return st;
+        if ((st = ensure(c, &c->d_dec, &k3, (size_t)c->n)) != SNK_OK) return st;
+        c->sel_cap = (size_t)c->n;
+    }
+    a.cell_start = c->d_cell_start;
+    a.cell_fill = c->d_cell_fill;
+    a.items = c->d_items;
+    a.cell_of = c->d_cell_of;
+    a.dec = c->d_dec;
+    a.kept = c->d_counters + 1;
+    HIPTRY(c, hipMemsetAsync(c->d_counters + 1, 0, sizeof(unsigned long long), c->stream));
+    a.mode = mode;
+    a.grace = grace;
+    // a culling pass ranks by the Monte-Carlo energy the last iteration left in the state
+    if (mode == 0) HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, true, c->stream));
+    HIPTRY(c, snk::launch_select(a, c->P.dim, reinterpret_cast<int *>(c->d_counters + 2), c->stream));
+    return SNK_OK;
 }
 
 }  // namespace
@@ -549,45 +600,70 @@ snk_status snk_finalize(snk_ctx *c) {
         st = run_prepass(c);
         if (st != SNK_OK) return st;
     }
-    snk::JobDev a{};
-    a.p = job_params(c);
-    a.st = c->d_st;
-    a.e_vox = c->d_evox;
-    a.n = (int)c->n;
-    a.target = 0;
-    a.e0 = (float)c->P.e0;
-    int G3[3];
-    double cell = 0.0;
-    const int64_t G = snk_grid_for(c->P, c->nx, c->ny, c->nz, G3, &cell);
-    for (int i = 0; i < 3; ++i) a.G[i] = G3[i];
-    a.cell = (float)cell;
-    st = ensure(c, &c->d_cell_start, &c->grid_cap, (size_t)G + 1);
-    if (st != SNK_OK) return st;
-    st = ensure(c, &c->d_cell_fill, &c->grid_fill_cap, (size_t)G + 1);
-    if (st != SNK_OK) return st;
-    if (c->sel_cap < (size_t)c->n) {
-        for (int **p : {&c->d_items, &c->d_cell_of, &c->d_dec}) {
-            if (*p) (void)hipFree(*p);
-            *p = nullptr;
-        }
-        size_t k1 = 0, k2 = 0, k3 = 0;
-        if ((st = ensure(c, &c->d_items, &k1, (size_t)c->n)) != SNK_OK) return st;
-        if ((st = ensure(c, &c->d_cell_of, &k2, (size_t)c->n)) != SNK_OK) return st;
-        if ((st = ensure(c, &c->d_dec, &k3, (size_t)c->n)) != SNK_OK) return st;
-        c->sel_cap = (size_t)c->n;
-    }
-    a.cell_start = c->d_cell_start;
-    a.cell_fill = c->d_cell_fill;
-    a.items = c->d_items;
-    a.cell_of = c->d_cell_of;
-    a.dec = c->d_dec;
-    a.kept = c->d_counters + 1;
-    HIPTRY(c, hipMemsetAsync(c->d_counters + 1, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
-    HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, c->stream));
-    HIPTRY(c, snk::launch_select(a, c->P.dim, reinterpret_cast<int *>(c->d_counters + 2), c->stream));
+    st = run_select(c, 0, 0);
+    if (st != SNK_OK) return st;
     HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
     c->ev_fin = true;
+    return SNK_OK;
+}
+
+snk_status snk_seed_lattice(snk_ctx *c, double pitch, int64_t *n_out) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    if (!(pitch > 0.0)) pitch = sqrt(1.5) * c->P.r_init;
+    if (!(pitch > 0.0) || !isfinite(pitch)) return fail(c, SNK_EINVAL, "lattice pitch must be > 0 (or r_init > 0)");
+    const int64_t nn[3] = {c->nx, c->ny, c->nz};
+    int64_t k[3] = {1, 1, 1};
+    double o[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < c->P.dim; ++a) {
+        const double ext = (double)(nn[a] - 1) * c->P.spacing[a];
+        k[a] = std::max<int64_t>(1, (int64_t)floor(ext / pitch));
+        o[a] = 0.5 * (ext - (double)(k[a] - 1) * pitch);
+    }
+    const int64_t n = k[0] * k[1] * k[2];
+    if (n >= ((int64_t)1 << 31)) return fail(c, SNK_EINVAL, "lattice too fine (>= 2^31 contours)");
+    std::vector<double> cen((size_t)n * 3);
+    int64_t m = 0;
+    for (int64_t iz = 0; iz < k[2]; ++iz)
+        for (int64_t iy = 0; iy < k[1]; ++iy)
+            for (int64_t ix = 0; ix < k[0]; ++ix, ++m) {
+                cen[m * 3 + 0] = o[0] + (double)ix * pitch;
+                cen[m * 3 + 1] = o[1] + (double)iy * pitch;
+                cen[m * 3 + 2] = c->P.dim == 3 ? o[2] + (double)iz * pitch : 0.0;
+            }
+    if (n_out) *n_out = n;
+    return snk_load_seeds(c, cen.data(), nullptr, nullptr, n);
+}
+
+snk_status snk_evolve_cull(snk_ctx *c, int32_t n_iter, int32_t cull_every, int32_t grace_iters) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (n_iter < 0 || grace_iters < 0 || (n_iter > 0 && cull_every <= 0))
+        return fail(c, SNK_EINVAL, "n_iter >= 0, cull_every > 0 and grace_iters >= 0 required");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    if (c->n == 0) return SNK_OK;
+    (void)hipSetDevice(c->device);
+    if (c->J_dirty) {
+        st = run_prepass(c);
+        if (st != SNK_OK) return st;
+    }
+    HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
+    HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
+    int32_t done = 0;
+    do {
+        const int32_t k = std::min(cull_every > 0 ? cull_every : 0, n_iter - done);
+        if (k > 0) {
+            st = run_evolve(c, k, false, false);
+            if (st != SNK_OK) return st;
+        }
+        st = run_select(c, 1, grace_iters);
+        if (st != SNK_OK) return st;
+        done += k;
+    } while (done < n_iter);
+    HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
+    c->ev_evo = true;
     return SNK_OK;
 }
 
@@ -645,7 +721,7 @@ snk_status snk_set_state(snk_ctx *c, const double *centers, const float *radii, 
     for (int64_t i = 0; i < n; ++i) {
         if (!(radii[i] > 0.0f) || !(radii[i] <= (float)c->P.r_max) || iters[i] < 0)
             return fail(c, SNK_EINVAL, "state radius outside (0, r_max] or negative iteration count");
-        if ((status[i] & 0x0f) > SNK_NONFINITE) return fail(c, SNK_EINVAL, "bad status value");
+        if ((status[i] & 0x0f) > SNK_CULLED) return fail(c, SNK_EINVAL, "bad status value");
         to_anchor(c, &centers[i * 3], h[i]);
         h[i].R = radii[i];
         h[i].iters = iters[i];

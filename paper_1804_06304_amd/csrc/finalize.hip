@@ -44,7 +44,7 @@ __device__ __forceinline__ float weight_S(float r, float R, float dR) {
 }
 
 template <int DIM>
-__device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) {
+__device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out, bool finalize = true) {
     constexpr int EV_T = ev_threads<DIM>();
     __shared__ double part[EV_T / 64];
     const int t = threadIdx.x;
@@ -54,7 +54,7 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) 
     if (!isfinite(R) || !(R > 0.0f) || !(R <= p.r_hi) || (s.status & 0x0f) == SNK_NONFINITE) {
         if (t == 0) {
             *e_out = NAN;
-            slot->e_vox = NAN;
+            if (finalize) slot->e_vox = NAN;
         }
         return;
     }
@@ -112,18 +112,20 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out) 
         for (int i = 0; i < DIM; ++i) norm *= 2.0 * (double)R;
         const double e = tot * meas / norm;
         *e_out = e;
-        DevContour o = s;
-        o.e_vox = (float)e;
-        if ((o.status & 0x0f) == SNK_ACTIVE) o.status = (uint8_t)((o.status & SNK_CLAMPED) | SNK_MAXITER);
-        *slot = o;
+        if (finalize) {
+            DevContour o = s;
+            o.e_vox = (float)e;
+            if ((o.status & 0x0f) == SNK_ACTIVE) o.status = (uint8_t)((o.status & SNK_CLAMPED) | SNK_MAXITER);
+            *slot = o;
+        }
     }
 }
 
 template <int DIM>
 __global__ __launch_bounds__(ev_threads<DIM>()) void energy_vox_kernel(JobParams p, DevContour *st, double *e_vox,
-                                                                      int n) {
+                                                                      int n, int finalize) {
     const int cid = blockIdx.x;
-    if (cid < n) energy_one<DIM>(p, st + cid, e_vox + cid);
+    if (cid < n) energy_one<DIM>(p, st + cid, e_vox + cid, finalize != 0);
 }
 
 template <int DIM>
@@ -152,6 +154,12 @@ __device__ __forceinline__ bool overlaps(const DevContour &x, const DevContour &
     return sqrtf(d2) < thr;
 }
 
+// Energy that ranks contour i: E_vox for the final selection, the last Monte-Carlo energy for a
+// culling pass during evolution.
+__device__ __forceinline__ double rank_energy(const JobDev &a, int i, const DevContour &s) {
+    return a.mode == 0 ? a.e_vox[i] : (double)s.e_mc;
+}
+
 // One decision step for contour i (no-op unless undecided): reject if an overlapping neighbour is
 // accepted, accept if it has the smallest (E_vox, id) among its undecided overlapping neighbours.
 // Decisions of other contours may change concurrently; every decision taken is final and
@@ -163,7 +171,7 @@ __device__ int decide(const JobDev &a, int i) {
     if (dec[i] != DEC_UNDECIDED) return dec[i];
     const Geometry &g = a.p.g;
     const DevContour si = a.st[i];
-    const double ei = a.e_vox[i];
+    const double ei = rank_energy(a, i, si);
     const int cell = a.cell_of[i];
     const int gi[3] = {cell % a.G[0], (cell / a.G[0]) % a.G[1], cell / (a.G[0] * a.G[1])};
     bool accepted_nb = false, minimal = true;
@@ -184,7 +192,7 @@ __device__ int decide(const JobDev &a, int i) {
                         accepted_nb = true;
                         break;
                     }
-                    const double ej = a.e_vox[j];
+                    const double ej = rank_energy(a, j, sj);
                     if (ej < ei || (ej == ei && sj.id < si.id)) minimal = false;
                 }
             }
@@ -199,8 +207,12 @@ __device__ __forceinline__ void bin_one(const JobDev &a, int i) {
     const Geometry &g = a.p.g;
     const DevContour s = a.st[i];
     const int st = s.status & 0x0f;
-    const double e = a.e_vox[i];
-    const bool cand = (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0;
+    const double e = rank_energy(a, i, s);
+    // final selection: stopped contours at or below E0; culling pass: live contours below E0 or
+    // still within their grace period
+    const bool cand = a.mode == 0 ? (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0
+                                  : (st == SNK_ACTIVE || st == SNK_CONVERGED) && isfinite(e) &&
+                                        (s.iters < a.grace || e <= (double)a.e0);
     a.dec[i] = cand ? DEC_UNDECIDED : DEC_NONE;
     int cell = -1;
     if (cand) {
@@ -276,13 +288,25 @@ __device__ void select_job(const JobDev &a, bool binned) {
         __threadfence_block();
         any = __syncthreads_or(local) != 0;
     }
-    unsigned long long kept = 0;
-    for (int i = t; i < n; i += SEL_T) {
-        const uint8_t k = dec[i] == DEC_ACCEPT ? 1 : 0;
-        a.st[i].keep = k;
-        kept += k;
+    unsigned long long count = 0;
+    if (a.mode == 0) {
+        for (int i = t; i < n; i += SEL_T) {
+            const uint8_t k = dec[i] == DEC_ACCEPT ? 1 : 0;
+            a.st[i].keep = k;
+            count += k;
+        }
+    } else {
+        // culling pass: live contours that lost or are no candidates stop
+        for (int i = t; i < n; i += SEL_T) {
+            const uint8_t s8 = a.st[i].status;
+            const int st = s8 & 0x0f;
+            if ((st == SNK_ACTIVE || st == SNK_CONVERGED) && dec[i] != DEC_ACCEPT) {
+                a.st[i].status = (uint8_t)((s8 & SNK_CLAMPED) | SNK_CULLED);
+                count += 1;
+            }
+        }
     }
-    if (kept) atomicAdd(a.kept, kept);
+    if (count) atomicAdd(a.kept, count);
 }
 
 template <int DIM>
@@ -352,10 +376,12 @@ hipError_t select_grid(const JobDev &j, int *rounds, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, hipStream_t s) {
+hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, bool finalize,
+                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(n), dim3(ev_threads<2>()), 0, s, p, st, e_vox, n);
-    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(n), dim3(ev_threads<3>()), 0, s, p, st, e_vox, n);
+    const int f = finalize ? 1 : 0;
+    if (dim == 2) hipLaunchKernelGGL(energy_vox_kernel<2>, dim3(n), dim3(ev_threads<2>()), 0, s, p, st, e_vox, n, f);
+    else hipLaunchKernelGGL(energy_vox_kernel<3>, dim3(n), dim3(ev_threads<3>()), 0, s, p, st, e_vox, n, f);
     return hipGetLastError();
 }
 

@@ -92,7 +92,9 @@ struct JobDev {
     int *cell_start, *cell_fill, *items, *cell_of, *dec;   // selection scratch
     int G[3];
     float cell;
-    unsigned long long *kept;
+    unsigned long long *kept;    // final selection: contours kept; culling pass: contours retired
+    int mode;                    // 0: final selection, 1: culling pass during evolution
+    int grace;                   // culling pass: iterations before E_vox > e0 retires a contour
 };
 
 struct BatchArgs {
@@ -138,7 +140,10 @@ hipError_t launch_reset_items(const JobDev *jobs, const int2 *items, int n_items
                               hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_count_unfinished(const JobDev *jobs, const int2 *items, int n_items, int *unfinished, hipStream_t s);
-hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, hipStream_t s);
+// finalize: contours still ACTIVE become MAXITER and E_vox is stored in the state (else only in
+// e_vox).
+hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, bool finalize,
+                             hipStream_t s);
 // rounds: 3 ints of device scratch for the grid-wide rounds (null: one workgroup does everything).
 hipError_t launch_select(const JobDev &j, int dim, int *rounds, hipStream_t s);
 hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s);

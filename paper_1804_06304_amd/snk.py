@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(HERE, "libsnk.so")
 
 SNK_OK, SNK_EINVAL, SNK_ENOMEM, SNK_EDEVICE, SNK_ESTATE, SNK_EBUSY, SNK_ERANGE = 0, -1, -2, -3, -4, -5, -6
 SNK_U8, SNK_U16, SNK_F32 = 0, 1, 2
-ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CLAMPED = 0, 1, 2, 3, 4, 0x10
+ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CULLED, CLAMPED = 0, 1, 2, 3, 4, 5, 0x10
 TRACE_W = 16
 
 EXPORTS = [
     "snk_create", "snk_destroy", "snk_set_params", "snk_set_launch", "snk_set_directions",
     "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
-    "snk_sync", "snk_last_error", "snk_version",
+    "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull",
     "snk_engine_create", "snk_engine_destroy", "snk_engine_last_error", "snk_engine_set_launch",
     "snk_engine_submit", "snk_engine_run", "snk_engine_step", "snk_engine_poll", "snk_engine_read",
     "snk_engine_job_times", "snk_engine_release", "snk_engine_get_stats",
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
         "snk_prepass": [vp],
         "snk_load_seeds": [vp, vp, vp, vp, i64],
         "snk_evolve": [vp, i32],
+        "snk_seed_lattice": [vp, C.c_double, C.POINTER(i64)],
+        "snk_evolve_cull": [vp, i32, i32, i32],
         "snk_finalize": [vp],
         "snk_read": [vp, vp, vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64)],
         "snk_get_state": [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64)],
@@ -219,6 +221,17 @@ def snk_load_seeds(h, centers, r0=None, ids=None) -> None:
 
 def snk_evolve(h, n_iter: int) -> None:
     _check(h, load().snk_evolve(h, int(n_iter)))
+
+
+def snk_seed_lattice(h, pitch: float = 0.0) -> int:
+    """Seeds on the initial lattice (pitch <= 0: sqrt(1.5) * r_init); returns the contour count."""
+    n = C.c_int64(0)
+    _check(h, load().snk_seed_lattice(h, float(pitch), C.byref(n)))
+    return int(n.value)
+
+
+def snk_evolve_cull(h, n_iter: int, cull_every: int, grace_iters: int) -> None:
+    _check(h, load().snk_evolve_cull(h, int(n_iter), int(cull_every), int(grace_iters)))
 
 
 def snk_finalize(h) -> None:

@@ -1,0 +1,140 @@
+"""GPU parity of the unattended workflow: the initial contour lattice and culling passes during
+evolution (snk_seed_lattice, snk_evolve_cull), against the oracle's lattice and culling passes.
+
+Bars: lattice centres within FP32 rounding of the oracle's; one culling pass from identical
+(teacher-forced) states retires the same contours as the oracle apart from decisions the oracle
+flags as within 1e-4 (energy) or 1e-3 voxel (overlap) of a threshold; a free run with culling
+agrees on >= 95% of the final statuses, and where status and iteration count agree, radii within
+0.05 and centres within 0.5 voxel; with nothing to cull, culled evolution is bit-identical to plain
+evolution.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def snk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1804_06304_amd import snk as mod
+    mod.load()
+    return mod
+
+
+def make_ctx(snk, wl):
+    import torch
+    ctx = snk.Context(0, torch.cuda.current_stream())
+    ctx.set_params(wl.params)
+    ctx.set_directions(wl.dirs)
+    ctx.load_volume(wl.raw)
+    return ctx
+
+
+@pytest.mark.parametrize("which", ["tiny", "aniso", "plane"])
+def test_lattice_matches_oracle(snk, which):
+    if which == "tiny":
+        wl = synth.tiny_config()
+    elif which == "aniso":
+        wl = synth.slab_config(n_target=60, shape_xyz=(100, 77, 23), n_iter=10)
+    else:
+        wl = synth.plane_config(n_target=120, size=256, n_iter=50)
+    ctx = make_ctx(snk, wl)
+    n = ctx.seed_lattice()
+    ref = oracle.lattice_seeds(wl.params, wl.raw.shape)
+    say(f"lattice {which}: {n} contours")
+    assert n == len(ref)
+    got = ctx.get_state()
+    assert np.max(np.abs(got["centers"] - ref)) < 1e-4
+    assert np.all(got["iters"] == 0) and np.all(got["status"] == oracle.ACTIVE)
+    ctx.close()
+
+
+def _oracle_lattice_state(wl, J, n_iter):
+    seeds = oracle.lattice_seeds(wl.params, wl.raw.shape)
+    st = oracle.init_state(wl.params, seeds, ids=np.arange(len(seeds), dtype=np.uint32), shape_zyx=wl.raw.shape)
+    if n_iter:
+        oracle.evolve(J, wl.params, wl.dirs, st, n_iter)
+    return st
+
+
+@pytest.mark.parametrize("which,n_iter,grace", [("tiny", 30, 20), ("tiny", 12, 5), ("plane", 20, 10)])
+def test_cull_pass_parity(snk, which, n_iter, grace):
+    """From the oracle's state (rounded to FP32) both sides run one iteration, which leaves E_mc
+    in the state, then one culling pass."""
+    wl = synth.tiny_config() if which == "tiny" else synth.plane_config(n_target=200, size=320, n_iter=60)
+    J = oracle.prepass(wl.raw, wl.params)
+    st = _oracle_lattice_state(wl, J, n_iter)
+    st.c[:] = st.c.astype(np.float32).astype(np.float64)
+    st.R[:] = st.R.astype(np.float32).astype(np.float64)
+    ctx = make_ctx(snk, wl)
+    ctx.seed_lattice()
+    ctx.set_state(st.c, st.R.astype(np.float32), st.iters, st.status, st.streak)
+    ctx.evolve_cull(1, 1, grace)
+    got = ctx.get_state()
+    ctx.close()
+    oracle.evolve(J, wl.params, wl.dirs, st, 1)
+    before = st.status.copy()
+    k = oracle.cull_pass(wl.params, st, grace)
+    live = np.isin(before & 0x0F, [oracle.ACTIVE, oracle.CONVERGED])
+    amb = np.zeros(len(st.R), bool)
+    li = np.where(live)[0]
+    amb[li] = oracle.cull_ambiguity(wl.params, st.c[li], st.R[li], st.e_mc[li]) != 0
+    diff = got["status"] != st.status
+    retired_gpu = int(((got["status"] & 0x0F) == oracle.CULLED).sum() - ((before & 0x0F) == oracle.CULLED).sum())
+    say(f"cull pass {which} after {n_iter} + 1: {int(live.sum())} live, oracle retired {k}, GPU retired "
+        f"{retired_gpu}, ambiguous {int(amb.sum())}, differing {int(diff.sum())}")
+    assert k > 0
+    assert not np.any(diff & ~amb), np.where(diff & ~amb)[0][:10]
+
+
+def test_cull_free_run(snk):
+    wl = synth.tiny_config()
+    ctx = make_ctx(snk, wl)
+    ctx.seed_lattice()
+    ctx.evolve_cull(wl.n_iter, 20, 40)
+    got = ctx.get_state()
+    t = ctx.get_timing()
+    ctx.close()
+    J = oracle.prepass(wl.raw, wl.params)
+    st = _oracle_lattice_state(wl, J, 0)
+    ran = oracle.evolve_cull(J, wl.params, wl.dirs, st, wl.n_iter, 20, 40)
+    same = got["status"] == st.status
+    say(f"culled free run: {len(st.R)} contours, {int((st.status & 0x0F == oracle.CULLED).sum())} culled "
+        f"(oracle), status agreement {same.mean():.3f}, contour-iterations GPU {t['evolved']} oracle {ran}")
+    assert same.mean() >= 0.95
+    both = same & (got["iters"] == st.iters)
+    assert np.max(np.abs(got["radii"] - st.R)[both]) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[both]) <= 0.5
+    assert abs(t["evolved"] - ran) <= 0.05 * ran
+
+
+def test_cull_without_losers_equals_plain_evolve(snk):
+    """Separated seeds and E0 above every energy: no pass retires anything, and the chunked,
+    culled evolution is bit-identical to one plain evolve."""
+    wl = synth.tiny_config()
+    wl.params = wl.params.replace(e0=1e9)
+    a = make_ctx(snk, wl)
+    a.load_seeds(wl.seeds, ids=wl.ids)
+    a.evolve_cull(wl.n_iter, 25, 0)
+    ga = a.get_state()
+    a.close()
+    b = make_ctx(snk, wl)
+    b.load_seeds(wl.seeds, ids=wl.ids)
+    b.evolve(wl.n_iter)
+    gb = b.get_state()
+    b.close()
+    assert not np.any((ga["status"] & 0x0F) == oracle.CULLED)
+    for k in ("centers", "radii", "iters", "status", "streak"):
+        assert np.array_equal(ga[k], gb[k]), k
