@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per contour: 16..256 (0: automatic)")
     ap.add_argument("--unroll", type=int, default=0, help="pair-points in flight per lane (0: automatic)")
     ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="LDS box per contour in voxels (-1: automatic, 0: off)")
     ap.add_argument("--exact", action="store_true",
                     help="exact lattice sums instead of Monte-Carlo samples (params flags bit 1); reports "
                          "contour-iterations/s next to the Monte-Carlo path's")
@@ -101,6 +103,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="only time the evolve kernel for every (lanes, pair-points in flight, layout) shape")
+    ap.add_argument("--sweep-prepass", action="store_true",
+                    help="sweeps: re-run the pre-pass before every timed evolve, as a bench step does")
+    ap.add_argument("--sweep-tile", action="store_true",
+                    help="only time the evolve kernel for whole-wave shapes x LDS box capacities, checking "
+                         "that every capacity reproduces the box-free result bit for bit")
     ap.add_argument("--workload", default="slab", choices=["slab", "plane", "batched", "served", "lattice"],
                     help="slab: the plain path on the slab volume (default); plane: the plain path on the "
                          "8192^2 2D image; batched: 256 uneven subvolumes through the engine vs the plain "
@@ -152,9 +159,35 @@ def main():
     ctx = snk.Context(0, stream)
     ctx.set_params(p)
     ctx.set_launch(args.lanes, args.unroll, args.layout)
+    ctx.set_tile(args.tile)
     ctx.set_directions(wl.dirs)
     ctx.load_volume(raw)
     torch.cuda.synchronize()
+
+    if args.sweep_tile:
+        layout = 2 if p.dim == 3 else 1
+        for g in (64, 128, 256):
+            for u in (1, 2):
+                ref = None
+                for cap in (0, -1, 2048, 3072, 3584, 4096, 4224, 6144):
+                    ctx.set_launch(g, u, layout)
+                    ctx.set_tile(cap)
+                    ms = []
+                    for _ in range(3):
+                        ctx.load_seeds(wl.seeds, ids=wl.ids)
+                        if args.sweep_prepass:
+                            ctx.prepass()
+                        ctx.evolve(wl.n_iter)
+                        ms.append(ctx.get_timing()["evolve_ms"])
+                    st = ctx.get_state()
+                    if ref is None:
+                        ref = st
+                    same = all(np.array_equal(st[k], ref[k]) for k in ref)
+                    cap = ctx.get_timing()["tile_voxels"] if cap < 0 else cap
+                    log(f"sweep-tile lanes={g} pairs_in_flight={u} tile={cap}: evolve {min(ms):.3f} ms "
+                        f"(min of 3; {[round(v, 3) for v in ms]}) bitwise={'yes' if same else 'NO'}")
+        ctx.close()
+        return
 
     if args.sweep:
         for layout in (2, 1):
@@ -164,6 +197,8 @@ def main():
                     ms = []
                     for _ in range(3):
                         ctx.load_seeds(wl.seeds, ids=wl.ids)
+                        if args.sweep_prepass:
+                            ctx.prepass()
                         ctx.evolve(wl.n_iter)
                         ms.append(ctx.get_timing()["evolve_ms"])
                     log(f"sweep layout={layout} lanes={g} pairs_in_flight={u}: evolve {min(ms):.3f} ms "
@@ -202,7 +237,8 @@ def main():
     achieved = per_launch_vu * bytes_per_vu / (ev_ms * 1e-3) / 1e9
     log(f"per step: prepass {np.mean(prepass_ms):.3f} ms, evolve {ev_ms:.3f} ms, finalize {np.mean(finalize_ms):.3f} ms,"
         f" wall {secs / args.steps * 1e3:.3f} ms; vertex-updates/step {per_launch_vu:.4g};"
-        f" kept {int(out['keep'].sum())}/{len(out['keep'])}")
+        f" kept {int(out['keep'].sum())}/{len(out['keep'])}; launch lanes {tm['lanes_per_contour']}"
+        f" pairs {tm['pairs_in_flight']} layout {tm['layout']} tile {tm['tile_voxels']}")
     line = {
         "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
@@ -212,12 +248,18 @@ def main():
                    "contours": len(wl.seeds),
                    "n_iter": wl.n_iter, "n_dirs": p.n_dirs, "n_rays": M, "n_radial": L,
                    "lanes_per_contour": args.lanes or "auto", "pairs_in_flight": args.unroll or "auto",
-                   "layout": {0: "auto", 1: "plain", 2: "quad"}[args.layout]},
+                   "layout": {0: "auto", 1: "plain", 2: "quad"}[args.layout],
+                   "tile_voxels": "auto" if args.tile < 0 else args.tile,
+                   "resolved_launch": {"lanes_per_contour": tm["lanes_per_contour"],
+                                       "pairs_in_flight": tm["pairs_in_flight"],
+                                       "layout": {0: "plain64", 1: "plain", 2: "quad"}[tm["layout"]],
+                                       "tile_voxels": tm["tile_voxels"]}},
         "kernels_ms": {"prepass": float(np.mean(prepass_ms)), "evolve": ev_ms,
                        "finalize": float(np.mean(finalize_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(wl.name, args.lanes == 0 and args.unroll == 0 and args.layout == 0),
+                     "traffic": measured_traffic(wl.name, args.lanes == 0 and args.unroll == 0 and args.layout == 0
+                                                 and args.tile < 0),
                      "kernel": f"evolve_kernel<{d},*,false>",
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }

@@ -132,6 +132,16 @@ snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
  * FP32 summation order. */
 snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs_in_flight, int32_t layout);
 
+/* LDS box of the Monte-Carlo evolution (whole-wave launch shapes, layouts 1 and 2): each contour
+ * keeps a box of the smoothed volume around its sample ball (Sec. II-E) in on-chip memory, staged
+ * with a margin and re-staged only when the ball leaves it, and reads the trilinear corners of its
+ * samples from there. tile_voxels = -1: automatic capacity, 0: off (every corner read from the
+ * volume), 1..16384: capacity in voxels (4 bytes each). An iteration whose ball does not fit, or
+ * reaches the volume's edge, reads the volume. Results are bit-identical with and without the box.
+ * SNK_EINVAL if tile_voxels is out of range, or at the next evolve if the box and the kernel's other
+ * LDS exceed 64 KiB per workgroup. */
+snk_status snk_set_tile(snk_ctx *ctx, int32_t tile_voxels);
+
 /* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288. D must
  * equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per
  * contour-iteration, carry the Monte-Carlo rays. */
@@ -219,6 +229,9 @@ typedef struct snk_timing {
     double finalize_ms;
     int64_t evolved;
     int64_t evolve_launches;
+    /* shape of the last evolve launch as resolved from snk_set_launch / snk_set_tile (the automatic
+     * shape depends on the contour count, so a contour's FP32 summation order can too) */
+    int32_t lanes_per_contour, pairs_in_flight, layout, tile_voxels;
 } snk_timing;
 snk_status snk_get_timing(snk_ctx *ctx, snk_timing *t);
 

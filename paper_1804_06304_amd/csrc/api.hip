@@ -23,6 +23,11 @@ struct snk_ctx {
     int lanes = 0;   // lanes per contour (0: automatic)
     int unroll = 0;  // pair-points in flight (0: automatic)
     int layout_req = 0;  // volume layout: 0 automatic, 1 plain, 2 quad
+    int tile_req = -1;   // LDS box per contour, voxels: -1 automatic, 0 off
+    int cus = 0;         // compute units of the device
+    int lds_per_cu = 0;  // LDS bytes per compute unit
+    int stage_key = -1, stage_blocks = 0;  // registers-limited workgroups per CU of the last staged shape
+    int last_lanes = 0, last_unroll = 0, last_layout = 0, last_tile = 0;  // last evolve launch
     int layout = snk::kGlobalPlain;  // layout of the current pre-pass output
 
     std::vector<float> dirs_host;
@@ -277,6 +282,50 @@ snk::JobParams job_params(const snk_ctx *c) {
     return p;
 }
 
+struct McShape {
+    int lanes, unroll, tile;
+};
+
+// Launch shape of a Monte-Carlo evolve over `layout`. Explicit knobs are taken as set. The automatic
+// LDS box applies when every contour can stay resident at once, ceil(n / CUs) workgroups per CU
+// (the common case of one volume with a few thousand cells): two waves per contour when a contour
+// has at least four pair-points per lane of them, else one (unless set), two pair-points in flight,
+// and the largest box whose LDS still leaves room for all of them. Otherwise no box and the lane
+// rule of pick_lanes.
+McShape mc_shape(snk_ctx *c, int M, int layout) {
+    McShape s;
+    s.lanes = pick_lanes(c);
+    s.unroll = c->unroll > 0 ? c->unroll : (s.lanes >= 64 ? 2 : 1);
+    s.tile = 0;
+    if (c->tile_req > 0) {
+        s.tile = c->tile_req;
+        return s;
+    }
+    if (c->tile_req == 0 || c->n <= 0 || c->cus <= 0 || c->lds_per_cu <= 0) return s;
+    if (layout != snk::kBufferQuad && layout != snk::kBufferPlain) return s;
+    const int64_t pairs = (int64_t)(M / 2) * c->P.n_radial;
+    const int G = c->lanes > 0 ? c->lanes : (pairs >= 512 ? 128 : (pairs >= 128 ? 64 : 0));
+    if (G < 64) return s;
+    const int U = c->unroll > 0 ? c->unroll : 2;
+    const int key = ((c->P.dim * 512 + G) * 4 + U) * 4 + layout;
+    if (key != c->stage_key) {
+        c->stage_blocks = snk::evolve_stage_blocks_per_cu(c->P.dim, G, U, layout);
+        c->stage_key = key;
+    }
+    const int64_t per_cu = (c->n + c->cus - 1) / c->cus;
+    if (per_cu > c->stage_blocks) return s;
+    const size_t other = snk::evolve_lds_bytes(c->P.dim, G, M, 0);
+    // LDS is handed out in 512-byte blocks
+    const size_t budget = std::min<size_t>((size_t)c->lds_per_cu / (size_t)per_cu, 65536) & ~(size_t)511;
+    if (budget <= other) return s;
+    const int tile = (int)std::min<size_t>((budget - other) / 4, 16384) & ~63;
+    if (tile < 1024) return s;
+    s.lanes = G;
+    s.unroll = U;
+    s.tile = tile;
+    return s;
+}
+
 // Re-packs the current J when the requested layout changed after the pre-pass.
 snk_status ensure_layout(snk_ctx *c) {
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
@@ -309,18 +358,34 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
     const bool exact = (c->P.flags & snk::kFlagExact) != 0;
-    const int lanes = exact ? (c->lanes > 0 ? c->lanes : 256) : pick_lanes(c);
-    if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M) > 65536)
+    // exact sums read single voxels from J (the plain layout)
+    const int layout = exact && c->layout == snk::kBufferQuad ? snk::kBufferPlain : c->layout;
+    int lanes, unroll;
+    if (exact) {
+        lanes = c->lanes > 0 ? c->lanes : 256;
+        unroll = 1;
+    } else {
+        const McShape sh = mc_shape(c, a.p.M, layout);
+        lanes = sh.lanes;
+        unroll = sh.unroll;
+        // LDS boxes: whole-wave groups over a buffer layout
+        if (sh.tile > 0 && (lanes < 64 || layout == snk::kGlobalPlain))
+            return fail(c, SNK_EINVAL, "LDS boxes need lanes_per_contour >= 64 and layout 1 or 2");
+        a.tile_cap = sh.tile;
+    }
+    if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M, 0) > 65536)
         return fail(c, SNK_EINVAL, "n_rays too large for the evolve kernel's LDS (64 KiB per workgroup)");
+    if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M, a.tile_cap) > 65536)
+        return fail(c, SNK_EINVAL, "LDS box too large (the evolve kernel's LDS is 64 KiB per workgroup)");
     if (standalone) {
         HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
         HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     }
-    // two pair-points in flight pay off once a contour spans whole waves
-    const int unroll = c->unroll > 0 ? c->unroll : (lanes >= 64 ? 2 : 1);
-    // exact sums read single voxels from J (the plain layout)
-    const int layout = exact && c->layout == snk::kBufferQuad ? snk::kBufferPlain : c->layout;
     HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
+    c->last_lanes = lanes;
+    c->last_unroll = exact ? 1 : unroll;
+    c->last_layout = layout;
+    c->last_tile = a.tile_cap;
     if (standalone) {
         HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
         c->ev_evo = true;
@@ -408,6 +473,10 @@ snk_status snk_create(snk_ctx **out, int device, void *hip_stream) {
     if (!c) return fail(nullptr, SNK_ENOMEM, "host allocation failed");
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) c->cus = 0;
+    if (hipDeviceGetAttribute(&c->lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) !=
+        hipSuccess)
+        c->lds_per_cu = 0;
     for (auto &ev : c->ev) {
         e = hipEventCreate(&ev);
         if (e != hipSuccess) {
@@ -462,6 +531,14 @@ snk_status snk_set_launch(snk_ctx *c, int32_t lanes_per_contour, int32_t pairs_i
     c->lanes = lanes_per_contour;
     c->unroll = pairs_in_flight;
     c->layout_req = layout;
+    return SNK_OK;
+}
+
+snk_status snk_set_tile(snk_ctx *c, int32_t tile_voxels) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (tile_voxels < -1 || tile_voxels > 16384)
+        return fail(c, SNK_EINVAL, "tile_voxels must be -1 (auto), 0 (off) or at most 16384");
+    c->tile_req = tile_voxels;
     return SNK_OK;
 }
 
@@ -773,6 +850,10 @@ snk_status snk_get_timing(snk_ctx *c, snk_timing *t) {
     HIPTRY(c, hipMemcpy(&cnt, c->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
     t->evolved = (int64_t)cnt;
     t->evolve_launches = c->evolve_launches;
+    t->lanes_per_contour = c->last_lanes;
+    t->pairs_in_flight = c->last_unroll;
+    t->layout = c->last_layout;
+    t->tile_voxels = c->last_tile;
     return SNK_OK;
 }
 

@@ -504,7 +504,7 @@ snk_status launch_classes(snk_engine *e, const ItemPlan &pl, int chunk, const st
         const ClassKey &k = pl.classes[c].first;
         const int b = pl.classes[c].second.first, end = pl.classes[c].second.second;
         const Launch &L = shapes[c];
-        if (snk::evolve_lds_bytes(k.dim, L.lanes, k.M) > 65536)
+        if (snk::evolve_lds_bytes(k.dim, L.lanes, k.M, 0) > 65536)
             return efail(e, SNK_EINVAL, "n_rays too large for this launch shape's LDS");
         snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk);
         EHIP(e, snk::launch_evolve_batch(a, k.dim, L.lanes, L.unroll, e->layout, L.persistent != 0, L.grid,
@@ -531,7 +531,7 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
             const int trial_iters = 6;
             float best_ms = 1e30f;
             for (int g : {64, 128, 256}) {
-                if (snk::evolve_lds_bytes(k.dim, g, k.M) > 65536) continue;
+                if (snk::evolve_lds_bytes(k.dim, g, k.M, 0) > 65536) continue;
                 for (int u : {1, 2}) {
                     for (int pers : {0, 1}) {
                         Launch T{g, u, pers, 1};

@@ -50,8 +50,10 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
                                          uint32_t k1, uint32_t out[4]) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -117,32 +119,43 @@ struct Grp {
     static constexpr int WAVES = NT / 64;
 };
 
-// Iterations per block of draws: one draw per lane of the group, at least two (the rotation of a
-// block is applied one iteration after its draws).
+// Iterations per block of draws. A block takes ceil(K (MH + 1) / G) rounds of one draw per lane;
+// K is the smallest block size (at least two: the rotation of a block is applied one iteration
+// after its draws) whose rounds per iteration come within 30% of the ideal (MH + 1) / G, else the
+// one with the fewest rounds per iteration.
 __host__ __device__ __forceinline__ int block_iters(int G, int MH) {
-    int K = G / (MH + 1);
-    return K < 2 ? 2 : (K > 16 ? 16 : K);
+    const int per = MH + 1;
+    int best = 2;
+    float best_cost = 1e30f;
+    for (int K = 2; K <= 16; ++K) {
+        const float cost = (float)((K * per + G - 1) / G) / (float)K;
+        if (cost * (float)G <= 1.3f * (float)per) return K;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = K;
+        }
+    }
+    return best;
 }
 
 // Floats of one contour's draw buffers (two blocks), a multiple of 4.
 __host__ __device__ __forceinline__ int draw_floats(int G, int MH) {
     const int K = block_iters(G, MH);
-    return 2 * K * (5 * MH + 12);
+    return 2 * K * (4 * MH + 12);
 }
 
 // One contour's draw buffers: for each of 2 blocks x K iterations,
-//   pu[m] = (u_x/h_x, u_y/h_y, u_z/h_z, xi) per pair m, rot = Q (9 floats, 12 reserved), kk[m] = k.
+//   pu[m] = (u_x/h_x, u_y/h_y, u_z/h_z, xi) per pair m (between the two phases pu[m].x holds the
+//   table row k), rot = Q (9 floats, 12 reserved).
 struct Draws {
     float4 *pu;
     float *rot;
-    int *kk;
     int K, MH;
     __device__ __forceinline__ Draws(float *base, int G, int MH_) {
         MH = MH_;
         K = block_iters(G, MH_);
         pu = reinterpret_cast<float4 *>(base);
         rot = base + 2 * K * 4 * MH;
-        kk = reinterpret_cast<int *>(rot + 2 * K * 12);
     }
     __device__ __forceinline__ int slot(int buf, int s) const { return buf * K + s; }
 };
@@ -161,7 +174,7 @@ __device__ __forceinline__ void divmod_small(int j, int d, float inv_d, int &q, 
 }
 
 // Phase 1 of block b: the Philox draws of its K iterations (n_first .. n_first + K - 1), one per
-// lane: pair draws -> kk, xi; rotation draws -> Q.
+// lane: pair draws -> table row k (parked in pu.x) and xi; rotation draws -> Q.
 template <int DIM, int G>
 __device__ __forceinline__ void draws_phase1(const Draws &d, int buf, uint32_t n_first, uint32_t id,
                                              const JobParams &p, int gl) {
@@ -176,7 +189,7 @@ __device__ __forceinline__ void draws_phase1(const Draws &d, int buf, uint32_t n
         philox10(pair ? (uint32_t)r : 0u, n_first + (uint32_t)s, id, pair ? 1u : 0u, p.key0, p.key1, x);
         const int sl = d.slot(buf, s);
         if (pair) {
-            d.kk[sl * d.MH + r] = (int)__umulhi(x[0], (uint32_t)p.D);
+            d.pu[sl * d.MH + r].x = __int_as_float((int)__umulhi(x[0], (uint32_t)p.D));
             d.pu[sl * d.MH + r].w = unit_open(x[1]);
         } else {
             float Q[9];
@@ -201,12 +214,12 @@ __device__ __forceinline__ void draws_phase2(const Draws &d, int buf, const JobP
         int s, m;
         divmod_small(j, d.MH, inv, s, m);
         const int sl = d.slot(buf, s);
-        const int k = d.kk[sl * d.MH + m];
+        float4 &o = d.pu[sl * d.MH + m];
+        const int k = __float_as_int(o.x);
         const float *Q = d.rot + sl * 12;
         float t[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int i = 0; i < DIM; ++i) t[i] = p.dirs[k * DIM + i];
-        float4 &o = d.pu[sl * d.MH + m];
         float u[3];
 #pragma unroll
         for (int i = 0; i < DIM; ++i) {
@@ -279,6 +292,7 @@ struct Corners {
 
 template <int DIM, int LAYOUT>
 struct Vol {
+    static constexpr bool kSmall = LAYOUT != kGlobalPlain;  // 24-bit index arithmetic
     const float *J;
     __amdgpu_buffer_rsrc_t rsrc;
     int n[3];
@@ -361,6 +375,30 @@ struct Vol {
                 c.v[6] = f.lo;
                 c.v[7] = f.hi;
             }
+        }
+    }
+};
+
+// Corner reads from a box of the smoothed volume staged in LDS (x fastest; nx = box row length,
+// nxy = box plane size). Indices are relative to the box, so they stay small.
+template <int DIM>
+struct TileVol {
+    static constexpr bool kSmall = true;
+    const float *t;
+    int n[3];
+    int nx, nxy;
+    __device__ __forceinline__ void load(long idx, Corners<DIM> &c) const {
+        const float *q = t + (int)idx;
+        c.v[0] = q[0];
+        c.v[1] = q[1];
+        c.v[2] = q[nx];
+        c.v[3] = q[nx + 1];
+        if constexpr (DIM == 3) {
+            const float *r = q + nxy;
+            c.v[4] = r[0];
+            c.v[5] = r[1];
+            c.v[6] = r[nx];
+            c.v[7] = r[nx + 1];
         }
     }
 };
@@ -451,8 +489,8 @@ __device__ __forceinline__ float cube_or_square_root(float tau) {
 
 // Sums of one lane for one iteration over pair-points q = gl, gl + G, ... < P (pair m = q / L,
 // radial index l = q % L), U pair-points in flight.
-template <int DIM, int G, int U, bool CLAMP, int LAYOUT>
-__device__ __forceinline__ void lane_sums(const Vol<DIM, LAYOUT> &vol, const Frame<DIM> &fr, const float4 *pu,
+template <int DIM, int G, int U, bool CLAMP, typename V>
+__device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, const float4 *pu,
                                           int P, int L, float invL, int gl, int l0, int m0, int dl, int dm,
                                           float acc[2 + DIM]) {
     int l = l0, m = m0;
@@ -475,7 +513,7 @@ __device__ __forceinline__ void lane_sums(const Vol<DIM, LAYOUT> &vol, const Fra
                 wp[a] = fmaf(rad[k], du[a], fr.off[a]);
                 wm[a] = fmaf(-rad[k], du[a], fr.off[a]);
             }
-            constexpr bool SMALL = LAYOUT != kGlobalPlain;
+            constexpr bool SMALL = V::kSmall;
             const long ip = locate<DIM, CLAMP, SMALL>(fr, vol.n, vol.nx, vol.nxy, wp, fp[k]);
             const long im = locate<DIM, CLAMP, SMALL>(fr, vol.n, vol.nx, vol.nxy, wm, fm[k]);
             vol.load(ip, cp[k]);
@@ -487,9 +525,11 @@ __device__ __forceinline__ void lane_sums(const Vol<DIM, LAYOUT> &vol, const Fra
                 m += 1;
             }
         }
+        // branch-free: a pair-point past P (it read pair 0, in bounds) gets zero weights, so its
+        // gathers are consumed unconditionally and those of all U pair-points stay in flight
+        // together
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            if (!ok[k]) continue;
             const float Ip = trilerp<DIM>(cp[k], fp[k]);
             const float Im = trilerp<DIM>(cm[k], fm[k]);
             const float d1 = rad[k] - fr.ain, d2 = rad[k] - fr.R;
@@ -499,9 +539,9 @@ __device__ __forceinline__ void lane_sums(const Vol<DIM, LAYOUT> &vol, const Fra
             const float sout = __builtin_amdgcn_fmed3f(fmaf(-d2, fr.os, 0.5f), 0.0f, 1.0f);
             // the inner profile is +1 wherever the outer one is below 1 (R >= the geometric
             // minimum keeps the regions disjoint), and vice versa
-            const float S = fminf(sin_, sout);
-            const float cC = r1 ? fr.is : (r2 ? -fr.os : 0.0f);  // dS/dr on the ramps
-            const float cR = r1 ? -fr.rho_is : -cC;               // dS/dR on the ramps
+            const float S = ok[k] ? fminf(sin_, sout) : 0.0f;
+            const float cC = ok[k] ? (r1 ? fr.is : (r2 ? -fr.os : 0.0f)) : 0.0f;  // dS/dr on the ramps
+            const float cR = ok[k] ? (r1 ? -fr.rho_is : -cC) : 0.0f;               // dS/dR on the ramps
             const float Is = Ip + Im, Id = Ip - Im;
             acc[0] = fmaf(S, Is, acc[0]);
             acc[1] = fmaf(cR, Is, acc[1]);
@@ -597,6 +637,97 @@ __device__ __forceinline__ void lattice_sums(const Vol<DIM, LAYOUT> &vol, const 
 }
 
 // ---------------------------------------------------------------------------------------------
+// LDS tile of the sample ball
+// ---------------------------------------------------------------------------------------------
+
+// A box of the smoothed volume held in LDS by one whole-wave group: voxels lo[a] .. lo[a] + n[a] - 1
+// per axis, x fastest (n[2] = 1 in 2D). An iteration whose samples, trilinear corners included,
+// all fall inside the box reads its corners from LDS; the box is staged again only when the ball
+// leaves it. It is staged with a margin, so a contour that moves and grows slowly keeps its box
+// for many iterations, and its corners stop costing scattered global loads.
+struct Tile {
+    int lo[3], n[3];
+    bool valid;
+};
+
+constexpr int kTileMargin = 2;  // voxels added on each side of the ball's range, when they fit
+
+// Voxel range lo .. hi per axis that the corners of an iteration's samples can touch (the ball of
+// radius s_max around the centre, with the same rounding margin as the interior test).
+template <int DIM>
+__device__ __forceinline__ void ball_range(const Frame<DIM> &fr, const float inv_h[3], int lo[3], int hi[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = hi[a] = 0;
+        if (a < DIM) {
+            const float e = fmaf(fr.smax * inv_h[a], 1.0001f, 1e-3f);
+            lo[a] = fr.anc[a] + (int)floorf(fr.off[a] - e);
+            hi[a] = fr.anc[a] + (int)floorf(fr.off[a] + e) + 1;
+        }
+    }
+}
+
+// New box for the range lo .. hi (inside the volume): the largest margin of kTileMargin .. 0
+// voxels per side whose box holds at most `cap` voxels, clamped to the volume. False if even the
+// bare range does not fit.
+template <int DIM>
+__device__ __forceinline__ bool choose_tile(const int lo[3], const int hi[3], const int nvol[3], int cap, Tile &t) {
+    for (int m = kTileMargin; m >= 0; --m) {
+        int n[3] = {1, 1, 1};
+        int size = 1;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            n[a] = min(hi[a] - lo[a] + 1 + 2 * m, nvol[a]);
+            size *= n[a];
+        }
+        if (size <= cap) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                t.n[a] = n[a];
+                t.lo[a] = a < DIM ? min(max(lo[a] - m, 0), nvol[a] - n[a]) : 0;
+            }
+            t.valid = true;
+            return true;
+        }
+    }
+    t.valid = false;
+    return false;
+}
+
+// All G lanes copy the box from the plain FP32 volume into LDS, 8 loads in flight per lane. The
+// caller synchronises the group before the box is read.
+template <int G>
+__device__ __forceinline__ void stage_tile(float *tile, const float *J, int nx, int nxy, const Tile &t, int gl) {
+    const int n0 = t.n[0], n1 = t.n[1];
+    const int total = n0 * n1 * t.n[2];
+    const float *src = J + ((long)t.lo[2] * nxy + (long)t.lo[1] * nx + t.lo[0]);
+    // element e = gl + k G of the box -> (x, y, z), advanced by G without a division
+    int x = gl % n0, y = (gl / n0) % n1, z = gl / (n0 * n1);
+    const int sx = G % n0, sy = G / n0;
+    constexpr int B = 8;
+    for (int e0 = gl; e0 < total; e0 += B * G) {
+        float v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            v[k] = e0 + k * G < total ? src[(long)z * nxy + y * nx + x] : 0.0f;
+            x += sx;
+            if (x >= n0) {
+                x -= n0;
+                y += 1;
+            }
+            y += sy;
+            while (y >= n1) {
+                y -= n1;
+                z += 1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (e0 + k * G < total) tile[e0 + k * G] = v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Per-contour iteration loop
 // ---------------------------------------------------------------------------------------------
 
@@ -629,9 +760,13 @@ __device__ __forceinline__ int uni(int v) {
 // Run up to n_iter iterations of the group's contour (slot == nullptr: no contour), stopping early at
 // iteration `target` or when it leaves SNK_ACTIVE. All lanes of the workgroup call this; the loop
 // and its barriers are workgroup-uniform.
-template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false>
+// STAGE (whole-wave groups): iterations whose ball fits a box of tile_cap voxels read their corners
+// from an LDS box at lds_tile, the others from the volume in LAYOUT.
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false>
 __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int target, float *trace_row,
-                          float *lds_draws, float *lds_red, unsigned long long *counter) {
+                          float *lds_draws, float *lds_red, unsigned long long *counter, float *lds_tile = nullptr,
+                          int tile_cap = 0) {
+    static_assert(!STAGE || (G >= 64 && !EXACT), "LDS boxes are staged by whole-wave Monte-Carlo groups");
     constexpr int NR = 2 + DIM;
     constexpr int WAVES = Grp<G>::WAVES;
     constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
@@ -678,6 +813,8 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
     const float inv_npts = 1.0f / (float)(p.M * p.L);
     const float tol2 = p.conv_tol * p.conv_tol;
     int ran = 0;
+    Tile tile;
+    tile.valid = false;
 
     for (int it = 0;; ++it) {
         const bool active = it < budget && (status & 0x0f) == SNK_ACTIVE;
@@ -728,10 +865,40 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                     lattice_sums<DIM, G, true, LAYOUT>(vol, fr, hh, inv_h, gl, acc);
             } else {
                 const float4 *pu = dr.pu + dr.slot(blk & 1, sl) * MH;
-                if (interior)
-                    lane_sums<DIM, G, U, false, LAYOUT>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
-                else
-                    lane_sums<DIM, G, U, true, LAYOUT>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                bool staged = false;
+                if constexpr (STAGE) {
+                    if (interior && tile_cap > 0) {
+                        int lo[3], hi[3];
+                        ball_range<DIM>(fr, inv_h, lo, hi);
+                        bool covered = tile.valid;
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a)
+                            covered = covered && lo[a] >= tile.lo[a] && hi[a] < tile.lo[a] + tile.n[a];
+                        if (!covered && choose_tile<DIM>(lo, hi, vol.n, tile_cap, tile)) {
+                            // the previous iteration's reads of the box ended at its reduction barrier
+                            stage_tile<G>(lds_tile, p.g.J, vol.nx, vol.nxy, tile, gl);
+                            __syncthreads();
+                        }
+                        staged = tile.valid;
+                    }
+                }
+                if (staged) {
+                    TileVol<DIM> tv;
+                    tv.t = lds_tile;
+                    tv.n[0] = tile.n[0];
+                    tv.n[1] = tile.n[1];
+                    tv.n[2] = tile.n[2];
+                    tv.nx = tile.n[0];
+                    tv.nxy = tile.n[0] * tile.n[1];
+                    Frame<DIM> ft = fr;
+                    ft.base = (anc[0] - tile.lo[0]) + (anc[1] - tile.lo[1]) * tv.nx;
+                    if constexpr (DIM == 3) ft.base += (anc[2] - tile.lo[2]) * tv.nxy;
+                    lane_sums<DIM, G, U, false>(tv, ft, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                } else if (interior) {
+                    lane_sums<DIM, G, U, false>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                } else {
+                    lane_sums<DIM, G, U, true>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                }
             }
         }
 
@@ -904,7 +1071,8 @@ __host__ __device__ __forceinline__ int lds_floats(int MH) {
 
 // Whole-wave groups with one pair-point in flight fit 64 vector registers: ask for 8 waves per SIMD
 // (a full CU of 4-wave groups holds 8 contours).
-template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT>
+// STAGE: the workgroup's LDS ends with a box of a.tile_cap voxels.
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT, bool STAGE>
 __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolve_kernel(EvolveArgs a) {
     extern __shared__ float lds[];
     const int MH = a.p.M / 2;
@@ -912,9 +1080,10 @@ __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolv
     const int sub = G < 64 ? (int)threadIdx.x / G : 0;
     const int cid = blockIdx.x * Grp<G>::CPB + sub;
     DevContour *slot = cid < a.n ? a.st + cid : nullptr;
-    run_group<DIM, G, U, TRACE, LAYOUT, EXACT>(a.p, slot, a.n_iter, 0x7fffffff,
-                                               TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
-                                               lds + sub * per, lds + Grp<G>::CPB * per, a.counter);
+    run_group<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE>(a.p, slot, a.n_iter, 0x7fffffff,
+                                                      TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
+                                                      lds + sub * per, lds + Grp<G>::CPB * per, a.counter,
+                                                      lds + lds_floats<DIM, G>(MH), STAGE ? a.tile_cap : 0);
 }
 
 // Batched launch over (job, contour) items, one workgroup (G >= 64 lanes) per item. PERSISTENT: a
@@ -951,11 +1120,12 @@ __global__ __launch_bounds__(G, U == 1 ? 8 : 1) void evolve_batch_kernel(BatchAr
 // Host launchers
 // ---------------------------------------------------------------------------------------------
 
-template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false>
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false>
 hipError_t launch_t(const EvolveArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(float) * (size_t)lds_floats<DIM, G>(a.p.M / 2);
+    const size_t lds = sizeof(float) * ((size_t)lds_floats<DIM, G>(a.p.M / 2) + (STAGE ? (size_t)a.tile_cap : 0));
     const int blocks = (a.n + Grp<G>::CPB - 1) / Grp<G>::CPB;
-    hipLaunchKernelGGL((evolve_kernel<DIM, G, U, TRACE, LAYOUT, EXACT>), dim3(blocks), dim3(Grp<G>::NT), lds, s, a);
+    hipLaunchKernelGGL((evolve_kernel<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE>), dim3(blocks), dim3(Grp<G>::NT), lds,
+                       s, a);
     return hipGetLastError();
 }
 
@@ -979,6 +1149,16 @@ hipError_t launch_exact_g(const EvolveArgs &a, int lanes, int layout, hipStream_
 
 template <int DIM, int G, int U, bool TRACE>
 hipError_t launch_l(const EvolveArgs &a, int layout, hipStream_t s) {
+    if constexpr (G >= 64) {
+        // LDS boxes, with a buffer layout for the iterations whose ball does not fit
+        if (a.tile_cap > 0) {
+            if (layout == kBufferQuad) return launch_t<DIM, G, U, TRACE, kBufferQuad, false, true>(a, s);
+            if (layout == kBufferPlain) return launch_t<DIM, G, U, TRACE, kBufferPlain, false, true>(a, s);
+            return hipErrorInvalidValue;
+        }
+    } else {
+        if (a.tile_cap > 0) return hipErrorInvalidValue;
+    }
     switch (layout) {
         case kBufferQuad: return launch_t<DIM, G, U, TRACE, kBufferQuad>(a, s);
         case kBufferPlain: return launch_t<DIM, G, U, TRACE, kBufferPlain>(a, s);
@@ -1093,13 +1273,48 @@ int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_
     return dim == 2 ? max_blocks_g<2>(lanes, unroll, layout, max_M) : max_blocks_g<3>(lanes, unroll, layout, max_M);
 }
 
-size_t evolve_lds_bytes(int dim, int lanes, int M) {
+namespace {
+
+template <int DIM, int G, int U>
+int stage_blocks_t(int layout) {
+    int nb = 0;
+    hipError_t e = layout == kBufferQuad
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, evolve_kernel<DIM, G, U, false, kBufferQuad, false, true>, Grp<G>::NT, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, evolve_kernel<DIM, G, U, false, kBufferPlain, false, true>, Grp<G>::NT, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+template <int DIM, int G>
+int stage_blocks_u(int unroll, int layout) {
+    return unroll >= 2 ? stage_blocks_t<DIM, G, 2>(layout) : stage_blocks_t<DIM, G, 1>(layout);
+}
+
+template <int DIM>
+int stage_blocks_g(int lanes, int unroll, int layout) {
+    switch (lanes) {
+        case 64: return stage_blocks_u<DIM, 64>(unroll, layout);
+        case 128: return stage_blocks_u<DIM, 128>(unroll, layout);
+        case 256: return stage_blocks_u<DIM, 256>(unroll, layout);
+        default: return 0;
+    }
+}
+
+}  // namespace
+
+int evolve_stage_blocks_per_cu(int dim, int lanes, int unroll, int layout) {
+    if (layout != kBufferQuad && layout != kBufferPlain) return 0;
+    return dim == 2 ? stage_blocks_g<2>(lanes, unroll, layout) : stage_blocks_g<3>(lanes, unroll, layout);
+}
+
+size_t evolve_lds_bytes(int dim, int lanes, int M, int tile_cap) {
     const int MH = M / 2;
     const int G = lanes;
     const int per = (draw_floats(G, MH) + 3) & ~3;
     const int cpb = G < 64 ? 64 / G : 1;
     const int waves = G > 64 ? G / 64 : 1;
-    return sizeof(float) * ((size_t)cpb * per + (G > 64 ? 2 * (2 + dim) * waves + 16 : 0));
+    return sizeof(float) * ((size_t)cpb * per + (G > 64 ? 2 * (2 + dim) * waves + 16 : 0) + (size_t)tile_cap);
 }
 
 }  // namespace snk

@@ -79,6 +79,7 @@ struct EvolveArgs {
     int n_iter;
     float *trace;                // n x SNK_TRACE_W or null
     unsigned long long *counter; // contour-iterations evolved
+    int tile_cap;                // voxels of the per-contour LDS box (0: corners read from the volume)
 };
 
 // One job of a batch, resident in device memory.
@@ -127,13 +128,16 @@ bool prepass_lds_limit_ok(int rx, int ry, int rz);
 // Pack J into the quad layout (one record per voxel, neighbours clamped at the upper edges).
 hipError_t launch_pack_quad(const float *J, float4 *Jq, int nx, int ny, int nz, hipStream_t s);
 // lanes: contour group size 16, 32, 64, 128 or 256; unroll: pair-points in flight (1 or 2);
-// layout: a VolumeLayout (batched launches: buffer layouts only).
+// layout: a VolumeLayout (batched launches and LDS boxes: buffer layouts only). a.tile_cap > 0
+// (whole-wave groups, Monte-Carlo sums) stages each contour's ball in an LDS box of that many voxels.
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, int layout, bool trace,
                          hipStream_t s);
 hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unroll, int layout, bool persistent,
                                int grid, hipStream_t s);
 int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M);
-size_t evolve_lds_bytes(int dim, int lanes, int M);
+size_t evolve_lds_bytes(int dim, int lanes, int M, int tile_cap);
+// Workgroups per CU that registers allow for a launch shape with LDS boxes (0: no such shape).
+int evolve_stage_blocks_per_cu(int dim, int lanes, int unroll, int layout);
 
 // Engine helpers (engine_kernels.hip).
 hipError_t launch_reset_items(const JobDev *jobs, const int2 *items, int n_items, const DevContour *const *init,

@@ -23,7 +23,7 @@ ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CULLED, CLAMPED = 0, 1, 2, 3, 4, 5, 
 TRACE_W = 16
 
 EXPORTS = [
-    "snk_create", "snk_destroy", "snk_set_params", "snk_set_launch", "snk_set_directions",
+    "snk_create", "snk_destroy", "snk_set_params", "snk_set_launch", "snk_set_tile", "snk_set_directions",
     "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
     "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull",
@@ -50,7 +50,8 @@ class snk_params(C.Structure):
 
 class snk_timing(C.Structure):
     _fields_ = [("prepass_ms", C.c_double), ("evolve_ms", C.c_double), ("finalize_ms", C.c_double),
-                ("evolved", C.c_int64), ("evolve_launches", C.c_int64)]
+                ("evolved", C.c_int64), ("evolve_launches", C.c_int64), ("lanes_per_contour", C.c_int32),
+                ("pairs_in_flight", C.c_int32), ("layout", C.c_int32), ("tile_voxels", C.c_int32)]
 
 
 class snk_engine_stats(C.Structure):
@@ -78,6 +79,7 @@ def load(path: str = LIB_PATH):
         "snk_destroy": [vp],
         "snk_set_params": [vp, C.POINTER(snk_params)],
         "snk_set_launch": [vp, i32, i32, i32],
+        "snk_set_tile": [vp, i32],
         "snk_set_directions": [vp, vp, i32],
         "snk_load_volume": [vp, vp, C.c_int, i64, i64, i64, C.c_int],
         "snk_prepass": [vp],
@@ -179,6 +181,10 @@ def snk_set_params(h, params) -> None:
 
 def snk_set_launch(h, lanes_per_contour: int = 0, pairs_in_flight: int = 0, layout: int = 0) -> None:
     _check(h, load().snk_set_launch(h, int(lanes_per_contour), int(pairs_in_flight), int(layout)))
+
+
+def snk_set_tile(h, tile_voxels: int = -1) -> None:
+    _check(h, load().snk_set_tile(h, int(tile_voxels)))
 
 
 def snk_set_directions(h, dirs) -> None:
@@ -293,7 +299,9 @@ def snk_get_timing(h) -> dict:
     t = snk_timing()
     _check(h, load().snk_get_timing(h, C.byref(t)))
     return {"prepass_ms": t.prepass_ms, "evolve_ms": t.evolve_ms, "finalize_ms": t.finalize_ms,
-            "evolved": int(t.evolved), "evolve_launches": int(t.evolve_launches)}
+            "evolved": int(t.evolved), "evolve_launches": int(t.evolve_launches),
+            "lanes_per_contour": int(t.lanes_per_contour), "pairs_in_flight": int(t.pairs_in_flight),
+            "layout": int(t.layout), "tile_voxels": int(t.tile_voxels)}
 
 
 def snk_sync(h) -> None:

@@ -41,11 +41,12 @@ def stream():
     return torch.cuda.current_stream()
 
 
-def make_ctx(snk, stream, wl, lanes=0, on_device=True, unroll=0, layout=0):
+def make_ctx(snk, stream, wl, lanes=0, on_device=True, unroll=0, layout=0, tile=-1):
     import torch
     ctx = snk.Context(0, stream)
     ctx.set_params(wl.params)
     ctx.set_launch(lanes, unroll, layout)
+    ctx.set_tile(tile)
     ctx.set_directions(wl.dirs)
     if on_device:
         raw = torch.from_numpy(np.ascontiguousarray(wl.raw)).to("cuda:0")
@@ -207,6 +208,44 @@ def test_layouts_bitwise(snk, stream):
     for o in outs[1:]:
         for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
             assert np.array_equal(outs[0][k], o[k]), k
+
+
+@pytest.mark.parametrize("which", ["tiny", "aniso", "plane"])
+def test_lds_box_bitwise(snk, stream, which):
+    """LDS boxes hold exact copies of the volume and the corner arithmetic is unchanged, so a free
+    run gives identical results with boxes of any capacity (tiny ones: most iterations read the
+    volume; mid-sized ones: iterations switch between box and volume as R changes) and without
+    them, for every whole-wave launch shape; seeds near and on the faces take the clamped path."""
+    rng = np.random.default_rng(11)
+    if which == "tiny":
+        wl = synth.tiny_config()
+    elif which == "aniso":
+        wl = synth.slab_config(n_target=40, shape_xyz=(96, 80, 40), n_iter=60)
+    else:
+        wl = synth.plane_config(n_target=120, size=256, n_iter=60)
+    seeds = np.concatenate([wl.seeds, extra_seeds(wl, 24, rng)])
+    ids = np.arange(len(seeds), dtype=np.uint32)
+    n_iter = min(wl.n_iter, 60)
+    layout = 2 if wl.params.dim == 3 else 1
+    for lanes, unroll in ((64, 2), (128, 1), (256, 2)):
+        ref = None
+        for tile in (0, 512, 3000, -1):
+            say(f"lds box {which}: lanes {lanes} pairs {unroll} tile {tile}")
+            ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout, tile=tile)
+            ctx.load_seeds(seeds, ids=ids)
+            ctx.evolve(n_iter)
+            got = ctx.get_state()
+            e_mc = ctx.read()["e_mc"]
+            used = ctx.get_timing()["tile_voxels"]
+            ctx.close()
+            if tile == -1:
+                assert used > 0, "automatic shape with few contours should stage boxes"
+            if ref is None:
+                ref = (got, e_mc)
+                continue
+            for k in got:
+                assert np.array_equal(got[k], ref[0][k]), (k, lanes, unroll, tile)
+            assert np.array_equal(e_mc, ref[1]), (lanes, unroll, tile)
 
 
 def test_one_step_parity_many_rays(snk, stream):
