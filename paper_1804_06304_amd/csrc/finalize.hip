@@ -228,29 +228,51 @@ __device__ __forceinline__ void bin_one(const JobDev &a, int i) {
     a.cell_of[i] = cell;
 }
 
-// In-place inclusive scan of cell_start[1..G] by one workgroup: cell_start[c] = first slot of cell c.
-__device__ void scan_cells(const JobDev &a, int G, int *chunk_sum) {
-    const int t = threadIdx.x;
-    const int per = (G + SEL_T - 1) / SEL_T;
-    const int b = 1 + t * per, e = min(G + 1, b + per);
-    int run = 0;
-    for (int c = b; c < e; ++c) {
-        run += a.cell_start[c];
-        a.cell_start[c] = run;
-    }
-    chunk_sum[t] = run;
-    __syncthreads();
-    if (t == 0) {
-        int acc = 0;
-        for (int k = 0; k < SEL_T; ++k) {
-            const int v = chunk_sum[k];
-            chunk_sum[k] = acc;
-            acc += v;
+// Inclusive running sum of the cell counts cell_start[1..G], in place, by one workgroup: tiles of
+// SEL_T * 8 cells, 8 consecutive cells per thread, a shuffle scan of the thread sums inside each
+// wave, the wave totals scanned through LDS (ws: SEL_T / 64 + 1 ints), a carry across tiles.
+__device__ void scan_cells(const JobDev &a, int G, int *ws) {
+    constexpr int V = 8;
+    constexpr int W = SEL_T / 64;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int *cs = a.cell_start + 1;
+    int carry = 0;
+    for (int base = 0; base < G; base += SEL_T * V) {
+        const int i0 = base + t * V;
+        int v[V];
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            s += i0 + k < G ? cs[i0 + k] : 0;
+            v[k] = s;
         }
+        int incl = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        if (lane == 63) ws[w] = incl;
+        __syncthreads();
+        if (w == 0) {
+            const int x = lane < W ? ws[lane] : 0;
+            int sc = x;
+#pragma unroll
+            for (int d = 1; d < W; d <<= 1) {
+                const int y = __shfl_up(sc, d, 64);
+                if (lane >= d) sc += y;
+            }
+            if (lane < W) ws[lane] = sc - x;  // exclusive prefix of the wave totals
+            if (lane == W - 1) ws[W] = sc;    // tile total
+        }
+        __syncthreads();
+        const int off = carry + ws[w] + (incl - s);
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if (i0 + k < G) cs[i0 + k] = v[k] + off;
+        carry += ws[W];
+        __syncthreads();
     }
-    __syncthreads();
-    const int add = chunk_sum[t];
-    for (int c = b; c < e; ++c) a.cell_start[c] += add;
 }
 
 __device__ __forceinline__ void scatter_one(const JobDev &a, int i) {

@@ -8,7 +8,9 @@
 // tile column to each lane. Per input plane: stage the plane with its x/y halo in LDS from
 // registers that were fetched while the previous plane was filtered (A), filter along x (B), filter
 // along y into a ring of 2*rz+1 planes that each thread reads back for the z filter (C, D), then
-// write J and the quad records of the tile from an LDS copy of the filtered plane (E).
+// write J and the quad records of the tile from an LDS copy of the filtered plane (E). Each thread
+// z-filters only the elements it y-filtered, so with compile-time radii the ring lives in its
+// registers (less LDS per workgroup, more workgroups per CU); the generic instance keeps it in LDS.
 // Thread-to-element maps use shifts only: no integer division in any loop. HBM traffic: the raw read (halo re-reads mostly hit L2), 4 B of J and 16 B of quad
 // records per voxel.
 #include <algorithm>
@@ -25,15 +27,19 @@ constexpr int NT = 256;
 constexpr int RS = NT / EX;     // row stride of the thread map (4)
 
 template <typename T>
-__device__ __forceinline__ float raw_value(const void *raw, long i) {
-    return static_cast<float>(static_cast<const T *>(raw)[i]);
+__device__ __forceinline__ T raw_value(const void *raw, long i) {
+    return static_cast<const T *>(raw)[i];
 }
 
 // RXY / RZ >= 0: the filter radii are compile-time constants (tap loops unroll, taps live in scalar
-// registers); -1: taken from the arguments. EY: evaluated rows per tile.
-template <typename T, int EY, int RXY, int RZ>
+// registers); -1: taken from the arguments. EY: evaluated rows per tile. QUAD: also write the quad
+// records.
+template <typename T, int EY, int RXY, int RZ, bool QUAD>
 __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk) {
     constexpr int TY = EY - 1;  // output rows (the last evaluated one is the +y neighbour)
+    constexpr bool REG_RING = RZ >= 0;
+    constexpr int KR = REG_RING ? 2 * RZ + 1 : 1;   // register ring depth
+    constexpr int NRT = (EY + RS - 1) / RS;          // y-filtered rows per thread
     constexpr int RMAX = RXY >= 0 ? RXY : kPrepassMaxR;
     constexpr int NRA = (EY + 2 * RMAX + RS - 1) / RS;  // plane rows per thread (upper bound)
     constexpr int NCA = (EX + 2 * RMAX + EX - 1) / EX;  // plane columns per thread (upper bound)
@@ -46,8 +52,14 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
     const int K = 2 * rz + 1;              // ring depth
     float *plane = lds;                    // PH x PW
     float *tmp = plane + PH * PW;          // PH x EX (x-filtered)
-    float *ring = tmp + PH * EX;           // K x EY x EX (xy-filtered)
-    float *out = ring + K * EY * EX;       // EY x EX (filtered plane)
+    float *ring = tmp + PH * EX;           // K x EY x EX (xy-filtered; generic instance only)
+    float *out = ring + (REG_RING ? 0 : K * EY * EX);  // EY x EX (filtered plane)
+    // register ring: rr[i][k] = y-filtered row ty + RS i of plane zi - (KR - 1) + k
+    float rr[NRT][KR];
+#pragma unroll
+    for (int i = 0; i < NRT; ++i)
+#pragma unroll
+        for (int k = 0; k < KR; ++k) rr[i][k] = 0.0f;
 
     const int x0 = blockIdx.x * TX;
     const int y0 = blockIdx.y * TY;
@@ -57,31 +69,38 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
     const int tx = t & (EX - 1);           // tile column of this lane in every phase
     const int ty = t >> 6;                 // rows ty, ty + 4, ...
     const long nxy = (long)a.nx * a.ny;
+    // output column of this lane: the evaluated +x neighbour column and columns past the volume
+    // store the value of the last output column inside it again (a duplicate write of the same
+    // value), so every thread issues the same number of stores per plane and waiting for the next
+    // plane's loads never has to wait for this plane's stores
+    const int xc = min(x0 + min(tx, TX - 1), a.nx - 1);
+    const int tc = xc - x0;
     // neighbour column of the quad records, clamped to the last voxel of the volume
-    const int cx1 = min(min(x0 + tx + 1, a.nx - 1) - x0, EX - 1);
+    const int cx1 = min(min(xc + 1, a.nx - 1) - x0, EX - 1);
 
-    // raw plane values of this thread (rows ty + 4i, columns tx + 64j), clamp-to-edge
-    float pre[NRA][NCA];
+    // raw plane values of this thread (rows ty + 4i, columns tx + 64j), clamp-to-edge. Every load is
+    // issued unconditionally (slots past the plane read a clamped, valid address and are never
+    // stored), so no branch forces a wait between them and they stay in flight while the current
+    // plane is filtered.
+    T pre[NRA][NCA];  // raw values: converted only when staged, so nothing waits on the loads earlier
     auto fetch = [&](int zi) {
         const long zoff = (long)min(max(zi, 0), a.nz - 1) * nxy;
 #pragma unroll
         for (int i = 0; i < NRA; ++i) {
-            const int r = ty + RS * i;
-            if (r < PH) {
-                const long yoff = zoff + (long)min(max(y0 + r - ry, 0), a.ny - 1) * a.nx;
+            const int r = min(ty + RS * i, PH - 1);
+            const long yoff = zoff + (long)min(max(y0 + r - ry, 0), a.ny - 1) * a.nx;
 #pragma unroll
-                for (int j = 0; j < NCA; ++j) {
-                    const int c = tx + EX * j;
-                    if (c < PW) pre[i][j] = raw_value<T>(a.raw, yoff + min(max(x0 + c - rx, 0), a.nx - 1));
-                }
+            for (int j = 0; j < NCA; ++j) {
+                const int c = min(tx + EX * j, PW - 1);
+                pre[i][j] = raw_value<T>(a.raw, yoff + min(max(x0 + c - rx, 0), a.nx - 1));
             }
         }
     };
 
     int slot = 0;                          // ring slot of the plane being filtered
-    fetch(z0 - rz);
-    for (int zi = z0 - rz; zi < z1 + rz; ++zi) {
-        // A: the plane (fetched during the previous plane) into LDS, then fetch the next one
+    // A: the plane (fetched during the previous plane) into LDS, then fetch the next one (always:
+    // past the chunk it re-reads a clamped plane, so every plane issues the same loads)
+    auto stage = [&](int zi) {
 #pragma unroll
         for (int i = 0; i < NRA; ++i) {
             const int r = ty + RS * i;
@@ -89,13 +108,15 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
 #pragma unroll
                 for (int j = 0; j < NCA; ++j) {
                     const int c = tx + EX * j;
-                    if (c < PW) plane[r * PW + c] = (pre[i][j] - a.i_offset) * a.i_scale;
+                    if (c < PW) plane[r * PW + c] = ((float)pre[i][j] - a.i_offset) * a.i_scale;
                 }
             }
         }
         __syncthreads();
-        if (zi + 1 < z1 + rz) fetch(zi + 1);
-        // B: x filter
+        fetch(zi + 1);
+    };
+    // B: x filter; C: y filter into the ring (each thread later reads back only its own elements)
+    auto filter_xy = [&]() {
 #pragma unroll
         for (int i = 0; i < NRA; ++i) {
             const int r = ty + RS * i;
@@ -107,52 +128,77 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
             }
         }
         __syncthreads();
-        // C: y filter into the ring (each thread later reads back only its own elements)
 #pragma unroll
-        for (int r = ty; r < EY; r += RS) {
-            float acc = 0.0f;
-            for (int k = 0; k <= 2 * ry; ++k) acc = fmaf(a.gy[k], tmp[(r + k) * EX + tx], acc);
-            ring[(slot * EY + r) * EX + tx] = acc;
-        }
-        const int zo = zi - rz;
-        if (zo >= z0) {
-            // D: z filter over planes zo - rz .. zo + rz (ring slots slot - 2rz .. slot, in order)
-            int s0 = slot + 1;
-            if (s0 == K) s0 = 0;
-#pragma unroll
-            for (int r = ty; r < EY; r += RS) {
+        for (int i = 0; i < NRT; ++i) {
+            const int r = ty + RS * i;
+            if (r < EY) {
                 float acc = 0.0f;
-                int s = s0;
-                for (int k = 0; k < K; ++k) {
-                    acc = fmaf(a.gz[k], ring[(s * EY + r) * EX + tx], acc);
-                    s = s + 1 == K ? 0 : s + 1;
+                for (int k = 0; k <= 2 * ry; ++k) acc = fmaf(a.gy[k], tmp[(r + k) * EX + tx], acc);
+                if constexpr (REG_RING) {
+#pragma unroll
+                    for (int k = 0; k + 1 < KR; ++k) rr[i][k] = rr[i][k + 1];
+                    rr[i][KR - 1] = acc;
+                } else {
+                    ring[(slot * EY + r) * EX + tx] = acc;
+                }
+            }
+        }
+    };
+
+    fetch(z0 - rz);
+    // the first 2 rz planes only fill the ring
+    int zi = z0 - rz;
+    for (; zi < z0 + rz; ++zi) {
+        stage(zi);
+        filter_xy();
+        slot = slot + 1 == K ? 0 : slot + 1;
+    }
+    for (; zi < z1 + rz; ++zi) {
+        stage(zi);
+        filter_xy();
+        const int zo = zi - rz;
+        // D: z filter over planes zo - rz .. zo + rz (oldest ring entry first)
+        int s0 = slot + 1;
+        if (s0 == K) s0 = 0;
+#pragma unroll
+        for (int i = 0; i < NRT; ++i) {
+            const int r = ty + RS * i;
+            if (r < EY) {
+                float acc = 0.0f;
+                if constexpr (REG_RING) {
+#pragma unroll
+                    for (int k = 0; k < KR; ++k) acc = fmaf(a.gz[k], rr[i][k], acc);
+                } else {
+                    int s = s0;
+                    for (int k = 0; k < K; ++k) {
+                        acc = fmaf(a.gz[k], ring[(s * EY + r) * EX + tx], acc);
+                        s = s + 1 == K ? 0 : s + 1;
+                    }
                 }
                 out[r * EX + tx] = acc;
             }
-            __syncthreads();
-            // E: J and the quad records of the tile
-            const int x = x0 + tx;
-            if (tx < TX && x < a.nx) {
+        }
+        __syncthreads();
+        // E: J and the quad records of the tile (rows past the tile or the volume store the last
+        // row inside both again)
 #pragma unroll
-                for (int r = ty; r < TY; r += RS) {
-                    const int y = y0 + r;
-                    if (y < a.ny) {
-                        const int r1 = min(y + 1, a.ny - 1) - y0;
-                        const long o = zo * nxy + (long)y * a.nx + x;
-                        const float v = out[r * EX + tx];
-                        a.J[o] = v;
-                        if (a.Jq)
-                            a.Jq[o] = make_float4(v, out[r * EX + cx1], out[r1 * EX + tx], out[r1 * EX + cx1]);
-                    }
-                }
-            }
+        for (int i = 0; i < (TY + RS - 1) / RS; ++i) {
+            const int y = min(y0 + min(ty + RS * i, TY - 1), a.ny - 1);
+            const int r = y - y0;
+            const int r1 = min(y + 1, a.ny - 1) - y0;
+            const long o = zo * nxy + (long)y * a.nx + xc;
+            const float v = out[r * EX + tc];
+            a.J[o] = v;
+            if constexpr (QUAD) a.Jq[o] = make_float4(v, out[r * EX + cx1], out[r1 * EX + tc], out[r1 * EX + cx1]);
         }
         slot = slot + 1 == K ? 0 : slot + 1;
     }
 }
 
-size_t prepass_lds_bytes(int rx, int ry, int rz, int ey) {
-    return sizeof(float) * ((ey + 2 * ry) * (EX + 2 * rx) + (ey + 2 * ry) * EX + (2 * rz + 1) * ey * EX + ey * EX);
+// ring_lds: the z ring is held in LDS (generic instance) rather than in registers.
+size_t prepass_lds_bytes(int rx, int ry, int rz, int ey, bool ring_lds = true) {
+    return sizeof(float) * ((ey + 2 * ry) * (EX + 2 * rx) + (ey + 2 * ry) * EX + (ring_lds ? (2 * rz + 1) * ey * EX : 0) +
+                            ey * EX);
 }
 
 int prepass_rows(int rx, int ry, int rz) {
@@ -161,8 +207,8 @@ int prepass_rows(int rx, int ry, int rz) {
     return 0;
 }
 
-template <typename T, int EY, int RXY, int RZ>
-hipError_t launch_ty(const PrepassArgs &a, hipStream_t s) {
+template <typename T, int EY, int RXY, int RZ, bool QUAD>
+hipError_t launch_q(const PrepassArgs &a, hipStream_t s) {
     const int bx = (a.nx + TX - 1) / TX;
     const int by = (a.ny + EY - 2) / (EY - 1);
     const long bxy = (long)bx * by;
@@ -172,9 +218,15 @@ hipError_t launch_ty(const PrepassArgs &a, hipStream_t s) {
     int z_chunk = (a.nz + chunks - 1) / chunks;
     z_chunk = std::max(z_chunk, std::min(a.nz, 4));
     const int bz = (a.nz + z_chunk - 1) / z_chunk;
-    const size_t lds = prepass_lds_bytes(a.rx, a.ry, a.rz, EY);
-    hipLaunchKernelGGL((prepass_kernel<T, EY, RXY, RZ>), dim3(bx, by, bz), dim3(NT), lds, s, a, z_chunk);
+    const size_t lds = prepass_lds_bytes(a.rx, a.ry, a.rz, EY, RZ < 0);
+    hipLaunchKernelGGL((prepass_kernel<T, EY, RXY, RZ, QUAD>), dim3(bx, by, bz), dim3(NT), lds, s, a, z_chunk);
     return hipGetLastError();
+}
+
+template <typename T, int EY, int RXY, int RZ>
+hipError_t launch_ty(const PrepassArgs &a, hipStream_t s) {
+    if (!a.Jq) return launch_q<T, EY, RXY, RZ, false>(a, s);
+    return launch_q<T, EY, RXY, RZ, true>(a, s);
 }
 
 // Radii of sigma_pre = 1 on unit (x, y) spacing with z spacing 1, 2 or a 2D image get unrolled
