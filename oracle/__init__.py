@@ -63,6 +63,8 @@ def lib():
         L.orc_weight_many.argtypes = [C.c_int, vp, i64, d, d, vp]
         L.orc_prepass.argtypes = [vp, C.c_int, i64, i64, i64, P(_Params), vp]
         L.orc_interp.argtypes = [vp, i64, i64, i64, C.c_int, d, d, d]; L.orc_interp.restype = d
+        L.orc_interp_grad.argtypes = [vp, i64, i64, i64, C.c_int, d, d, d, P(d)]
+        L.orc_interp_grad.restype = d
         L.orc_rotation.argtypes = [P(_Params), u32, u32, P(d)]
         L.orc_initial_radius.argtypes = [P(_Params), d]; L.orc_initial_radius.restype = d
         L.orc_evolve.argtypes = [vp, i64, i64, i64, P(_Params), vp, i64, vp, vp, vp, vp, vp, vp, vp,
@@ -160,6 +162,16 @@ def interp(J: np.ndarray, dim: int, v) -> float:
     nz, ny, nx = J.shape
     return lib().orc_interp(_ptr(J), nx, ny, nz, int(dim), float(v[0]), float(v[1]),
                             float(v[2]) if len(v) > 2 else 0.0)
+
+
+def interp_grad(J: np.ndarray, dim: int, v):
+    """Trilinear (bilinear) value at voxel coordinates v and its gradient with respect to them
+    (zero along axes outside [0, n - 1])."""
+    nz, ny, nx = J.shape
+    g = (C.c_double * 3)()
+    val = lib().orc_interp_grad(_ptr(J), nx, ny, nz, int(dim), float(v[0]), float(v[1]),
+                                float(v[2]) if len(v) > 2 else 0.0, g)
+    return val, np.array(g[:dim])
 
 
 def initial_radius(p, r0: float) -> float:

@@ -23,6 +23,12 @@
  *   - optionally (flags bit 1) the same sums taken exactly over every lattice point of the ball of
  *     radius R + dR/2, i.e. the gradient of the discrete energy of Eq. (5) itself, the full
  *     voxel-sum evolution the paper compares its Monte-Carlo estimate with (Sec. II-E);
+ *   - optionally (flags bit 2) the centre force in its image-gradient form: with the sample
+ *     offsets y = x - c held fixed, E = (2R)^-d * integral S(|y|) I(c + y) dy, so
+ *     dE/dc = (2R)^-d * integral S(|y|) grad I(c + y) dy, estimated from the same samples with the
+ *     gradient of the trilinear interpolant (zero along axes clamped at the faces). It has the
+ *     same expectation as the weight-derivative form of Eqs. (7)-(10) (a variance-reduction
+ *     option, not in the paper); the radius force is unchanged;
  *   - stopping on maximum iterations or convergence, overlap competition with the lower energy
  *     surviving (||c' - c''|| < max(R', R'')*rho), and the energy threshold E0 (Results).
  *
@@ -56,6 +62,7 @@
 #define ORC_KINK_REL 4e-6
 #define ORC_FLAG_NOROT 1   /* flags bit 0: rotation Q = I */
 #define ORC_FLAG_EXACT 2   /* flags bit 1: exact lattice sums instead of Monte-Carlo samples */
+#define ORC_FLAG_GRADI 4   /* flags bit 2: centre force from the image gradient (Monte-Carlo only) */
 
 static const double ORC_PI = 3.14159265358979323846;
 
@@ -267,6 +274,47 @@ double orc_interp(const double *J, int64_t nx, int64_t ny, int64_t nz, int dim, 
     return acc;
 }
 
+/* Trilinear (bilinear) value and its gradient with respect to the voxel coordinates, in the cell
+ * the value is interpolated from; an axis whose coordinate lies outside [0, n - 1] (clamped to the
+ * face) has zero derivative. */
+double orc_interp_grad(const double *J, int64_t nx, int64_t ny, int64_t nz, int dim, double vx, double vy,
+                       double vz, double g[3])
+{
+    const double v[3] = {vx, vy, vz};
+    const int64_t n[3] = {nx, ny, nz};
+    int64_t i0[3], i1[3];
+    double f[3];
+    int inside[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a >= dim) { i0[a] = i1[a] = 0; f[a] = 0.0; inside[a] = 0; continue; }
+        split_coord(v[a], n[a], &i0[a], &i1[a], &f[a]);
+        inside[a] = n[a] > 1 && v[a] >= 0.0 && v[a] <= (double)(n[a] - 1);
+    }
+    double acc = 0.0;
+    g[0] = g[1] = g[2] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                if (dim == 2 && dz) continue;
+                const int d[3] = {dx, dy, dz};
+                double w[3];
+                for (int a = 0; a < 3; ++a) w[a] = a >= dim ? 1.0 : (d[a] ? f[a] : 1.0 - f[a]);
+                int64_t xi = dx ? i1[0] : i0[0], yi = dy ? i1[1] : i0[1], zi = dz ? i1[2] : i0[2];
+                const double Jc = J[(zi * ny + yi) * nx + xi];
+                acc += w[0] * w[1] * w[2] * Jc;
+                for (int a = 0; a < dim; ++a) {
+                    /* derivative of the corner's weight along axis a: +1 or -1 times the others */
+                    double dw = d[a] ? 1.0 : -1.0;
+                    for (int b = 0; b < 3; ++b)
+                        if (b != a) dw *= w[b];
+                    g[a] += dw * Jc;
+                }
+            }
+    for (int a = 0; a < dim; ++a)
+        if (!inside[a]) g[a] = 0.0;
+    return acc;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Random rotation of the direction table for (contour id, iteration n): Philox with counter    */
 /* (0, n, id, 0). 3D: Shoemake's uniform unit quaternion (Graphics Gems III, 1992) from three   */
@@ -332,6 +380,7 @@ static void accumulate_samples(const orc_vol *vol, const double c[3], double R, 
     double a = rho * R, dr = rho * p->dR;
     double kinks[4] = {a - 0.5 * dr, a + 0.5 * dr, R - 0.5 * p->dR, R + 0.5 * p->dR};
     int M = p->n_rays, L = p->n_radial;
+    const int gradi = (p->flags & ORC_FLAG_GRADI) != 0;
     memset(sm, 0, sizeof(*sm));
     int idx = 0;
     for (int m = 0; m < M / 2; ++m) {
@@ -354,8 +403,16 @@ static void accumulate_samples(const orc_vol *vol, const double c[3], double R, 
                 double s = smax * (dim == 3 ? cbrt(tau) : sqrt(tau));
                 double pos[3];
                 for (int i = 0; i < 3; ++i) pos[i] = c[i] + s * us[i];
-                double I = orc_interp(vol->J, vol->nx, vol->ny, vol->nz, dim, pos[0] / p->spacing[0],
-                                      pos[1] / p->spacing[1], dim == 3 ? pos[2] / p->spacing[2] : 0.0);
+                const double vv[3] = {pos[0] / p->spacing[0], pos[1] / p->spacing[1],
+                                      dim == 3 ? pos[2] / p->spacing[2] : 0.0};
+                double I, gI[3] = {0.0, 0.0, 0.0};
+                if (gradi) {
+                    double gv[3];
+                    I = orc_interp_grad(vol->J, vol->nx, vol->ny, vol->nz, dim, vv[0], vv[1], vv[2], gv);
+                    for (int i = 0; i < dim; ++i) gI[i] = gv[i] / p->spacing[i];  /* physical gradient */
+                } else {
+                    I = orc_interp(vol->J, vol->nx, vol->ny, vol->nz, dim, vv[0], vv[1], vv[2]);
+                }
                 double w[3];
                 orc_weight(dim, s, R, p->dR, w);
                 double S = w[0], Sr = w[1], SR = w[2];
@@ -363,18 +420,37 @@ static void accumulate_samples(const orc_vol *vol, const double c[3], double R, 
                 sm->Aabs += fabs(S * I);
                 sm->BR += SR * I;
                 sm->BRabs += fabs(SR * I);
+                /* derivative of the integrand with respect to c_a: -Sr u_a I (weight form, the
+                 * sample points fixed), or S dI/dx_a (gradient form, the offsets fixed) */
+                double dc_int[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < dim; ++i) dc_int[i] = gradi ? S * gI[i] : -Sr * I * us[i];
                 for (int i = 0; i < dim; ++i) {
-                    sm->Bc[i] += -Sr * I * us[i];
-                    sm->Bcabs[i] += fabs(Sr * I * us[i]);
+                    sm->Bc[i] += dc_int[i];
+                    sm->Bcabs[i] += fabs(dc_int[i]);
                 }
-                /* Eqs. (7)-(10): c = (p+q)/2, R = (q_x - p_x)/2 along x (Eq. (6));
-                 * dr/dc = -u, so dS/dp_a = -Sr u_a / 2 - SR [a == x] / 2 and
-                 * dS/dq_a = -Sr u_a / 2 + SR [a == x] / 2. */
+                /* Eqs. (7)-(10): c = (p+q)/2, R = (q_x - p_x)/2 along x (Eq. (6)), so
+                 * d/dp_a = (d/dc_a) / 2 - [a == x] (d/dR) / 2 and d/dq_a = (d/dc_a) / 2 + [a == x] (d/dR) / 2;
+                 * in the weight form dr/dc = -u gives dS/dp_a = -Sr u_a / 2 - SR [a == x] / 2. */
                 for (int i = 0; i < dim; ++i) {
-                    double dSdp = -0.5 * Sr * us[i] - (i == 0 ? 0.5 * SR : 0.0);
-                    double dSdq = -0.5 * Sr * us[i] + (i == 0 ? 0.5 * SR : 0.0);
-                    sm->Sp[i] += dSdp * I;
-                    sm->Sq[i] += dSdq * I;
+                    sm->Sp[i] += 0.5 * dc_int[i] - (i == 0 ? 0.5 * SR * I : 0.0);
+                    sm->Sq[i] += 0.5 * dc_int[i] + (i == 0 ? 0.5 * SR * I : 0.0);
+                }
+                /* gradient form: the normal derivative of the interpolant jumps across voxel faces
+                 * (and at the volume's faces); record the jump for samples an FP32 evaluation may
+                 * place in the neighbouring cell */
+                if (gradi) {
+                    for (int a = 0; a < dim; ++a) {
+                        const double tol = ORC_KINK_REL * smax / p->spacing[a];
+                        if (fabs(vv[a] - nearbyint(vv[a])) <= tol) {
+                            double vl[3] = {vv[0], vv[1], vv[2]}, vr[3] = {vv[0], vv[1], vv[2]}, gl[3], gr[3];
+                            vl[a] = nearbyint(vv[a]) - 1e-9;
+                            vr[a] = nearbyint(vv[a]) + 1e-9;
+                            orc_interp_grad(vol->J, vol->nx, vol->ny, vol->nz, dim, vl[0], vl[1], vl[2], gl);
+                            orc_interp_grad(vol->J, vol->nx, vol->ny, vol->nz, dim, vr[0], vr[1], vr[2], gr);
+                            sm->slBc[a] += fabs(S * (gr[a] - gl[a]) / p->spacing[a]);
+                            sm->n_kink += 1;
+                        }
+                    }
                 }
                 /* samples within ORC_KINK_REL * s_max of a kink of S: an FP32 evaluation may place
                  * them on the other side; record how much dS/dr and dS/dR could change. */
@@ -384,7 +460,8 @@ static void accumulate_samples(const orc_vol *vol, const double c[3], double R, 
                         orc_weight(dim, kinks[kk] - 1e-9 * smax, R, p->dR, wl);
                         orc_weight(dim, kinks[kk] + 1e-9 * smax, R, p->dR, wr);
                         sm->slBR += fabs((wr[2] - wl[2]) * I);
-                        for (int i = 0; i < dim; ++i) sm->slBc[i] += fabs((wr[1] - wl[1]) * I * us[i]);
+                        if (!gradi)
+                            for (int i = 0; i < dim; ++i) sm->slBc[i] += fabs((wr[1] - wl[1]) * I * us[i]);
                         sm->n_kink += 1;
                     }
                 }

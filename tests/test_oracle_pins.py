@@ -405,6 +405,111 @@ def test_mc_estimator_unbiased(orc, dim):
     assert np.all(z < 4.5), (mean, ref, z)
 
 
+# ------------------------------------------------------------------------------------------
+# centre force in its image-gradient form (flags bit 2)
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,spacing,near_face", [(3, (1.0, 1.0, 1.0), False), (3, (1.0, 1.0, 2.0), False),
+                                                   (3, (1.0, 1.0, 1.0), True), (2, (1.0, 1.0, 1.0), False),
+                                                   (2, (1.0, 1.0, 1.0), True)])
+def test_gradient_form_is_derivative_with_offsets_fixed(orc, dim, spacing, near_face):
+    """Flags bit 2: the centre force equals the central difference of the same-sample energy
+    estimator when the sample offsets (not the sample points) are held fixed, i.e. the whole sample
+    cloud moves with c, samples clamped beyond a face included. The trilinear interpolant is
+    linear along each axis inside a cell, so the difference is exact unless a sample crosses a
+    voxel face within the step (such cases are detected and skipped)."""
+    if dim == 3:
+        J = _smooth_volume((20, 26, 28))
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, spacing=spacing, flags=4)
+        dirs = synth.icosphere(2)
+        c = np.array([1.5, 12.1, 2.3 * spacing[2]]) if near_face else np.array([13.3, 12.1, 9.7 * spacing[2]])
+    else:
+        J = _smooth_volume((1, 40, 44))
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16, flags=4)
+        dirs = synth.circle_directions(64)
+        c = np.array([2.1, 19.6, 0.0]) if near_face else np.array([21.3, 19.6, 0.0])
+    h = np.array(spacing[:dim] if dim == 3 else spacing[:2])
+    R = 6.4
+    checked = 0
+    for n in (1, 2, 7, 33):
+        t = orc.mc_terms(J, p, dirs, c, R, n, 5, want_samples=True)
+        pts, sc = t["pts"], t["scale"]
+
+        def E(shift):
+            moved = pts.copy()
+            moved[:, :dim] += shift[:dim]
+            vals = np.array([orc.interp(J, dim, moved[j, :dim] / h) for j in range(len(moved))])
+            return orc.energy_fixed(dim, p.dR, moved, vals, sc, c + shift, R)
+
+        d = 1e-7
+        g = t["g_c"]
+        for a in range(dim):
+            e = np.zeros(3); e[a] = d
+            vox = pts[:, a] / h[a]
+            nmax = J.shape[2 - a] - 1 if dim == 3 else J.shape[2 - a] - 1
+            inside = (vox > 0) & (vox < nmax)
+            crosses = np.floor((pts[:, a] + d) / h[a]) != np.floor((pts[:, a] - d) / h[a])
+            if np.any(crosses & inside):
+                continue
+            fd = (E(e) - E(-e)) / (2 * d)
+            assert abs(fd - g[a]) < 1e-6 * (np.abs(g).max() + 1e-3), (n, a, fd, g[a])
+            checked += 1
+    assert checked >= 3 * dim
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_form_linear_field(orc, dim):
+    """Flags bit 2 on an affine image I = b + a . v (v in voxel coordinates): the trilinear
+    interpolant reproduces it exactly, so every interior sample sees grad I = a / h and the centre
+    force is sum_j S_j * (a / h) times the same scale, where sum_j S_j times the scale is the A term
+    of the same samples on the constant image I = 1."""
+    a = np.array([0.37, -0.21, 0.13])
+    if dim == 3:
+        shape, spacing = (30, 32, 34), (1.0, 1.0, 2.0)
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, spacing=spacing, flags=4)
+        dirs = synth.icosphere(2)
+        c = np.array([16.3, 15.2, 14.1 * 2.0])
+    else:
+        shape, spacing = (1, 40, 44), (1.0, 1.0, 1.0)
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16, flags=4)
+        dirs = synth.circle_directions(64)
+        c = np.array([21.3, 19.6, 0.0])
+    z, y, x = np.meshgrid(*[np.arange(k, dtype=np.float64) for k in shape], indexing="ij")
+    J = 2.0 + a[0] * x + a[1] * y + (a[2] * z if dim == 3 else 0.0)
+    ones = np.ones(shape)
+    R = 6.4
+    for n in (1, 5, 40):
+        t = orc.mc_terms(J, p, dirs, c, R, n, 3)
+        t1 = orc.mc_terms(ones, p, dirs, c, R, n, 3)
+        expect = t1["A"] * a[:dim] / np.array(spacing[:dim])
+        assert np.allclose(t["B_c"][:dim], expect, rtol=1e-9, atol=1e-12), (t["B_c"], expect)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_form_unbiased(orc, dim):
+    """Flags bit 2 estimates the same centre force as the weight form: its mean over many
+    iterations' draws agrees with an independent i.i.d. estimate of -integral dS/dr u I over the
+    ball (the expectation of the weight form), while A and B_R are unchanged."""
+    if dim == 3:
+        J = _smooth_volume((18, 20, 22), seed=5)
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, spacing=(1.0, 1.0, 1.0), flags=4)
+        dirs = synth.icosphere(2)
+        c = np.array([10.2, 9.6, 8.9])
+    else:
+        J = _smooth_volume((1, 30, 34), seed=5)
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16, flags=4)
+        dirs = synth.circle_directions(64)
+        c = np.array([16.2, 14.4, 0.0])
+    R = 5.5
+    K = 1500
+    samples = np.array([np.concatenate([[t["A"], t["B_R"]], t["B_c"][:dim]]) for t in
+                        (orc.mc_terms(J, p, dirs, c, R, n, 2) for n in range(1, K + 1))])
+    mean, se = samples.mean(0), samples.std(0) / math.sqrt(K)
+    ref, ref_se = _iid_reference(orc, J, dim, p.spacing, c, R, p.dR, 1_500_000, seed=9)
+    z = np.abs(mean - ref) / np.sqrt(se ** 2 + ref_se ** 2)
+    assert np.all(z < 4.5), (mean, ref, z)
+
+
 def test_constant_image_has_no_force(orc):
     """Constant image: the c-force vanishes exactly for antithetic pairs, and A, B_R are zero in
     expectation (Sec. II-B: the energy does not move contours in uniform regions)."""
