@@ -81,6 +81,15 @@ typedef enum { SNK_U8 = 0, SNK_U16 = 1, SNK_F32 = 2 } snk_dtype;
  *                measure, instead of the Monte-Carlo estimate: the gradient of the exact discrete
  *                energy, deterministic (no random numbers; n_dirs, n_rays, n_radial and seed are
  *                not used). Plain context path only (snk_engine_submit rejects it).
+ *                bit 2: centre force in its image-gradient form: with the sample offsets from the
+ *                centre held fixed, E = (2R)^-d * integral over the ball of S(|y|) I(c + y), so
+ *                dE/dc = (2R)^-d * integral S(|y|) grad I(c + y); B_c (trace columns 2..4)
+ *                becomes (V/N) sum S * grad I, with the gradient of the trilinear interpolant of
+ *                the same corners (zero along axes beyond the volume's faces). Same expectation as
+ *                the weight form (Eqs. (7)-(10)), every sample contributes instead of only those
+ *                in the two ramps; A and B_R are unchanged (not in the paper: a variance-reduction
+ *                option). Monte-Carlo only (SNK_EINVAL with bit 1); lanes_per_contour >= 64 and
+ *                layout 1 or 2 (two pair-points in flight are used); plain context path only.
  *                Other bits must be zero.
  */
 typedef struct snk_params {
@@ -101,7 +110,7 @@ typedef struct snk_params {
 
 /* Width of one contour's row written by snk_trace_step. Layout:
  *  0 A = (V/N) sum S*I          1 B_R = (V/N) sum dS/dR * I
- *  2..4 B_c = -(V/N) sum dS/dr * I * u  (x, y, z; z = 0 in 2D)
+ *  2..4 B_c = -(V/N) sum dS/dr * I * u  (x, y, z; z = 0 in 2D; flags bit 2: (V/N) sum S grad I)
  *  5 E_mc = A / (2R)^d          6 dR step = -(eps/2) (B_R - (d/R) A) / (2R)^d  (before clamping)
  *  7..9 dc step = -(eps/2) B_c / (2R)^d                                             (physical)
  *  10 n (iteration number)      11 R before the step       12 eps

@@ -126,7 +126,10 @@ snk_status check_params(snk_ctx *c, const snk_params &p) {
     if (!(p.conv_tol >= 0.0) || p.conv_window < 0 || p.conv_window > 255)
         return fail(c, SNK_EINVAL, "conv_tol >= 0 and 0 <= conv_window <= 255 required");
     if (!isfinite(p.e0)) return fail(c, SNK_EINVAL, "e0 not finite");
-    if (p.flags & ~(snk::kFlagNoRotation | snk::kFlagExact)) return fail(c, SNK_EINVAL, "unknown flag bits");
+    if (p.flags & ~(snk::kFlagNoRotation | snk::kFlagExact | snk::kFlagGradI))
+        return fail(c, SNK_EINVAL, "unknown flag bits");
+    if ((p.flags & snk::kFlagExact) && (p.flags & snk::kFlagGradI))
+        return fail(c, SNK_EINVAL, "flags bits 1 (exact sums) and 2 (gradient-form centre force) exclude each other");
     return SNK_OK;
 }
 
@@ -372,6 +375,15 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
         if (sh.tile > 0 && (lanes < 64 || layout == snk::kGlobalPlain))
             return fail(c, SNK_EINVAL, "LDS boxes need lanes_per_contour >= 64 and layout 1 or 2");
         a.tile_cap = sh.tile;
+        if (c->P.flags & snk::kFlagGradI) {
+            // gradient-form centre force: whole-wave groups, two pair-points in flight
+            if (c->lanes > 0 && c->lanes < 64)
+                return fail(c, SNK_EINVAL, "the gradient-form centre force needs lanes_per_contour >= 64");
+            if (layout == snk::kGlobalPlain)
+                return fail(c, SNK_EINVAL, "the gradient-form centre force needs layout 1 or 2");
+            lanes = std::max(lanes, 64);
+            unroll = 2;
+        }
     }
     if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M, 0) > 65536)
         return fail(c, SNK_EINVAL, "n_rays too large for the evolve kernel's LDS (64 KiB per workgroup)");

@@ -418,6 +418,36 @@ __device__ __forceinline__ float trilerp(const Corners<DIM> &c, const float f[3]
     }
 }
 
+// Trilinear (bilinear) value with the same operations as trilerp, and its gradient with respect to
+// the voxel coordinates in the same cell.
+template <int DIM>
+__device__ __forceinline__ float trilerp_grad(const Corners<DIM> &c, const float f[3], float g[3]) {
+    const float d0 = c.v[1] - c.v[0], d1 = c.v[3] - c.v[2];
+    const float a0 = fmaf(f[0], d0, c.v[0]);
+    const float a1 = fmaf(f[0], d1, c.v[2]);
+    const float e0 = a1 - a0;
+    const float b0 = fmaf(f[1], e0, a0);
+    const float q0 = fmaf(f[1], d1 - d0, d0);
+    if constexpr (DIM == 2) {
+        g[0] = q0;
+        g[1] = e0;
+        g[2] = 0.0f;
+        return b0;
+    } else {
+        const float d2 = c.v[5] - c.v[4], d3 = c.v[7] - c.v[6];
+        const float a2 = fmaf(f[0], d2, c.v[4]);
+        const float a3 = fmaf(f[0], d3, c.v[6]);
+        const float e1 = a3 - a2;
+        const float b1 = fmaf(f[1], e1, a2);
+        const float q1 = fmaf(f[1], d3 - d2, d2);
+        const float gz = b1 - b0;
+        g[0] = fmaf(f[2], q1 - q0, q0);
+        g[1] = fmaf(f[2], e1 - e0, e0);
+        g[2] = gz;
+        return fmaf(f[2], gz, b0);
+    }
+}
+
 // Per-contour quantities of one iteration that the sampler reads.
 template <int DIM>
 struct Frame {
@@ -436,9 +466,11 @@ struct Frame {
 // Point x = anchor + off + rad * du (voxel units) -> corner index and fractions. CLAMP = false is
 // used only when every sample of the iteration is known to lie inside, where both agree. SMALL: the
 // row and plane strides fit 24-bit multiplies (buffer layouts).
+// out (CLAMP only, may be null): per axis 0.0 where the coordinate lies beyond the volume's faces
+// (the clamped interpolant is flat there), else 1.0; the last face itself counts as inside.
 template <int DIM, bool CLAMP, bool SMALL>
 __device__ __forceinline__ long locate(const Frame<DIM> &fr, const int n[3], int nx, int nxy, const float w[3],
-                                       float f[3]) {
+                                       float f[3], float *in = nullptr) {
     if constexpr (!CLAMP) {
         int i[3] = {0, 0, 0};
 #pragma unroll
@@ -463,6 +495,7 @@ __device__ __forceinline__ long locate(const Frame<DIM> &fr, const int n[3], int
             const float fl = floorf(w[a]);
             int i = fr.anc[a] + (int)fl;
             float fa = w[a] - fl;
+            if (in) in[a] = (i < 0 || i > n[a] - 1 || (i == n[a] - 1 && fa > 0.0f)) ? 0.0f : 1.0f;
             if (i < 0) {
                 i = 0;
                 fa = 0.0f;
@@ -489,14 +522,17 @@ __device__ __forceinline__ float cube_or_square_root(float tau) {
 
 // Sums of one lane for one iteration over pair-points q = gl, gl + G, ... < P (pair m = q / L,
 // radial index l = q % L), U pair-points in flight.
-template <int DIM, int G, int U, bool CLAMP, typename V>
+// GRADI: the centre sums are sum S grad I (voxel-coordinate gradient of the interpolant, zero along
+// axes beyond a face) instead of sum -dS/dr I u / h.
+template <int DIM, int G, int U, bool CLAMP, bool GRADI = false, typename V>
 __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, const float4 *pu,
                                           int P, int L, float invL, int gl, int l0, int m0, int dl, int dm,
                                           float acc[2 + DIM]) {
     int l = l0, m = m0;
     for (int q = gl; q < P; q += G * U) {
         Corners<DIM> cp[U], cm[U];
-        float fp[U][3], fm[U][3], rad[U];
+        float fp[U][3], fm[U][3], d1s[U], d2s[U];
+        float inp[U][3], inm[U][3];
         int mk[U];
         bool ok[U];
 #pragma unroll
@@ -505,17 +541,23 @@ __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, co
             mk[k] = ok[k] ? m : 0;
             const float4 d = pu[mk[k]];
             const float tau = ((float)l + d.w) * invL;
-            rad[k] = fr.smax * cube_or_square_root<DIM>(tau);
+            const float e = cube_or_square_root<DIM>(tau);
+            const float rad = fr.smax * e;
+            // offsets from the ramp centres, fused explicitly so every instance rounds them alike
+            d1s[k] = fmaf(fr.smax, e, -fr.ain);
+            d2s[k] = fmaf(fr.smax, e, -fr.R);
             float wp[3] = {0.0f, 0.0f, 0.0f}, wm[3] = {0.0f, 0.0f, 0.0f};
             const float du[3] = {d.x, d.y, d.z};
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                wp[a] = fmaf(rad[k], du[a], fr.off[a]);
-                wm[a] = fmaf(-rad[k], du[a], fr.off[a]);
+                wp[a] = fmaf(rad, du[a], fr.off[a]);
+                wm[a] = fmaf(-rad, du[a], fr.off[a]);
             }
             constexpr bool SMALL = V::kSmall;
-            const long ip = locate<DIM, CLAMP, SMALL>(fr, vol.n, vol.nx, vol.nxy, wp, fp[k]);
-            const long im = locate<DIM, CLAMP, SMALL>(fr, vol.n, vol.nx, vol.nxy, wm, fm[k]);
+            const long ip = locate<DIM, CLAMP, SMALL>(fr, vol.n, vol.nx, vol.nxy, wp, fp[k],
+                                                      GRADI && CLAMP ? inp[k] : nullptr);
+            const long im = locate<DIM, CLAMP, SMALL>(fr, vol.n, vol.nx, vol.nxy, wm, fm[k],
+                                                      GRADI && CLAMP ? inm[k] : nullptr);
             vol.load(ip, cp[k]);
             vol.load(im, cm[k]);
             l += dl;
@@ -530,9 +572,10 @@ __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, co
         // together
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const float Ip = trilerp<DIM>(cp[k], fp[k]);
-            const float Im = trilerp<DIM>(cm[k], fm[k]);
-            const float d1 = rad[k] - fr.ain, d2 = rad[k] - fr.R;
+            float gp[3], gm[3];
+            const float Ip = GRADI ? trilerp_grad<DIM>(cp[k], fp[k], gp) : trilerp<DIM>(cp[k], fp[k]);
+            const float Im = GRADI ? trilerp_grad<DIM>(cm[k], fm[k], gm) : trilerp<DIM>(cm[k], fm[k]);
+            const float d1 = d1s[k], d2 = d2s[k];
             const bool r1 = d1 >= -fr.hd && d1 < fr.hd;   // inner ramp
             const bool r2 = d2 >= -fr.hD && d2 < fr.hD;   // outer ramp
             const float sin_ = __builtin_amdgcn_fmed3f(d1 * fr.is, -1.0f, 1.0f);
@@ -545,11 +588,20 @@ __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, co
             const float Is = Ip + Im, Id = Ip - Im;
             acc[0] = fmaf(S, Is, acc[0]);
             acc[1] = fmaf(cR, Is, acc[1]);
-            const float g = cC * Id;
-            const float4 d = pu[mk[k]];
-            acc[2] = fmaf(-g, d.x, acc[2]);
-            acc[3] = fmaf(-g, d.y, acc[3]);
-            if constexpr (DIM == 3) acc[4] = fmaf(-g, d.z, acc[4]);
+            if constexpr (GRADI) {
+                // both points share the radius, hence S
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const float gsum = CLAMP ? fmaf(gp[a], inp[k][a], gm[a] * inm[k][a]) : gp[a] + gm[a];
+                    acc[2 + a] = fmaf(S, gsum, acc[2 + a]);
+                }
+            } else {
+                const float g = cC * Id;
+                const float4 d = pu[mk[k]];
+                acc[2] = fmaf(-g, d.x, acc[2]);
+                acc[3] = fmaf(-g, d.y, acc[3]);
+                if constexpr (DIM == 3) acc[4] = fmaf(-g, d.z, acc[4]);
+            }
         }
     }
 }
@@ -762,7 +814,7 @@ __device__ __forceinline__ int uni(int v) {
 // and its barriers are workgroup-uniform.
 // STAGE (whole-wave groups): iterations whose ball fits a box of tile_cap voxels read their corners
 // from an LDS box at lds_tile, the others from the volume in LAYOUT.
-template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false>
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false, bool GRADI = false>
 __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int target, float *trace_row,
                           float *lds_draws, float *lds_red, unsigned long long *counter, float *lds_tile = nullptr,
                           int tile_cap = 0) {
@@ -893,11 +945,11 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                     Frame<DIM> ft = fr;
                     ft.base = (anc[0] - tile.lo[0]) + (anc[1] - tile.lo[1]) * tv.nx;
                     if constexpr (DIM == 3) ft.base += (anc[2] - tile.lo[2]) * tv.nxy;
-                    lane_sums<DIM, G, U, false>(tv, ft, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    lane_sums<DIM, G, U, false, GRADI>(tv, ft, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
                 } else if (interior) {
-                    lane_sums<DIM, G, U, false>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    lane_sums<DIM, G, U, false, GRADI>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
                 } else {
-                    lane_sums<DIM, G, U, true>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    lane_sums<DIM, G, U, true, GRADI>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
                 }
             }
         }
@@ -925,6 +977,12 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                 }
                 tot[k] = v;
             }
+        }
+        // gradient form: sum S dI/dv_a (voxel coordinates) -> the units of the weight form's
+        // sum -dS/dr I u_a / h_a, i.e. the physical force divided by h_a
+        if constexpr (GRADI) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) tot[2 + a] *= inv_h[a] * inv_h[a];
         }
 
         // descent step, identical in every lane of the group (multi-wave groups: wave 0 only, the
@@ -1071,8 +1129,9 @@ __host__ __device__ __forceinline__ int lds_floats(int MH) {
 
 // Whole-wave groups with one pair-point in flight fit 64 vector registers: ask for 8 waves per SIMD
 // (a full CU of 4-wave groups holds 8 contours).
-// STAGE: the workgroup's LDS ends with a box of a.tile_cap voxels.
-template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT, bool STAGE>
+// STAGE: the workgroup's LDS ends with a box of a.tile_cap voxels. GRADI: centre force in its
+// image-gradient form.
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT, bool STAGE, bool GRADI>
 __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolve_kernel(EvolveArgs a) {
     extern __shared__ float lds[];
     const int MH = a.p.M / 2;
@@ -1080,7 +1139,7 @@ __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolv
     const int sub = G < 64 ? (int)threadIdx.x / G : 0;
     const int cid = blockIdx.x * Grp<G>::CPB + sub;
     DevContour *slot = cid < a.n ? a.st + cid : nullptr;
-    run_group<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE>(a.p, slot, a.n_iter, 0x7fffffff,
+    run_group<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE, GRADI>(a.p, slot, a.n_iter, 0x7fffffff,
                                                       TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
                                                       lds + sub * per, lds + Grp<G>::CPB * per, a.counter,
                                                       lds + lds_floats<DIM, G>(MH), STAGE ? a.tile_cap : 0);
@@ -1120,13 +1179,37 @@ __global__ __launch_bounds__(G, U == 1 ? 8 : 1) void evolve_batch_kernel(BatchAr
 // Host launchers
 // ---------------------------------------------------------------------------------------------
 
-template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false>
+template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false, bool GRADI = false>
 hipError_t launch_t(const EvolveArgs &a, hipStream_t s) {
     const size_t lds = sizeof(float) * ((size_t)lds_floats<DIM, G>(a.p.M / 2) + (STAGE ? (size_t)a.tile_cap : 0));
     const int blocks = (a.n + Grp<G>::CPB - 1) / Grp<G>::CPB;
-    hipLaunchKernelGGL((evolve_kernel<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE>), dim3(blocks), dim3(Grp<G>::NT), lds,
-                       s, a);
+    hipLaunchKernelGGL((evolve_kernel<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE, GRADI>), dim3(blocks),
+                       dim3(Grp<G>::NT), lds, s, a);
     return hipGetLastError();
+}
+
+// Gradient-form centre force: whole-wave groups, two pair-points in flight, buffer layouts, with or
+// without LDS boxes.
+template <int DIM, int G, bool TRACE>
+hipError_t launch_gradi_l(const EvolveArgs &a, int layout, hipStream_t s) {
+    const bool stage = a.tile_cap > 0;
+    if (layout == kBufferQuad)
+        return stage ? launch_t<DIM, G, 2, TRACE, kBufferQuad, false, true, true>(a, s)
+                     : launch_t<DIM, G, 2, TRACE, kBufferQuad, false, false, true>(a, s);
+    if (layout == kBufferPlain)
+        return stage ? launch_t<DIM, G, 2, TRACE, kBufferPlain, false, true, true>(a, s)
+                     : launch_t<DIM, G, 2, TRACE, kBufferPlain, false, false, true>(a, s);
+    return hipErrorInvalidValue;
+}
+
+template <int DIM, bool TRACE>
+hipError_t launch_gradi_g(const EvolveArgs &a, int lanes, int layout, hipStream_t s) {
+    switch (lanes) {
+        case 64: return launch_gradi_l<DIM, 64, TRACE>(a, layout, s);
+        case 128: return launch_gradi_l<DIM, 128, TRACE>(a, layout, s);
+        case 256: return launch_gradi_l<DIM, 256, TRACE>(a, layout, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // Exact lattice sums read single voxels: plain layouts only.
@@ -1251,6 +1334,11 @@ int max_blocks_g(int lanes, int unroll, int layout, int max_M) {
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, int layout, bool trace,
                          hipStream_t s) {
     if (a.n <= 0 || a.n_iter <= 0) return hipSuccess;
+    if (a.p.flags & kFlagGradI) {
+        if (a.p.flags & kFlagExact) return hipErrorInvalidValue;
+        if (dim == 2) return trace ? launch_gradi_g<2, true>(a, lanes, layout, s) : launch_gradi_g<2, false>(a, lanes, layout, s);
+        return trace ? launch_gradi_g<3, true>(a, lanes, layout, s) : launch_gradi_g<3, false>(a, lanes, layout, s);
+    }
     if (a.p.flags & kFlagExact) {
         if (layout == kBufferQuad) return hipErrorInvalidValue;
         if (dim == 2) return trace ? launch_exact_g<2, true>(a, lanes, layout, s) : launch_exact_g<2, false>(a, lanes, layout, s);
@@ -1280,9 +1368,9 @@ int stage_blocks_t(int layout) {
     int nb = 0;
     hipError_t e = layout == kBufferQuad
                        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, evolve_kernel<DIM, G, U, false, kBufferQuad, false, true>, Grp<G>::NT, 0)
+                             &nb, evolve_kernel<DIM, G, U, false, kBufferQuad, false, true, false>, Grp<G>::NT, 0)
                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, evolve_kernel<DIM, G, U, false, kBufferPlain, false, true>, Grp<G>::NT, 0);
+                             &nb, evolve_kernel<DIM, G, U, false, kBufferPlain, false, true, false>, Grp<G>::NT, 0);
     return e == hipSuccess ? nb : 0;
 }
 

@@ -49,6 +49,7 @@ struct JobParams {
 // snk_params.flags bits.
 constexpr int kFlagNoRotation = 1;  // random rotation off (Q = I)
 constexpr int kFlagExact = 2;       // exact lattice sums over the ball instead of Monte-Carlo samples
+constexpr int kFlagGradI = 4;       // centre force from sum S grad I (Monte-Carlo, whole-wave groups)
 
 // How the evolve kernels read the smoothed volume.
 enum VolumeLayout {

@@ -12,6 +12,8 @@ Bars (stated per test):
 """
 import sys
 
+import copy
+
 import numpy as np
 import pytest
 
@@ -81,7 +83,7 @@ def tol_check(name, got, ref, ref_abs, slack, rel=1e-5):
 
 
 def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, unroll=0, layout=0,
-                    max_kinked=0.2):
+                    max_kinked=0.2, tile=-1):
     p = wl.params
     rng = np.random.default_rng(seed)
     seeds = np.concatenate([wl.seeds, extra_seeds(wl, n_extra, rng)]) if n_extra else wl.seeds
@@ -90,7 +92,7 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, 
     r0[: len(wl.seeds)] = p.r_init
     J = oracle.prepass(wl.raw, p)
     st = oracle.init_state(p, seeds, r0=r0, ids=ids, shape_zyx=wl.raw.shape)
-    ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout)
+    ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout, tile=tile)
     ctx.load_seeds(seeds, r0=r0.astype(np.float32), ids=ids)
     worst = {}
     kinked = 0
@@ -289,6 +291,63 @@ def test_free_run_exact(snk, stream):
     ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
     st = ref["state"]
     assert np.array_equal(got["iters"], st.iters)
+    assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+
+
+@pytest.mark.parametrize("which,lanes,layout,tile", [("tiny", 0, 0, -1), ("tiny", 64, 1, 0), ("tiny", 256, 2, 0),
+                                                      ("aniso", 0, 0, -1), ("aniso", 128, 1, 2048),
+                                                      ("plane", 0, 0, -1), ("plane", 128, 1, 0)])
+def test_one_step_parity_gradient_form(snk, stream, which, lanes, layout, tile):
+    """Centre force in its image-gradient form (flags bit 2) against the oracle's, teacher forced,
+    with and without LDS boxes; contours near and beyond the faces take the clamped path, where
+    the gradient along a clamped axis is zero."""
+    if which == "tiny":
+        wl = synth.tiny_config()
+    elif which == "aniso":
+        wl = synth.slab_config(n_target=60, shape_xyz=(100, 77, 23), n_iter=10)
+    else:
+        wl = synth.plane_config(n_target=120, size=256, n_iter=50)
+    wl.params = wl.params.replace(flags=4)
+    say(f"one-step parity, gradient-form centre force: {which}, lanes {lanes}, layout {layout}, tile {tile}")
+    # samples next to a voxel face also count as near a kink (the normal derivative jumps there)
+    one_step_parity(snk, stream, wl, [0, 6], n_extra=48, lanes=lanes, layout=layout, tile=tile, max_kinked=0.6)
+
+
+def test_gradient_form_leaves_energy_and_radius_terms(snk, stream):
+    """Flags bit 2 changes only the centre sums: A, B_R, E_mc and the radius step of one iteration
+    are bit-identical to the weight form's at the same state and launch shape."""
+    wl = synth.tiny_config()
+    rng = np.random.default_rng(4)
+    seeds = np.concatenate([wl.seeds, extra_seeds(wl, 24, rng)])
+    ctx = make_ctx(snk, stream, wl, lanes=128, unroll=2, layout=2)
+    ctx.load_seeds(seeds)
+    ctx.evolve(3)
+    s = ctx.get_state()
+    ctx.close()
+    rows = []
+    for flags in (0, 4):
+        w = copy.copy(wl)
+        w.params = wl.params.replace(flags=flags)
+        ctx = make_ctx(snk, stream, w, lanes=128, unroll=2, layout=2)
+        ctx.load_seeds(seeds)
+        ctx.set_state(s["centers"], s["radii"], s["iters"], s["status"], s["streak"])
+        rows.append(ctx.trace_step())
+        ctx.close()
+    assert np.any(rows[0][:, 2:5] != rows[1][:, 2:5])
+    for col in (0, 1, 5, 6):
+        assert np.array_equal(rows[0][:, col], rows[1][:, col]), col
+
+
+def test_free_run_gradient_form(snk, stream):
+    wl = synth.tiny_config()
+    wl.params = wl.params.replace(flags=4)
+    say("free run tiny, gradient-form centre force: 100 iterations")
+    got = free_run(snk, stream, wl)
+    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    st = ref["state"]
+    assert np.array_equal(got["iters"], st.iters)
+    assert np.array_equal(got["status"], st.status)
     assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
     assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
 
