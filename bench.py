@@ -108,11 +108,14 @@ def main():
     ap.add_argument("--sweep-tile", action="store_true",
                     help="only time the evolve kernel for whole-wave shapes x LDS box capacities, checking "
                          "that every capacity reproduces the box-free result bit for bit")
-    ap.add_argument("--workload", default="slab", choices=["slab", "plane", "batched", "served", "lattice"],
+    ap.add_argument("--workload", default="slab", choices=["slab", "plane", "batched", "served", "lattice", "gradient"],
                     help="slab: the plain path on the slab volume (default); plane: the plain path on the "
                          "8192^2 2D image; batched: 256 uneven subvolumes through the engine vs the plain "
                          "per-volume loop; served: Poisson tile requests; lattice: the slab volume seeded with "
-                         "the initial contour lattice, evolved with and without culling passes")
+                         "the initial contour lattice, evolved with and without culling passes; "
+                         "gradient: the slab with the centre force in its weight form and its image-gradient "
+                         "form (flags bit 2): variance of one iteration's force at fixed states, and "
+                         "accuracy and time of free runs with 64, 32 and 16 rays")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="served: arrival window (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: mean arrivals per second")
     ap.add_argument("--chunk", type=int, default=25, help="served: iterations per engine step")
@@ -148,6 +151,8 @@ def main():
         return bench_served(args)
     if args.workload == "lattice":
         return bench_lattice(args)
+    if args.workload == "gradient":
+        return bench_gradient(args)
     t0 = time.perf_counter()
     wl = synth.slab_config() if args.workload == "slab" else synth.plane_config()
     if args.exact:
@@ -294,6 +299,96 @@ def match_truth(kept, truth, dmax):
             used_t.add(t)
             m += 1
     return m
+
+
+def bench_gradient(args):
+    """Centre force in its weight form (Eqs. (7)-(10)) against its image-gradient form (flags bit 2)
+    on the slab workload. (1) Variance: from the states after 100 iterations, one iteration's
+    centre force is drawn 64 times (iteration numbers 101..164, i.e. independent draws) in both
+    forms; per contour the ratio of the variances is the factor by which the gradient form needs
+    fewer samples for the same noise. (2) Free runs (500 iterations, selection) with 64, 32 and 16
+    rays per iteration and two Philox seeds: median centre error against the generator's nuclei,
+    median distance between the two seeds' final centres (the Monte-Carlo spread), recall, time."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1804_06304_amd import snk
+
+    wl = synth.slab_config()
+    raw = torch.from_numpy(wl.raw).to("cuda:0")
+    truth = wl.truth["centers"]
+    stream = torch.cuda.current_stream()
+
+    def context(params):
+        ctx = snk.Context(0, stream)
+        ctx.set_params(params)
+        ctx.set_directions(wl.dirs)
+        ctx.load_volume(raw)
+        return ctx
+
+    # (1) variance of one iteration's centre force at fixed states
+    base = context(wl.params)
+    base.load_seeds(wl.seeds, ids=wl.ids)
+    base.evolve(100)
+    s = base.get_state()
+    base.close()
+    live = (s["status"] & 0x0F) == 0
+    draws = {}
+    for flags in (0, 4):
+        ctx = context(wl.params.replace(flags=flags))
+        ctx.load_seeds(wl.seeds, ids=wl.ids)
+        rows = []
+        for k in range(64):
+            ctx.set_state(s["centers"], s["radii"], s["iters"] * 0 + 100 + k, s["status"], s["streak"])
+            rows.append(ctx.trace_step()[:, 7:10].copy())
+        ctx.close()
+        draws[flags] = np.stack(rows)  # (64, n, 3): centre steps
+    v_w = draws[0].var(0).sum(1)[live]
+    v_g = draws[4].var(0).sum(1)[live]
+    ok = v_g > 0
+    ratio = v_w[ok] / v_g[ok]
+    mean_gap = np.linalg.norm(draws[0].mean(0) - draws[4].mean(0), axis=1)[live]
+    sd_w = np.sqrt(v_w / 64.0)
+    log(f"variance: {int(live.sum())} live contours after 100 iterations; var(weight)/var(gradient) median "
+        f"{np.median(ratio):.2f}, quartiles {np.percentile(ratio, 25):.2f} / {np.percentile(ratio, 75):.2f}; "
+        f"|mean difference| / sd of the weight-form mean: median {np.median(mean_gap / np.maximum(sd_w, 1e-12)):.2f}")
+
+    # (2) free runs
+    runs = []
+    for flags, M in ((0, 64), (4, 64), (0, 32), (4, 32), (4, 16)):
+        finals = []
+        ms = []
+        for seed in (wl.params.seed, wl.params.seed + 1):
+            ctx = context(wl.params.replace(flags=flags, n_rays=M, seed=seed))
+            ctx.load_seeds(wl.seeds, ids=wl.ids)
+            ctx.evolve(wl.n_iter)
+            ms.append(ctx.get_timing()["evolve_ms"])
+            ctx.finalize()
+            finals.append(ctx.read())
+            ctx.close()
+        a, b = finals
+        err = np.linalg.norm(a["centers"] - truth, axis=1)
+        spread = np.linalg.norm(a["centers"] - b["centers"], axis=1)
+        rspread = np.abs(a["radii"] - b["radii"])
+        kept = a["keep"].astype(bool)
+        m = match_truth(a["centers"][kept], truth, 4.0)
+        row = {"form": "gradient" if flags else "weight", "n_rays": M, "evolve_ms": float(np.mean(ms)),
+               "median_centre_error": float(np.median(err)), "median_seed_spread_centre": float(np.median(spread)),
+               "p90_seed_spread_centre": float(np.percentile(spread, 90)),
+               "median_seed_spread_radius": float(np.median(rspread)), "kept": int(kept.sum()),
+               "recall": m / len(truth), "mean_iterations": float(np.mean(a["iters"]))}
+        runs.append(row)
+        log(f"{row['form']:8s} M {M:2d}: evolve {row['evolve_ms']:.3f} ms, centre error {row['median_centre_error']:.3f}, "
+            f"seed spread centre {row['median_seed_spread_centre']:.3f} (p90 {row['p90_seed_spread_centre']:.3f}), "
+            f"radius {row['median_seed_spread_radius']:.3f}, kept {row['kept']}, recall {row['recall']:.3f}, "
+            f"iterations {row['mean_iterations']:.0f}")
+    line = {"metric": "centre-force variance ratio and fixed-accuracy runs, weight vs image-gradient form",
+            "unit": "ratio", "value": float(np.median(ratio)), "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": wl.name, "state": "after 100 iterations", "draws": 64},
+            "variance_ratio_quartiles": [float(np.percentile(ratio, q)) for q in (25, 50, 75)],
+            "runs": runs}
+    print(json.dumps(line), flush=True)
 
 
 def bench_lattice(args):
