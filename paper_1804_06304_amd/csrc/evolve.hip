@@ -463,6 +463,13 @@ struct Frame {
     float rho_is;          // rho * is
 };
 
+// floor(x) as an integer in one instruction (|x| far below 2^31 here).
+__device__ __forceinline__ int floor_to_int(float x) {
+    int i;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(x));
+    return i;
+}
+
 // Point x = anchor + off + rad * du (voxel units) -> corner index and fractions. CLAMP = false is
 // used only when every sample of the iteration is known to lie inside, where both agree. SMALL: the
 // row and plane strides fit 24-bit multiplies (buffer layouts).
@@ -475,7 +482,7 @@ __device__ __forceinline__ long locate(const Frame<DIM> &fr, const int n[3], int
         int i[3] = {0, 0, 0};
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            i[a] = (int)floorf(w[a]);
+            i[a] = floor_to_int(w[a]);
             f[a] = __builtin_amdgcn_fractf(w[a]);
         }
         if constexpr (SMALL) {

@@ -22,7 +22,7 @@ namespace snk {
 namespace {
 
 constexpr int SEL_T = 1024;
-constexpr int kSelectGridMin = 4096;   // contours above which the plain path bins and decides grid-wide
+constexpr int kSelectGridMin = 1024;   // contours above which the plain path bins and decides grid-wide
 constexpr int kSelectGridRounds = 6;   // grid-wide decision rounds before the single-workgroup finish
 
 // Threads per contour of the exact energy: a 3D ball holds thousands of lattice points, a disk
