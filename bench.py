@@ -485,6 +485,7 @@ def bench_batched(args):
     vu_of = lambda outs: sum(int(o["iters"].sum()) * w.params.n_rays for w, o in zip(jobs, outs))
 
     ctx = snk.Context(0, stream)
+    ctx.set_tile(args.tile)
     outs = [plain_pass(snk, ctx, w, r) for w, r in zip(jobs[:8], raws[:8])]   # warm up
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -144,8 +144,10 @@ snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs
 /* LDS box of the Monte-Carlo evolution (whole-wave launch shapes, layouts 1 and 2): each contour
  * keeps a box of the smoothed volume around its sample ball (Sec. II-E) in on-chip memory, staged
  * with a margin and re-staged only when the ball leaves it, and reads the trilinear corners of its
- * samples from there. tile_voxels = -1: automatic capacity, 0: off (every corner read from the
- * volume), 1..16384: capacity in voxels (4 bytes each). An iteration whose ball does not fit, or
+ * samples from there. tile_voxels = -1: automatic (boxes only when more than four contours per
+ * compute unit must stay resident, where their footprints overflow the L2: the largest capacity
+ * that keeps them all resident), 0: off (every corner read from the volume), 1..16384: capacity in
+ * voxels (4 bytes each). An iteration whose ball does not fit, or
  * reaches the volume's edge, reads the volume. Results are bit-identical with and without the box.
  * SNK_EINVAL if tile_voxels is out of range, or at the next evolve if the box and the kernel's other
  * LDS exceed 64 KiB per workgroup. */

@@ -290,11 +290,12 @@ struct McShape {
 };
 
 // Launch shape of a Monte-Carlo evolve over `layout`. Explicit knobs are taken as set. The automatic
-// LDS box applies when every contour can stay resident at once, ceil(n / CUs) workgroups per CU
-// (the common case of one volume with a few thousand cells): two waves per contour when a contour
-// has at least four pair-points per lane of them, else one (unless set), two pair-points in flight,
-// and the largest box whose LDS still leaves room for all of them. Otherwise no box and the lane
-// rule of pick_lanes.
+// LDS box applies when every contour can stay resident at once, ceil(n / CUs) workgroups per CU,
+// and there are more than four of them per CU (the common case of one volume with a few thousand
+// cells: their footprints overflow the L2, which a handful of contours per CU do not, where
+// staging only adds latency): two waves per contour when a contour has at least four pair-points
+// per lane of them, else one (unless set), two pair-points in flight, and the largest box whose
+// LDS still leaves room for all of them. Otherwise no box and the lane rule of pick_lanes.
 McShape mc_shape(snk_ctx *c, int M, int layout) {
     McShape s;
     s.lanes = pick_lanes(c);
@@ -307,6 +308,8 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
     if (c->tile_req == 0 || c->n <= 0 || c->cus <= 0 || c->lds_per_cu <= 0) return s;
     if (layout != snk::kBufferQuad && layout != snk::kBufferPlain) return s;
     const int64_t pairs = (int64_t)(M / 2) * c->P.n_radial;
+    const int64_t per_cu = (c->n + c->cus - 1) / c->cus;
+    if (per_cu <= 4) return s;
     const int G = c->lanes > 0 ? c->lanes : (pairs >= 512 ? 128 : (pairs >= 128 ? 64 : 0));
     if (G < 64) return s;
     const int U = c->unroll > 0 ? c->unroll : 2;
@@ -315,7 +318,6 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
         c->stage_blocks = snk::evolve_stage_blocks_per_cu(c->P.dim, G, U, layout);
         c->stage_key = key;
     }
-    const int64_t per_cu = (c->n + c->cus - 1) / c->cus;
     if (per_cu > c->stage_blocks) return s;
     const size_t other = snk::evolve_lds_bytes(c->P.dim, G, M, 0);
     // LDS is handed out in 512-byte blocks

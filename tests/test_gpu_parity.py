@@ -231,7 +231,7 @@ def test_lds_box_bitwise(snk, stream, which):
     layout = 2 if wl.params.dim == 3 else 1
     for lanes, unroll in ((64, 2), (128, 1), (256, 2)):
         ref = None
-        for tile in (0, 512, 3000, -1):
+        for tile in (0, 512, 3000, 12000, -1):
             say(f"lds box {which}: lanes {lanes} pairs {unroll} tile {tile}")
             ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout, tile=tile)
             ctx.load_seeds(seeds, ids=ids)
@@ -241,7 +241,8 @@ def test_lds_box_bitwise(snk, stream, which):
             used = ctx.get_timing()["tile_voxels"]
             ctx.close()
             if tile == -1:
-                assert used > 0, "automatic shape with few contours should stage boxes"
+                # a few contours per CU fit the L2: the automatic shape stages no boxes
+                assert used == 0
             if ref is None:
                 ref = (got, e_mc)
                 continue
