@@ -65,6 +65,13 @@ def lib():
         L.orc_interp.argtypes = [vp, i64, i64, i64, C.c_int, d, d, d]; L.orc_interp.restype = d
         L.orc_interp_grad.argtypes = [vp, i64, i64, i64, C.c_int, d, d, d, P(d)]
         L.orc_interp_grad.restype = d
+        L.orc_star_tables.argtypes = [C.c_int, vp, i32, vp, vp, vp, i32]
+        L.orc_star_tables.restype = i32
+        L.orc_star_step_terms.argtypes = [vp, i64, i64, i64, P(_Params), vp, vp, vp, vp, d, P(d), vp, u32, u32,
+                                          P(d), vp, vp, vp, vp, vp, vp]
+        L.orc_star_evolve.argtypes = [vp, i64, i64, i64, P(_Params), vp, vp, vp, vp, d, i64, vp, vp, vp, vp,
+                                      vp, vp, vp, vp, i32]
+        L.orc_star_evolve.restype = i64
         L.orc_rotation.argtypes = [P(_Params), u32, u32, P(d)]
         L.orc_initial_radius.argtypes = [P(_Params), d]; L.orc_initial_radius.restype = d
         L.orc_evolve.argtypes = [vp, i64, i64, i64, P(_Params), vp, i64, vp, vp, vp, vp, vp, vp, vp,
@@ -172,6 +179,86 @@ def interp_grad(J: np.ndarray, dim: int, v):
     val = lib().orc_interp_grad(_ptr(J), nx, ny, nz, int(dim), float(v[0]), float(v[1]),
                                 float(v[2]) if len(v) > 2 else 0.0, g)
     return val, np.array(g[:dim])
+
+
+def star_tables(dirs, dim: int):
+    """Direction tables of the star contour: (anti, nb_off, nb_idx); raises if the table has no
+    antipodes."""
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    D = len(d)
+    anti = np.zeros(D, np.int32)
+    off = np.zeros(D + 1, np.int32)
+    cap = 16 * D
+    idx = np.zeros(cap, np.int32)
+    r = lib().orc_star_tables(int(dim), _ptr(d), D, _ptr(anti), _ptr(off), _ptr(idx), cap)
+    if r < 0:
+        raise ValueError("direction table without antipodes" if r == -1 else "direction graph too large")
+    return anti, off, idx[:r].copy()
+
+
+def star_step_terms(J, p, dirs, tables, lam, c, Rk, n, cid, want_samples=False):
+    """One star iteration's terms at (c, R_k) without updating: E, g_c, dc (+ magnitudes, slack)
+    and the radius steps before clamping (+ magnitudes, slack)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    anti, off, idx = tables
+    ps = params_struct(p)
+    D = p.n_dirs
+    out = (C.c_double * 18)()
+    cc = (C.c_double * 3)(*[float(v) for v in list(c) + [0.0] * (3 - len(c))])
+    R = np.ascontiguousarray(Rk, dtype=np.float64)
+    dR, dRa, dRs = np.zeros(D), np.zeros(D), np.zeros(D)
+    N = p.n_rays * p.n_radial
+    pts = np.zeros((N, 3)) if want_samples else None
+    vals = np.zeros(N) if want_samples else None
+    rdir = np.zeros(N, np.int32) if want_samples else None
+    lib().orc_star_step_terms(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), _ptr(anti), _ptr(off), _ptr(idx),
+                              float(lam), cc, _ptr(R), int(n), int(cid), out, _ptr(dR), _ptr(dRa), _ptr(dRs),
+                              _ptr(pts) if want_samples else None, _ptr(vals) if want_samples else None,
+                              _ptr(rdir) if want_samples else None)
+    o = np.array(out[:])
+    res = {"E": o[0], "E_abs": o[1], "g_c": o[2:5], "g_c_abs": o[5:8], "dc": o[8:11], "dc_abs": o[11:14],
+           "dc_slack": o[14:17], "n_kink": int(o[17]), "dR": dR, "dR_abs": dRa, "dR_slack": dRs}
+    if want_samples:
+        res["pts"], res["vals"], res["ray_dir"] = pts, vals, rdir
+    return res
+
+
+class StarState:
+    """Star contours: centres (n x 3 physical), radii per direction (n x D), mean radii, counters."""
+
+    def __init__(self, c, Rk, ids):
+        n = len(c)
+        self.c = np.ascontiguousarray(c, dtype=np.float64).copy()
+        self.Rk = np.ascontiguousarray(Rk, dtype=np.float64).copy()
+        self.R = self.Rk.mean(axis=1)
+        self.ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        self.iters = np.zeros(n, np.int32)
+        self.status = np.zeros(n, np.uint8)
+        self.streak = np.zeros(n, np.uint8)
+        self.e_mc = np.zeros(n)
+
+
+def star_init(p, seeds, r0=None, ids=None, shape_zyx=None):
+    """Initial star state: every direction's radius at the clamped R0 (as init_state), centres at
+    the seeds (OUT when a seed lies outside the volume)."""
+    st = init_state(p, seeds, r0=r0, ids=ids, shape_zyx=shape_zyx)
+    s = StarState(st.c, np.repeat(st.R[:, None], p.n_dirs, axis=1), st.ids)
+    s.status[:] = st.status
+    return s
+
+
+def star_evolve(J, p, dirs, tables, lam, st: StarState, n_iter: int) -> int:
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    anti, off, idx = tables
+    ps = params_struct(p)
+    n = len(st.c)
+    return lib().orc_star_evolve(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), _ptr(anti), _ptr(off), _ptr(idx),
+                                 float(lam), n, _ptr(st.ids), _ptr(st.c), _ptr(st.Rk), _ptr(st.R),
+                                 _ptr(st.iters), _ptr(st.status), _ptr(st.streak), _ptr(st.e_mc), int(n_iter))
 
 
 def initial_radius(p, r0: float) -> float:

@@ -29,6 +29,9 @@
  *     gradient of the trilinear interpolant (zero along axes clamped at the faces). It has the
  *     same expectation as the weight-derivative form of Eqs. (7)-(10) (a variance-reduction
  *     option, not in the paper); the radius force is unchanged;
+ *   - star-shaped contours (not in the paper: a builder-defined extension whose radius varies with
+ *     the table direction, with a smoothing energy over the direction graph; it reduces to the
+ *     sphere when the radii are tied; see the block before orc_star_tables);
  *   - stopping on maximum iterations or convergence, overlap competition with the lower energy
  *     surviving (||c' - c''|| < max(R', R'')*rho), and the energy threshold E0 (Results).
  *
@@ -954,6 +957,298 @@ int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const dou
     free(acc);
     free(keys);
     return retired;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Star-shaped contours (not in the paper: a builder-defined extension of its sphere). A contour */
+/* has one radius R_k per table direction T_k; the directions stay fixed in space (no rotation). */
+/* Energy: the table average of per-direction radial energies,                                  */
+/*   E = (1/D) sum_k e_k,  e_k = (2 R_k)^-d omega_d d integral_0^inf S(s; R_k) I(c + s T_k) s^(d-1) ds, */
+/* which is the sphere's energy (Eq. (5), the direction integral taken as the table average)    */
+/* when every R_k equals R. Smoothing over the direction graph: each radius relaxes toward the   */
+/* mean m_k of its neighbours' by the fraction min(1, eps lambda / 2) (a Laplacian step whose    */
+/* rate is capped, so it stays stable while eps is large).                                      */
+/* One iteration draws the sphere sampler's Philox pairs with Q = I: pair m picks k; its rays run */
+/* along +T_k with radius R_k and along -T_k with the radius of the antipodal direction; ray     */
+/* points s = (R + dR/2) ((l + xi)/L)^(1/d). With the per-point weight                          */
+/*   q(R) = (2R)^-d omega_d (R + dR/2)^d / (M L)                                                  */
+/* E = sum q S I, g_c = sum q (-dS/dr I u), and for each sampled direction k                     */
+/*   g_k = sum over the rays along k of q (B_R,ray - (d / R_k) A_ray),                           */
+/* an unbiased estimate of dE/dR_k (a ray picks k with probability 1/D). Step: c -= (eps/2) g_c; */
+/* R_k -= (eps/2) D g_k + min(1, eps lambda / 2) (R_k - m_k), all from the old radii: each radius */
+/* is stepped as if it were the contour's only one, so tied radii take the sphere's step on      */
+/* average (and the smoothing leaves tied radii alone).                                          */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Direction tables of the star contour: anti[k] = the direction opposite T_k (|T_j + T_k| <
+ * 1e-4, else -1 is returned), and the direction graph: the 6 (3D) or 2 (2D) nearest directions of
+ * each (largest dot product, ties to the lower index), made symmetric; N(k) is
+ * nb_idx[nb_off[k] .. nb_off[k+1]) in ascending order. Returns the number of entries, or -2 if
+ * they exceed cap. */
+int32_t orc_star_tables(int dim, const double *dirs, int32_t D, int32_t *anti, int32_t *nb_off, int32_t *nb_idx,
+                        int32_t cap)
+{
+    const int deg = dim == 3 ? 6 : 2;
+    for (int32_t k = 0; k < D; ++k) {
+        int32_t best = -1;
+        double bd = 1e30;
+        for (int32_t j = 0; j < D; ++j) {
+            double e2 = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                double t = dirs[j * dim + a] + dirs[k * dim + a];
+                e2 += t * t;
+            }
+            if (e2 < bd) { bd = e2; best = j; }
+        }
+        if (!(sqrt(bd) < 1e-4)) return -1;
+        anti[k] = best;
+    }
+    /* k-nearest lists */
+    int32_t *knn = (int32_t *)malloc(sizeof(int32_t) * (size_t)D * deg);
+    for (int32_t k = 0; k < D; ++k) {
+        int taken = 0;
+        while (taken < deg) {
+            int32_t best = -1;
+            double bd = -2.0;
+            for (int32_t j = 0; j < D; ++j) {
+                if (j == k) continue;
+                int used = 0;
+                for (int t = 0; t < taken; ++t) used |= knn[k * deg + t] == j;
+                if (used) continue;
+                double dt = 0.0;
+                for (int a = 0; a < dim; ++a) dt += dirs[j * dim + a] * dirs[k * dim + a];
+                if (dt > bd) { bd = dt; best = j; }
+            }
+            knn[k * deg + taken++] = best;
+        }
+    }
+    /* symmetric closure, ascending */
+    int32_t total = 0;
+    nb_off[0] = 0;
+    for (int32_t k = 0; k < D; ++k) {
+        for (int32_t j = 0; j < D; ++j) {
+            if (j == k) continue;
+            int edge = 0;
+            for (int t = 0; t < deg; ++t) edge |= knn[k * deg + t] == j || knn[j * deg + t] == k;
+            if (!edge) continue;
+            if (total >= cap) { free(knn); return -2; }
+            nb_idx[total++] = j;
+        }
+        nb_off[k + 1] = total;
+    }
+    free(knn);
+    return total;
+}
+
+typedef struct {
+    double E, Eabs, gc[3], gcabs[3], gcsl[3];
+    double *gk, *gkabs, *gksl;  /* D each */
+    int n_kink;
+    double *pts, *vals;         /* optional: sample positions (N x 3) and values (N) */
+    int32_t *ray_dir;           /* optional: direction whose radius each sample's ray used (N) */
+} orc_star_sums;
+
+/* Sums of one star iteration at (c, R_k) for iteration n (see the block comment above). */
+static void star_sums(const orc_vol *vol, const int32_t *anti, const double c[3], const double *Rk, uint32_t n,
+                      uint32_t id, orc_star_sums *sm)
+{
+    const orc_params *p = vol->p;
+    const int dim = p->dim, M = p->n_rays, L = p->n_radial, D = p->n_dirs;
+    const double rho = rho_of(dim);
+    sm->E = sm->Eabs = 0.0;
+    for (int i = 0; i < 3; ++i) sm->gc[i] = sm->gcabs[i] = sm->gcsl[i] = 0.0;
+    for (int k = 0; k < D; ++k) sm->gk[k] = sm->gkabs[k] = sm->gksl[k] = 0.0;
+    sm->n_kink = 0;
+    for (int m = 0; m < M / 2; ++m) {
+        uint32_t x[4];
+        philox_at(p, (uint32_t)m, n, id, 1u, x);
+        uint32_t k = (uint32_t)(((uint64_t)x[0] * (uint64_t)(uint32_t)D) >> 32);
+        double xi = orc_uniform(x[1]);
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < dim; ++i) t[i] = vol->dirs[(int64_t)k * dim + i];
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            const int32_t kr = sgn ? anti[k] : (int32_t)k;
+            const double R = Rk[kr];
+            const double smax = R + 0.5 * p->dR;
+            const double q = ball_measure(dim) * pow(smax, dim) / pow(2.0 * R, dim) / ((double)M * (double)L);
+            const double a = rho * R, dr = rho * p->dR;
+            const double kinks[4] = {a - 0.5 * dr, a + 0.5 * dr, R - 0.5 * p->dR, R + 0.5 * p->dR};
+            double us[3];
+            for (int i = 0; i < 3; ++i) us[i] = sgn ? -t[i] : t[i];
+            double A = 0.0, Aabs = 0.0, BR = 0.0, BRabs = 0.0, slBR = 0.0;
+            for (int l = 0; l < L; ++l) {
+                double tau = ((double)l + xi) / (double)L;
+                double s = smax * (dim == 3 ? cbrt(tau) : sqrt(tau));
+                double pos[3];
+                for (int i = 0; i < 3; ++i) pos[i] = c[i] + s * us[i];
+                double I = orc_interp(vol->J, vol->nx, vol->ny, vol->nz, dim, pos[0] / p->spacing[0],
+                                      pos[1] / p->spacing[1], dim == 3 ? pos[2] / p->spacing[2] : 0.0);
+                double w[3];
+                orc_weight(dim, s, R, p->dR, w);
+                A += w[0] * I; Aabs += fabs(w[0] * I);
+                BR += w[2] * I; BRabs += fabs(w[2] * I);
+                if (sm->pts) {
+                    const int64_t idx = ((int64_t)m * 2 + sgn) * L + l;
+                    for (int i = 0; i < 3; ++i) sm->pts[idx * 3 + i] = pos[i];
+                    sm->vals[idx] = I;
+                    sm->ray_dir[idx] = kr;
+                }
+                sm->E += q * w[0] * I; sm->Eabs += fabs(q * w[0] * I);
+                for (int i = 0; i < dim; ++i) {
+                    sm->gc[i] += q * (-w[1] * I * us[i]);
+                    sm->gcabs[i] += fabs(q * w[1] * I * us[i]);
+                }
+                for (int kk = 0; kk < 4; ++kk) {
+                    if (fabs(s - kinks[kk]) <= ORC_KINK_REL * smax) {
+                        double wl[3], wr[3];
+                        orc_weight(dim, kinks[kk] - 1e-9 * smax, R, p->dR, wl);
+                        orc_weight(dim, kinks[kk] + 1e-9 * smax, R, p->dR, wr);
+                        slBR += fabs((wr[2] - wl[2]) * I);
+                        for (int i = 0; i < dim; ++i) sm->gcsl[i] += fabs(q * (wr[1] - wl[1]) * I * us[i]);
+                        sm->n_kink += 1;
+                    }
+                }
+            }
+            sm->gk[kr] += q * (BR - (double)dim / R * A);
+            sm->gkabs[kr] += q * (BRabs + (double)dim / R * Aabs);
+            sm->gksl[kr] += q * slBR;
+        }
+    }
+}
+
+/* Smoothing fraction of iteration eps. */
+static double star_relax(double eps, double lambda)
+{
+    double f = 0.5 * eps * lambda;
+    return f < 1.0 ? f : 1.0;
+}
+
+/* Radius steps of one star iteration before clamping:
+ * dR_k = -(eps/2) D g_k - min(1, eps lambda / 2) (R_k - m_k). */
+static void star_radius_steps(const orc_params *p, const int32_t *nb_off, const int32_t *nb_idx, double lambda,
+                              const double *Rk, const orc_star_sums *sm, double eps, double *dRk)
+{
+    const double f = star_relax(eps, lambda);
+    for (int32_t k = 0; k < p->n_dirs; ++k) {
+        double sum = 0.0;
+        for (int32_t e = nb_off[k]; e < nb_off[k + 1]; ++e) sum += Rk[nb_idx[e]];
+        const double mk = nb_off[k + 1] > nb_off[k] ? sum / (double)(nb_off[k + 1] - nb_off[k]) : Rk[k];
+        dRk[k] = -0.5 * eps * (double)p->n_dirs * sm->gk[k] - f * (Rk[k] - mk);
+    }
+}
+
+/* Terms of one star iteration at (c, R_k), iteration n, without updating. out: [E, E_abs,
+ * g_c (3), g_c_abs (3), dc (3), dc_abs (3), dc_slack (3), n_kink] (18 values); dRk / dRk_abs /
+ * dRk_slack (D each): the radius steps before clamping, their magnitude scale and kink slack. */
+void orc_star_step_terms(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                         const double *dirs, const int32_t *anti, const int32_t *nb_off, const int32_t *nb_idx,
+                         double lambda, const double c[3], const double *Rk, uint32_t n, uint32_t id, double *out,
+                         double *dRk, double *dRk_abs, double *dRk_slack, double *pts, double *vals,
+                         int32_t *ray_dir)
+{
+    orc_vol vol = {J, nx, ny, nz, p, dirs};
+    const int D = p->n_dirs;
+    orc_star_sums sm;
+    sm.gk = (double *)malloc(sizeof(double) * 3 * (size_t)D);
+    sm.gkabs = sm.gk + D;
+    sm.gksl = sm.gk + 2 * D;
+    sm.pts = pts;
+    sm.vals = vals;
+    sm.ray_dir = ray_dir;
+    star_sums(&vol, anti, c, Rk, n, id, &sm);
+    const double eps = p->eps0 / sqrt((double)n);
+    out[0] = sm.E; out[1] = sm.Eabs;
+    for (int i = 0; i < 3; ++i) {
+        out[2 + i] = sm.gc[i]; out[5 + i] = sm.gcabs[i];
+        out[8 + i] = -0.5 * eps * sm.gc[i]; out[11 + i] = 0.5 * eps * sm.gcabs[i];
+        out[14 + i] = 0.5 * eps * sm.gcsl[i];
+    }
+    out[17] = (double)sm.n_kink;
+    star_radius_steps(p, nb_off, nb_idx, lambda, Rk, &sm, eps, dRk);
+    const double f = star_relax(eps, lambda);
+    for (int32_t k = 0; k < D; ++k) {
+        double mabs = 0.0;
+        for (int32_t e = nb_off[k]; e < nb_off[k + 1]; ++e) mabs += fabs(Rk[nb_idx[e]]);
+        if (nb_off[k + 1] > nb_off[k]) mabs /= (double)(nb_off[k + 1] - nb_off[k]);
+        dRk_abs[k] = 0.5 * eps * (double)D * sm.gkabs[k] + f * (fabs(Rk[k]) + mabs);
+        dRk_slack[k] = 0.5 * eps * (double)D * sm.gksl[k];
+    }
+    free(sm.gk);
+}
+
+/* Evolve star contours: c (n x 3 physical), Rk (n x D), Rmean (n, written: the mean of R_k), and
+ * the sphere path's per-contour counters; same stop rules, with the move of an iteration the
+ * largest of |dR_k| (after clamping) and |dc|. Returns the contour-iterations run. */
+int64_t orc_star_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                        const double *dirs, const int32_t *anti, const int32_t *nb_off, const int32_t *nb_idx,
+                        double lambda, int64_t n, const uint32_t *ids, double *c, double *Rk, double *Rmean,
+                        int32_t *iters, uint8_t *status, uint8_t *streak, double *e_mc, int32_t n_iter)
+{
+    orc_vol vol = {J, nx, ny, nz, p, dirs};
+    const int dim = p->dim, D = p->n_dirs;
+    int64_t done = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : done)
+    for (int64_t i = 0; i < n; ++i) {
+        double *R = &Rk[i * D];
+        orc_star_sums sm;
+        sm.pts = sm.vals = NULL;
+        sm.ray_dir = NULL;
+        sm.gk = (double *)malloc(sizeof(double) * 4 * (size_t)D);
+        sm.gkabs = sm.gk + D;
+        sm.gksl = sm.gk + 2 * D;
+        double *dR = sm.gk + 3 * D;
+        for (int32_t it = 0; it < n_iter; ++it) {
+            if ((status[i] & 0x0f) != ORC_ACTIVE) break;
+            uint32_t nn = (uint32_t)(iters[i] + 1);
+            iters[i] = (int32_t)nn;
+            double *ci = &c[i * 3];
+            star_sums(&vol, anti, ci, R, nn, ids[i], &sm);
+            const double eps = p->eps0 / sqrt((double)nn);
+            star_radius_steps(p, nb_off, nb_idx, lambda, R, &sm, eps, dR);
+            const double lo = r_low(p), hi = p->r_max;
+            uint8_t flag = status[i] & ORC_CLAMPED;
+            double move = 0.0, sum = 0.0;
+            int finite = isfinite(sm.E);
+            for (int32_t k = 0; k < D; ++k) {
+                double Rn = R[k] + dR[k];
+                if (Rn < lo) { Rn = lo; flag = ORC_CLAMPED; }
+                if (Rn > hi) { Rn = hi; flag = ORC_CLAMPED; }
+                finite = finite && isfinite(Rn);
+                if (fabs(Rn - R[k]) > move) move = fabs(Rn - R[k]);
+                R[k] = Rn;
+                sum += Rn;
+            }
+            double dcn = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                double d = -0.5 * eps * sm.gc[a];
+                ci[a] += d;
+                dcn += d * d;
+                finite = finite && isfinite(ci[a]);
+            }
+            dcn = sqrt(dcn);
+            if (dcn > move) move = dcn;
+            Rmean[i] = sum / (double)D;
+            e_mc[i] = sm.E;
+            uint8_t st = ORC_ACTIVE;
+            if (!finite) {
+                st = ORC_NONFINITE;
+            } else {
+                for (int a = 0; a < dim; ++a) {
+                    int64_t na = a == 0 ? nx : (a == 1 ? ny : nz);
+                    if (ci[a] < 0.0 || ci[a] > (double)(na - 1) * p->spacing[a]) st = ORC_OUT;
+                }
+            }
+            if (st == ORC_ACTIVE) {
+                if (move < p->conv_tol) streak[i] = (uint8_t)(streak[i] < 255 ? streak[i] + 1 : 255);
+                else streak[i] = 0;
+                if (p->conv_window > 0 && streak[i] >= p->conv_window) st = ORC_CONVERGED;
+            }
+            status[i] = (uint8_t)(st | flag);
+            done += 1;
+        }
+        free(sm.gk);
+    }
+    return done;
 }
 
 int orc_num_threads(void)

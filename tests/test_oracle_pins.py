@@ -510,6 +510,171 @@ def test_gradient_form_unbiased(orc, dim):
     assert np.all(z < 4.5), (mean, ref, z)
 
 
+# ------------------------------------------------------------------------------------------
+# star-shaped contours (per-direction radii; not in the paper)
+# ------------------------------------------------------------------------------------------
+
+def test_star_tables_geometry(orc):
+    """Antipodes are the opposite directions; the 2D ring's graph links each angle to its two
+    neighbours only; the icosphere graph is symmetric, contains every vertex's nearest neighbour
+    and has degrees 5..8 (6-nearest made symmetric)."""
+    ring = synth.circle_directions(64)
+    anti, off, idx = orc.star_tables(ring, 2)
+    assert np.allclose(ring[anti], -ring, atol=1e-12)
+    for k in range(64):
+        assert sorted(idx[off[k]:off[k + 1]]) == sorted([(k - 1) % 64, (k + 1) % 64])
+    for sub in (2, 3):
+        ico = synth.icosphere(sub)
+        anti, off, idx = orc.star_tables(ico, 3)
+        assert np.allclose(ico[anti], -ico, atol=1e-6)
+        D = len(ico)
+        nb = [set(idx[off[k]:off[k + 1]].tolist()) for k in range(D)]
+        dots = ico @ ico.T
+        np.fill_diagonal(dots, -2.0)
+        for k in range(D):
+            assert 5 <= len(nb[k]) <= 8
+            assert int(np.argmax(dots[k])) in nb[k]
+            for j in nb[k]:
+                assert k in nb[j]
+
+
+def _star_case(orc, dim):
+    if dim == 3:
+        J = _smooth_volume((24, 26, 28))
+        p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, flags=1)
+        dirs = synth.icosphere(2)
+        c = np.array([13.3, 12.1, 11.7])
+    else:
+        J = _smooth_volume((1, 40, 44))
+        p = synth.Params(dim=2, dR=1.0, n_dirs=64, n_rays=16, n_radial=16, flags=1)
+        dirs = synth.circle_directions(64)
+        c = np.array([21.3, 19.6, 0.0])
+    return J, p, dirs, c
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_star_with_tied_radii_is_the_sphere(orc, dim):
+    """With every R_k equal to R, one star iteration reproduces the sphere's estimator with the
+    rotation off (same Philox draws and points): the energy, the centre force, and the mean over
+    directions of the radius steps (the smoothing terms cancel in it), whatever lambda is."""
+    J, p, dirs, c = _star_case(orc, dim)
+    tables = orc.star_tables(dirs, dim)
+    R = 6.4
+    for n in (1, 2, 9):
+        sph = orc.mc_terms(J, p, dirs, c, R, n, 5)
+        for lam in (0.0, 0.7):
+            st = orc.star_step_terms(J, p, dirs, tables, lam, c, np.full(p.n_dirs, R), n, 5)
+            assert abs(st["E"] - sph["E"]) < 1e-12 * max(1.0, abs(sph["E"]))
+            assert np.allclose(st["g_c"][:dim], sph["g_c"][:dim], rtol=1e-11, atol=1e-14)
+            eps = p.eps0 / math.sqrt(n)
+            assert abs(st["dR"].mean() - (-0.5 * eps * sph["g_R"])) < 1e-11 * (abs(sph["g_R"]) * eps + 1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_star_radius_force_is_frozen_point_derivative(orc, dim):
+    """Untied radii: for each direction sampled in the iteration, D g_k (from the radius step with
+    lambda = 0) equals D times the central difference in R_k of the estimator with its sample points
+    and volume factors held fixed, E = sum over rays of (V_ray / (M L)) (2 R_ray)^-d sum_l S I
+    (the minus ray takes the radius of the antipodal direction)."""
+    J, p, dirs, c = _star_case(orc, dim)
+    tables = orc.star_tables(dirs, dim)
+    rng = np.random.default_rng(3)
+    Rk = rng.uniform(5.5, 7.5, size=p.n_dirs)
+    D, M, L = p.n_dirs, p.n_rays, p.n_radial
+    V = (4.0 / 3.0 * math.pi if dim == 3 else math.pi)
+    for n in (1, 4):
+        t = orc.star_step_terms(J, p, dirs, tables, 0.0, c, Rk, n, 7, want_samples=True)
+        pts, vals, rdir = t["pts"], t["vals"], t["ray_dir"]
+        r = np.linalg.norm(pts[:, :dim] - c[:dim], axis=1)
+        vol = V * (Rk[rdir] + 0.5 * p.dR) ** dim
+
+        def E(R):
+            w = np.array([orc.weight(dim, r[j], R[rdir[j]], p.dR)[0] for j in range(len(r))])
+            return float(np.sum(vol / (M * L) * (2.0 * R[rdir]) ** (-dim) * w * vals))
+
+        # pair m's rays are samples [2m L, (2m + 1) L) along +T_k and [(2m + 1) L, (2m + 2) L) along
+        # -T_k: the minus ray uses the antipodal direction's radius, and at each radial index the
+        # two distances are in the ratio of the rays' R + dR/2
+        anti = tables[0]
+        plus = (np.arange(M // 2)[:, None] * 2 * L + np.arange(L)[None, :]).ravel()
+        minus = plus + L
+        assert np.all(rdir[minus] == anti[rdir[plus]])
+        ratio = r[minus] / r[plus]
+        expect = (Rk[rdir[minus]] + 0.5 * p.dR) / (Rk[rdir[plus]] + 0.5 * p.dR)
+        assert np.allclose(ratio, expect, rtol=1e-12)
+        u = (pts[plus, :dim] - c[:dim]) / r[plus, None]
+        assert np.allclose(u, dirs[rdir[plus]][:, :dim], atol=1e-12)
+        eps = p.eps0 / math.sqrt(n)
+        gk = -2.0 * t["dR"] / (eps * D)
+        assert abs(E(Rk) - t["E"]) < 1e-12 * max(1.0, abs(t["E"]))
+        sampled = np.unique(rdir)
+        assert np.all(gk[np.setdiff1d(np.arange(D), sampled)] == 0.0)
+        h = 1e-6
+        for k in sampled[:12]:
+            Rp, Rm = Rk.copy(), Rk.copy()
+            Rp[k] += h
+            Rm[k] -= h
+            fd = (E(Rp) - E(Rm)) / (2 * h)
+            assert abs(fd - gk[k]) < 1e-6 * (np.abs(gk).max() + 1e-9), (n, k, fd, gk[k])
+
+
+def test_star_smoothing_step_on_empty_image(orc):
+    """On a zero image the radius steps are the smoothing alone: each radius moves toward the mean
+    of its graph neighbours by min(1, eps lambda / 2) of the gap (the neighbour means taken from the
+    graph's symmetric edge list), and tied radii do not move."""
+    J = np.zeros((20, 22, 24))
+    p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=32, n_radial=16, flags=1)
+    dirs = synth.icosphere(2)
+    tables = orc.star_tables(dirs, 3)
+    anti, off, idx = tables
+    nb = {k: set() for k in range(p.n_dirs)}
+    for k in range(p.n_dirs):
+        for j in idx[off[k]:off[k + 1]]:
+            nb[k].add(int(j)); nb[int(j)].add(k)
+    rng = np.random.default_rng(5)
+    Rk = rng.uniform(5.0, 8.0, size=p.n_dirs)
+    c = np.array([10.0, 11.0, 9.5])
+    for lam, n in ((0.35, 3), (0.35, 100), (5.0, 2)):
+        t = orc.star_step_terms(J, p, dirs, tables, lam, c, Rk, n, 1)
+        f = min(1.0, 0.5 * p.eps0 / math.sqrt(n) * lam)
+        for k in range(p.n_dirs):
+            mk = np.mean([Rk[j] for j in nb[k]])
+            assert abs(t["dR"][k] - (-f * (Rk[k] - mk))) < 1e-12
+        assert t["E"] == 0.0 and np.all(t["g_c"] == 0.0)
+    t = orc.star_step_terms(J, p, dirs, tables, 2.0, c, np.full(p.n_dirs, 6.0), 4, 1)
+    assert np.all(t["dR"] == 0.0)
+
+
+def test_star_fits_an_ellipsoid(orc):
+    """Behaviour (not a pin): radii started tied at 8 on a blurred axis-aligned ellipsoid (semi-axes
+    9, 6, 5) spread along its axes without smoothing: along the long axis they end above, along the
+    short axis below, the tied start, apart by most of the cube root of 2 times the axes'
+    difference (the per-direction optimum of the energy is that multiple of the blob's radial
+    extent); strong smoothing keeps them nearly tied; the centre stays on the blob's."""
+    shape = (48, 48, 48)
+    z, y, x = np.meshgrid(*[np.arange(k, dtype=np.float64) for k in shape], indexing="ij")
+    ax = np.array([9.0, 6.0, 5.0])
+    cen = np.array([23.7, 24.2, 23.9])
+    ind = (((x - cen[0]) / ax[0]) ** 2 + ((y - cen[1]) / ax[1]) ** 2 + ((z - cen[2]) / ax[2]) ** 2 < 1.0)
+    from scipy.ndimage import gaussian_filter
+    J = gaussian_filter(ind.astype(float), 1.0)
+    dirs = synth.icosphere(2)
+    p = synth.Params(dim=3, dR=1.0, n_dirs=162, n_rays=64, n_radial=16, flags=1, eps0=8.0, r_max=20.0,
+                     conv_window=0, r_init=8.0)
+    tables = orc.star_tables(dirs, 3)
+    spread = {}
+    for lam in (0.0, 5.0):
+        st = orc.star_init(p, cen[None, :])
+        orc.star_evolve(J, p, dirs, tables, lam, st, 300)
+        along = lambda a: st.Rk[0][np.abs(dirs[:, a]) > 0.9].mean()
+        spread[lam] = along(0) - along(2)
+        if lam == 0.0:
+            assert along(0) > 8.0 > along(2)
+        assert np.linalg.norm(st.c[0] - cen) < 0.5
+    assert spread[0.0] > 0.6 * 2 ** (1 / 3) * (ax[0] - ax[2]), spread
+    assert abs(spread[5.0]) < 0.25 * spread[0.0], spread
+
+
 def test_constant_image_has_no_force(orc):
     """Constant image: the c-force vanishes exactly for antithetic pairs, and A, B_R are zero in
     expectation (Sec. II-B: the energy does not move contours in uniform regions)."""
