@@ -108,14 +108,18 @@ def main():
     ap.add_argument("--sweep-tile", action="store_true",
                     help="only time the evolve kernel for whole-wave shapes x LDS box capacities, checking "
                          "that every capacity reproduces the box-free result bit for bit")
-    ap.add_argument("--workload", default="slab", choices=["slab", "plane", "batched", "served", "lattice", "gradient"],
+    ap.add_argument("--smooth", type=float, default=0.3, help="star: smoothing weight of the star contours")
+    ap.add_argument("--workload", default="slab",
+                    choices=["slab", "plane", "batched", "served", "lattice", "gradient", "star"],
                     help="slab: the plain path on the slab volume (default); plane: the plain path on the "
                          "8192^2 2D image; batched: 256 uneven subvolumes through the engine vs the plain "
                          "per-volume loop; served: Poisson tile requests; lattice: the slab volume seeded with "
                          "the initial contour lattice, evolved with and without culling passes; "
                          "gradient: the slab with the centre force in its weight form and its image-gradient "
                          "form (flags bit 2): variance of one iteration's force at fixed states, and "
-                         "accuracy and time of free runs with 64, 32 and 16 rays")
+                         "accuracy and time of free runs with 64, 32 and 16 rays; star: the slab with "
+                         "star-shaped contours (per-direction radii) against the sphere: time and fit to the "
+                         "generator's ellipsoids")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="served: arrival window (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: mean arrivals per second")
     ap.add_argument("--chunk", type=int, default=25, help="served: iterations per engine step")
@@ -153,6 +157,8 @@ def main():
         return bench_lattice(args)
     if args.workload == "gradient":
         return bench_gradient(args)
+    if args.workload == "star":
+        return bench_star(args)
     t0 = time.perf_counter()
     wl = synth.slab_config() if args.workload == "slab" else synth.plane_config()
     if args.exact:
@@ -299,6 +305,71 @@ def match_truth(kept, truth, dmax):
             used_t.add(t)
             m += 1
     return m
+
+
+def bench_star(args):
+    """Star-shaped contours (one radius per table direction, snk_set_star) against the sphere on the
+    slab workload (500 iterations, selection), both from the same seeds and R0: evolve time and
+    vertex-updates/s, and the fit to the generator's ellipsoids. For each contour kept and matched
+    to its own nucleus, the cell-radius estimate rho R_k along every table direction T_k (rho R for
+    the sphere) is compared with the nucleus' radial extent a(T_k) from its centre: the relative
+    error sum_k |rho R_k - a(T_k)| / sum_k a(T_k), median over contours; also the centre error."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1804_06304_amd import snk
+
+    wl = synth.slab_config()
+    p = wl.params
+    raw = torch.from_numpy(wl.raw).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    truth = wl.truth
+    rho = 2.0 ** (-1.0 / 3.0)
+    T = wl.dirs.astype(np.float64)
+
+    def extent(i):
+        local = T @ truth["rots"][i]          # direction components along the principal axes
+        return 1.0 / np.sqrt(((local / truth["axes"][i]) ** 2).sum(axis=1))
+
+    rows = []
+    for smooth in (-1.0, args.smooth, 0.0):
+        ctx = snk.Context(0, stream)
+        ctx.set_params(p)
+        ctx.set_star(smooth)
+        ctx.set_directions(wl.dirs)
+        ctx.load_volume(raw)
+        ms = []
+        for _ in range(1 + max(1, args.steps)):
+            ctx.load_seeds(wl.seeds, ids=wl.ids)
+            ctx.prepass()
+            ctx.evolve(wl.n_iter)
+            ms.append(ctx.get_timing()["evolve_ms"])
+        evolved = ctx.get_timing()["evolved"]
+        ctx.finalize()
+        out = ctx.read()
+        Rk = ctx.get_star_radii() if smooth >= 0 else np.repeat(out["radii"][:, None], p.n_dirs, axis=1)
+        ctx.close()
+        kept = np.where(out["keep"].astype(bool))[0]
+        cerr = np.linalg.norm(out["centers"][kept] - truth["centers"][kept], axis=1)
+        own = kept[cerr < 4.0]
+        fit = np.array([np.abs(rho * Rk[i] - extent(i)).sum() / extent(i).sum() for i in own])
+        ev = float(np.mean(ms[1:]))
+        row = {"contour": "sphere" if smooth < 0 else "star", "smooth": None if smooth < 0 else smooth,
+               "evolve_ms": ev, "vertex_updates_per_s": evolved * p.n_rays / (ev * 1e-3),
+               "kept": int(len(kept)), "matched": int(len(own)),
+               "median_fit_error": float(np.median(fit)), "p90_fit_error": float(np.percentile(fit, 90)),
+               "median_centre_error": float(np.median(cerr[cerr < 4.0]))}
+        rows.append(row)
+        log(f"{row['contour']:6s} smooth {smooth:5.2f}: evolve {ev:.3f} ms ({row['vertex_updates_per_s']:.3g} "
+            f"vertex-updates/s), kept {row['kept']}, fit error median {row['median_fit_error']:.3f} "
+            f"(p90 {row['p90_fit_error']:.3f}), centre error {row['median_centre_error']:.3f}")
+    line = {"metric": "star-shaped vs spherical contours on the slab: time and fit to the nuclei",
+            "unit": "relative radial error", "value": rows[1]["median_fit_error"], "n_gpus": 1,
+            "data": "synthetic", "config": {"workload": wl.name, "n_dirs": p.n_dirs, "n_rays": p.n_rays,
+                                            "n_iter": wl.n_iter},
+            "runs": rows}
+    print(json.dumps(line), flush=True)
 
 
 def bench_gradient(args):

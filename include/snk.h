@@ -153,6 +153,36 @@ snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs
  * LDS exceed 64 KiB per workgroup. */
 snk_status snk_set_tile(snk_ctx *ctx, int32_t tile_voxels);
 
+/* Star-shaped contours (not in the paper: a builder-defined extension of its sphere). With
+ * smooth >= 0 the following evolves give each contour one radius R_k per table direction T_k; the
+ * directions stay fixed in space (no random rotation). The energy is the table average of
+ * per-direction radial energies, E = (1/D) sum_k (2R_k)^-d omega_d d integral S(s; R_k)
+ * I(c + s T_k) s^(d-1) ds (Eq. (5)'s weight and normalisation along each direction; the sphere's
+ * energy when every R_k is equal). Each iteration draws the sphere sampler's Philox pairs: pair m
+ * picks k, its rays run along +T_k with radius R_k and along -T_k with the radius of the opposite
+ * table direction, at the sphere's radial points (R + dR/2)((l + xi)/L)^(1/d). The centre force
+ * sums every ray's (Eqs. (7)-(10) along each ray); each sampled direction gets the unbiased
+ * estimate g_k of dE/dR_k from its rays. Step: c -= (eps/2) g_c; R_k -= (eps/2) D g_k +
+ * min(1, eps smooth / 2) (R_k - mean of its neighbours' radii), from the old radii; the neighbours
+ * are the 6 (3D) or 2 (2D) directions nearest to T_k, made symmetric. Clamps, OUT and the stop
+ * rule as for the sphere (the move of an iteration is the largest |dR_k| and |dc|); status bit
+ * 0x10 when any radius was clamped. snk_read's radius is the mean of the R_k and its e_vox is the
+ * last Monte-Carlo energy, which snk_finalize's selection ranks by (overlaps against the mean
+ * radius). Needs a direction table with every opposite direction (else SNK_EINVAL at the next
+ * evolve), n_radial = 16, and flags bits 1 and 2 clear; runs one wave per contour and ignores
+ * snk_set_launch / snk_set_tile; snk_trace_step returns SNK_EINVAL. smooth < 0: the sphere
+ * (default). Radii start tied at each contour's R after snk_load_seeds, snk_set_state or
+ * snk_set_directions. */
+snk_status snk_set_star(snk_ctx *ctx, double smooth);
+
+/* Per-direction radii of the star contours, n x n_dirs in seed order (row k = direction k); cap in
+ * floats (SNK_ERANGE with *n_out = n * n_dirs if smaller). */
+snk_status snk_get_star_radii(snk_ctx *ctx, float *radii, int64_t cap, int64_t *n_out);
+
+/* Replace the per-direction radii (n x n_dirs, each in (0, r_max]); n must equal the seeded count.
+ * Call after snk_set_state, which resets them to the tied radius. */
+snk_status snk_set_star_radii(snk_ctx *ctx, const float *radii, int64_t n);
+
 /* Direction table: D rows of `dim` floats (host pointer), unit vectors, D * dim <= 12288. D must
  * equal params.n_dirs at evolve time. Sec. II-E: the table's directions, randomly rotated per
  * contour-iteration, carry the Monte-Carlo rays. */

@@ -982,7 +982,8 @@ int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const dou
 
 /* Direction tables of the star contour: anti[k] = the direction opposite T_k (|T_j + T_k| <
  * 1e-4, else -1 is returned), and the direction graph: the 6 (3D) or 2 (2D) nearest directions of
- * each (largest dot product, ties to the lower index), made symmetric; N(k) is
+ * each (largest dot product; dot products within 1e-6 tie and the lower index wins, so a table
+ * rounded to FP32 gives the same graph), made symmetric; N(k) is
  * nb_idx[nb_off[k] .. nb_off[k+1]) in ascending order. Returns the number of entries, or -2 if
  * they exceed cap. */
 int32_t orc_star_tables(int dim, const double *dirs, int32_t D, int32_t *anti, int32_t *nb_off, int32_t *nb_idx,
@@ -1017,7 +1018,8 @@ int32_t orc_star_tables(int dim, const double *dirs, int32_t D, int32_t *anti, i
                 if (used) continue;
                 double dt = 0.0;
                 for (int a = 0; a < dim; ++a) dt += dirs[j * dim + a] * dirs[k * dim + a];
-                if (dt > bd) { bd = dt; best = j; }
+                /* dot products within 1e-6 tie (the table's symmetric neighbours); the lower index wins */
+                if (best < 0 || dt > bd + 1e-6) { bd = dt; best = j; }
             }
             knn[k * deg + taken++] = best;
         }

@@ -28,6 +28,15 @@ struct snk_ctx {
     int lds_per_cu = 0;  // LDS bytes per compute unit
     int stage_key = -1, stage_blocks = 0;  // registers-limited workgroups per CU of the last staged shape
     int last_lanes = 0, last_unroll = 0, last_layout = 0, last_tile = 0;  // last evolve launch
+
+    // star-shaped contours (lambda < 0: off)
+    double star_lambda = -1.0;
+    int *d_anti = nullptr, *d_nb_off = nullptr, *d_nb_idx = nullptr;
+    size_t anti_cap = 0, nb_off_cap = 0, nb_idx_cap = 0;
+    std::vector<float> star_dirs;    // the table the star tables were built from
+    float *d_Rk = nullptr;           // n x D radii
+    size_t Rk_cap = 0;
+    bool Rk_valid = false;
     int layout = snk::kGlobalPlain;  // layout of the current pre-pass output
 
     std::vector<float> dirs_host;
@@ -345,6 +354,128 @@ snk_status ensure_layout(snk_ctx *c) {
     return SNK_OK;
 }
 
+// Direction tables of the star contour from the context's direction table: the opposite direction
+// of each (|T_j + T_k| < 1e-4, else SNK_EINVAL), and a symmetric graph: the 6 (3D) or 2 (2D)
+// directions of largest dot product with T_k (ties to the lower index), closed under symmetry,
+// neighbours in ascending order.
+snk_status star_tables(snk_ctx *c) {
+    const int dim = c->P.dim, D = c->D;
+    if (c->star_dirs == c->dirs_host && c->d_anti) return SNK_OK;
+    const std::vector<float> &T = c->dirs_host;
+    std::vector<int> anti(D), off(D + 1, 0), idx;
+    for (int k = 0; k < D; ++k) {
+        int best = -1;
+        double bd = 1e30;
+        for (int j = 0; j < D; ++j) {
+            double e2 = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                const double t = (double)T[j * dim + a] + (double)T[k * dim + a];
+                e2 += t * t;
+            }
+            if (e2 < bd) {
+                bd = e2;
+                best = j;
+            }
+        }
+        if (!(sqrt(bd) < 1e-4)) return fail(c, SNK_EINVAL, "star contours need a direction table with antipodes");
+        anti[k] = best;
+    }
+    const int deg = dim == 3 ? 6 : 2;
+    std::vector<int> knn((size_t)D * deg, -1);
+    std::vector<double> dots(D);
+    std::vector<char> used(D);
+    for (int k = 0; k < D; ++k) {
+        for (int j = 0; j < D; ++j) {
+            double dt = 0.0;
+            for (int a = 0; a < dim; ++a) dt += (double)T[j * dim + a] * (double)T[k * dim + a];
+            dots[j] = dt;
+            used[j] = j == k;
+        }
+        // repeated maximum; dot products within 1e-6 tie and the lower index wins, so a table given
+        // in FP32 yields the graph its exact directions define
+        for (int t = 0; t < deg && t < D - 1; ++t) {
+            int best = -1;
+            for (int j = 0; j < D; ++j)
+                if (!used[j] && (best < 0 || dots[j] > dots[best] + 1e-6)) best = j;
+            used[best] = 1;
+            knn[(size_t)k * deg + t] = best;
+        }
+    }
+    for (int k = 0; k < D; ++k) {
+        for (int j = 0; j < D; ++j) {
+            if (j == k) continue;
+            bool edge = false;
+            for (int t = 0; t < deg; ++t)
+                edge = edge || knn[(size_t)k * deg + t] == j || knn[(size_t)j * deg + t] == k;
+            if (edge) idx.push_back(j);
+        }
+        off[k + 1] = (int)idx.size();
+    }
+    snk_status st = ensure(c, &c->d_anti, &c->anti_cap, (size_t)D);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_nb_off, &c->nb_off_cap, (size_t)D + 1);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_nb_idx, &c->nb_idx_cap, std::max<size_t>(idx.size(), 1));
+    if (st != SNK_OK) return st;
+    HIPTRY(c, hipMemcpyAsync(c->d_anti, anti.data(), sizeof(int) * D, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipMemcpyAsync(c->d_nb_off, off.data(), sizeof(int) * (D + 1), hipMemcpyHostToDevice, c->stream));
+    if (!idx.empty())
+        HIPTRY(c, hipMemcpyAsync(c->d_nb_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    c->star_dirs = c->dirs_host;
+    return SNK_OK;
+}
+
+// Per-direction radii of every contour, set tied to its R unless already valid.
+snk_status star_radii(snk_ctx *c) {
+    snk_status st = ensure(c, &c->d_Rk, &c->Rk_cap, (size_t)std::max<int64_t>(c->n * c->D, 1));
+    if (st != SNK_OK) return st;
+    if (!c->Rk_valid) {
+        HIPTRY(c, snk::launch_star_init(c->d_st, c->d_Rk, (int)c->n, c->D, c->stream));
+        c->Rk_valid = true;
+    }
+    return SNK_OK;
+}
+
+snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
+    if (c->P.flags & (snk::kFlagExact | snk::kFlagGradI))
+        return fail(c, SNK_EINVAL, "star contours take Monte-Carlo sums with the weight-form centre force");
+    if (c->P.n_radial != 16) return fail(c, SNK_EINVAL, "star contours need n_radial = 16");
+    if (snk::star_lds_bytes(c->P.dim, c->D, c->P.n_rays) > 65536)
+        return fail(c, SNK_EINVAL, "n_dirs / n_rays too large for the star kernel's LDS (64 KiB)");
+    snk_status st = star_tables(c);
+    if (st != SNK_OK) return st;
+    st = star_radii(c);
+    if (st != SNK_OK) return st;
+    snk::EvolveArgs a{};
+    a.p = job_params(c);
+    a.st = c->d_st;
+    a.n = (int)c->n;
+    a.n_iter = n_iter;
+    a.counter = c->d_counters;
+    snk::StarArgs sa{};
+    sa.anti = c->d_anti;
+    sa.nb_off = c->d_nb_off;
+    sa.nb_idx = c->d_nb_idx;
+    sa.Rk = c->d_Rk;
+    sa.lambda = (float)c->star_lambda;
+    if (standalone) {
+        HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
+        HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
+    }
+    HIPTRY(c, snk::launch_star(a, sa, c->P.dim, c->layout, c->stream));
+    if (standalone) {
+        HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
+        c->ev_evo = true;
+    }
+    c->last_lanes = 64;
+    c->last_unroll = 1;
+    c->last_layout = c->layout;
+    c->last_tile = 0;
+    c->evolve_launches += 1;
+    return SNK_OK;
+}
+
 // standalone: zero the contour-iteration counter and record the evolve events around the launch
 // (off for the chunks of snk_evolve_cull, which brackets the whole call).
 snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = true) {
@@ -355,6 +486,10 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     }
     snk_status lst = ensure_layout(c);
     if (lst != SNK_OK) return lst;
+    if (c->star_lambda >= 0.0) {
+        if (trace) return fail(c, SNK_EINVAL, "snk_trace_step does not cover star contours");
+        return run_star(c, n_iter, standalone);
+    }
     snk::EvolveArgs a{};
     a.p = job_params(c);
     a.st = c->d_st;
@@ -462,6 +597,7 @@ snk_status run_select(snk_ctx *c, int mode, int grace) {
     a.grace = grace;
     // a culling pass ranks by the Monte-Carlo energy the last iteration left in the state
     if (mode == 0) HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, true, c->stream));
+    if (mode == 2) HIPTRY(c, snk::launch_mark_maxiter(a.st, a.n, c->stream));
     HIPTRY(c, snk::launch_select(a, c->P.dim, reinterpret_cast<int *>(c->d_counters + 2), c->stream));
     return SNK_OK;
 }
@@ -512,7 +648,8 @@ snk_status snk_destroy(snk_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->Jq, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
-                    c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters};
+                    c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters, c->d_anti, c->d_nb_off,
+                    c->d_nb_idx, c->d_Rk};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &ev : c->ev)
@@ -556,6 +693,48 @@ snk_status snk_set_tile(snk_ctx *c, int32_t tile_voxels) {
     return SNK_OK;
 }
 
+snk_status snk_set_star(snk_ctx *c, double smooth) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (!isfinite(smooth)) return fail(c, SNK_EINVAL, "smooth must be finite");
+    c->star_lambda = smooth < 0.0 ? -1.0 : smooth;
+    return SNK_OK;
+}
+
+snk_status snk_get_star_radii(snk_ctx *c, float *radii, int64_t cap, int64_t *n_out) {
+    if (!c || !radii) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = need(c, true, true);
+    if (st != SNK_OK) return st;
+    const int64_t total = c->n * c->D;
+    if (n_out) *n_out = total;
+    if (cap < total) return fail(c, SNK_ERANGE, "capacity smaller than n x n_dirs");
+    (void)hipSetDevice(c->device);
+    st = star_radii(c);
+    if (st != SNK_OK) return st;
+    if (total > 0)
+        HIPTRY(c, hipMemcpyAsync(radii, c->d_Rk, sizeof(float) * total, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    return SNK_OK;
+}
+
+snk_status snk_set_star_radii(snk_ctx *c, const float *radii, int64_t n) {
+    if (!c || !radii) return fail(c, SNK_EINVAL, "NULL argument");
+    snk_status st = need(c, true, true);
+    if (st != SNK_OK) return st;
+    if (n != c->n) return fail(c, SNK_EINVAL, "n must equal the number of seeded contours");
+    const int64_t total = n * c->D;
+    for (int64_t i = 0; i < total; ++i)
+        if (!(radii[i] > 0.0f) || !(radii[i] <= (float)c->P.r_max))
+            return fail(c, SNK_EINVAL, "star radius outside (0, r_max]");
+    (void)hipSetDevice(c->device);
+    st = ensure(c, &c->d_Rk, &c->Rk_cap, (size_t)std::max<int64_t>(total, 1));
+    if (st != SNK_OK) return st;
+    if (total > 0)
+        HIPTRY(c, hipMemcpyAsync(c->d_Rk, radii, sizeof(float) * total, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipStreamSynchronize(c->stream));
+    c->Rk_valid = true;
+    return SNK_OK;
+}
+
 snk_status snk_set_directions(snk_ctx *c, const float *dirs, int32_t D) {
     if (!c || !dirs || D <= 0) return fail(c, SNK_EINVAL, "bad direction table");
     snk_status st = need(c, false, false);
@@ -571,6 +750,7 @@ snk_status snk_set_directions(snk_ctx *c, const float *dirs, int32_t D) {
     st = ensure(c, &c->d_dirs, &c->dirs_cap, (size_t)D * dim);
     if (st != SNK_OK) return st;
     c->dirs_host.assign(dirs, dirs + (size_t)D * dim);
+    c->Rk_valid = false;
     HIPTRY(c, hipMemcpyAsync(c->d_dirs, c->dirs_host.data(), sizeof(float) * D * dim, hipMemcpyHostToDevice,
                              c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
@@ -652,6 +832,7 @@ snk_status snk_load_seeds(snk_ctx *c, const double *centers, const float *r0, co
         HIPTRY(c, hipMemcpyAsync(c->d_st, h.data(), sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
     c->n = n;
+    c->Rk_valid = false;
     return SNK_OK;
 }
 
@@ -692,7 +873,8 @@ snk_status snk_finalize(snk_ctx *c) {
         if (st != SNK_OK) return st;
     }
     HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
-    st = run_select(c, 0, 0);
+    // star contours rank by their last Monte-Carlo energy (no exact star energy is formed)
+    st = run_select(c, c->star_lambda >= 0.0 ? 2 : 0, 0);
     if (st != SNK_OK) return st;
     HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
     c->ev_fin = true;
@@ -772,7 +954,7 @@ snk_status snk_read(snk_ctx *c, float *radii, double *centers, float *e_mc, floa
         if (radii) radii[i] = s.R;
         if (centers) centre_of(c, s, &centers[i * 3]);
         if (e_mc) e_mc[i] = s.e_mc;
-        if (e_vox) e_vox[i] = s.e_vox;
+        if (e_vox) e_vox[i] = c->star_lambda >= 0.0 ? s.e_mc : s.e_vox;
         if (iters) iters[i] = s.iters;
         if (status) status[i] = s.status;
         if (keep) keep[i] = s.keep;
@@ -823,6 +1005,7 @@ snk_status snk_set_state(snk_ctx *c, const double *centers, const float *radii, 
     if (n > 0)
         HIPTRY(c, hipMemcpyAsync(c->d_st, h.data(), sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
+    c->Rk_valid = false;
     return SNK_OK;
 }
 

@@ -263,6 +263,18 @@ __device__ __forceinline__ float wave_sum_to_63(float v) {
     return v;
 }
 
+// Maximum of the wave in lane 63 (row shifts, then row broadcasts; values are >= 0 here, so the
+// zero filled in by the shifts is harmless).
+__device__ __forceinline__ float wave_max_to_63(float v) {
+    v = fmaxf(v, dpp<0x111>(v));             // row_shr:1
+    v = fmaxf(v, dpp<0x112>(v));             // row_shr:2
+    v = fmaxf(v, dpp<0x114>(v));             // row_shr:4
+    v = fmaxf(v, dpp<0x118>(v));             // row_shr:8
+    v = fmaxf(v, dpp<0x142, 0xa, false>(v)); // row_bcast:15
+    v = fmaxf(v, dpp<0x143, 0xc, false>(v)); // row_bcast:31
+    return v;
+}
+
 template <int G>
 __device__ __forceinline__ float group_sum_wave(float v) {
     if constexpr (G == 16) {
@@ -1336,6 +1348,295 @@ int max_blocks_g(int lanes, int unroll, int layout, int max_M) {
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Star-shaped contours (builder-defined extension: one radius per table direction)
+// ---------------------------------------------------------------------------------------------
+//
+// One wave per contour. The table directions stay fixed in space (no rotation). Per iteration the
+// Philox pair draws pick directions k; each pair's rays run along +T_k with radius R_k and along
+// -T_k with the radius of the antipodal direction, with the sphere's radial points
+// s = (R + dR/2) ((l + xi)/L)^(1/d) (L = 16: one DPP row of lanes per ray pair). With the per-point
+// weight q(R) = (2R)^-d omega_d (R + dR/2)^d / (M L): E = sum q S I, g_c = sum q (-dS/dr I u), and
+// every sampled direction k collects g_k = sum over its rays of q (B_R,ray - (d/R_k) A_ray)
+// (rays that drew the same direction are summed in ray order by the first of them, so the result
+// does not depend on timing). Step: c -= (eps/2) g_c; R_k -= (eps/2) D g_k + min(1, eps lambda / 2)
+// (R_k - mean of its graph neighbours), from the old radii (double-buffered in LDS).
+
+template <int DIM>
+__host__ __device__ __forceinline__ int star_lds_floats(int D, int M) {
+    const int per = (draw_floats(64, M / 2) + 3) & ~3;
+    return per + 3 * D + 2 * M;
+}
+
+template <int DIM, int LAYOUT>
+__global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
+    extern __shared__ float lds[];
+    constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
+    constexpr float BALL = DIM == 3 ? 4.18879020478639098462f : 3.14159265358979323846f;
+    const JobParams &p = a.p;
+    const int cid = blockIdx.x;
+    if (cid >= a.n) return;
+    const int lane = threadIdx.x;
+    const int D = p.D, M = p.M, MH = M / 2, L = p.L;
+    DevContour *slot = a.st + cid;
+    DevContour s = uniform_copy(slot);
+    const int n0 = s.iters;
+    const int budget = (s.status & 0x0f) == SNK_ACTIVE ? a.n_iter : 0;
+    const int per = (draw_floats(64, MH) + 3) & ~3;
+    const Draws dr(lds, 64, MH);
+    float *Ra = lds + per;
+    float *Rb = Ra + D;
+    float *gk = Rb + D;
+    int *ray_dir = reinterpret_cast<int *>(gk + D);
+    float *ray_g = reinterpret_cast<float *>(ray_dir + M);
+    float *Rg = sa.Rk + (long)cid * D;
+    for (int k = lane; k < D; k += 64) {
+        Ra[k] = Rg[k];
+        gk[k] = 0.0f;
+    }
+    const Vol<DIM, LAYOUT> vol(p.g);
+    const float inv_h[3] = {p.g.inv_h[0], p.g.inv_h[1], p.g.inv_h[2]};
+    const float hh[3] = {p.g.h[0], p.g.h[1], p.g.h[2]};
+    const uint32_t id = s.id;
+    if (budget > 0) draws_phase1<DIM, 64>(dr, 0, (uint32_t)(n0 + 1), id, p, lane);
+    __syncthreads();
+    // largest radius (interior test) and the clamp flag of the radii
+    float rmax = 0.0f;
+    for (int k = lane; k < D; k += 64) rmax = fmaxf(rmax, Ra[k]);
+    rmax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(rmax)), 63));
+
+    int anc[3] = {s.anc[0], s.anc[1], s.anc[2]};
+    float off[3] = {s.off[0], s.off[1], s.off[2]};
+    float Rmean = s.R;
+    int n = n0;
+    uint8_t status = s.status;
+    int streak = s.streak;
+    float e_mc = s.e_mc;
+    const float invL = 1.0f / (float)L;
+    const float inv_ml = 1.0f / (float)(M * L);
+    const float tol2 = p.conv_tol * p.conv_tol;
+    const float hd = 0.5f * RHO * p.dR, hD = 0.5f * p.dR;
+    int ran = 0;
+    float *Rold = Ra, *Rnew = Rb;
+
+    for (int it = 0; it < budget && (status & 0x0f) == SNK_ACTIVE; ++it) {
+        const int blk = it / dr.K, sl = it - blk * dr.K;
+        if (sl == 0) draws_phase1<DIM, 64>(dr, (blk + 1) & 1, (uint32_t)(n0 + 1 + (blk + 1) * dr.K), id, p, lane);
+        const float4 *pu = dr.pu + dr.slot(blk & 1, sl) * MH;
+        Frame<DIM> fr;
+        long base = 0;
+        const long stride[3] = {1, vol.nx, vol.nxy};
+        bool interior = true;
+        const float ext_r = rmax + 0.5f * p.dR;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            fr.anc[ax] = anc[ax];
+            fr.off[ax] = off[ax];
+        }
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            base += (long)anc[ax] * stride[ax];
+            const float ext = fmaf(ext_r * inv_h[ax], 1.0001f, 1e-3f);
+            interior = interior && (off[ax] - ext > (float)(-anc[ax])) && (off[ax] + ext < (float)(vol.n[ax] - 1 - anc[ax]));
+        }
+        fr.base = base;
+        float accE = 0.0f, accc[3] = {0.0f, 0.0f, 0.0f};
+        // pair-points q = lane + 64 j: pair m = q / 16, radial index l = q % 16 (one DPP row per pair)
+        for (int q = lane; q < MH * L; q += 64) {
+            const int m = q >> 4, l = q & 15;
+            const float4 d = pu[m];
+            const int k = __float_as_int(d.x);
+            const int ka = sa.anti[k];
+            float u[3] = {0.0f, 0.0f, 0.0f}, du[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                u[ax] = p.dirs[k * DIM + ax];
+                du[ax] = u[ax] * inv_h[ax];
+            }
+            const float e = cube_or_square_root<DIM>(((float)l + d.w) * invL);
+            float Ival[2], Sv[2], cCv[2], cRv[2], qv[2], Rv[2];
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const float R = Rold[sg ? ka : k];
+                const float smax = R + 0.5f * p.dR;
+                const float rad = smax * e;
+                float w[3] = {0.0f, 0.0f, 0.0f}, f[3];
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) w[ax] = fmaf(sg ? -rad : rad, du[ax], off[ax]);
+                Corners<DIM> cr;
+                if (interior) vol.load(locate<DIM, false, Vol<DIM, LAYOUT>::kSmall>(fr, vol.n, vol.nx, vol.nxy, w, f), cr);
+                else vol.load(locate<DIM, true, Vol<DIM, LAYOUT>::kSmall>(fr, vol.n, vol.nx, vol.nxy, w, f), cr);
+                const float I = trilerp<DIM>(cr, f);
+                const float d1 = fmaf(smax, e, -RHO * R), d2 = fmaf(smax, e, -R);
+                const float is = p.in_slope, os = p.out_slope;
+                const bool r1 = d1 >= -hd && d1 < hd;
+                const bool r2 = d2 >= -hD && d2 < hD;
+                const float sin_ = __builtin_amdgcn_fmed3f(d1 * is, -1.0f, 1.0f);
+                const float sout = __builtin_amdgcn_fmed3f(fmaf(-d2, os, 0.5f), 0.0f, 1.0f);
+                const float inv2R = __builtin_amdgcn_rcpf(2.0f * R);
+                float nrm = inv2R, sm_d = smax;
+#pragma unroll
+                for (int i = 1; i < DIM; ++i) {
+                    nrm *= inv2R;
+                    sm_d *= smax;
+                }
+                Ival[sg] = I;
+                Sv[sg] = fminf(sin_, sout);
+                cCv[sg] = r1 ? is : (r2 ? -os : 0.0f);
+                cRv[sg] = r1 ? -RHO * is : -cCv[sg];
+                qv[sg] = BALL * sm_d * nrm * inv_ml;
+                Rv[sg] = R;
+            }
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const float qI = qv[sg] * Ival[sg];
+                accE = fmaf(Sv[sg], qI, accE);
+                const float gcs = -cCv[sg] * qI * (sg ? -1.0f : 1.0f);
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) accc[ax] = fmaf(gcs, u[ax], accc[ax]);
+            }
+            // per-ray sums over the row's 16 radial points
+            float Ap = row_sum16(Sv[0] * Ival[0]), Bp = row_sum16(cRv[0] * Ival[0]);
+            float Am = row_sum16(Sv[1] * Ival[1]), Bm = row_sum16(cRv[1] * Ival[1]);
+            if (l == 0) {
+                ray_dir[2 * m] = k;
+                ray_g[2 * m] = qv[0] * (Bp - ((float)DIM / Rv[0]) * Ap);
+                ray_dir[2 * m + 1] = ka;
+                ray_g[2 * m + 1] = qv[1] * (Bm - ((float)DIM / Rv[1]) * Am);
+            }
+        }
+        const float E = group_sum_wave<64>(accE);
+        float gc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) gc[ax] = group_sum_wave<64>(accc[ax]);
+        __syncthreads();
+        // sampled directions: the first ray of each direction sums its rays in order
+        for (int r = lane; r < M; r += 64) {
+            const int dk = ray_dir[r];
+            bool first = true;
+            for (int r2 = 0; r2 < r; ++r2) first = first && ray_dir[r2] != dk;
+            if (first) {
+                float g = 0.0f;
+                for (int r2 = r; r2 < M; ++r2)
+                    if (ray_dir[r2] == dk) g += ray_g[r2];
+                gk[dk] = g;
+            }
+        }
+        __syncthreads();
+        n += 1;
+        const float eps = p.eps0 * __builtin_amdgcn_rsqf((float)n);
+        const float half_eps = 0.5f * eps;
+        const float relax = fminf(1.0f, half_eps * sa.lambda);
+        float mv = 0.0f, sum = 0.0f, mx = 0.0f;
+        int clamped = 0, finite_r = 1;
+        for (int k = lane; k < D; k += 64) {
+            const int b0 = sa.nb_off[k], b1 = sa.nb_off[k + 1];
+            float ms = 0.0f;
+            for (int b = b0; b < b1; ++b) ms += Rold[sa.nb_idx[b]];
+            const float Rk0 = Rold[k];
+            const float mk = b1 > b0 ? ms / (float)(b1 - b0) : Rk0;
+            float Rn = Rk0 - half_eps * (float)D * gk[k] - relax * (Rk0 - mk);
+            if (Rn < p.r_lo) {
+                Rn = p.r_lo;
+                clamped = 1;
+            }
+            if (Rn > p.r_hi) {
+                Rn = p.r_hi;
+                clamped = 1;
+            }
+            finite_r = finite_r && isfinite(Rn);
+            mv = fmaxf(mv, fabsf(Rn - Rk0));
+            sum += Rn;
+            mx = fmaxf(mx, Rn);
+            Rnew[k] = Rn;
+            gk[k] = 0.0f;
+        }
+        mv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(mv)), 63));
+        mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(mx)), 63));
+        sum = group_sum_wave<64>(sum);
+        clamped = __builtin_amdgcn_ballot_w64(clamped != 0) != 0;
+        const bool fin_r = __builtin_amdgcn_ballot_w64(!finite_r) == 0;
+        rmax = mx;
+        Rmean = sum / (float)D;
+        e_mc = E;
+        float dc2 = 0.0f;
+        bool finite = fin_r && isfinite(E);
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            const float dcp = -half_eps * gc[ax];
+            dc2 = fmaf(dcp, dcp, dc2);
+            off[ax] += dcp * inv_h[ax];
+            finite = finite && isfinite(off[ax]);
+        }
+        uint8_t flag = (status & SNK_CLAMPED) | (clamped ? SNK_CLAMPED : 0);
+        uint8_t st = SNK_ACTIVE;
+        if (!finite) {
+            st = SNK_NONFINITE;
+        } else {
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) {
+                if (fabsf(off[ax]) >= 0.5f) {
+                    const float kk = rintf(off[ax]);
+                    anc[ax] += (int)kk;
+                    off[ax] -= kk;
+                }
+                if (off[ax] < (float)(-anc[ax]) || off[ax] > (float)(vol.n[ax] - 1 - anc[ax])) st = SNK_OUT;
+            }
+        }
+        if (st == SNK_ACTIVE) {
+            const bool small = mv * mv < tol2 && dc2 < tol2;
+            streak = small ? min(streak + 1, 255) : 0;
+            if (p.conv_window > 0 && streak >= p.conv_window) st = SNK_CONVERGED;
+        }
+        status = (uint8_t)uni<64>((int)(st | flag));
+        streak = uni<64>(streak);
+#pragma unroll
+        for (int ax = 0; ax < DIM; ++ax) {
+            off[ax] = uni<64>(off[ax]);
+            anc[ax] = uni<64>(anc[ax]);
+        }
+        float *t = Rold;
+        Rold = Rnew;
+        Rnew = t;
+        ++ran;
+        __syncthreads();
+    }
+    if (budget > 0) {
+        for (int k = lane; k < D; k += 64) Rg[k] = Rold[k];
+        if (lane == 0) {
+            DevContour o = s;
+            for (int i = 0; i < 3; ++i) {
+                o.anc[i] = anc[i];
+                o.off[i] = off[i];
+            }
+            o.R = Rmean;
+            o.e_mc = e_mc;
+            o.iters = n;
+            o.status = status;
+            o.streak = (uint8_t)streak;
+            *slot = o;
+            atomicAdd(a.counter, (unsigned long long)ran);
+        }
+    }
+}
+
+template <int DIM>
+hipError_t launch_star_d(const EvolveArgs &a, const StarArgs &sa, int layout, hipStream_t s) {
+    const size_t lds = sizeof(float) * (size_t)star_lds_floats<DIM>(a.p.D, a.p.M);
+    switch (layout) {
+        case kBufferQuad:
+            hipLaunchKernelGGL((star_kernel<DIM, kBufferQuad>), dim3(a.n), dim3(64), lds, s, a, sa);
+            break;
+        case kBufferPlain:
+            hipLaunchKernelGGL((star_kernel<DIM, kBufferPlain>), dim3(a.n), dim3(64), lds, s, a, sa);
+            break;
+        default:
+            hipLaunchKernelGGL((star_kernel<DIM, kGlobalPlain>), dim3(a.n), dim3(64), lds, s, a, sa);
+            break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, int layout, bool trace,
@@ -1362,6 +1663,29 @@ hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unrol
     if (layout != kBufferQuad && layout != kBufferPlain) return hipErrorInvalidValue;
     if (dim == 2) return batch_g<2>(a, lanes, unroll, layout, persistent, grid, s);
     return batch_g<3>(a, lanes, unroll, layout, persistent, grid, s);
+}
+
+namespace {
+__global__ __launch_bounds__(256) void star_init_kernel(const DevContour *st, float *Rk, int n, int D) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i < (long)n * D) Rk[i] = st[i / D].R;
+}
+}  // namespace
+
+hipError_t launch_star_init(const DevContour *st, float *Rk, int n, int D, hipStream_t s) {
+    const long total = (long)n * D;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(star_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, st, Rk, n, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int layout, hipStream_t s) {
+    if (a.n <= 0 || a.n_iter <= 0) return hipSuccess;
+    return dim == 2 ? launch_star_d<2>(a, sa, layout, s) : launch_star_d<3>(a, sa, layout, s);
+}
+
+size_t star_lds_bytes(int dim, int D, int M) {
+    return sizeof(float) * (size_t)(dim == 2 ? star_lds_floats<2>(D, M) : star_lds_floats<3>(D, M));
 }
 
 int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M) {

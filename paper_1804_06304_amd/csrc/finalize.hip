@@ -154,8 +154,9 @@ __device__ __forceinline__ bool overlaps(const DevContour &x, const DevContour &
     return sqrtf(d2) < thr;
 }
 
-// Energy that ranks contour i: E_vox for the final selection, the last Monte-Carlo energy for a
-// culling pass during evolution.
+// Energy that ranks contour i: E_vox for the final selection (mode 0), the last Monte-Carlo
+// energy for a culling pass during evolution (mode 1) and for the final selection of star-shaped
+// contours (mode 2).
 __device__ __forceinline__ double rank_energy(const JobDev &a, int i, const DevContour &s) {
     return a.mode == 0 ? a.e_vox[i] : (double)s.e_mc;
 }
@@ -210,7 +211,7 @@ __device__ __forceinline__ void bin_one(const JobDev &a, int i) {
     const double e = rank_energy(a, i, s);
     // final selection: stopped contours at or below E0; culling pass: live contours below E0 or
     // still within their grace period
-    const bool cand = a.mode == 0 ? (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0
+    const bool cand = a.mode != 1 ? (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0
                                   : (st == SNK_ACTIVE || st == SNK_CONVERGED) && isfinite(e) &&
                                         (s.iters < a.grace || e <= (double)a.e0);
     a.dec[i] = cand ? DEC_UNDECIDED : DEC_NONE;
@@ -311,7 +312,7 @@ __device__ void select_job(const JobDev &a, bool binned) {
         any = __syncthreads_or(local) != 0;
     }
     unsigned long long count = 0;
-    if (a.mode == 0) {
+    if (a.mode != 1) {
         for (int i = t; i < n; i += SEL_T) {
             const uint8_t k = dec[i] == DEC_ACCEPT ? 1 : 0;
             a.st[i].keep = k;
@@ -397,6 +398,19 @@ hipError_t select_grid(const JobDev &j, int *rounds, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace {
+__global__ __launch_bounds__(256) void mark_maxiter_kernel(DevContour *st, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n && (st[i].status & 0x0f) == SNK_ACTIVE) st[i].status = (uint8_t)((st[i].status & SNK_CLAMPED) | SNK_MAXITER);
+}
+}  // namespace
+
+hipError_t launch_mark_maxiter(DevContour *st, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mark_maxiter_kernel, dim3((n + 255) / 256), dim3(256), 0, s, st, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, bool finalize,
                              hipStream_t s) {

@@ -73,6 +73,16 @@ inline int volume_layout(int dim, int64_t nx, int64_t ny, int64_t nz, int reques
     return quad_ok ? kBufferQuad : (plain_ok ? kBufferPlain : kGlobalPlain);
 }
 
+// Star-shaped contours: direction tables (antipode, symmetric neighbour graph in CSR form), the
+// per-direction radii (n x D) and the smoothing weight.
+struct StarArgs {
+    const int *anti;
+    const int *nb_off;
+    const int *nb_idx;
+    float *Rk;
+    float lambda;
+};
+
 struct EvolveArgs {
     JobParams p;
     DevContour *st;
@@ -95,7 +105,8 @@ struct JobDev {
     int G[3];
     float cell;
     unsigned long long *kept;    // final selection: contours kept; culling pass: contours retired
-    int mode;                    // 0: final selection, 1: culling pass during evolution
+    int mode;                    // 0: final selection, 1: culling pass during evolution, 2: final
+                                 // selection ranked by the last Monte-Carlo energy (star contours)
     int grace;                   // culling pass: iterations before E_vox > e0 retires a contour
 };
 
@@ -137,6 +148,11 @@ hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unrol
                                int grid, hipStream_t s);
 int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M);
 size_t evolve_lds_bytes(int dim, int lanes, int M, int tile_cap);
+// Star-shaped contours (one wave per contour, n_radial 16).
+hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int layout, hipStream_t s);
+size_t star_lds_bytes(int dim, int D, int M);
+// Every direction's radius of contour i set to its R.
+hipError_t launch_star_init(const DevContour *st, float *Rk, int n, int D, hipStream_t s);
 // Workgroups per CU that registers allow for a launch shape with LDS boxes (0: no such shape).
 int evolve_stage_blocks_per_cu(int dim, int lanes, int unroll, int layout);
 
@@ -149,6 +165,8 @@ hipError_t launch_count_unfinished(const JobDev *jobs, const int2 *items, int n_
 // e_vox).
 hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, int n, int dim, bool finalize,
                              hipStream_t s);
+// Contours still ACTIVE become MAXITER (the end of evolution without the exact energy).
+hipError_t launch_mark_maxiter(DevContour *st, int n, hipStream_t s);
 // rounds: 3 ints of device scratch for the grid-wide rounds (null: one workgroup does everything).
 hipError_t launch_select(const JobDev &j, int dim, int *rounds, hipStream_t s);
 hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s);

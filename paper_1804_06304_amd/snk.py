@@ -23,7 +23,8 @@ ACTIVE, CONVERGED, MAXITER, OUT, NONFINITE, CULLED, CLAMPED = 0, 1, 2, 3, 4, 5, 
 TRACE_W = 16
 
 EXPORTS = [
-    "snk_create", "snk_destroy", "snk_set_params", "snk_set_launch", "snk_set_tile", "snk_set_directions",
+    "snk_create", "snk_destroy", "snk_set_params", "snk_set_launch", "snk_set_tile", "snk_set_star",
+    "snk_get_star_radii", "snk_set_star_radii", "snk_set_directions",
     "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
     "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull",
@@ -80,6 +81,9 @@ def load(path: str = LIB_PATH):
         "snk_set_params": [vp, C.POINTER(snk_params)],
         "snk_set_launch": [vp, i32, i32, i32],
         "snk_set_tile": [vp, i32],
+        "snk_set_star": [vp, C.c_double],
+        "snk_get_star_radii": [vp, vp, C.c_int64, C.POINTER(C.c_int64)],
+        "snk_set_star_radii": [vp, vp, C.c_int64],
         "snk_set_directions": [vp, vp, i32],
         "snk_load_volume": [vp, vp, C.c_int, i64, i64, i64, C.c_int],
         "snk_prepass": [vp],
@@ -185,6 +189,25 @@ def snk_set_launch(h, lanes_per_contour: int = 0, pairs_in_flight: int = 0, layo
 
 def snk_set_tile(h, tile_voxels: int = -1) -> None:
     _check(h, load().snk_set_tile(h, int(tile_voxels)))
+
+
+def snk_set_star(h, smooth: float = -1.0) -> None:
+    _check(h, load().snk_set_star(h, float(smooth)))
+
+
+def snk_get_star_radii(h) -> np.ndarray:
+    n = _count(h)
+    got = C.c_int64(0)
+    probe = np.zeros(1, np.float32)
+    load().snk_get_star_radii(h, _ptr(probe), 0, C.byref(got))
+    out = np.zeros(max(int(got.value), 1), np.float32)
+    _check(h, load().snk_get_star_radii(h, _ptr(out), len(out), C.byref(got)))
+    return out[: int(got.value)].reshape(n, -1) if n else out[:0].reshape(0, 0)
+
+
+def snk_set_star_radii(h, radii) -> None:
+    r = np.ascontiguousarray(radii, dtype=np.float32)
+    _check(h, load().snk_set_star_radii(h, _ptr(r), r.shape[0]))
 
 
 def snk_set_directions(h, dirs) -> None:
