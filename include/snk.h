@@ -207,7 +207,9 @@ snk_status snk_load_seeds(snk_ctx *ctx, const double *centers, const float *r0, 
 
 /* Run up to n_iter further iterations of every SNK_ACTIVE contour (Eqs. (7)-(15) with
  * Monte-Carlo sums, Sec. II-E); each contour continues its own iteration counter, so
- * evolve(a) then evolve(b) equals evolve(a + b). Runs the pre-pass first if needed. */
+ * evolve(a) then evolve(b) equals evolve(a + b). Runs the pre-pass first if needed. With 64 or
+ * more iterations (and no per-iteration trace) the iterations are enqueued as two kernel launches
+ * of about half each, which only changes how the still-active contours are spread over the CUs. */
 snk_status snk_evolve(snk_ctx *ctx, int32_t n_iter);
 
 /* End of evolution (Results): contours still ACTIVE become SNK_MAXITER; compute the exact

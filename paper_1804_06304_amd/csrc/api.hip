@@ -530,7 +530,17 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
         HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
         HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     }
-    HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
+    // A long evolve runs as two launches of half the iterations each: the second one starts only
+    // the contours still active, spread over every CU, instead of leaving them on the CUs the
+    // first launch gave them (the results are identical: every draw depends on the contour's id
+    // and iteration only).
+    const int parts = (!trace && n_iter >= 64) ? 2 : 1;
+    for (int part = 0, done = 0; part < parts; ++part) {
+        a.n_iter = (int)((int64_t)n_iter * (part + 1) / parts) - done;
+        done += a.n_iter;
+        HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
+    }
+    c->evolve_launches += parts - 1;
     c->last_lanes = lanes;
     c->last_unroll = exact ? 1 : unroll;
     c->last_layout = layout;
