@@ -29,9 +29,10 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "evolve_slab_counters.json")
 
 
-def measured_traffic(workload, launch_auto):
-    """HBM bytes per evolve launch from the committed FETCH_SIZE / WRITE_SIZE counters (scaled by the
-    copy-kernel calibration), or None when they were taken on other evolve sources or shapes."""
+def measured_traffic(workload, launch_auto, launches):
+    """HBM bytes per evolve call (summed over its launches) from the committed FETCH_SIZE / WRITE_SIZE
+    counters, scaled by the copy-kernel calibration; None when they were taken on other evolve
+    sources, shapes or launch counts."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -42,9 +43,10 @@ def measured_traffic(workload, launch_auto):
                 h.update(f.read())
     except (OSError, KeyError, ValueError):
         return None
-    if h.hexdigest() != c["source_sha256"] or c["workload"] != workload or not launch_auto:
+    if (h.hexdigest() != c["source_sha256"] or c["workload"] != workload or not launch_auto
+            or c.get("launches_per_evolve") != launches):
         return None
-    return float(c["hbm_bytes_per_dispatch"])
+    return float(c["hbm_bytes_per_evolve"])
 METRIC = "contour vertex-updates/s at fixed accuracy"
 
 
@@ -229,6 +231,7 @@ def main():
         step()
     torch.cuda.synchronize()
     evolve_ms, prepass_ms, finalize_ms, evolved = [], [], [], 0
+    launches0 = ctx.get_timing()["evolve_launches"]
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out, tm = step()
@@ -238,6 +241,7 @@ def main():
         evolved += tm["evolved"]
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    launches_per_evolve = (tm["evolve_launches"] - launches0) // args.steps
     ctx.close()
 
     M, L, d = p.n_rays, p.n_radial, p.dim
@@ -270,8 +274,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(wl.name, args.lanes == 0 and args.unroll == 0 and args.layout == 0
-                                                 and args.tile < 0),
+                                                 and args.tile < 0, launches_per_evolve),
                      "kernel": f"evolve_kernel<{d},*,false>",
+                     "launches_per_evolve": launches_per_evolve,
+                     "per": "one evolve call: its launches back to back on one stream, HIP events around them",
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }
     if args.exact:
