@@ -40,7 +40,9 @@
  * normalisation of Eq. (4); finite differences of the same-sample estimator against Eqs. (7)-(11);
  * the p,q <-> c,R identity; Monte-Carlo unbiasedness against quadrature; the pre-pass against a
  * library Gaussian filter; exact energy against a brute-force sum; greedy selection on
- * hand-built cases. End-to-end trajectories are "parity unpinned" beyond these pieces.
+ * hand-built cases; whole runs settling at the argmin of an independent quadrature of the
+ * continuous energy (ball, anisotropic ellipsoid, disk). A single stream's exact trajectory is
+ * fixed only by these pieces.
  *
  * Build: gcc -O2 -std=c11 -fopenmp -fPIC -shared snk_oracle.c -o libsnk_oracle.so -lm
  */

@@ -801,6 +801,115 @@ def test_cube_symmetry_exact(orc):
 
 
 # ------------------------------------------------------------------------------------------
+# the whole iteration settles at the minimiser of the continuous energy
+# ------------------------------------------------------------------------------------------
+
+def _fibonacci_sphere(n):
+    k = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * k / n
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    s = np.sqrt(1.0 - z * z)
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z], 1)
+
+
+def _quadrature_energy(orc, J, h, dim, dR, c, R, dirs, ngl):
+    """(2R)^-d times the integral of S(|x - c|; R) I(x) over the ball |x - c| < R + dR/2 (Eq. (5)
+    with the lattice sum replaced by the integral the sampler estimates), I the trilinear
+    (bilinear) interpolant of J by scipy: Gauss-Legendre in r on each interval where S is linear,
+    times an equal-weight angular rule."""
+    from scipy.ndimage import map_coordinates
+    from scipy.special import roots_legendre
+    rho = 2.0 ** (-1.0 / dim)
+    a, dr = rho * R, rho * dR
+    br = [0.0, a - dr / 2, a + dr / 2, R - dR / 2, R + dR / 2]
+    x, w = roots_legendre(ngl)
+    r = np.concatenate([lo + (hi - lo) * (x + 1) / 2 for lo, hi in zip(br[:-1], br[1:])])
+    wr = np.concatenate([w * (hi - lo) / 2 for lo, hi in zip(br[:-1], br[1:])])
+    S = orc.weight_vec(dim, r, R, dR)[:, 0]
+    P = c[None, None, :dim] + r[None, :, None] * dirs[:, None, :]
+    v = P / np.asarray(h[:dim])
+    Jd = J if dim == 3 else J[0]
+    I = map_coordinates(Jd, [v[..., ax].ravel() for ax in range(dim)][::-1], order=1,
+                        mode="nearest").reshape(P.shape[:2])
+    sphere = 4.0 * math.pi if dim == 3 else 2.0 * math.pi
+    return sphere * float((I * (S * wr * r ** (dim - 1))[None, :]).mean(0).sum()) / (2.0 * R) ** dim
+
+
+def _quadrature_minimiser(orc, J, h, dim, dR, c, lo, hi):
+    """argmin over R of the quadrature energy at the fixed centre c: coarse scan, then a parabola
+    through a fine scan around the best coarse point."""
+    if dim == 3:
+        coarse, fine = _fibonacci_sphere(2000), _fibonacci_sphere(20000)
+    else:
+        t = (np.arange(4096) + 0.5) * 2.0 * math.pi / 4096
+        coarse = fine = np.stack([np.cos(t), np.sin(t)], 1)
+    Rs = np.arange(lo, hi, 0.1)
+    Es = [_quadrature_energy(orc, J, h, dim, dR, c, R, coarse, 8) for R in Rs]
+    Rf = np.linspace(-0.1, 0.1, 11) + Rs[int(np.argmin(Es))]
+    Ef = [_quadrature_energy(orc, J, h, dim, dR, c, R, fine, 24) for R in Rf]
+    cf = np.polyfit(Rf, Ef, 2)
+    assert cf[0] > 0
+    return -cf[1] / (2.0 * cf[0])
+
+
+def _symmetric_blob(which):
+    """A blob point-symmetric about a lattice point c0 (so that c0 is a stationary centre of the
+    interpolated image too), with its volume J, parameters and direction table."""
+    if which == "ball":
+        h, shape, c0 = (1.0, 1.0, 1.0), (49, 49, 49), np.array([24.0, 24.0, 24.0])
+        z, y, x = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+        J = synth.blurred_ball(np.sqrt((x - 24.0) ** 2 + (y - 24.0) ** 2 + (z - 24.0) ** 2), 6.0, 1.0, 3)
+        p = synth.Params(dim=3, spacing=h, dR=1.0, n_dirs=642, n_rays=64)
+        dirs = synth.icosphere(3)
+    elif which == "ellipsoid":
+        # semi-axes 7, 5, 4 in a random orientation on the anisotropic grid h = (1, 1, 2)
+        h, shape, c0 = (1.0, 1.0, 2.0), (25, 49, 49), np.array([24.0, 24.0, 24.0])
+        rot = synth._random_rotation(np.random.default_rng(7))
+        cov = synth.render_ellipsoids(shape, h, c0[None], np.array([[7.0, 5.0, 4.0]]), rot[None], ss=4)
+        J = synth._blur(cov, 1.0)
+        p = synth.Params(dim=3, spacing=h, dR=0.75, n_dirs=642, n_rays=64)
+        dirs = synth.icosphere(3)
+    else:
+        h, shape, c0 = (1.0, 1.0, 1.0), (1, 65, 65), np.array([32.0, 32.0, 0.0])
+        y, x = np.meshgrid(np.arange(65), np.arange(65), indexing="ij")
+        J = synth.blurred_ball(np.sqrt((x - 32.0) ** 2 + (y - 32.0) ** 2), 8.0, 1.0, 2)[None]
+        p = synth.Params(dim=2, spacing=h, dR=1.0, n_dirs=64, n_rays=16)
+        dirs = synth.circle_directions(64)
+    p = p.replace(sigma_pre=0.0, i_offset=0.0, i_scale=1.0, eps0=8.0, r_min=0.0, r_max=20.0,
+                  n_radial=16, conv_window=0)
+    return np.ascontiguousarray(J, dtype=np.float64), h, c0, p, dirs
+
+
+@pytest.mark.parametrize("which,starts,n_iter,tol", [
+    ("ball", (6.2, 9.5), 1500, 0.01),
+    ("disk", (9.0, 14.0), 1500, 0.01),
+    ("ellipsoid", (6.2, 8.0), 4000, 0.015),
+])
+def test_iteration_settles_at_the_continuous_minimiser(orc, which, starts, n_iter, tol):
+    """The sampler's forces are unbiased estimates of the exact derivatives of the continuous energy
+    (S vanishes on the ball's outer edge, so moving that edge contributes nothing), hence the
+    descent with steps eps0 / sqrt(n) (Sec. II-D) settles where an independent quadrature of that
+    energy (scipy interpolation, Gauss-Legendre and angular rules) has its minimum over R at the
+    blob's centre. Contours started below and above the optimum, 32 Philox streams each, must end
+    with mean radius within tol of that minimiser and mean centre at the blob's centre. A dropped
+    normalisation term, a wrong sign, or a sampler that is not uniform in the ball moves the
+    settling point far beyond tol."""
+    J, h, c0, p, dirs = _symmetric_blob(which)
+    dim = p.dim
+    rstar = _quadrature_minimiser(orc, J, h, dim, p.dR, c0, 5.0, 16.0)
+    K = 32
+    rng = np.random.default_rng(3)
+    seeds = c0[None] + rng.uniform(-1.0, 1.0, size=(K, 3)) * (np.arange(3) < dim)
+    for r0 in starts:
+        st = orc.init_state(p, seeds, r0=r0, ids=np.arange(K, dtype=np.uint32) * 7 + 3, shape_zyx=J.shape)
+        orc.evolve(J, p, dirs, st, n_iter)
+        assert np.all(st.status == orc.ACTIVE) and np.all(st.iters == n_iter)
+        assert abs(st.R.mean() - rstar) < tol, (which, r0, st.R.mean(), rstar)
+        assert st.R.std() < 0.05, (which, r0, st.R.std())
+        assert np.max(np.abs(st.c.mean(0) - c0)[:dim]) < 0.05, (which, r0, st.c.mean(0))
+
+
+# ------------------------------------------------------------------------------------------
 # stop rule and selection (Results)
 # ------------------------------------------------------------------------------------------
 
