@@ -29,10 +29,10 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "evolve_slab_counters.json")
 
 
-def measured_traffic(workload, launch_auto, launches):
-    """HBM bytes per evolve call (summed over its launches) from the committed FETCH_SIZE / WRITE_SIZE
-    counters, scaled by the copy-kernel calibration; None when they were taken on other evolve
-    sources, shapes or launch counts."""
+def measured_counters(workload, launch_auto, launches):
+    """The committed counters of the evolve kernel: HBM bytes per evolve call (FETCH_SIZE and
+    WRITE_SIZE summed over its launches, scaled by the copy-kernel calibration) and VALU busy; None
+    when they were taken on other evolve sources, shapes or launch counts."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -46,7 +46,7 @@ def measured_traffic(workload, launch_auto, launches):
     if (h.hexdigest() != c["source_sha256"] or c["workload"] != workload or not launch_auto
             or c.get("launches_per_evolve") != launches):
         return None
-    return float(c["hbm_bytes_per_evolve"])
+    return c
 METRIC = "contour vertex-updates/s at fixed accuracy"
 
 
@@ -254,6 +254,9 @@ def main():
         f" wall {secs / args.steps * 1e3:.3f} ms; vertex-updates/step {per_launch_vu:.4g};"
         f" kept {int(out['keep'].sum())}/{len(out['keep'])}; launch lanes {tm['lanes_per_contour']}"
         f" pairs {tm['pairs_in_flight']} layout {tm['layout']} tile {tm['tile_voxels']}")
+    ctr = measured_counters(wl.name, args.lanes == 0 and args.unroll == 0 and args.layout == 0 and args.tile < 0,
+                            launches_per_evolve)
+    traffic = float(ctr["hbm_bytes_per_evolve"]) if ctr else None
     line = {
         "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
@@ -273,8 +276,11 @@ def main():
                        "finalize": float(np.mean(finalize_ms))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(wl.name, args.lanes == 0 and args.unroll == 0 and args.layout == 0
-                                                 and args.tile < 0, launches_per_evolve),
+                     "traffic": traffic,
+                     # beside the logical yardstick: the measured HBM rate and VALU busy (a fraction
+                     # of logical bytes above 1 means caches and LDS serve the gathers)
+                     "traffic_gbs": traffic / (ev_ms * 1e-3) / 1e9 if traffic else None,
+                     "valu_busy_pct": ctr.get("valu_busy_pct") if ctr else None,
                      "kernel": f"evolve_kernel<{d},*,false>",
                      "launches_per_evolve": launches_per_evolve,
                      "per": "one evolve call: its launches back to back on one stream, HIP events around them",

@@ -132,13 +132,14 @@ snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
 
 /* Launch shape of the evolution kernel: lanes per contour (0 = automatic; 16 or 32: several
  * contours share one wave64; 64: one wave; 128 or 256: a workgroup of 2 or 4 waves), antithetic
- * pair-points whose gathers one lane issues before consuming them (0 = automatic, 1 or 2), and the
+ * pair-points whose gathers one lane issues before consuming them (0 = automatic, 1, 2 or 4; 4 is
+ * taken with 64 or 128 lanes and outside snk_trace_step, otherwise it runs as 2), and the
  * layout the kernel reads the smoothed volume from (0 = automatic: quad when it fits, 1 = plain FP32,
  * 2 = quad: one 16-byte record per voxel with its +x, +y, +xy neighbours, 4x the FP32 volume; needs
  * 16 * nx*ny*nz below 2 GiB and ny, nz <= 65535, else SNK_EINVAL at the next evolve; 3 = plain FP32
  * with 64-bit addressing, the path of volumes beyond 2 GiB). Layouts change only how voxels are
- * fetched: results are bit-identical across layouts, and depend on the other two knobs only through
- * FP32 summation order. */
+ * fetched: results are bit-identical across layouts and across pair-point counts, and depend on
+ * lanes_per_contour only through FP32 summation order. */
 snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs_in_flight, int32_t layout);
 
 /* LDS box of the Monte-Carlo evolution (whole-wave launch shapes, layouts 1 and 2): each contour

@@ -303,8 +303,9 @@ struct McShape {
 // and there are more than four of them per CU (the common case of one volume with a few thousand
 // cells: their footprints overflow the L2, which a handful of contours per CU do not, where
 // staging only adds latency): two waves per contour when a contour has at least four pair-points
-// per lane of them, else one (unless set), two pair-points in flight, and the largest box whose
-// LDS still leaves room for all of them. Otherwise no box and the lane rule of pick_lanes.
+// per lane of them, else one (unless set), four pair-points in flight with two waves (two if that
+// would leave contours waiting, or with one wave), and the largest box whose LDS still leaves room
+// for all of them. Otherwise no box and the lane rule of pick_lanes.
 McShape mc_shape(snk_ctx *c, int M, int layout) {
     McShape s;
     s.lanes = pick_lanes(c);
@@ -321,13 +322,19 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
     if (per_cu <= 4) return s;
     const int G = c->lanes > 0 ? c->lanes : (pairs >= 512 ? 128 : (pairs >= 128 ? 64 : 0));
     if (G < 64) return s;
-    const int U = c->unroll > 0 ? c->unroll : 2;
-    const int key = ((c->P.dim * 512 + G) * 4 + U) * 4 + layout;
-    if (key != c->stage_key) {
-        c->stage_blocks = snk::evolve_stage_blocks_per_cu(c->P.dim, G, U, layout);
-        c->stage_key = key;
+    // two-wave groups with at least four pair-points per lane take all four in one pass when the
+    // contours still fit at that register count
+    int U = c->unroll > 0 ? c->unroll : ((G == 128 && pairs >= 4 * G) ? 4 : 2);
+    for (;;) {
+        const int key = ((c->P.dim * 512 + G) * 8 + U) * 4 + layout;
+        if (key != c->stage_key) {
+            c->stage_blocks = snk::evolve_stage_blocks_per_cu(c->P.dim, G, U, layout);
+            c->stage_key = key;
+        }
+        if (per_cu <= c->stage_blocks) break;
+        if (c->unroll > 0 || U == 2) return s;
+        U = 2;
     }
-    if (per_cu > c->stage_blocks) return s;
     const size_t other = snk::evolve_lds_bytes(c->P.dim, G, M, 0);
     // LDS is handed out in 512-byte blocks
     const size_t budget = std::min<size_t>((size_t)c->lds_per_cu / (size_t)per_cu, 65536) & ~(size_t)511;
@@ -685,8 +692,8 @@ snk_status snk_set_launch(snk_ctx *c, int32_t lanes_per_contour, int32_t pairs_i
     if (lanes_per_contour != 0 && lanes_per_contour != 16 && lanes_per_contour != 32 && lanes_per_contour != 64 &&
         lanes_per_contour != 128 && lanes_per_contour != 256)
         return fail(c, SNK_EINVAL, "lanes_per_contour must be 0 (auto), 16, 32, 64, 128 or 256");
-    if (pairs_in_flight < 0 || pairs_in_flight > 2)
-        return fail(c, SNK_EINVAL, "pairs_in_flight must be 0 (auto), 1 or 2");
+    if (pairs_in_flight < 0 || pairs_in_flight > 4 || pairs_in_flight == 3)
+        return fail(c, SNK_EINVAL, "pairs_in_flight must be 0 (auto), 1, 2 or 4");
     if (layout < 0 || layout > 3)
         return fail(c, SNK_EINVAL, "layout must be 0 (auto), 1 (plain), 2 (quad) or 3 (plain, 64-bit addressing)");
     c->lanes = lanes_per_contour;

@@ -1268,8 +1268,12 @@ hipError_t launch_l(const EvolveArgs &a, int layout, hipStream_t s) {
     }
 }
 
+// Four pair-points in flight: one- and two-wave groups, outside the per-iteration trace (there the
+// order of a lane's sums is the same as with two, so the trace runs the two-pair-point instance).
 template <int DIM, int G, bool TRACE>
 hipError_t launch_u(const EvolveArgs &a, int unroll, int layout, hipStream_t s) {
+    if constexpr (!TRACE && (G == 64 || G == 128))
+        if (unroll >= 4) return launch_l<DIM, G, 4, TRACE>(a, layout, s);
     return unroll >= 2 ? launch_l<DIM, G, 2, TRACE>(a, layout, s) : launch_l<DIM, G, 1, TRACE>(a, layout, s);
 }
 
@@ -1707,6 +1711,8 @@ int stage_blocks_t(int layout) {
 
 template <int DIM, int G>
 int stage_blocks_u(int unroll, int layout) {
+    if constexpr (G == 64 || G == 128)
+        if (unroll >= 4) return stage_blocks_t<DIM, G, 4>(layout);
     return unroll >= 2 ? stage_blocks_t<DIM, G, 2>(layout) : stage_blocks_t<DIM, G, 1>(layout);
 }
 

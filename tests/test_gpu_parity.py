@@ -185,10 +185,11 @@ def test_one_step_parity_2d(snk, stream, lanes, layout):
 
 
 @pytest.mark.parametrize("lanes,unroll,layout", [(16, 1, 0), (16, 2, 1), (32, 1, 2), (32, 2, 3), (64, 1, 1),
-                                                 (64, 2, 2), (128, 1, 3), (128, 2, 1), (256, 1, 2), (256, 2, 0)])
+                                                 (64, 2, 2), (64, 4, 3), (128, 1, 3), (128, 2, 1), (128, 4, 2),
+                                                 (256, 1, 2), (256, 2, 0)])
 def test_one_step_parity_launch_shapes(snk, stream, lanes, unroll, layout):
     """Every contour group size (several contours per wave, one wave, 2 and 4 waves per contour),
-    one or two pair-points in flight, and every volume layout."""
+    one, two or four pair-points in flight, and every volume layout."""
     say(f"one-step parity tiny, {lanes} lanes per contour, {unroll} pair-points in flight, layout {layout}")
     one_step_parity(snk, stream, synth.tiny_config(), [0, 12], n_extra=24, lanes=lanes, unroll=unroll,
                     layout=layout)
@@ -213,6 +214,35 @@ def test_layouts_bitwise(snk, stream):
 
 
 @pytest.mark.parametrize("which", ["tiny", "aniso", "plane"])
+def test_pair_points_in_flight_bitwise(snk, stream, which):
+    """A lane consumes its pair-points in the same order whatever number it keeps in flight (past
+    the last one, masked slots add exact zeros), so free runs with 1, 2 and 4 in flight are
+    identical for the same lanes per contour, with and without LDS boxes."""
+    if which == "tiny":
+        wl = synth.tiny_config()
+    elif which == "aniso":
+        wl = synth.slab_config(n_target=40, shape_xyz=(96, 80, 40), n_iter=80)
+    else:
+        wl = synth.plane_config(n_target=120, size=256, n_iter=80)
+    layout = 2 if wl.params.dim == 3 else 1
+    for lanes, tile in ((64, 0), (128, 0), (128, 3000)):
+        ref = None
+        for unroll in (1, 2, 4):
+            say(f"pair-points in flight {which}: lanes {lanes} pairs {unroll} tile {tile}")
+            ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout, tile=tile)
+            ctx.load_seeds(wl.seeds, ids=wl.ids)
+            ctx.evolve(wl.n_iter)
+            out = ctx.read()
+            assert ctx.get_timing()["pairs_in_flight"] == unroll
+            ctx.close()
+            if ref is None:
+                ref = out
+                continue
+            for k in ("radii", "centers", "e_mc", "iters", "status"):
+                assert np.array_equal(out[k], ref[k]), (k, lanes, unroll, tile)
+
+
+@pytest.mark.parametrize("which", ["tiny", "aniso", "plane"])
 def test_lds_box_bitwise(snk, stream, which):
     """LDS boxes hold exact copies of the volume and the corner arithmetic is unchanged, so a free
     run gives identical results with boxes of any capacity (tiny ones: most iterations read the
@@ -229,7 +259,7 @@ def test_lds_box_bitwise(snk, stream, which):
     ids = np.arange(len(seeds), dtype=np.uint32)
     n_iter = min(wl.n_iter, 60)
     layout = 2 if wl.params.dim == 3 else 1
-    for lanes, unroll in ((64, 2), (128, 1), (256, 2)):
+    for lanes, unroll in ((64, 2), (128, 1), (128, 4), (256, 2)):
         ref = None
         for tile in (0, 512, 3000, 12000, -1):
             say(f"lds box {which}: lanes {lanes} pairs {unroll} tile {tile}")
@@ -496,6 +526,43 @@ def test_full_size_slab_sampled(snk, stream):
     assert np.array_equal(got["iters"], st.iters)
     assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
     assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+
+
+def test_full_size_slab_free_run(snk, stream):
+    """The benchmark workload end to end as the benchmark runs it (automatic launch shape, all 500
+    iterations as one evolve call, then exact energy and selection): per-contour iteration counts,
+    states, radii and centres against the oracle's 500-iteration run; E_vox and the kept set
+    against the oracle evaluated at the GPU's own final state."""
+    wl = synth.slab_config()
+    p = wl.params
+    say(f"full-size slab free run: {wl.name}, {wl.n_iter} iterations")
+    ctx = make_ctx(snk, stream, wl)
+    ctx.load_seeds(wl.seeds, ids=wl.ids)
+    l0 = ctx.get_timing()["evolve_launches"]
+    ctx.evolve(wl.n_iter)
+    ctx.finalize()
+    got = ctx.read()
+    tm = ctx.get_timing()
+    ctx.close()
+    say(f"  launch lanes {tm['lanes_per_contour']} pairs {tm['pairs_in_flight']} layout {tm['layout']} "
+        f"tile {tm['tile_voxels']}, {tm['evolve_launches'] - l0} launches")
+    assert tm["evolve_launches"] - l0 == 2
+    ref = oracle.run(wl.raw, p, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    st = ref["state"]
+    same = got["iters"] == st.iters
+    assert same.mean() >= 0.99, same.mean()
+    assert np.array_equal(got["status"][same], st.status[same])
+    assert np.max(np.abs(got["radii"] - st.R)[same]) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[same]) <= 0.5
+    e_ref, e_abs = oracle.energy_vox(ref["J"], p, got["centers"], got["radii"].astype(np.float64))
+    tol_check("E_vox", got["e_vox"], e_ref, e_abs, 0.0, rel=2e-5)
+    amb = oracle.cull_ambiguity(p, got["centers"], got["radii"], e_ref)
+    keep_ref = oracle.cull(p, got["centers"], got["radii"], got["e_vox"].astype(np.float64), got["status"], wl.ids)
+    ok = amb == 0
+    assert ok.mean() >= 0.99
+    assert np.array_equal(got["keep"][ok], keep_ref[ok])
+    say(f"  same iterations {same.mean():.4f}, max |dR| {np.max(np.abs(got['radii'] - st.R)[same]):.4f}, "
+        f"kept {int(got['keep'].sum())} (oracle run {int(ref['keep'].sum())}), ambiguous {int(amb.sum())}")
 
 
 def test_full_size_plane_sampled(snk, stream):
