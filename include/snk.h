@@ -233,9 +233,11 @@ snk_status snk_seed_lattice(snk_ctx *ctx, double pitch, int64_t *n_out);
 /* snk_evolve with a culling pass after every `cull_every` (> 0) iterations and after the last one.
  * A pass ranks the live contours (ACTIVE or CONVERGED) by the Monte-Carlo energy of their last
  * iteration (e_mc of snk_read; the exact energy is left to snk_finalize): candidates are the live
- * contours with a finite energy that are younger than `grace_iters` iterations or have
- * e_mc <= params.e0; overlapping candidates compete as in snk_finalize (the lower (e_mc, id)
- * survives); the losers and the live non-candidates become SNK_CULLED (clamp flag kept) and stop.
+ * contours with a finite energy, all of them while fewer than `grace_iters` iterations of this call
+ * have run, afterwards those with e_mc <= params.e0 (a contour that stopped early is judged like the
+ * others once the grace period is over); overlapping candidates compete as in snk_finalize (the
+ * lower (e_mc, id) survives); the losers and the live non-candidates become SNK_CULLED (clamp flag
+ * kept) and stop.
  * n_iter = 0 runs one culling pass. Timing (snk_get_timing): evolve_ms covers the evolve launches
  * and the passes; evolved counts every contour-iteration of the call. */
 snk_status snk_evolve_cull(snk_ctx *ctx, int32_t n_iter, int32_t cull_every, int32_t grace_iters);

@@ -87,7 +87,7 @@ def lib():
         L.orc_num_threads.restype = C.c_int
         L.orc_lattice_seeds.argtypes = [P(_Params), i64, i64, i64, d, vp, i64]
         L.orc_lattice_seeds.restype = i64
-        L.orc_cull_pass.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, vp, i32]
+        L.orc_cull_pass.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, i32]
         L.orc_cull_pass.restype = i64
         _lib = L
     return _lib
@@ -405,25 +405,29 @@ def lattice_seeds(p, shape_zyx, pitch=None):
     return out
 
 
-def cull_pass(p, st: State, grace: int) -> int:
-    """One culling pass at the current state (in place, ranking by E_mc); returns the number
-    retired."""
+def cull_pass(p, st: State, young: bool) -> int:
+    """One culling pass at the current state (in place, ranking by E_mc); young: the run is still in
+    its grace period, so every live contour with a finite energy competes, not only those at or
+    below E0. Returns the number retired."""
     ps = params_struct(p)
-    return int(lib().orc_cull_pass(C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.iters), _ptr(st.e_mc),
-                                   _ptr(st.status), _ptr(st.ids), int(grace)))
+    return int(lib().orc_cull_pass(C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.e_mc), _ptr(st.status),
+                                   _ptr(st.ids), int(bool(young))))
 
 
 def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int):
-    """Evolution in chunks of `every` iterations with a culling pass after each chunk; returns the
-    number of contour-iterations run."""
+    """Evolution in chunks of `every` iterations with a culling pass after each chunk (the pass after
+    `done` iterations of the run is young while done < grace); returns the number of
+    contour-iterations run."""
     done, total = 0, 0
-    while done < n_iter:
+    while True:
         k = min(every, n_iter - done)
-        _, ran = evolve(J, p, dirs, st, k)
-        total += ran
-        done += k
-        cull_pass(p, st, grace)
-    return total
+        if k > 0:
+            _, ran = evolve(J, p, dirs, st, k)
+            total += ran
+            done += k
+        cull_pass(p, st, done < grace)
+        if done >= n_iter:
+            return total
 
 
 def run(raw, p, dirs, seeds, n_iter, r0=None, ids=None):

@@ -914,13 +914,14 @@ int64_t orc_lattice_seeds(const orc_params *p, int64_t nx, int64_t ny, int64_t n
 
 /* One culling pass at the current state, ranking live contours (ACTIVE or CONVERGED) by the
  * Monte-Carlo energy of their last iteration (the exact energy stays with the final selection):
- * candidates are the live contours with a finite energy that either are younger than `grace`
- * iterations or have E_mc <= E0; overlapping candidates compete as in the final selection
- * (sequential greedy in ascending (E_mc, id)) and the losers are retired, as are the live contours
- * that are not candidates. Retired contours keep their state with status CULLED (clamp flag kept).
- * Returns the number retired. */
-int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const double *R, const int32_t *iters,
-                      const double *e_mc, uint8_t *status, const uint32_t *ids, int32_t grace)
+ * candidates are the live contours with a finite energy, all of them while the run is young (its
+ * grace period, counted in the run's iterations, has not ended), afterwards only those with
+ * E_mc <= E0; overlapping candidates compete as in the final selection (sequential greedy in
+ * ascending (E_mc, id)) and the losers are retired, as are the live contours that are not
+ * candidates. Retired contours keep their state with status CULLED (clamp flag kept). Returns the
+ * number retired. */
+int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const double *R, const double *e_mc,
+                      uint8_t *status, const uint32_t *ids, int32_t young)
 {
     int dim = p->dim;
     double rho = rho_of(dim);
@@ -929,7 +930,7 @@ int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const dou
     for (int64_t i = 0; i < n; ++i) {
         int st = status[i] & 0x0f;
         if (st != ORC_ACTIVE && st != ORC_CONVERGED) continue;
-        if (isfinite(e_mc[i]) && (iters[i] < grace || e_mc[i] <= p->e0)) {
+        if (isfinite(e_mc[i]) && (young || e_mc[i] <= p->e0)) {
             keys[nc].e = e_mc[i]; keys[nc].id = ids[i]; keys[nc].idx = i; ++nc;
         } else {
             status[i] = (uint8_t)((status[i] & ORC_CLAMPED) | ORC_CULLED);

@@ -948,9 +948,11 @@ snk_status snk_evolve_cull(snk_ctx *c, int32_t n_iter, int32_t cull_every, int32
             st = run_evolve(c, k, false, false);
             if (st != SNK_OK) return st;
         }
-        st = run_select(c, 1, grace_iters);
-        if (st != SNK_OK) return st;
+        // the grace period counts the iterations of this call: until it ends every live contour
+        // competes (the pass's age test is passed for all of them), afterwards none is young
         done += k;
+        st = run_select(c, 1, done < grace_iters ? INT32_MAX : 0);
+        if (st != SNK_OK) return st;
     } while (done < n_iter);
     HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
     c->ev_evo = true;

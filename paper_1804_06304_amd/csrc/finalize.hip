@@ -209,8 +209,8 @@ __device__ __forceinline__ void bin_one(const JobDev &a, int i) {
     const DevContour s = a.st[i];
     const int st = s.status & 0x0f;
     const double e = rank_energy(a, i, s);
-    // final selection: stopped contours at or below E0; culling pass: live contours below E0 or
-    // still within their grace period
+    // final selection: stopped contours at or below E0; culling pass: live contours below E0, or all
+    // of them during the run's grace period (the host passes a grace above every count then, else 0)
     const bool cand = a.mode != 1 ? (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0
                                   : (st == SNK_ACTIVE || st == SNK_CONVERGED) && isfinite(e) &&
                                         (s.iters < a.grace || e <= (double)a.e0);
@@ -284,10 +284,29 @@ __device__ __forceinline__ void scatter_one(const JobDev &a, int i) {
     }
 }
 
+// Outcome of the decisions for contour i: keep flag (final selection) or retirement (culling pass);
+// returns 1 when it counts (kept, or retired).
+__device__ __forceinline__ int apply_one(const JobDev &a, int i, int d) {
+    if (a.mode != 1) {
+        const uint8_t k = d == DEC_ACCEPT ? 1 : 0;
+        a.st[i].keep = k;
+        return k;
+    }
+    // culling pass: live contours that lost or are no candidates stop
+    const uint8_t s8 = a.st[i].status;
+    const int st = s8 & 0x0f;
+    if ((st == SNK_ACTIVE || st == SNK_CONVERGED) && d != DEC_ACCEPT) {
+        a.st[i].status = (uint8_t)((s8 & SNK_CLAMPED) | SNK_CULLED);
+        return 1;
+    }
+    return 0;
+}
+
 // Whole selection of one job by one workgroup. binned: the grid (cell_start, items, cell_of, dec)
-// was already built and some decisions may already be taken.
+// was already built and some decisions may already be taken; then a scan of the decisions decides
+// whether the decision loop is needed at all. apply = false leaves the outcome to sel_apply_kernel.
 template <int DIM>
-__device__ void select_job(const JobDev &a, bool binned) {
+__device__ void select_job(const JobDev &a, bool binned, bool apply = true) {
     __shared__ int chunk_sum[SEL_T];
     const int t = threadIdx.x;
     const int n = a.n;
@@ -305,36 +324,29 @@ __device__ void select_job(const JobDev &a, bool binned) {
         __syncthreads();
     }
     bool any = true;
+    if (binned) {
+        // no decision is written while this scan runs, so plain loads (issued back to back) serve
+        const int *dn = a.dec;
+        int local = 0;
+#pragma unroll 8
+        for (int i = t; i < n; i += SEL_T) local |= dn[i] == DEC_UNDECIDED ? 1 : 0;
+        any = __syncthreads_or(local) != 0;
+    }
     while (any) {
         int local = 0;
         for (int i = t; i < n; i += SEL_T) local |= decide<DIM>(a, i) == DEC_UNDECIDED ? 1 : 0;
         __threadfence_block();
         any = __syncthreads_or(local) != 0;
     }
+    if (!apply) return;
     unsigned long long count = 0;
-    if (a.mode != 1) {
-        for (int i = t; i < n; i += SEL_T) {
-            const uint8_t k = dec[i] == DEC_ACCEPT ? 1 : 0;
-            a.st[i].keep = k;
-            count += k;
-        }
-    } else {
-        // culling pass: live contours that lost or are no candidates stop
-        for (int i = t; i < n; i += SEL_T) {
-            const uint8_t s8 = a.st[i].status;
-            const int st = s8 & 0x0f;
-            if ((st == SNK_ACTIVE || st == SNK_CONVERGED) && dec[i] != DEC_ACCEPT) {
-                a.st[i].status = (uint8_t)((s8 & SNK_CLAMPED) | SNK_CULLED);
-                count += 1;
-            }
-        }
-    }
+    for (int i = t; i < n; i += SEL_T) count += apply_one(a, i, dec[i]);
     if (count) atomicAdd(a.kept, count);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(SEL_T) void select_kernel(JobDev j, int binned) {
-    if (j.n > 0) select_job<DIM>(j, binned != 0);
+__global__ __launch_bounds__(SEL_T) void select_kernel(JobDev j, int binned, int apply) {
+    if (j.n > 0) select_job<DIM>(j, binned != 0, apply != 0);
 }
 
 template <int DIM>
@@ -383,6 +395,14 @@ __global__ __launch_bounds__(SG_T) void sel_round_kernel(JobDev a, int r, int *r
     if (__builtin_amdgcn_ballot_w64(left != 0) != 0 && (threadIdx.x & 63) == 0) atomicAdd(&rounds[r % 3], 1);
 }
 
+// The outcome of every decision, grid-wide (after the decisions are complete).
+__global__ __launch_bounds__(SG_T) void sel_apply_kernel(JobDev a) {
+    const int i = blockIdx.x * SG_T + threadIdx.x;
+    const int c = i < a.n ? apply_one(a, i, a.dec[i]) : 0;
+    const int total = __syncthreads_count(c);
+    if (threadIdx.x == 0 && total) atomicAdd(a.kept, (unsigned long long)total);
+}
+
 template <int DIM>
 hipError_t select_grid(const JobDev &j, int *rounds, hipStream_t s) {
     const int G = j.G[0] * j.G[1] * j.G[2];
@@ -393,7 +413,8 @@ hipError_t select_grid(const JobDev &j, int *rounds, hipStream_t s) {
     hipLaunchKernelGGL(sel_scatter_kernel, dim3(bn), dim3(SG_T), 0, s, j);
     for (int r = 0; r < kSelectGridRounds; ++r)
         hipLaunchKernelGGL(sel_round_kernel<DIM>, dim3(bn), dim3(SG_T), 0, s, j, r, rounds);
-    hipLaunchKernelGGL(select_kernel<DIM>, dim3(1), dim3(SEL_T), 0, s, j, 1);
+    hipLaunchKernelGGL(select_kernel<DIM>, dim3(1), dim3(SEL_T), 0, s, j, 1, 0);
+    hipLaunchKernelGGL(sel_apply_kernel, dim3(bn), dim3(SG_T), 0, s, j);
     return hipGetLastError();
 }
 
@@ -424,8 +445,8 @@ hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, 
 hipError_t launch_select(const JobDev &j, int dim, int *rounds, hipStream_t s) {
     if (j.n <= 0) return hipSuccess;
     if (j.n > kSelectGridMin && rounds) return dim == 2 ? select_grid<2>(j, rounds, s) : select_grid<3>(j, rounds, s);
-    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, j, 0);
-    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, j, 0);
+    if (dim == 2) hipLaunchKernelGGL(select_kernel<2>, dim3(1), dim3(SEL_T), 0, s, j, 0, 1);
+    else hipLaunchKernelGGL(select_kernel<3>, dim3(1), dim3(SEL_T), 0, s, j, 0, 1);
     return hipGetLastError();
 }
 

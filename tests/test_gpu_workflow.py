@@ -61,18 +61,19 @@ def test_lattice_matches_oracle(snk, which):
     ctx.close()
 
 
-def _oracle_lattice_state(wl, J, n_iter):
-    seeds = oracle.lattice_seeds(wl.params, wl.raw.shape)
+def _oracle_lattice_state(wl, J, n_iter, pitch=None):
+    seeds = oracle.lattice_seeds(wl.params, wl.raw.shape, pitch=pitch)
     st = oracle.init_state(wl.params, seeds, ids=np.arange(len(seeds), dtype=np.uint32), shape_zyx=wl.raw.shape)
     if n_iter:
         oracle.evolve(J, wl.params, wl.dirs, st, n_iter)
     return st
 
 
-@pytest.mark.parametrize("which,n_iter,grace", [("tiny", 30, 20), ("tiny", 12, 5), ("plane", 20, 10)])
+@pytest.mark.parametrize("which,n_iter,grace", [("tiny", 30, 1), ("tiny", 12, 0), ("plane", 20, 1)])
 def test_cull_pass_parity(snk, which, n_iter, grace):
     """From the oracle's state (rounded to FP32) both sides run one iteration, which leaves E_mc
-    in the state, then one culling pass."""
+    in the state, then one culling pass after the grace period (E0 retires contours as well as the
+    competition)."""
     wl = synth.tiny_config() if which == "tiny" else synth.plane_config(n_target=200, size=320, n_iter=60)
     J = oracle.prepass(wl.raw, wl.params)
     st = _oracle_lattice_state(wl, J, n_iter)
@@ -86,7 +87,7 @@ def test_cull_pass_parity(snk, which, n_iter, grace):
     ctx.close()
     oracle.evolve(J, wl.params, wl.dirs, st, 1)
     before = st.status.copy()
-    k = oracle.cull_pass(wl.params, st, grace)
+    k = oracle.cull_pass(wl.params, st, 1 < grace)
     live = np.isin(before & 0x0F, [oracle.ACTIVE, oracle.CONVERGED])
     amb = np.zeros(len(st.R), bool)
     li = np.where(live)[0]
@@ -95,6 +96,37 @@ def test_cull_pass_parity(snk, which, n_iter, grace):
     retired_gpu = int(((got["status"] & 0x0F) == oracle.CULLED).sum() - ((before & 0x0F) == oracle.CULLED).sum())
     say(f"cull pass {which} after {n_iter} + 1: {int(live.sum())} live, oracle retired {k}, GPU retired "
         f"{retired_gpu}, ambiguous {int(amb.sum())}, differing {int(diff.sum())}")
+    assert k > 0
+    assert not np.any(diff & ~amb), np.where(diff & ~amb)[0][:10]
+
+
+@pytest.mark.parametrize("which,grace", [("tiny", 5), ("tiny", 0), ("plane", 10)])
+def test_cull_pass_dense_lattice(snk, which, grace):
+    """A lattice dense enough for neighbours to overlap (pitch 0.6 R0), 8 iterations on the GPU, then
+    one culling pass alone (snk_evolve_cull with no iterations: inside the grace period unless it is
+    0). The oracle's pass on the GPU's own pre-pass state (centres, radii, E_mc, statuses) must
+    retire the same contours: in a dense set one flipped decision would cascade, so the pass is
+    checked on identical inputs here; decisions within rounding of a threshold are excluded."""
+    wl = synth.tiny_config() if which == "tiny" else synth.plane_config(n_target=200, size=320, n_iter=60)
+    p = wl.params
+    ctx = make_ctx(snk, wl)
+    n = ctx.seed_lattice(0.6 * p.r_init)
+    ctx.evolve(8)
+    pre = ctx.read()
+    ctx.evolve_cull(0, 1, grace)
+    got = ctx.get_state()
+    ctx.close()
+    st = oracle.State(c=pre["centers"].astype(np.float64), R=pre["radii"].astype(np.float64),
+                      iters=pre["iters"].copy(), status=pre["status"].copy(), streak=np.zeros(n, np.uint8),
+                      e_mc=pre["e_mc"].astype(np.float64), ids=np.arange(n, dtype=np.uint32))
+    k = oracle.cull_pass(p, st, grace > 0)
+    live = np.isin(pre["status"] & 0x0F, [oracle.ACTIVE, oracle.CONVERGED])
+    amb = np.zeros(n, bool)
+    li = np.where(live)[0]
+    amb[li] = oracle.cull_ambiguity(p, st.c[li], st.R[li], st.e_mc[li]) != 0
+    diff = got["status"] != st.status
+    say(f"dense cull pass {which} grace {grace}: {n} contours, {int(live.sum())} live, oracle retired {k}, "
+        f"ambiguous {int(amb.sum())}, differing {int(diff.sum())}")
     assert k > 0
     assert not np.any(diff & ~amb), np.where(diff & ~amb)[0][:10]
 

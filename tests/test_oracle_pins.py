@@ -1006,10 +1006,10 @@ def test_lattice_seeds(orc):
     assert np.all(pts2[:, 2] == 0.0) and len(pts2) == int(29 // np.sqrt(37.5)) * int(39 // np.sqrt(37.5))
 
 
-def _greedy_cull(c, R, e, live, iters, ids, grace, e0, dim):
+def _greedy_cull(c, R, e, live, ids, young, e0, dim):
     """Brute-force reference of one culling pass: which live contours survive."""
     rho = 2.0 ** (-1.0 / dim)
-    cand = [i for i in range(len(R)) if live[i] and np.isfinite(e[i]) and (iters[i] < grace or e[i] <= e0)]
+    cand = [i for i in range(len(R)) if live[i] and np.isfinite(e[i]) and (young or e[i] <= e0)]
     cand.sort(key=lambda i: (e[i], ids[i]))
     acc = []
     for i in cand:
@@ -1018,11 +1018,11 @@ def _greedy_cull(c, R, e, live, iters, ids, grace, e0, dim):
     return set(acc)
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_cull_pass_matches_brute_force(orc, seed):
+@pytest.mark.parametrize("seed,young", [(0, False), (1, False), (2, True), (3, True)])
+def test_cull_pass_matches_brute_force(orc, seed, young):
     """A culling pass retires exactly the live contours that lose the greedy competition (ranked by
-    E_mc) or are past the grace period above E0; other statuses are untouched and keep their clamp
-    flag."""
+    E_mc), and after the run's grace period also those above E0; other statuses are untouched and
+    keep their clamp flag."""
     rng = np.random.default_rng(seed)
     p = synth.Params(dim=3, dR=1.0, e0=-0.01)
     n = 120
@@ -1036,9 +1036,9 @@ def test_cull_pass_matches_brute_force(orc, seed):
     e_mc[::29] = np.nan
     st = orc.State(c=c.copy(), R=R.copy(), iters=iters.copy(), status=status.copy(),
                    streak=np.zeros(n, np.uint8), e_mc=e_mc.copy(), ids=ids)
-    k = orc.cull_pass(p, st, grace=30)
+    k = orc.cull_pass(p, st, young)
     live = np.isin(status & 0x0F, [orc.ACTIVE, orc.CONVERGED])
-    keep = _greedy_cull(c, R, e_mc, live, iters, ids, 30, p.e0, 3)
+    keep = _greedy_cull(c, R, e_mc, live, ids, young, p.e0, 3)
     for i in range(n):
         if not live[i]:
             assert st.status[i] == status[i]
