@@ -565,6 +565,29 @@ def test_full_size_slab_free_run(snk, stream):
         f"kept {int(got['keep'].sum())} (oracle run {int(ref['keep'].sum())}), ambiguous {int(amb.sum())}")
 
 
+def test_full_size_split_calls_identical(snk, stream):
+    """The benchmark workload in its automatic shape (LDS boxes, each call of 64 or more iterations
+    as two launches): the same 500 iterations split into calls of different lengths give
+    bit-identical contours."""
+    wl = synth.slab_config()
+    say(f"split calls: {wl.name}")
+    ref, tm_ref = None, None
+    for chunks in ([500], [200, 300], [256, 244], [300, 200], [100, 100, 100, 200]):
+        ctx = make_ctx(snk, stream, wl)
+        ctx.load_seeds(wl.seeds, ids=wl.ids)
+        for k in chunks:
+            ctx.evolve(k)
+        out = ctx.read()
+        tm = ctx.get_timing()
+        ctx.close()
+        if ref is None:
+            ref, tm_ref = out, tm
+            continue
+        for k in ("radii", "centers", "e_mc", "iters", "status"):
+            assert np.array_equal(out[k], ref[k]), (chunks, k)
+    assert tm_ref["lanes_per_contour"] == 128 and tm_ref["tile_voxels"] > 0
+
+
 def test_full_size_plane_sampled(snk, stream):
     """The 2D workload at full size (8192^2 u8, 40,000 cells, D 64, M 16) in the benchmark's launch
     configuration: one-step parity of every contour from the seeds and after 20 iterations, and a
