@@ -85,6 +85,20 @@ def cpu_baseline(wl, gpu_out, n_sample):
             "sample": (f"first {S} of {n} contours, all {wl.n_iter} iterations, FP64 oracle "
                        f"(gcc -O2, OpenMP over contours); pre-pass over the full volume prorated by {S}/{n}; "
                        f"{secs:.1f} s of CPU work")}
+    # one thread on a bounded subset: the first 40 contours' evolution (pre-pass excluded)
+    threads = oracle.num_threads()
+    S1 = min(40, n)
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        st1 = oracle.init_state(p, wl.seeds[:S1], ids=wl.ids[:S1], shape_zyx=wl.raw.shape)
+        _, done1 = oracle.evolve(J, p, wl.dirs, st1, wl.n_iter)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    base["single_thread"] = {"value": done1 * p.n_rays / t1, "unit": "vertex-updates/s", "cores": 1,
+                             "sample": f"first {S1} contours, all {wl.n_iter} iterations, evolution only, "
+                                       f"{t1:.1f} s"}
     return base, parity
 
 
@@ -286,6 +300,13 @@ def main():
                      "per": "one evolve call: its launches back to back on one stream, HIP events around them",
                      "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
     }
+    # the evolve kernel alone (HIP events around its launches) and its rates in other units
+    ci_step = evolved / args.steps
+    line["evolve_only"] = {"vertex_updates_per_s": per_launch_vu / (ev_ms * 1e-3),
+                           "contour_iterations_per_s": ci_step / (ev_ms * 1e-3),
+                           "sample_points_per_s": per_launch_vu * L / (ev_ms * 1e-3),
+                           "note": f"a sample point is one {2 ** d}-tap interpolated gather; "
+                                   f"{L} per vertex-update"}
     if args.exact:
         # no rays are sampled: report contour-iterations/s (and its time per contour-iteration) to
         # set beside the Monte-Carlo path's on the same workload

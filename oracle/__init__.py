@@ -85,6 +85,8 @@ def lib():
         L.orc_cull_ambiguity.argtypes = [P(_Params), i64, vp, vp, vp, d, d, vp]
         L.orc_cull_ambiguity.restype = i64
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         L.orc_lattice_seeds.argtypes = [P(_Params), i64, i64, i64, d, vp, i64]
         L.orc_lattice_seeds.restype = i64
         L.orc_cull_pass.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, i32]
@@ -443,3 +445,8 @@ def run(raw, p, dirs, seeds, n_iter, r0=None, ids=None):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's loops over contours (timing only)."""
+    lib().orc_set_num_threads(int(n))

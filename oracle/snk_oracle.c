@@ -1256,6 +1256,17 @@ int64_t orc_star_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, con
     return done;
 }
 
+/* Threads the parallel loops over contours use from now on (timing only; results do not depend
+ * on it: every contour is computed by one thread in a fixed order). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
