@@ -31,8 +31,10 @@ struct snk_ctx {
 
     // star-shaped contours (lambda < 0: off)
     double star_lambda = -1.0;
-    int *d_anti = nullptr, *d_nb_off = nullptr, *d_nb_idx = nullptr;
-    size_t anti_cap = 0, nb_off_cap = 0, nb_idx_cap = 0;
+    int *d_anti = nullptr;
+    uint16_t *d_nb = nullptr;  // neighbour rows, nb_chunks x 8 entries each, 0xffff past the last
+    int nb_chunks = 0;
+    size_t anti_cap = 0, nb_cap = 0;
     std::vector<float> star_dirs;    // the table the star tables were built from
     float *d_Rk = nullptr;           // n x D radii
     size_t Rk_cap = 0;
@@ -420,14 +422,20 @@ snk_status star_tables(snk_ctx *c) {
     }
     snk_status st = ensure(c, &c->d_anti, &c->anti_cap, (size_t)D);
     if (st != SNK_OK) return st;
-    st = ensure(c, &c->d_nb_off, &c->nb_off_cap, (size_t)D + 1);
-    if (st != SNK_OK) return st;
-    st = ensure(c, &c->d_nb_idx, &c->nb_idx_cap, std::max<size_t>(idx.size(), 1));
+    // rows of whole 16-byte chunks (8 entries, in the order above, 0xffff after the last), so the
+    // kernel loads a direction's neighbours with independent vector loads
+    if (D >= 0xffff) return fail(c, SNK_EINVAL, "star contours need fewer than 65535 directions");
+    int maxdeg = 1;
+    for (int k = 0; k < D; ++k) maxdeg = std::max(maxdeg, off[k + 1] - off[k]);
+    const int chunks = (maxdeg + 7) / 8;
+    std::vector<uint16_t> nb((size_t)D * chunks * 8, 0xffff);
+    for (int k = 0; k < D; ++k)
+        for (int b = off[k]; b < off[k + 1]; ++b) nb[(size_t)k * chunks * 8 + (b - off[k])] = (uint16_t)idx[b];
+    st = ensure(c, &c->d_nb, &c->nb_cap, nb.size());
     if (st != SNK_OK) return st;
     HIPTRY(c, hipMemcpyAsync(c->d_anti, anti.data(), sizeof(int) * D, hipMemcpyHostToDevice, c->stream));
-    HIPTRY(c, hipMemcpyAsync(c->d_nb_off, off.data(), sizeof(int) * (D + 1), hipMemcpyHostToDevice, c->stream));
-    if (!idx.empty())
-        HIPTRY(c, hipMemcpyAsync(c->d_nb_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipMemcpyAsync(c->d_nb, nb.data(), sizeof(uint16_t) * nb.size(), hipMemcpyHostToDevice, c->stream));
+    c->nb_chunks = chunks;
     HIPTRY(c, hipStreamSynchronize(c->stream));
     c->star_dirs = c->dirs_host;
     return SNK_OK;
@@ -462,8 +470,8 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
     a.counter = c->d_counters;
     snk::StarArgs sa{};
     sa.anti = c->d_anti;
-    sa.nb_off = c->d_nb_off;
-    sa.nb_idx = c->d_nb_idx;
+    sa.nb = c->d_nb;
+    sa.nb_chunks = c->nb_chunks;
     sa.Rk = c->d_Rk;
     sa.lambda = (float)c->star_lambda;
     if (standalone) {
@@ -665,8 +673,8 @@ snk_status snk_destroy(snk_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->Jq, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
-                    c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters, c->d_anti, c->d_nb_off,
-                    c->d_nb_idx, c->d_Rk};
+                    c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters, c->d_anti, c->d_nb,
+                    c->d_Rk};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &ev : c->ev)

@@ -1369,7 +1369,7 @@ int max_blocks_g(int lanes, int unroll, int layout, int max_M) {
 template <int DIM>
 __host__ __device__ __forceinline__ int star_lds_floats(int D, int M) {
     const int per = (draw_floats(64, M / 2) + 3) & ~3;
-    return per + 3 * D + 2 * M;
+    return per + 3 * D + 2 * M + (M / 2) * (2 + DIM);
 }
 
 template <int DIM, int LAYOUT>
@@ -1393,6 +1393,10 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
     float *gk = Rb + D;
     int *ray_dir = reinterpret_cast<int *>(gk + D);
     float *ray_g = reinterpret_cast<float *>(ray_dir + M);
+    // this iteration's ray pairs: direction, antipode, unit vector
+    int *rk = reinterpret_cast<int *>(ray_g + M);
+    int *rka = rk + MH;
+    float *ru = reinterpret_cast<float *>(rka + MH);
     float *Rg = sa.Rk + (long)cid * D;
     for (int k = lane; k < D; k += 64) {
         Ra[k] = Rg[k];
@@ -1444,69 +1448,109 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
             interior = interior && (off[ax] - ext > (float)(-anc[ax])) && (off[ax] + ext < (float)(vol.n[ax] - 1 - anc[ax]));
         }
         fr.base = base;
+        // the ray pairs' tables entries, once per iteration (the pair-points below read them from LDS)
+        for (int m = lane; m < MH; m += 64) {
+            const int k = __float_as_int(pu[m].x);
+            rk[m] = k;
+            rka[m] = sa.anti[k];
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) ru[m * DIM + ax] = p.dirs[k * DIM + ax];
+        }
+        __syncthreads();
         float accE = 0.0f, accc[3] = {0.0f, 0.0f, 0.0f};
-        // pair-points q = lane + 64 j: pair m = q / 16, radial index l = q % 16 (one DPP row per pair)
-        for (int q = lane; q < MH * L; q += 64) {
-            const int m = q >> 4, l = q & 15;
-            const float4 d = pu[m];
-            const int k = __float_as_int(d.x);
-            const int ka = sa.anti[k];
-            float u[3] = {0.0f, 0.0f, 0.0f}, du[3] = {0.0f, 0.0f, 0.0f};
+        // pair-points q = lane + 64 j: pair m = q / 16, radial index l = q % 16 (one DPP row per pair);
+        // two of them in flight, consumed in order
+        const int PP = MH * L;
+        for (int q0 = lane; q0 - lane < PP; q0 += 128) {
+            Corners<DIM> cr[2][2];
+            float fv[2][2][3], Rv[2][2], ev[2], uv[2][3];
+            int mv2[2], lv[2], kv[2][2];
+            bool on[2];
 #pragma unroll
-            for (int ax = 0; ax < DIM; ++ax) {
-                u[ax] = p.dirs[k * DIM + ax];
-                du[ax] = u[ax] * inv_h[ax];
-            }
-            const float e = cube_or_square_root<DIM>(((float)l + d.w) * invL);
-            float Ival[2], Sv[2], cCv[2], cRv[2], qv[2], Rv[2];
+            for (int h = 0; h < 2; ++h) {
+                const int q = q0 + 64 * h;
+                on[h] = q < PP;
+                if (!on[h]) continue;
+                const int m = q >> 4, l = q & 15;
+                mv2[h] = m;
+                lv[h] = l;
+                const int k = rk[m], ka = rka[m];
+                kv[h][0] = k;
+                kv[h][1] = ka;
+                float du[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int sg = 0; sg < 2; ++sg) {
-                const float R = Rold[sg ? ka : k];
-                const float smax = R + 0.5f * p.dR;
-                const float rad = smax * e;
-                float w[3] = {0.0f, 0.0f, 0.0f}, f[3];
+                for (int ax = 0; ax < 3; ++ax) uv[h][ax] = 0.0f;
 #pragma unroll
-                for (int ax = 0; ax < DIM; ++ax) w[ax] = fmaf(sg ? -rad : rad, du[ax], off[ax]);
-                Corners<DIM> cr;
-                if (interior) vol.load(locate<DIM, false, Vol<DIM, LAYOUT>::kSmall>(fr, vol.n, vol.nx, vol.nxy, w, f), cr);
-                else vol.load(locate<DIM, true, Vol<DIM, LAYOUT>::kSmall>(fr, vol.n, vol.nx, vol.nxy, w, f), cr);
-                const float I = trilerp<DIM>(cr, f);
-                const float d1 = fmaf(smax, e, -RHO * R), d2 = fmaf(smax, e, -R);
-                const float is = p.in_slope, os = p.out_slope;
-                const bool r1 = d1 >= -hd && d1 < hd;
-                const bool r2 = d2 >= -hD && d2 < hD;
-                const float sin_ = __builtin_amdgcn_fmed3f(d1 * is, -1.0f, 1.0f);
-                const float sout = __builtin_amdgcn_fmed3f(fmaf(-d2, os, 0.5f), 0.0f, 1.0f);
-                const float inv2R = __builtin_amdgcn_rcpf(2.0f * R);
-                float nrm = inv2R, sm_d = smax;
-#pragma unroll
-                for (int i = 1; i < DIM; ++i) {
-                    nrm *= inv2R;
-                    sm_d *= smax;
+                for (int ax = 0; ax < DIM; ++ax) {
+                    uv[h][ax] = ru[m * DIM + ax];
+                    du[ax] = uv[h][ax] * inv_h[ax];
                 }
-                Ival[sg] = I;
-                Sv[sg] = fminf(sin_, sout);
-                cCv[sg] = r1 ? is : (r2 ? -os : 0.0f);
-                cRv[sg] = r1 ? -RHO * is : -cCv[sg];
-                qv[sg] = BALL * sm_d * nrm * inv_ml;
-                Rv[sg] = R;
+                const float e = cube_or_square_root<DIM>(((float)l + pu[m].w) * invL);
+                ev[h] = e;
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                    const float R = Rold[sg ? ka : k];
+                    const float smax = R + 0.5f * p.dR;
+                    const float rad = smax * e;
+                    float w[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int ax = 0; ax < DIM; ++ax) w[ax] = fmaf(sg ? -rad : rad, du[ax], off[ax]);
+                    Rv[h][sg] = R;
+                    if (interior)
+                        vol.load(locate<DIM, false, Vol<DIM, LAYOUT>::kSmall>(fr, vol.n, vol.nx, vol.nxy, w, fv[h][sg]),
+                                 cr[h][sg]);
+                    else
+                        vol.load(locate<DIM, true, Vol<DIM, LAYOUT>::kSmall>(fr, vol.n, vol.nx, vol.nxy, w, fv[h][sg]),
+                                 cr[h][sg]);
+                }
             }
 #pragma unroll
-            for (int sg = 0; sg < 2; ++sg) {
-                const float qI = qv[sg] * Ival[sg];
-                accE = fmaf(Sv[sg], qI, accE);
-                const float gcs = -cCv[sg] * qI * (sg ? -1.0f : 1.0f);
+            for (int h = 0; h < 2; ++h) {
+                if (!on[h]) continue;
+                const int m = mv2[h], l = lv[h];
+                const float e = ev[h];
+                float Ival[2], Sv[2], cCv[2], cRv[2], qv[2];
 #pragma unroll
-                for (int ax = 0; ax < DIM; ++ax) accc[ax] = fmaf(gcs, u[ax], accc[ax]);
-            }
-            // per-ray sums over the row's 16 radial points
-            float Ap = row_sum16(Sv[0] * Ival[0]), Bp = row_sum16(cRv[0] * Ival[0]);
-            float Am = row_sum16(Sv[1] * Ival[1]), Bm = row_sum16(cRv[1] * Ival[1]);
-            if (l == 0) {
-                ray_dir[2 * m] = k;
-                ray_g[2 * m] = qv[0] * (Bp - ((float)DIM / Rv[0]) * Ap);
-                ray_dir[2 * m + 1] = ka;
-                ray_g[2 * m + 1] = qv[1] * (Bm - ((float)DIM / Rv[1]) * Am);
+                for (int sg = 0; sg < 2; ++sg) {
+                    const float R = Rv[h][sg];
+                    const float smax = R + 0.5f * p.dR;
+                    const float I = trilerp<DIM>(cr[h][sg], fv[h][sg]);
+                    const float d1 = fmaf(smax, e, -RHO * R), d2 = fmaf(smax, e, -R);
+                    const float is = p.in_slope, os = p.out_slope;
+                    const bool r1 = d1 >= -hd && d1 < hd;
+                    const bool r2 = d2 >= -hD && d2 < hD;
+                    const float sin_ = __builtin_amdgcn_fmed3f(d1 * is, -1.0f, 1.0f);
+                    const float sout = __builtin_amdgcn_fmed3f(fmaf(-d2, os, 0.5f), 0.0f, 1.0f);
+                    const float inv2R = __builtin_amdgcn_rcpf(2.0f * R);
+                    float nrm = inv2R, sm_d = smax;
+#pragma unroll
+                    for (int i = 1; i < DIM; ++i) {
+                        nrm *= inv2R;
+                        sm_d *= smax;
+                    }
+                    Ival[sg] = I;
+                    Sv[sg] = fminf(sin_, sout);
+                    cCv[sg] = r1 ? is : (r2 ? -os : 0.0f);
+                    cRv[sg] = r1 ? -RHO * is : -cCv[sg];
+                    qv[sg] = BALL * sm_d * nrm * inv_ml;
+                }
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                    const float qI = qv[sg] * Ival[sg];
+                    accE = fmaf(Sv[sg], qI, accE);
+                    const float gcs = -cCv[sg] * qI * (sg ? -1.0f : 1.0f);
+#pragma unroll
+                    for (int ax = 0; ax < DIM; ++ax) accc[ax] = fmaf(gcs, uv[h][ax], accc[ax]);
+                }
+                // per-ray sums over the row's 16 radial points
+                float Ap = row_sum16(Sv[0] * Ival[0]), Bp = row_sum16(cRv[0] * Ival[0]);
+                float Am = row_sum16(Sv[1] * Ival[1]), Bm = row_sum16(cRv[1] * Ival[1]);
+                if (l == 0) {
+                    ray_dir[2 * m] = kv[h][0];
+                    ray_g[2 * m] = qv[0] * (Bp - ((float)DIM / Rv[h][0]) * Ap);
+                    ray_dir[2 * m + 1] = kv[h][1];
+                    ray_g[2 * m + 1] = qv[1] * (Bm - ((float)DIM / Rv[h][1]) * Am);
+                }
             }
         }
         const float E = group_sum_wave<64>(accE);
@@ -1514,17 +1558,19 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
 #pragma unroll
         for (int ax = 0; ax < DIM; ++ax) gc[ax] = group_sum_wave<64>(accc[ax]);
         __syncthreads();
-        // sampled directions: the first ray of each direction sums its rays in order
+        // sampled directions: the first ray of each direction sums its rays in order (every lane
+        // walks all rays, reading each at one address, so the reads do not wait on each other)
         for (int r = lane; r < M; r += 64) {
             const int dk = ray_dir[r];
             bool first = true;
-            for (int r2 = 0; r2 < r; ++r2) first = first && ray_dir[r2] != dk;
-            if (first) {
-                float g = 0.0f;
-                for (int r2 = r; r2 < M; ++r2)
-                    if (ray_dir[r2] == dk) g += ray_g[r2];
-                gk[dk] = g;
+            float g = 0.0f;
+            for (int r2 = 0; r2 < M; ++r2) {
+                if (ray_dir[r2] == dk) {
+                    if (r2 < r) first = false;
+                    else g += ray_g[r2];
+                }
             }
+            if (first) gk[dk] = g;
         }
         __syncthreads();
         n += 1;
@@ -1533,27 +1579,54 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
         const float relax = fminf(1.0f, half_eps * sa.lambda);
         float mv = 0.0f, sum = 0.0f, mx = 0.0f;
         int clamped = 0, finite_r = 1;
-        for (int k = lane; k < D; k += 64) {
-            const int b0 = sa.nb_off[k], b1 = sa.nb_off[k + 1];
-            float ms = 0.0f;
-            for (int b = b0; b < b1; ++b) ms += Rold[sa.nb_idx[b]];
-            const float Rk0 = Rold[k];
-            const float mk = b1 > b0 ? ms / (float)(b1 - b0) : Rk0;
-            float Rn = Rk0 - half_eps * (float)D * gk[k] - relax * (Rk0 - mk);
-            if (Rn < p.r_lo) {
-                Rn = p.r_lo;
-                clamped = 1;
+        // neighbour rows of four directions are loaded before any of them is used
+        const uint4 *nbrow = reinterpret_cast<const uint4 *>(sa.nb);
+        const uint4 none = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+        for (int k0 = lane; k0 < D; k0 += 256) {
+            uint4 pre[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int k = k0 + 64 * b;
+                pre[b] = k < D ? nbrow[(long)k * sa.nb_chunks] : none;
             }
-            if (Rn > p.r_hi) {
-                Rn = p.r_hi;
-                clamped = 1;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int k = k0 + 64 * b;
+                if (k < D) {
+                    // neighbour mean in the rows' order
+                    float ms = 0.0f;
+                    int cnt = 0;
+                    for (int ch = 0; ch < sa.nb_chunks; ++ch) {
+                        const uint4 w = ch == 0 ? pre[b] : nbrow[(long)k * sa.nb_chunks + ch];
+                        const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                        for (int t8 = 0; t8 < 8; ++t8) {
+                            const uint32_t j = (wv[t8 >> 1] >> (16 * (t8 & 1))) & 0xffffu;
+                            if (j != 0xffffu) {
+                                ms += Rold[j];
+                                ++cnt;
+                            }
+                        }
+                    }
+                    const float Rk0 = Rold[k];
+                    const float mk = cnt > 0 ? ms / (float)cnt : Rk0;
+                    float Rn = Rk0 - half_eps * (float)D * gk[k] - relax * (Rk0 - mk);
+                    if (Rn < p.r_lo) {
+                        Rn = p.r_lo;
+                        clamped = 1;
+                    }
+                    if (Rn > p.r_hi) {
+                        Rn = p.r_hi;
+                        clamped = 1;
+                    }
+                    finite_r = finite_r && isfinite(Rn);
+                    mv = fmaxf(mv, fabsf(Rn - Rk0));
+                    sum += Rn;
+                    mx = fmaxf(mx, Rn);
+                    Rnew[k] = Rn;
+                    gk[k] = 0.0f;
+                }
             }
-            finite_r = finite_r && isfinite(Rn);
-            mv = fmaxf(mv, fabsf(Rn - Rk0));
-            sum += Rn;
-            mx = fmaxf(mx, Rn);
-            Rnew[k] = Rn;
-            gk[k] = 0.0f;
         }
         mv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(mv)), 63));
         mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(mx)), 63));

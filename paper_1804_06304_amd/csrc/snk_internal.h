@@ -76,9 +76,9 @@ inline int volume_layout(int dim, int64_t nx, int64_t ny, int64_t nz, int reques
 // Star-shaped contours: direction tables (antipode, symmetric neighbour graph in CSR form), the
 // per-direction radii (n x D) and the smoothing weight.
 struct StarArgs {
-    const int *anti;
-    const int *nb_off;
-    const int *nb_idx;
+    const int *anti;        // antipode of each direction
+    const uint16_t *nb;     // neighbours of each direction: nb_chunks x 8 entries, 0xffff past the last
+    int nb_chunks;
     float *Rk;
     float lambda;
 };
