@@ -370,6 +370,8 @@ def bench_star(args):
         ctx = snk.Context(0, stream)
         ctx.set_params(p)
         ctx.set_star(smooth)
+        if smooth >= 0.0:
+            ctx.set_launch(args.lanes, 0, 0)   # star contours: 64 or 128 lanes (0: automatic)
         ctx.set_directions(wl.dirs)
         ctx.load_volume(raw)
         ms = []

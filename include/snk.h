@@ -170,8 +170,9 @@ snk_status snk_set_tile(snk_ctx *ctx, int32_t tile_voxels);
  * 0x10 when any radius was clamped. snk_read's radius is the mean of the R_k and its e_vox is the
  * last Monte-Carlo energy, which snk_finalize's selection ranks by (overlaps against the mean
  * radius). Needs a direction table with every opposite direction (else SNK_EINVAL at the next
- * evolve), n_radial = 16, and flags bits 1 and 2 clear; runs one wave per contour and ignores
- * snk_set_launch / snk_set_tile; snk_trace_step returns SNK_EINVAL. smooth < 0: the sphere
+ * evolve), n_radial = 16, and flags bits 1 and 2 clear; runs 64 or 128 lanes per contour (the
+ * lanes_per_contour of snk_set_launch; 0: 128; other values SNK_EINVAL at the next evolve), ignores
+ * its other knobs and snk_set_tile; snk_trace_step returns SNK_EINVAL. smooth < 0: the sphere
  * (default). Radii start tied at each contour's R after snk_load_seeds, snk_set_state or
  * snk_set_directions. */
 snk_status snk_set_star(snk_ctx *ctx, double smooth);

@@ -456,7 +456,10 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
     if (c->P.flags & (snk::kFlagExact | snk::kFlagGradI))
         return fail(c, SNK_EINVAL, "star contours take Monte-Carlo sums with the weight-form centre force");
     if (c->P.n_radial != 16) return fail(c, SNK_EINVAL, "star contours need n_radial = 16");
-    if (snk::star_lds_bytes(c->P.dim, c->D, c->P.n_rays) > 65536)
+    // one or two waves per contour (lanes_per_contour 64 or 128; automatic: two)
+    const int lanes = c->lanes > 0 ? c->lanes : 128;
+    if (lanes != 64 && lanes != 128) return fail(c, SNK_EINVAL, "star contours take 64 or 128 lanes per contour");
+    if (snk::star_lds_bytes(c->P.dim, c->D, c->P.n_rays, lanes) > 65536)
         return fail(c, SNK_EINVAL, "n_dirs / n_rays too large for the star kernel's LDS (64 KiB)");
     snk_status st = star_tables(c);
     if (st != SNK_OK) return st;
@@ -478,13 +481,13 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
         HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
         HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     }
-    HIPTRY(c, snk::launch_star(a, sa, c->P.dim, c->layout, c->stream));
+    HIPTRY(c, snk::launch_star(a, sa, c->P.dim, lanes, c->layout, c->stream));
     if (standalone) {
         HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
         c->ev_evo = true;
     }
-    c->last_lanes = 64;
-    c->last_unroll = 1;
+    c->last_lanes = lanes;
+    c->last_unroll = 2;
     c->last_layout = c->layout;
     c->last_tile = 0;
     c->evolve_launches += 1;

@@ -1367,27 +1367,30 @@ int max_blocks_g(int lanes, int unroll, int layout, int max_M) {
 // (R_k - mean of its graph neighbours), from the old radii (double-buffered in LDS).
 
 template <int DIM>
-__host__ __device__ __forceinline__ int star_lds_floats(int D, int M) {
-    const int per = (draw_floats(64, M / 2) + 3) & ~3;
-    return per + 3 * D + 2 * M + (M / 2) * (2 + DIM);
+__host__ __device__ __forceinline__ int star_lds_floats(int D, int M, int NT) {
+    const int per = (draw_floats(NT, M / 2) + 3) & ~3;
+    return per + 3 * D + 2 * M + (M / 2) * (2 + DIM) + 8 * (NT / 64);
 }
 
-template <int DIM, int LAYOUT>
-__global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
+// NT threads per contour (64: one wave; 128: two waves, whose partial sums meet in LDS in wave
+// order).
+template <int DIM, int LAYOUT, int NT>
+__global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs a, StarArgs sa) {
     extern __shared__ float lds[];
     constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
     constexpr float BALL = DIM == 3 ? 4.18879020478639098462f : 3.14159265358979323846f;
     const JobParams &p = a.p;
     const int cid = blockIdx.x;
     if (cid >= a.n) return;
-    const int lane = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int NW = NT / 64;
     const int D = p.D, M = p.M, MH = M / 2, L = p.L;
     DevContour *slot = a.st + cid;
     DevContour s = uniform_copy(slot);
     const int n0 = s.iters;
     const int budget = (s.status & 0x0f) == SNK_ACTIVE ? a.n_iter : 0;
-    const int per = (draw_floats(64, MH) + 3) & ~3;
-    const Draws dr(lds, 64, MH);
+    const int per = (draw_floats(NT, MH) + 3) & ~3;
+    const Draws dr(lds, NT, MH);
     float *Ra = lds + per;
     float *Rb = Ra + D;
     float *gk = Rb + D;
@@ -1397,8 +1400,9 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
     int *rk = reinterpret_cast<int *>(ray_g + M);
     int *rka = rk + MH;
     float *ru = reinterpret_cast<float *>(rka + MH);
+    float *red = ru + MH * DIM;  // per-wave partials, 8 per wave
     float *Rg = sa.Rk + (long)cid * D;
-    for (int k = lane; k < D; k += 64) {
+    for (int k = t; k < D; k += NT) {
         Ra[k] = Rg[k];
         gk[k] = 0.0f;
     }
@@ -1406,12 +1410,19 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
     const float inv_h[3] = {p.g.inv_h[0], p.g.inv_h[1], p.g.inv_h[2]};
     const float hh[3] = {p.g.h[0], p.g.h[1], p.g.h[2]};
     const uint32_t id = s.id;
-    if (budget > 0) draws_phase1<DIM, 64>(dr, 0, (uint32_t)(n0 + 1), id, p, lane);
+    if (budget > 0) draws_phase1<DIM, NT>(dr, 0, (uint32_t)(n0 + 1), id, p, t);
     __syncthreads();
     // largest radius (interior test) and the clamp flag of the radii
     float rmax = 0.0f;
-    for (int k = lane; k < D; k += 64) rmax = fmaxf(rmax, Ra[k]);
+    for (int k = t; k < D; k += NT) rmax = fmaxf(rmax, Ra[k]);
     rmax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(rmax)), 63));
+    if constexpr (NW > 1) {
+        if (lane == 0) red[wave * 8] = rmax;
+        __syncthreads();
+        rmax = red[0];
+        for (int w = 1; w < NW; ++w) rmax = fmaxf(rmax, red[w * 8]);
+        __syncthreads();
+    }
 
     int anc[3] = {s.anc[0], s.anc[1], s.anc[2]};
     float off[3] = {s.off[0], s.off[1], s.off[2]};
@@ -1429,7 +1440,7 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
 
     for (int it = 0; it < budget && (status & 0x0f) == SNK_ACTIVE; ++it) {
         const int blk = it / dr.K, sl = it - blk * dr.K;
-        if (sl == 0) draws_phase1<DIM, 64>(dr, (blk + 1) & 1, (uint32_t)(n0 + 1 + (blk + 1) * dr.K), id, p, lane);
+        if (sl == 0) draws_phase1<DIM, NT>(dr, (blk + 1) & 1, (uint32_t)(n0 + 1 + (blk + 1) * dr.K), id, p, t);
         const float4 *pu = dr.pu + dr.slot(blk & 1, sl) * MH;
         Frame<DIM> fr;
         long base = 0;
@@ -1449,7 +1460,7 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
         }
         fr.base = base;
         // the ray pairs' tables entries, once per iteration (the pair-points below read them from LDS)
-        for (int m = lane; m < MH; m += 64) {
+        for (int m = t; m < MH; m += NT) {
             const int k = __float_as_int(pu[m].x);
             rk[m] = k;
             rka[m] = sa.anti[k];
@@ -1458,17 +1469,17 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
         }
         __syncthreads();
         float accE = 0.0f, accc[3] = {0.0f, 0.0f, 0.0f};
-        // pair-points q = lane + 64 j: pair m = q / 16, radial index l = q % 16 (one DPP row per pair);
+        // pair-points q = t + NT j: pair m = q / 16, radial index l = q % 16 (one DPP row per pair);
         // two of them in flight, consumed in order
         const int PP = MH * L;
-        for (int q0 = lane; q0 - lane < PP; q0 += 128) {
+        for (int q0 = t; q0 - t < PP; q0 += 2 * NT) {
             Corners<DIM> cr[2][2];
             float fv[2][2][3], Rv[2][2], ev[2], uv[2][3];
             int mv2[2], lv[2], kv[2][2];
             bool on[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int q = q0 + 64 * h;
+                const int q = q0 + NT * h;
                 on[h] = q < PP;
                 if (!on[h]) continue;
                 const int m = q >> 4, l = q & 15;
@@ -1553,14 +1564,35 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
                 }
             }
         }
-        const float E = group_sum_wave<64>(accE);
-        float gc[3] = {0.0f, 0.0f, 0.0f};
+        float E = 0.0f, gc[3] = {0.0f, 0.0f, 0.0f};
+        if constexpr (NW == 1) {
+            E = group_sum_wave<64>(accE);
 #pragma unroll
-        for (int ax = 0; ax < DIM; ++ax) gc[ax] = group_sum_wave<64>(accc[ax]);
+            for (int ax = 0; ax < DIM; ++ax) gc[ax] = group_sum_wave<64>(accc[ax]);
+        } else {
+            const float wE = wave_sum_to_63(accE);
+            float wc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) wc[ax] = wave_sum_to_63(accc[ax]);
+            if (lane == 63) {
+                red[wave * 8] = wE;
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) red[wave * 8 + 1 + ax] = wc[ax];
+            }
+            __syncthreads();
+            E = red[0];
+#pragma unroll
+            for (int ax = 0; ax < DIM; ++ax) gc[ax] = red[1 + ax];
+            for (int w = 1; w < NW; ++w) {
+                E += red[w * 8];
+#pragma unroll
+                for (int ax = 0; ax < DIM; ++ax) gc[ax] += red[w * 8 + 1 + ax];
+            }
+        }
         __syncthreads();
         // sampled directions: the first ray of each direction sums its rays in order (every lane
         // walks all rays, reading each at one address, so the reads do not wait on each other)
-        for (int r = lane; r < M; r += 64) {
+        for (int r = t; r < M; r += NT) {
             const int dk = ray_dir[r];
             bool first = true;
             float g = 0.0f;
@@ -1582,16 +1614,16 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
         // neighbour rows of four directions are loaded before any of them is used
         const uint4 *nbrow = reinterpret_cast<const uint4 *>(sa.nb);
         const uint4 none = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
-        for (int k0 = lane; k0 < D; k0 += 256) {
+        for (int k0 = t; k0 < D; k0 += 4 * NT) {
             uint4 pre[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int k = k0 + 64 * b;
+                const int k = k0 + NT * b;
                 pre[b] = k < D ? nbrow[(long)k * sa.nb_chunks] : none;
             }
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int k = k0 + 64 * b;
+                const int k = k0 + NT * b;
                 if (k < D) {
                     // neighbour mean in the rows' order
                     float ms = 0.0f;
@@ -1630,9 +1662,33 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
         }
         mv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(mv)), 63));
         mx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_max_to_63(mx)), 63));
-        sum = group_sum_wave<64>(sum);
         clamped = __builtin_amdgcn_ballot_w64(clamped != 0) != 0;
-        const bool fin_r = __builtin_amdgcn_ballot_w64(!finite_r) == 0;
+        bool fin_r = __builtin_amdgcn_ballot_w64(!finite_r) == 0;
+        if constexpr (NW == 1) {
+            sum = group_sum_wave<64>(sum);
+        } else {
+            const float ws = wave_sum_to_63(sum);
+            if (lane == 63) {
+                red[wave * 8] = mv;
+                red[wave * 8 + 1] = mx;
+                red[wave * 8 + 2] = ws;
+                red[wave * 8 + 3] = clamped ? 1.0f : 0.0f;
+                red[wave * 8 + 4] = fin_r ? 1.0f : 0.0f;
+            }
+            __syncthreads();
+            mv = red[0];
+            mx = red[1];
+            sum = red[2];
+            clamped = red[3] != 0.0f;
+            fin_r = red[4] != 0.0f;
+            for (int w = 1; w < NW; ++w) {
+                mv = fmaxf(mv, red[w * 8]);
+                mx = fmaxf(mx, red[w * 8 + 1]);
+                sum += red[w * 8 + 2];
+                clamped = clamped || red[w * 8 + 3] != 0.0f;
+                fin_r = fin_r && red[w * 8 + 4] != 0.0f;
+            }
+        }
         rmax = mx;
         Rmean = sum / (float)D;
         e_mc = E;
@@ -1679,8 +1735,8 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
         __syncthreads();
     }
     if (budget > 0) {
-        for (int k = lane; k < D; k += 64) Rg[k] = Rold[k];
-        if (lane == 0) {
+        for (int k = t; k < D; k += NT) Rg[k] = Rold[k];
+        if (t == 0) {
             DevContour o = s;
             for (int i = 0; i < 3; ++i) {
                 o.anc[i] = anc[i];
@@ -1697,21 +1753,28 @@ __global__ __launch_bounds__(64) void star_kernel(EvolveArgs a, StarArgs sa) {
     }
 }
 
-template <int DIM>
-hipError_t launch_star_d(const EvolveArgs &a, const StarArgs &sa, int layout, hipStream_t s) {
-    const size_t lds = sizeof(float) * (size_t)star_lds_floats<DIM>(a.p.D, a.p.M);
+template <int DIM, int NT>
+hipError_t launch_star_t(const EvolveArgs &a, const StarArgs &sa, int layout, hipStream_t s) {
+    const size_t lds = sizeof(float) * (size_t)star_lds_floats<DIM>(a.p.D, a.p.M, NT);
     switch (layout) {
         case kBufferQuad:
-            hipLaunchKernelGGL((star_kernel<DIM, kBufferQuad>), dim3(a.n), dim3(64), lds, s, a, sa);
+            hipLaunchKernelGGL((star_kernel<DIM, kBufferQuad, NT>), dim3(a.n), dim3(NT), lds, s, a, sa);
             break;
         case kBufferPlain:
-            hipLaunchKernelGGL((star_kernel<DIM, kBufferPlain>), dim3(a.n), dim3(64), lds, s, a, sa);
+            hipLaunchKernelGGL((star_kernel<DIM, kBufferPlain, NT>), dim3(a.n), dim3(NT), lds, s, a, sa);
             break;
         default:
-            hipLaunchKernelGGL((star_kernel<DIM, kGlobalPlain>), dim3(a.n), dim3(64), lds, s, a, sa);
+            hipLaunchKernelGGL((star_kernel<DIM, kGlobalPlain, NT>), dim3(a.n), dim3(NT), lds, s, a, sa);
             break;
     }
     return hipGetLastError();
+}
+
+template <int DIM>
+hipError_t launch_star_d(const EvolveArgs &a, const StarArgs &sa, int lanes, int layout, hipStream_t s) {
+    if (lanes == 128) return launch_star_t<DIM, 128>(a, sa, layout, s);
+    if (lanes == 64) return launch_star_t<DIM, 64>(a, sa, layout, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -1756,13 +1819,13 @@ hipError_t launch_star_init(const DevContour *st, float *Rk, int n, int D, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int layout, hipStream_t s) {
+hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int lanes, int layout, hipStream_t s) {
     if (a.n <= 0 || a.n_iter <= 0) return hipSuccess;
-    return dim == 2 ? launch_star_d<2>(a, sa, layout, s) : launch_star_d<3>(a, sa, layout, s);
+    return dim == 2 ? launch_star_d<2>(a, sa, lanes, layout, s) : launch_star_d<3>(a, sa, lanes, layout, s);
 }
 
-size_t star_lds_bytes(int dim, int D, int M) {
-    return sizeof(float) * (size_t)(dim == 2 ? star_lds_floats<2>(D, M) : star_lds_floats<3>(D, M));
+size_t star_lds_bytes(int dim, int D, int M, int lanes) {
+    return sizeof(float) * (size_t)(dim == 2 ? star_lds_floats<2>(D, M, lanes) : star_lds_floats<3>(D, M, lanes));
 }
 
 int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M) {

@@ -149,8 +149,8 @@ hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unrol
 int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M);
 size_t evolve_lds_bytes(int dim, int lanes, int M, int tile_cap);
 // Star-shaped contours (one wave per contour, n_radial 16).
-hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int layout, hipStream_t s);
-size_t star_lds_bytes(int dim, int D, int M);
+hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int lanes, int layout, hipStream_t s);
+size_t star_lds_bytes(int dim, int D, int M, int lanes);
 // Every direction's radius of contour i set to its R.
 hipError_t launch_star_init(const DevContour *st, float *Rk, int n, int D, hipStream_t s);
 // Workgroups per CU that registers allow for a launch shape with LDS boxes (0: no such shape).

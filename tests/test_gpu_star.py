@@ -37,10 +37,11 @@ def stream():
     return torch.cuda.current_stream()
 
 
-def make_ctx(snk, stream, wl, smooth):
+def make_ctx(snk, stream, wl, smooth, lanes=0):
     import torch
     ctx = snk.Context(0, stream)
     ctx.set_params(wl.params)
+    ctx.set_launch(lanes, 0, 0)
     ctx.set_star(smooth)
     ctx.set_directions(wl.dirs)
     raw = torch.from_numpy(np.ascontiguousarray(wl.raw)).to("cuda:0")
@@ -70,11 +71,13 @@ def inner_seeds(wl, n, rng):
     return np.concatenate([wl.seeds, s])
 
 
-@pytest.mark.parametrize("which,smooth", [("tiny", 0.0), ("tiny", 0.6), ("aniso", 0.3), ("plane", 0.3)])
-def test_star_one_step_parity(snk, stream, which, smooth):
+@pytest.mark.parametrize("which,smooth,lanes", [("tiny", 0.0, 0), ("tiny", 0.6, 64), ("aniso", 0.3, 0),
+                                                ("aniso", 0.3, 64), ("plane", 0.3, 0), ("plane", 0.3, 64)])
+def test_star_one_step_parity(snk, stream, which, smooth, lanes):
     """Teacher forced: both sides start from the oracle's state after a few star iterations (and,
     for the first check, from untied random radii), rounded to FP32; one GPU iteration must give
-    every direction's radius step, the centre step and the energy of the oracle's iteration."""
+    every direction's radius step, the centre step and the energy of the oracle's iteration; one
+    wave (64 lanes) or two (the automatic 128) per contour."""
     wl = workload(which)
     p = wl.params
     rng = np.random.default_rng(2)
@@ -86,7 +89,7 @@ def test_star_one_step_parity(snk, stream, which, smooth):
     D = p.n_dirs
     lo = oracle.r_geom_min(p.dim, p.dR)
     st.Rk[:] = rng.uniform(max(lo, 0.7 * p.r_init), 1.3 * p.r_init, size=st.Rk.shape)
-    ctx = make_ctx(snk, stream, wl, smooth)
+    ctx = make_ctx(snk, stream, wl, smooth, lanes)
     ctx.load_seeds(seeds, ids=ids)
     worst = {}
     for pre in (0, 4):
@@ -123,7 +126,8 @@ def test_star_one_step_parity(snk, stream, which, smooth):
     ctx.close()
 
 
-def test_star_free_run(snk, stream):
+@pytest.mark.parametrize("lanes", [0, 64])
+def test_star_free_run(snk, stream, lanes):
     """Tiny workload, star contours with smoothing: after 100 iterations the GPU's per-direction
     radii, centres, iteration counts and states follow the oracle's (FP32 against FP64: the Monte-
     Carlo trajectories drift apart only by rounding)."""
@@ -134,9 +138,10 @@ def test_star_free_run(snk, stream):
     tables = oracle.star_tables(wl.dirs, p.dim)
     st = oracle.star_init(p, wl.seeds, ids=wl.ids, shape_zyx=wl.raw.shape)
     oracle.star_evolve(J, p, wl.dirs, tables, smooth, st, wl.n_iter)
-    ctx = make_ctx(snk, stream, wl, smooth)
+    ctx = make_ctx(snk, stream, wl, smooth, lanes)
     ctx.load_seeds(wl.seeds, ids=wl.ids)
     ctx.evolve(wl.n_iter)
+    assert ctx.get_timing()["lanes_per_contour"] == (lanes or 128)
     ctx.finalize()
     got = ctx.read()
     Rg = ctx.get_star_radii()
@@ -163,7 +168,7 @@ def test_star_free_run(snk, stream):
 def test_star_error_paths(snk, stream):
     """n_radial other than 16, exact sums and the gradient-form centre force are refused at the next
     evolve; so is a direction table without antipodes; snk_trace_step is refused; the sphere is back
-    after snk_set_star(-1)."""
+    after snk_set_star(-1); lanes per contour other than 64 or 128 are refused."""
     wl = synth.tiny_config()
     for bad in (wl.params.replace(n_radial=8), wl.params.replace(flags=2), wl.params.replace(flags=4)):
         w = synth.tiny_config()
@@ -190,4 +195,10 @@ def test_star_error_paths(snk, stream):
         ctx.trace_step()
     ctx.set_star(-1.0)
     assert ctx.trace_step().shape[0] == len(wl.seeds)
+    ctx.close()
+    # star contours run one or two waves per contour
+    ctx = make_ctx(snk, stream, wl, 0.2, lanes=256)
+    ctx.load_seeds(wl.seeds)
+    with pytest.raises(snk.SnkError):
+        ctx.evolve(1)
     ctx.close()
