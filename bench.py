@@ -145,8 +145,9 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported: this build runs the path on one GPU "
-              "(DESIGN.md describes how it would shard over slabs).", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the path runs on one GPU (a large volume "
+              "would shard into slabs with halos, one per GPU, exchanging only border contours before the "
+              "selection).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
