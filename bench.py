@@ -54,6 +54,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(wl, gpu_out, n_sample):
     """The FP64 oracle on the first n_sample contours of the same workload (all iterations), with
     the pre-pass prorated by n_sample / n_contours. Also checks those contours against the GPU."""
@@ -96,6 +110,7 @@ def cpu_baseline(wl, gpu_out, n_sample):
         t1 = time.perf_counter() - t0
     finally:
         oracle.set_num_threads(threads)
+    base["host"] = host_cpu()
     base["single_thread"] = {"value": done1 * p.n_rays / t1, "unit": "vertex-updates/s", "cores": 1,
                              "sample": f"first {S1} contours, all {wl.n_iter} iterations, evolution only, "
                                        f"{t1:.1f} s"}
