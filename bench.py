@@ -110,6 +110,20 @@ def cpu_baseline(wl, gpu_out, n_sample):
         t1 = time.perf_counter() - t0
     finally:
         oracle.set_num_threads(threads)
+    # and the tiny workload (64^3, 8 contours, 100 iterations) whole, on one thread
+    import synth
+    tw = synth.tiny_config()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        Jt = oracle.prepass(tw.raw, tw.params)
+        stt = oracle.init_state(tw.params, tw.seeds, ids=tw.ids, shape_zyx=tw.raw.shape)
+        _, done_t = oracle.evolve(Jt, tw.params, tw.dirs, stt, tw.n_iter)
+        tt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    base["single_thread_tiny"] = {"value": done_t * tw.params.n_rays / tt, "unit": "vertex-updates/s", "cores": 1,
+                                  "sample": f"{tw.name}: pre-pass and all {tw.n_iter} iterations, {tt:.2f} s"}
     base["host"] = host_cpu()
     base["single_thread"] = {"value": done1 * p.n_rays / t1, "unit": "vertex-updates/s", "cores": 1,
                              "sample": f"first {S1} contours, all {wl.n_iter} iterations, evolution only, "
