@@ -77,6 +77,9 @@ def lib():
         L.orc_evolve.argtypes = [vp, i64, i64, i64, P(_Params), vp, i64, vp, vp, vp, vp, vp, vp, vp,
                                  i32, vp, P(i64)]
         L.orc_evolve.restype = i64
+        L.orc_evolve_log.argtypes = [vp, i64, i64, i64, P(_Params), vp, i64, vp, vp, vp, vp, vp, vp, vp,
+                                     i32, vp, vp, P(i64)]
+        L.orc_evolve_log.restype = i64
         L.orc_mc_terms.argtypes = [vp, i64, i64, i64, P(_Params), vp, P(d), d, u32, u32, P(d), vp, vp]
         L.orc_energy_fixed.argtypes = [C.c_int, d, vp, vp, i64, d, P(d), d]
         L.orc_energy_fixed.restype = d
@@ -336,23 +339,65 @@ def init_state(p, seeds, r0=None, ids=None, shape_zyx=None) -> State:
     return State(c, R, np.zeros(n, np.int32), status, np.zeros(n, np.uint8), np.zeros(n), ids)
 
 
-def evolve(J, p, dirs, st: State, n_iter: int, trace: bool = False):
+def evolve(J, p, dirs, st: State, n_iter: int, trace: bool = False, moves: np.ndarray | None = None):
     """Run up to n_iter further iterations on every ACTIVE contour (in place). Returns
-    (trace array or None, number of contour-iterations run). Raises if the p,q and c,R forms of
-    the gradient ever disagree."""
+    (trace array or None, number of contour-iterations run). With `moves` (an (n, n_iter) float64
+    array, NaN-filled by the caller) each step's move max(|R change|, |c change|) is written at
+    [contour, step of this call]. Raises if the p,q and c,R forms of the gradient ever disagree."""
     J = np.ascontiguousarray(J, dtype=np.float64)
     nz, ny, nx = J.shape
     d = np.ascontiguousarray(dirs, dtype=np.float64)
     ps = params_struct(p)
     n = len(st.R)
     tr = np.zeros((n, TRACE_W)) if trace else None
+    if moves is not None:
+        assert moves.shape == (n, n_iter) and moves.dtype == np.float64 and moves.flags.c_contiguous
     done = C.c_int64(0)
-    mism = lib().orc_evolve(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), n, _ptr(st.ids), _ptr(st.c),
-                            _ptr(st.R), _ptr(st.iters), _ptr(st.status), _ptr(st.streak), _ptr(st.e_mc),
-                            int(n_iter), _ptr(tr) if trace else None, C.byref(done))
+    mism = lib().orc_evolve_log(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), n, _ptr(st.ids), _ptr(st.c),
+                                _ptr(st.R), _ptr(st.iters), _ptr(st.status), _ptr(st.streak), _ptr(st.e_mc),
+                                int(n_iter), _ptr(tr) if trace else None,
+                                _ptr(moves) if moves is not None else None, C.byref(done))
     if mism:
         raise AssertionError(f"p,q and c,R gradient forms disagree on {mism} contour-iterations")
     return tr, int(done.value)
+
+
+def stop_ranges(moves: np.ndarray, p, delta: float):
+    """Where the stop rule (freeze after conv_window consecutive moves below conv_tol) ends a run
+    whose every step's move is known, and how far that end can move when each decision whose move
+    lies within delta * conv_tol of conv_tol may go either way.
+
+    moves: (n, n_iter) moves of runs from the seeds (streak 0) with the freeze switched off
+    (conv_window = 0), NaN after a run stopped for another reason (OUT, NONFINITE). Returns
+    (n_stop, n_lo, n_hi, converged): the iteration count at which the rule stops each contour (the
+    run's own end when it never converges), the earliest end when every near decision counts as
+    small and the latest when none does (the rule is monotone in its decisions), and whether the
+    exact decisions converge."""
+    n, N = moves.shape
+    W, tau = int(p.conv_window), float(p.conv_tol)
+    ran = np.sum(~np.isnan(moves), axis=1)          # steps each unfrozen run made
+    m = np.where(np.isnan(moves), np.inf, moves)
+    near = np.abs(m - tau) <= delta * tau
+
+    def first_stop(small):
+        # first step index (1-based) ending W consecutive small moves; 0 if none
+        out = np.zeros(n, np.int64)
+        if W <= 0:
+            return out
+        run = np.zeros(n, np.int64)
+        for k in range(N):
+            run = np.where(small[:, k], run + 1, 0)
+            hit = (run >= W) & (out == 0)
+            out[hit] = k + 1
+        return out
+
+    def end(conv):
+        return np.where((conv > 0) & (conv <= ran), conv, ran)
+
+    exact = first_stop(m < tau)
+    early = first_stop((m < tau) | near)
+    late = first_stop((m < tau) & ~near)
+    return end(exact), end(early), np.where(late > 0, end(late), ran), (exact > 0) & (exact <= ran)
 
 
 def finalize_status(st: State) -> None:

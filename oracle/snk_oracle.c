@@ -574,7 +574,7 @@ static double contour_sums(const orc_vol *vol, const double c[3], double R, uint
 /* One gradient-descent iteration of one contour (Eqs. (7)-(15)).                               */
 /* ------------------------------------------------------------------------------------------ */
 static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *iter, uint8_t *status,
-                        uint8_t *streak, double *e_mc, uint32_t id, double *trace)
+                        uint8_t *streak, double *e_mc, uint32_t id, double *trace, double *move_out)
 {
     const orc_params *p = vol->p;
     int dim = p->dim;
@@ -654,6 +654,7 @@ static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *ite
     for (int i = 0; i < dim; ++i) dcn += (c_new[i] - c[i]) * (c_new[i] - c[i]);
     dcn = sqrt(dcn);
     if (dcn > move) move = dcn;
+    if (move_out) *move_out = move;
 
     for (int i = 0; i < 3; ++i) c[i] = c_new[i];
     *R = R_new;
@@ -688,12 +689,14 @@ double orc_initial_radius(const orc_params *p, double r0)
 }
 
 /* Evolve every ACTIVE contour for up to n_iter further iterations. c: n x 3 physical. trace (n x
- * ORC_TRACE_W, may be NULL) receives the terms of the last iteration each contour ran. Returns the
+ * ORC_TRACE_W, may be NULL) receives the terms of the last iteration each contour ran. moves (n x
+ * n_iter, may be NULL) receives the move of every step this call ran, max(|R change|, |c change|),
+ * the quantity the stop rule compares with conv_tol (steps not run are left untouched). Returns the
  * number of contour-iterations whose p,q and c,R forms disagreed (must be 0). */
-int64_t orc_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
-                   const double *dirs, int64_t n, const uint32_t *ids, double *c, double *R,
-                   int32_t *iters, uint8_t *status, uint8_t *streak, double *e_mc, int32_t n_iter,
-                   double *trace, int64_t *evolved)
+int64_t orc_evolve_log(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                       const double *dirs, int64_t n, const uint32_t *ids, double *c, double *R,
+                       int32_t *iters, uint8_t *status, uint8_t *streak, double *e_mc, int32_t n_iter,
+                       double *trace, double *moves, int64_t *evolved)
 {
     orc_vol vol = {J, nx, ny, nz, p, dirs};
     int64_t mism = 0, done = 0;
@@ -702,12 +705,22 @@ int64_t orc_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, const or
         for (int32_t it = 0; it < n_iter; ++it) {
             if ((status[i] & 0x0f) != ORC_ACTIVE) break;
             mism += step_contour(&vol, &c[i * 3], &R[i], &iters[i], &status[i], &streak[i], &e_mc[i],
-                                 ids[i], trace ? &trace[i * ORC_TRACE_W] : NULL);
+                                 ids[i], trace ? &trace[i * ORC_TRACE_W] : NULL,
+                                 moves ? &moves[i * (int64_t)n_iter + it] : NULL);
             done += 1;
         }
     }
     if (evolved) *evolved = done;
     return mism;
+}
+
+int64_t orc_evolve(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                   const double *dirs, int64_t n, const uint32_t *ids, double *c, double *R,
+                   int32_t *iters, uint8_t *status, uint8_t *streak, double *e_mc, int32_t n_iter,
+                   double *trace, int64_t *evolved)
+{
+    return orc_evolve_log(J, nx, ny, nz, p, dirs, n, ids, c, R, iters, status, streak, e_mc, n_iter, trace, NULL,
+                          evolved);
 }
 
 /* Terms of one contour at (c, R) for iteration n without updating it (Monte-Carlo, or exact lattice
