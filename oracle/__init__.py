@@ -87,6 +87,8 @@ def lib():
         L.orc_cull.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, vp]; L.orc_cull.restype = i64
         L.orc_cull_ambiguity.argtypes = [P(_Params), i64, vp, vp, vp, d, d, vp]
         L.orc_cull_ambiguity.restype = i64
+        L.orc_cull_ambiguity_tol.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, vp]
+        L.orc_cull_ambiguity_tol.restype = i64
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_set_num_threads.restype = None
@@ -438,6 +440,19 @@ def cull_ambiguity(p, c, R, e_vox, rel_e=1e-4, tol_d=1e-3):
                              _ptr(np.ascontiguousarray(R, dtype=np.float64)),
                              _ptr(np.ascontiguousarray(e_vox, dtype=np.float64)), float(rel_e), float(tol_d),
                              _ptr(amb))
+    return amb
+
+
+def cull_ambiguity_tol(p, c, R, e_vox, tol_e, tol_d):
+    """Selection decisions within per-contour tolerances of a threshold (energy vs E0 or vs an
+    overlapping rival's energy; pair distance vs the overlap radius); see orc_cull_ambiguity_tol."""
+    n = len(R)
+    amb = np.zeros(n, np.uint8)
+    ps = params_struct(p)
+    f = lambda a: np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (n,) + np.shape(a)[1:]))
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    lib().orc_cull_ambiguity_tol(C.byref(ps), n, _ptr(cc), _ptr(f(R)), _ptr(f(e_vox)), _ptr(f(tol_e)),
+                                 _ptr(f(tol_d)), _ptr(amb))
     return amb
 
 

@@ -64,7 +64,14 @@
 #define ORC_CLAMPED 0x10
 
 #define ORC_TRACE_W 32
-#define ORC_KINK_REL 4e-6
+/* Samples within ORC_KINK_REL * s_max of a kink of S are flagged (reading R20): the FP32 kernels
+ * place a radial point relative to a kink with an error below about 3.2e-7 * s_max (cube root on the
+ * transcendental unit to ~2e-7 relative, one rounding each of s_max and rho * R, a fused offset), so
+ * 1.5e-6 leaves a margin near 5. Samples within ORC_FACE_REL * s_max / h_a of a voxel face (the
+ * image-gradient centre force) get the wider band, since their position also carries the FP32
+ * rotation of the ray direction. */
+#define ORC_KINK_REL 1.5e-6
+#define ORC_FACE_REL 4e-6
 #define ORC_FLAG_NOROT 1   /* flags bit 0: rotation Q = I */
 #define ORC_FLAG_EXACT 2   /* flags bit 1: exact lattice sums instead of Monte-Carlo samples */
 #define ORC_FLAG_GRADI 4   /* flags bit 2: centre force from the image gradient (Monte-Carlo only) */
@@ -445,7 +452,7 @@ static void accumulate_samples(const orc_vol *vol, const double c[3], double R, 
                  * place in the neighbouring cell */
                 if (gradi) {
                     for (int a = 0; a < dim; ++a) {
-                        const double tol = ORC_KINK_REL * smax / p->spacing[a];
+                        const double tol = ORC_FACE_REL * smax / p->spacing[a];
                         if (fabs(vv[a] - nearbyint(vv[a])) <= tol) {
                             double vl[3] = {vv[0], vv[1], vv[2]}, vr[3] = {vv[0], vv[1], vv[2]}, gl[3], gr[3];
                             vl[a] = nearbyint(vv[a]) - 1e-9;
@@ -885,6 +892,80 @@ int64_t orc_cull_ambiguity(const orc_params *p, int64_t n, const double *c, cons
             }
         }
     }
+    for (int64_t i = 0; i < n; ++i) cnt += amb[i];
+    return cnt;
+}
+
+/* Flags contours whose selection outcome two runs of the same contours may legitimately decide
+ * differently: the energy lies within tol_e[i] of E0, or, for an overlapping rival j, the energies
+ * lie within tol_e[i] + tol_e[j] of each other, or the pair distance lies within
+ * tol_d[i] + tol_d[j] of the overlap radius rho * max(R_i, R_j). The tolerances are per contour
+ * (e.g. how far the two runs' energies and centres/radii of that contour are apart), so a
+ * decision is flagged only when its margin is smaller than the disagreement in the very
+ * quantities it compares. Pairs are found by a sweep over x. Returns the count flagged. */
+typedef struct { double x; int64_t i; } orc_xkey;
+
+static int xkey_cmp(const void *a, const void *b)
+{
+    const orc_xkey *x = (const orc_xkey *)a, *y = (const orc_xkey *)b;
+    return x->x < y->x ? -1 : (x->x > y->x ? 1 : (x->i < y->i ? -1 : (x->i > y->i)));
+}
+
+int64_t orc_cull_ambiguity_tol(const orc_params *p, int64_t n, const double *c, const double *R,
+                               const double *e, const double *tol_e, const double *tol_d, uint8_t *amb)
+{
+    int dim = p->dim;
+    double rho = rho_of(dim);
+    double rmax = 0.0, tdmax = 0.0;
+    orc_xkey *k = (orc_xkey *)malloc(sizeof(orc_xkey) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        amb[i] = 0;
+        if (isfinite(e[i]) && fabs(e[i] - p->e0) <= tol_e[i]) amb[i] = 1;
+        if (R[i] > rmax) rmax = R[i];
+        if (tol_d[i] > tdmax) tdmax = tol_d[i];
+        k[i].x = c[i * 3];
+        k[i].i = i;
+    }
+    qsort(k, (size_t)n, sizeof(orc_xkey), xkey_cmp);
+    const double reach = rho * rmax + 2.0 * tdmax;
+    for (int64_t a = 0; a < n; ++a) {
+        int64_t i = k[a].i;
+        for (int64_t b = a + 1; b < n && k[b].x - k[a].x <= reach; ++b) {
+            int64_t j = k[b].i;
+            double d2 = 0.0;
+            for (int q = 0; q < dim; ++q) d2 += (c[i * 3 + q] - c[j * 3 + q]) * (c[i * 3 + q] - c[j * 3 + q]);
+            double d = sqrt(d2), thr = rho * (R[i] > R[j] ? R[i] : R[j]);
+            double td = tol_d[i] + tol_d[j];
+            if (fabs(d - thr) <= td) { amb[i] = 1; amb[j] = 1; }
+            if (d < thr + td && fabs(e[i] - e[j]) <= tol_e[i] + tol_e[j]) { amb[i] = 1; amb[j] = 1; }
+        }
+    }
+    free(k);
+    /* A flagged contour may be kept by one run and not the other, which changes what it suppresses:
+     * every candidate that may overlap a flagged contour earlier in the greedy order (smaller
+     * (E, id), within the tolerances) is flagged too, in that order, so the flags close over such
+     * chains. */
+    orc_key *o = (orc_key *)malloc(sizeof(orc_key) * (n > 0 ? n : 1));
+    int64_t no = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (isfinite(e[i])) { o[no].e = e[i]; o[no].id = (uint32_t)i; o[no].idx = i; ++no; }
+    qsort(o, (size_t)no, sizeof(orc_key), key_cmp);
+    int64_t *seen = (int64_t *)malloc(sizeof(int64_t) * (no > 0 ? no : 1));   /* flagged, in greedy order */
+    int64_t ns = 0;
+    for (int64_t a = 0; a < no; ++a) {
+        int64_t j = o[a].idx;
+        for (int64_t b = 0; b < ns && !amb[j]; ++b) {
+            int64_t i = seen[b];
+            double d2 = 0.0;
+            for (int q = 0; q < dim; ++q) d2 += (c[i * 3 + q] - c[j * 3 + q]) * (c[i * 3 + q] - c[j * 3 + q]);
+            double thr = rho * (R[i] > R[j] ? R[i] : R[j]);
+            if (sqrt(d2) < thr + tol_d[i] + tol_d[j]) amb[j] = 1;
+        }
+        if (amb[j]) seen[ns++] = j;
+    }
+    free(seen);
+    free(o);
+    int64_t cnt = 0;
     for (int64_t i = 0; i < n; ++i) cnt += amb[i];
     return cnt;
 }

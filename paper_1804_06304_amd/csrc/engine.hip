@@ -695,6 +695,14 @@ snk_status snk_engine_submit(snk_engine *e, const snk_params *p, const float *di
         P.n_rays / 2 > 768 || !(P.eps0 >= 0.0) || !(P.sigma_pre >= 0.0) || P.conv_window < 0 || P.conv_window > 255)
         return efail(e, SNK_EINVAL, "invalid parameters");
     if (D <= 0 || D != P.n_dirs || (int64_t)D * P.dim > 12288) return efail(e, SNK_EINVAL, "direction table size");
+    // the evolve kernels take |u| <= 1 for granted when they decide that a sample ball lies inside
+    // the volume (and skip clamping), so a row that is not a unit vector is refused as in
+    // snk_set_directions
+    for (int32_t k = 0; k < D; ++k) {
+        double n2 = 0.0;
+        for (int i = 0; i < P.dim; ++i) n2 += (double)dirs[k * P.dim + i] * dirs[k * P.dim + i];
+        if (!(fabs(n2 - 1.0) < 1e-5)) return efail(e, SNK_EINVAL, "direction table rows must be unit vectors");
+    }
     if (P.flags & ~snk::kFlagNoRotation)
         return efail(e, SNK_EINVAL, "engine jobs evolve by Monte-Carlo sums (exact lattice sums: snk_evolve)");
     if (e->dim != 0 && P.dim != e->dim) return efail(e, SNK_EINVAL, "all jobs of an engine must have the same dim");

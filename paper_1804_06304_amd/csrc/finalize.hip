@@ -32,15 +32,18 @@ constexpr int ev_threads() {
     return DIM == 3 ? 256 : 64;
 }
 
+// The weight S of Eq. (5) in FP64: the exact energy sums a few thousand terms once per contour, so
+// the distance and weight of each lattice point are formed in double and only the voxel value is
+// FP32 (as the smoothed volume is).
 template <int DIM>
-__device__ __forceinline__ float weight_S(float r, float R, float dR) {
-    constexpr float RHO = DIM == 3 ? 0.79370052598409973738f : 0.70710678118654752440f;
-    const float ain = RHO * R, dr = RHO * dR;
-    if (r < ain - 0.5f * dr) return -1.0f;
-    if (r < ain + 0.5f * dr) return (r - ain) * (2.0f / dr);
-    if (r < R - 0.5f * dR) return 1.0f;
-    if (r < R + 0.5f * dR) return 0.5f - (r - R) * (1.0f / dR);
-    return 0.0f;
+__device__ __forceinline__ double weight_S(double r, double R, double dR) {
+    constexpr double RHO = DIM == 3 ? 0.79370052598409973738 : 0.70710678118654752440;
+    const double ain = RHO * R, dr = RHO * dR;
+    if (r < ain - 0.5 * dr) return -1.0;
+    if (r < ain + 0.5 * dr) return 2.0 * (r - ain) / dr;
+    if (r < R - 0.5 * dR) return 1.0;
+    if (r < R + 0.5 * dR) return 0.5 - (r - R) / dR;
+    return 0.0;
 }
 
 template <int DIM>
@@ -59,6 +62,7 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out, 
         return;
     }
     const float smax = R + 0.5f * p.dR;
+    const double R_d = (double)R, dR_d = (double)p.dR, smax_d = R_d + 0.5 * dR_d;
     int lo[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
 #pragma unroll
     for (int i = 0; i < DIM; ++i) {
@@ -85,19 +89,19 @@ __device__ void energy_one(const JobParams &p, DevContour *slot, double *e_out, 
             ry -= cnt[1];
             rz += 1;
         }
-        float d2 = 0.0f;
+        double d2 = 0.0;
 #pragma unroll
         for (int i = 0; i < DIM; ++i) {
-            const float d = ((float)rel[i] - s.off[i]) * g.h[i];
-            d2 = fmaf(d, d, d2);
+            const double d = ((double)rel[i] - (double)s.off[i]) * (double)g.h[i];
+            d2 = fma(d, d, d2);
         }
-        const float r = sqrtf(d2);
-        if (!(r < smax)) continue;  // (the step above already advanced the coordinates)
+        const double r = sqrt(d2);
+        if (!(r < smax_d)) continue;  // (the step above already advanced the coordinates)
         int k[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < DIM; ++i) k[i] = min(max(s.anc[i] + rel[i], 0), nn[i] - 1);
         const float v = g.J[((long)k[2] * g.ny + k[1]) * g.nx + k[0]];
-        acc += (double)(weight_S<DIM>(r, R, p.dR) * v);
+        acc += weight_S<DIM>(r, R_d, dR_d) * (double)v;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);

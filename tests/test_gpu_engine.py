@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import synth
+from parity_util import check_free_run, oracle_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -66,11 +67,8 @@ def test_batched_equals_plain_and_oracle(snk, jobs):
         ref = plain(snk, w, 256, 2)
         for k in KEYS:
             assert np.array_equal(got[k], ref[k]), (w.name, k)
-        orc = oracle.run(w.raw, w.params, w.dirs, w.seeds, w.n_iter, ids=w.ids)
-        st = orc["state"]
-        assert np.array_equal(got["iters"], st.iters), w.name
-        assert np.max(np.abs(got["radii"] - st.R), initial=0.0) <= 0.05
-        assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1), initial=0.0) <= 0.5
+        ref = oracle_reference(w.raw, w.params, w.dirs, w.seeds, w.n_iter, ids=w.ids)
+        check_free_run(got, ref, w.params, f"batched {w.name}")
     # replay of the captured graph gives the same results
     first = {j: eng.read(j) for j in ids}
     eng.run()
@@ -131,6 +129,10 @@ def test_served_alone_equals_mix(snk, jobs):
     ref = plain(snk, target, 128, 1)
     for k in KEYS:
         assert np.array_equal(alone[k], ref[k]), k
+    # every served job against the oracle's own run of it
+    for w, j in zip(jobs[:2] + [target] + jobs[3:], others + [j1] + late):
+        oref = oracle_reference(w.raw, w.params, w.dirs, w.seeds, w.n_iter, ids=w.ids)
+        check_free_run(eng.read(j), oref, w.params, f"served {w.name}")
     s = eng.get_stats()
     assert s["bytes_in_use"] == 0 and s["running"] == 0
     eng.close()
@@ -177,4 +179,19 @@ def test_admission_by_budget(snk, jobs):
     eng.step(20)
     s = eng.get_stats()
     assert s["running"] == 1 and s["pending"] == 1, s
+    eng.close()
+
+
+def test_submit_rejects_non_unit_directions(snk, jobs):
+    """The evolve kernels decide that a sample ball lies inside the volume assuming |u| <= 1, so a
+    direction table with a row that is not a unit vector is refused at submission (SNK_EINVAL), as
+    snk_set_directions refuses it."""
+    w = jobs[0]
+    eng = snk.Engine(0, None, 1 << 30)
+    bad = np.array(w.dirs, dtype=np.float64)
+    bad[3] *= 1.5
+    with pytest.raises(snk.SnkError) as ex:
+        eng.submit(w.params, bad, w.raw, w.seeds, ids=w.ids, n_iter=5)
+    assert ex.value.code == snk.SNK_EINVAL
+    assert eng.get_stats()["submitted"] == 0
     eng.close()

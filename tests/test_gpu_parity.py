@@ -6,9 +6,14 @@ Bars (stated per test):
     {A, B_R, B_c, E_mc, dR, dc}, |X_gpu - X_ref| <= 1e-5 * max(|X_ref|, X_abs) + slack, where X_abs
     is X with every summand replaced by its magnitude and slack is the oracle's bound on what a
     sample lying within 4e-6 s_max of a kink of S can change when FP32 places it on the other side;
-  * free run: |R_gpu - R_ref| <= 0.05, |c_gpu - c_ref| <= 0.5 voxel, identical iteration counts;
-  * exact energy: |E_gpu - E_ref| <= 1e-5 * E_abs; selection: identical keep sets apart from
-    decisions the oracle flags as within 1e-4 (energy) or 1e-3 voxel (overlap) of a threshold.
+  * free run (parity_util.check_free_run): every contour within |R_gpu - R_ref| <= 0.05 and
+    |c_gpu - c_ref| <= 0.5 voxel of the oracle's own run; iteration counts identical, or within the
+    range the oracle's stop rule allows when each decision within 1% of the convergence tolerance
+    may go either way; the kept set equal to the oracle run's own, apart from decisions whose
+    margins are smaller than the two runs' disagreement in the quantities compared;
+  * exact energy: |E_gpu - E_ref| <= 1e-5 * max(|E_ref|, E_abs) at the GPU's final state;
+    selection on given states: identical keep sets apart from decisions the oracle flags as within
+    1e-4 (energy) or 1e-3 voxel (overlap) of a threshold.
 """
 import sys
 
@@ -19,8 +24,19 @@ import pytest
 
 import oracle
 import synth
+from parity_util import check_free_run, expected_kinked_steps, oracle_reference, tol_check
 
 pytestmark = pytest.mark.gpu
+
+_FULL = {}
+
+
+def full_workload(which):
+    """The full-size slab or plane workload, generated once per session (a shallow copy, so a test
+    may replace its parameter record)."""
+    if which not in _FULL:
+        _FULL[which] = synth.slab_config() if which == "slab" else synth.plane_config()
+    return copy.copy(_FULL[which])
 
 
 def say(*a):
@@ -72,18 +88,13 @@ def extra_seeds(wl, n, rng):
     return s
 
 
-def tol_check(name, got, ref, ref_abs, slack, rel=1e-5):
-    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
-    tol = rel * np.maximum(np.abs(ref), ref_abs) + slack + 1e-30
-    err = np.abs(got - ref)
-    bad = np.where(err > tol)[0]
-    assert len(bad) == 0, (f"{name}: {len(bad)} of {len(ref)} outside tolerance; worst "
-                           f"idx {bad[:5]} got {got[bad[:5]]} ref {ref[bad[:5]]} tol {tol[bad[:5]]}")
-    return float(np.max(err / tol)) if len(ref) else 0.0
-
-
 def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, unroll=0, layout=0,
-                    max_kinked=0.2, tile=-1):
+                    max_kinked=None, tile=-1):
+    """Teacher-forced one-step parity of every active contour at each prerun count. Contour-steps
+    whose slack is in use (a sample within the oracle's band around a kink of S, or for the
+    image-gradient force around a voxel face) are counted: for Monte-Carlo sums at most the
+    analytic expectation plus four Poisson deviations; for the exact and image-gradient forms at
+    most `max_kinked` of the steps."""
     p = wl.params
     rng = np.random.default_rng(seed)
     seeds = np.concatenate([wl.seeds, extra_seeds(wl, n_extra, rng)]) if n_extra else wl.seeds
@@ -98,6 +109,7 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, 
     kinked = 0
     steps = 0
     done = 0
+    expect = 0.0
     for target in prerun_iters:
         if target > done:
             oracle.evolve(J, p, wl.dirs, st, target - done)
@@ -125,6 +137,7 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, 
             worst[name] = max(worst.get(name, 0.0), tol_check(f"{name} at n={target}", gv, rv, ra, sl))
         kinked += int((tr[a, 28] > 0).sum())
         steps += len(a)
+        expect += expected_kinked_steps(p, tr[a, 30])
         # the state after the step matches too
         gs = ctx.get_state()
         assert np.all(gs["iters"][a] == ref.iters[a])
@@ -134,8 +147,11 @@ def one_step_parity(snk, stream, wl, prerun_iters, n_extra=56, seed=0, lanes=0, 
         assert np.all(np.linalg.norm(gs["centers"][a] - ref.c[a], axis=1) < 1e-4 + slack_c)
     ctx.close()
     say(f"  worst err/tol: " + ", ".join(f"{k} {v:.3f}" for k, v in worst.items()) +
-        f"; contour-steps with a near-kink sample: {kinked}/{steps}")
-    assert kinked <= max_kinked * steps
+        f"; contour-steps with a near-kink sample: {kinked}/{steps} (Monte-Carlo expectation {expect:.2f})")
+    if p.flags & 6:
+        assert kinked <= (0.3 if max_kinked is None else max_kinked) * steps
+    else:
+        assert kinked <= expect + 4.0 * np.sqrt(expect) + 1.0
     return worst
 
 
@@ -311,7 +327,7 @@ def test_one_step_parity_exact(snk, stream, which, lanes, layout):
     say(f"one-step parity, exact sums: {which}, lanes {lanes}, layout {layout}")
     # lattice points share radii by symmetry, so more contour-steps have a point within the kink
     # tolerance than with random samples (their effect is in the slack either way)
-    one_step_parity(snk, stream, wl, [0, 6], n_extra=32, lanes=lanes, layout=layout, max_kinked=0.6)
+    one_step_parity(snk, stream, wl, [0, 6], n_extra=32, lanes=lanes, layout=layout, max_kinked=0.3)
 
 
 def test_free_run_exact(snk, stream):
@@ -319,11 +335,8 @@ def test_free_run_exact(snk, stream):
     wl.params = wl.params.replace(flags=2)
     say("free run tiny, exact sums: 100 iterations")
     got = free_run(snk, stream, wl)
-    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
-    st = ref["state"]
-    assert np.array_equal(got["iters"], st.iters)
-    assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
-    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+    ref = oracle_reference(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    check_free_run(got, ref, wl.params, "tiny exact sums")
 
 
 @pytest.mark.parametrize("which,lanes,layout,tile", [("tiny", 0, 0, -1), ("tiny", 64, 1, 0), ("tiny", 256, 2, 0),
@@ -342,7 +355,7 @@ def test_one_step_parity_gradient_form(snk, stream, which, lanes, layout, tile):
     wl.params = wl.params.replace(flags=4)
     say(f"one-step parity, gradient-form centre force: {which}, lanes {lanes}, layout {layout}, tile {tile}")
     # samples next to a voxel face also count as near a kink (the normal derivative jumps there)
-    one_step_parity(snk, stream, wl, [0, 6], n_extra=48, lanes=lanes, layout=layout, tile=tile, max_kinked=0.6)
+    one_step_parity(snk, stream, wl, [0, 6], n_extra=48, lanes=lanes, layout=layout, tile=tile, max_kinked=0.3)
 
 
 def test_gradient_form_leaves_energy_and_radius_terms(snk, stream):
@@ -375,12 +388,8 @@ def test_free_run_gradient_form(snk, stream):
     wl.params = wl.params.replace(flags=4)
     say("free run tiny, gradient-form centre force: 100 iterations")
     got = free_run(snk, stream, wl)
-    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
-    st = ref["state"]
-    assert np.array_equal(got["iters"], st.iters)
-    assert np.array_equal(got["status"], st.status)
-    assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
-    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+    ref = oracle_reference(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    check_free_run(got, ref, wl.params, "tiny gradient form")
 
 
 def free_run(snk, stream, wl, seeds=None, ids=None, lanes=0, chunks=None):
@@ -400,35 +409,25 @@ def test_free_run_tiny(snk, stream):
     wl = synth.tiny_config()
     say("free run tiny: 100 iterations, then exact energy and selection")
     got = free_run(snk, stream, wl)
-    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
-    st = ref["state"]
-    assert np.array_equal(got["iters"], st.iters)
-    assert np.array_equal(got["status"], st.status)
-    assert np.max(np.abs(got["radii"] - st.R)) <= 0.05
-    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)) <= 0.5
+    ref = oracle_reference(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    r = check_free_run(got, ref, wl.params, "tiny")
+    assert r["differing_iters"] == 0
     assert got["timing"]["evolved"] == ref["evolved"]
-    # exact energy at the GPU's own final state
-    e_ref, e_abs = oracle.energy_vox(ref["J"], wl.params, got["centers"], got["radii"].astype(np.float64))
-    tol_check("E_vox", got["e_vox"], e_ref, e_abs, 0.0, rel=2e-5)
+    # the selection on the GPU's own final state equals the oracle's greedy there too
+    e_ref, _ = oracle.energy_vox(ref["J"], wl.params, got["centers"], got["radii"].astype(np.float64))
     amb = oracle.cull_ambiguity(wl.params, got["centers"], got["radii"], e_ref)
     keep_ref = oracle.cull(wl.params, got["centers"], got["radii"], got["e_vox"].astype(np.float64),
                            got["status"], wl.ids)
     ok = amb == 0
     assert np.array_equal(got["keep"][ok], keep_ref[ok])
-    assert np.array_equal(got["keep"][ok], ref["keep"][ok])
-    say(f"  kept {int(got['keep'].sum())}/{len(got['keep'])}, ambiguous {int(amb.sum())}")
 
 
 def test_free_run_2d(snk, stream):
     wl = synth.plane_config(n_target=200, size=320, n_iter=60)
     say("free run 2D: 320^2, 60 iterations")
     got = free_run(snk, stream, wl)
-    ref = oracle.run(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
-    st = ref["state"]
-    same = got["iters"] == st.iters
-    assert same.mean() >= 0.98
-    assert np.max(np.abs(got["radii"] - st.R)[same]) <= 0.05
-    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[same]) <= 0.5
+    ref = oracle_reference(wl.raw, wl.params, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    check_free_run(got, ref, wl.params, "2D 320^2")
 
 
 @pytest.mark.parametrize("n", [1500, 9000])
@@ -460,7 +459,7 @@ def test_selection_matches_greedy_dense(snk, stream, n):
     assert np.array_equal(got["keep"][ok], keep_ref[ok]), (np.where(got["keep"] != keep_ref)[0][:10])
     J = oracle.prepass(wl.raw, p)
     e_ref, e_abs = oracle.energy_vox(J, p, got["centers"], got["radii"].astype(np.float64))
-    tol_check("E_vox dense", got["e_vox"], e_ref, e_abs, 0.0, rel=2e-5)
+    tol_check("E_vox dense", got["e_vox"], e_ref, e_abs, 0.0, rel=1e-5)
 
 
 def test_determinism_split_and_order(snk, stream):
@@ -515,7 +514,7 @@ def test_full_size_slab_sampled(snk, stream):
     """The benchmark workload at full size (512x512x128 u16, ~2,000 nuclei, D 642, M 64) in the
     benchmark's launch configuration: one-step parity of every contour from the seeds and after
     20 iterations, and a 20-iteration free run of all contours."""
-    wl = synth.slab_config()
+    wl = full_workload("slab")
     say(f"full-size slab: {wl.name}")
     worst = one_step_parity(snk, stream, wl, [0, 20], n_extra=0)
     assert worst
@@ -530,10 +529,11 @@ def test_full_size_slab_sampled(snk, stream):
 
 def test_full_size_slab_free_run(snk, stream):
     """The benchmark workload end to end as the benchmark runs it (automatic launch shape, all 500
-    iterations as one evolve call, then exact energy and selection): per-contour iteration counts,
-    states, radii and centres against the oracle's 500-iteration run; E_vox and the kept set
-    against the oracle evaluated at the GPU's own final state."""
-    wl = synth.slab_config()
+    iterations as one evolve call, then exact energy and selection) against the oracle's own
+    500-iteration run of the same contours: every contour's iteration count within the oracle's
+    stop range, radii and centres of all contours, E_vox at 1e-5, and the kept set against the
+    oracle run's kept set (check_free_run)."""
+    wl = full_workload("slab")
     p = wl.params
     say(f"full-size slab free run: {wl.name}, {wl.n_iter} iterations")
     ctx = make_ctx(snk, stream, wl)
@@ -547,29 +547,29 @@ def test_full_size_slab_free_run(snk, stream):
     say(f"  launch lanes {tm['lanes_per_contour']} pairs {tm['pairs_in_flight']} layout {tm['layout']} "
         f"tile {tm['tile_voxels']}, {tm['evolve_launches'] - l0} launches")
     assert tm["evolve_launches"] - l0 == 2
-    ref = oracle.run(wl.raw, p, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
-    st = ref["state"]
-    same = got["iters"] == st.iters
-    assert same.mean() >= 0.99, same.mean()
-    assert np.array_equal(got["status"][same], st.status[same])
-    assert np.max(np.abs(got["radii"] - st.R)[same]) <= 0.05
-    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[same]) <= 0.5
-    e_ref, e_abs = oracle.energy_vox(ref["J"], p, got["centers"], got["radii"].astype(np.float64))
-    tol_check("E_vox", got["e_vox"], e_ref, e_abs, 0.0, rel=2e-5)
-    amb = oracle.cull_ambiguity(p, got["centers"], got["radii"], e_ref)
-    keep_ref = oracle.cull(p, got["centers"], got["radii"], got["e_vox"].astype(np.float64), got["status"], wl.ids)
-    ok = amb == 0
-    assert ok.mean() >= 0.99
-    assert np.array_equal(got["keep"][ok], keep_ref[ok])
-    say(f"  same iterations {same.mean():.4f}, max |dR| {np.max(np.abs(got['radii'] - st.R)[same]):.4f}, "
-        f"kept {int(got['keep'].sum())} (oracle run {int(ref['keep'].sum())}), ambiguous {int(amb.sum())}")
+    ref = oracle_reference(wl.raw, p, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    r = check_free_run(got, ref, p, "slab 500 iterations")
+    assert r["differing_iters"] <= 0.01 * r["contours"]
+
+
+def test_full_size_plane_free_run(snk, stream):
+    """The 2D workload at full size (8192^2 u8, 40,000 cells, D 64, M 16, L 16) for all 300
+    iterations in the benchmark's launch configuration, then exact energy and selection, against
+    the oracle's own 300-iteration run (check_free_run)."""
+    wl = full_workload("plane")
+    p = wl.params
+    say(f"full-size plane free run: {wl.name}, {wl.n_iter} iterations")
+    got = free_run(snk, stream, wl)
+    ref = oracle_reference(wl.raw, p, wl.dirs, wl.seeds, wl.n_iter, ids=wl.ids)
+    r = check_free_run(got, ref, p, "plane 300 iterations")
+    assert r["differing_iters"] <= 0.01 * r["contours"]
 
 
 def test_full_size_split_calls_identical(snk, stream):
     """The benchmark workload in its automatic shape (LDS boxes, each call of 64 or more iterations
     as two launches): the same 500 iterations split into calls of different lengths give
     bit-identical contours."""
-    wl = synth.slab_config()
+    wl = full_workload("slab")
     say(f"split calls: {wl.name}")
     ref, tm_ref = None, None
     for chunks in ([500], [200, 300], [256, 244], [300, 200], [100, 100, 100, 200]):
@@ -592,7 +592,7 @@ def test_full_size_plane_sampled(snk, stream):
     """The 2D workload at full size (8192^2 u8, 40,000 cells, D 64, M 16) in the benchmark's launch
     configuration: one-step parity of every contour from the seeds and after 20 iterations, and a
     20-iteration free run of all contours."""
-    wl = synth.plane_config()
+    wl = full_workload("plane")
     say(f"full-size plane: {wl.name}")
     worst = one_step_parity(snk, stream, wl, [0, 20], n_extra=0)
     assert worst
