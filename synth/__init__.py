@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "Params", "Workload", "icosphere", "circle_directions", "render_ellipsoids", "blurred_ball",
-    "tiny_config", "slab_config", "plane_config", "subvolume_batch", "served_tiles",
+    "tiny_config", "slab_params", "slab_config", "plane_config", "subvolume_batch", "served_tiles",
     "CONFIG_SEED_BASE",
 ]
 
@@ -300,6 +300,15 @@ def tiny_config(seed: int = CONFIG_SEED_BASE + 1) -> Workload:
                     {"centers": centers, "axes": axes, "rots": rots, "r0": r0})
 
 
+def slab_params(seed: int, n_dirs: int = 642, n_rays: int = 64) -> Params:
+    """Method parameters of the nuclei workloads (slab, batched subvolumes, served tiles): h = (1, 1, 2),
+    contrast-normalised counts (background 100, peak 900), dR 0.75, R0 = 2^(1/3) * 6.5, r_max 3 R0."""
+    r0 = 2.0 ** (1.0 / 3.0) * 6.5
+    return Params(dim=3, spacing=(1.0, 1.0, 2.0), sigma_pre=1.0, i_offset=100.0, i_scale=1.0 / 900.0,
+                  dR=0.75, eps0=8.0, r_min=0.0, r_max=3.0 * r0, r_init=r0, n_dirs=n_dirs, n_rays=n_rays,
+                  n_radial=16, seed=seed, conv_tol=1e-3, conv_window=10, e0=-0.05)
+
+
 def slab_config(seed: int = CONFIG_SEED_BASE + 2, n_target: int = 2000, shape_xyz=(512, 512, 128),
                 n_iter: int = 500) -> Workload:
     """512x512x128 uint16 slab, h = (1, 1, 2), ~2,000 ellipsoid nuclei (physical semi-axes 3..10,
@@ -328,9 +337,7 @@ def slab_config(seed: int = CONFIG_SEED_BASE + 2, n_target: int = 2000, shape_xy
     lam = (100.0 + 900.0 * blurred) * (1.0 - 0.3 * x)[None, None, :]
     raw = _quantise(rng.poisson(lam).astype(np.float64), np.uint16)
     r0 = 2.0 ** (1.0 / 3.0) * 6.5
-    p = Params(dim=3, spacing=(1.0, 1.0, 2.0), sigma_pre=1.0, i_offset=100.0, i_scale=1.0 / 900.0,
-               dR=0.75, eps0=8.0, r_min=0.0, r_max=3.0 * r0, r_init=r0, n_dirs=642, n_rays=64, n_radial=16,
-               seed=seed, conv_tol=1e-3, conv_window=10, e0=-0.05)
+    p = slab_params(seed)
     seeds = centers + rng.uniform(-1.0, 1.0, size=centers.shape) * h
     seeds = np.clip(seeds, 0.0, ext)
     return Workload("slab-512x512x128-u16-%dnuclei" % n, raw, p, icosphere(3), seeds,
