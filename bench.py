@@ -8,9 +8,12 @@ energy + selection, readback. Inputs (raw volume, direction table) are resident 
 timed region; the seeds are re-sent each step (48 KB).
 
 Prints ONE JSON line: vertex-updates/s (one vertex-update = one sampled ray of one active contour
-in one iteration), the evolve kernel's achieved logical-gather bandwidth against the 8 TB/s HBM
-peak (from HIP events recorded around each launch on the launch stream), and the FP64 oracle
-timed on a bounded sample on the host cores.
+in one iteration); the evolve kernel's roofline (algorithmic FP32 FLOPs over its HIP-event time
+against the vector ALU's rate, with the VALU issue rate and HBM traffic from the committed counters
+and the logical-gather bandwidth beside it); the FP64 oracle timed on a bounded sample on the host
+cores; and, under "workloads", the 2D image (8192^2, 40,000 cells), the batched subvolumes (256,
+engine against the plain loop) and the served tile stream (tiles cut from a 2048x2048x512 volume,
+Poisson arrivals, p50/p99 latency), each with its parity check and oracle figure (--quick skips them).
 """
 from __future__ import annotations
 
@@ -26,6 +29,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Algorithmic FP32 FLOPs per vertex-update (one ray of L = 16 radial points): per sample point the
+# position c + s u (3 FMA), voxel coordinates (3 mul), fractions (3 sub), the 7 (3D) / 3 (2D) lerps
+# of the interpolation (sub + FMA each), and the sums S I, dS/dR I, dS/dr I u (2 + 2 + 1 + 3 FMA):
+# 44 (3D) / 26 (2D) FLOPs, plus half of the radius, cube (square) root and weights that the two
+# antithetic points at one radius share: 47 / 29 per point.
+FLOP_PER_VU = {3: 16 * 47, 2: 16 * 29}
+# Unpacked FP32 FMA rate: 256 CUs x 64 lanes x 2 FLOPs x 2.4 GHz (the packed FP32 instructions that
+# double it to the published 157.3 TFLOP/s are switched off in this build's compile flags).
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# VALU lane-instruction issue rate: 256 CUs x 64 lanes x 2.4 GHz.
+LANE_ISSUE_PEAK = 256 * 64 * 2.4e9
 COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "evolve_slab_counters.json")
 
 
@@ -165,9 +179,19 @@ def main():
                          "accuracy and time of free runs with 64, 32 and 16 rays; star: the slab with "
                          "star-shaped contours (per-direction radii) against the sphere: time and fit to the "
                          "generator's ellipsoids")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="served: arrival window (s)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="served: arrival window (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: mean arrivals per second")
+    ap.add_argument("--rate-hi", type=float, default=2000.0,
+                    help="served: mean arrivals per second of the second, saturating stream")
+    ap.add_argument("--serve-seconds-hi", type=float, default=5.0, help="served: window of the saturating stream (s)")
     ap.add_argument("--chunk", type=int, default=25, help="served: iterations per engine step")
+    ap.add_argument("--chunk-idle", type=int, default=200,
+                    help="served: iterations per step while one job runs and none waits (0: always --chunk)")
+    ap.add_argument("--served-check", type=int, default=48,
+                    help="served: requests checked against the plain path (bitwise) and the FP64 oracle")
+    ap.add_argument("--quick", action="store_true",
+                    help="the slab line only (default: also the 2D, batched and served workloads as extra keys)")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of the 2D and batched extras")
     ap.add_argument("--cull-every", type=int, default=25, help="lattice: iterations between culling passes")
     ap.add_argument("--grace", type=int, default=50, help="lattice: iterations before E0 retires a contour")
     ap.add_argument("--copy-probe", action="store_true",
@@ -318,17 +342,7 @@ def main():
                                        "tile_voxels": tm["tile_voxels"]}},
         "kernels_ms": {"prepass": float(np.mean(prepass_ms)), "evolve": ev_ms,
                        "finalize": float(np.mean(finalize_ms))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     # beside the logical yardstick: the measured HBM rate and VALU busy (a fraction
-                     # of logical bytes above 1 means caches and LDS serve the gathers)
-                     "traffic_gbs": traffic / (ev_ms * 1e-3) / 1e9 if traffic else None,
-                     "valu_busy_pct": ctr.get("valu_busy_pct") if ctr else None,
-                     "kernel": f"evolve_kernel<{d},*,false>",
-                     "launches_per_evolve": launches_per_evolve,
-                     "per": "one evolve call: its launches back to back on one stream, HIP events around them",
-                     "algorithmic_bytes": f"{bytes_per_vu} B per vertex-update (L x 2^d taps x 4 B, logical gathers)"},
+        "roofline": roofline_of(per_launch_vu, d, ev_ms, achieved, ctr, launches_per_evolve),
     }
     # the evolve kernel alone (HIP events around its launches) and its rates in other units
     ci_step = evolved / args.steps
@@ -350,7 +364,54 @@ def main():
         base, parity = cpu_baseline(wl, out, args.cpu_sample)
         line["cpu_baseline"] = base
         line["parity_sample"] = parity
+    if not args.quick and args.workload == "slab" and not args.exact:
+        # the other workloads, as extra keys beside the slab line (a failure in one is recorded, not fatal)
+        extras = {}
+        for name, fn in (("plane", lambda: run_plane(args)),
+                         ("batched", lambda: run_batched(args, args.extra_steps, 1)),
+                         ("served", lambda: run_served(args))):
+            try:
+                extras[name] = fn()
+            except Exception as exc:   # keep the headline line
+                log(f"{name}: failed: {exc!r}")
+                extras[name] = {"error": repr(exc)}
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        line["workloads"] = extras
     print(json.dumps(line), flush=True)
+
+
+def roofline_of(vu_per_call, d, ev_ms, logical_gbs, ctr, launches):
+    """Roofline of the evolve kernel per evolve call. The kernel issues vector instructions faster
+    than it moves bytes (the committed counters: VALU busy, lane-instructions per sample point, HBM
+    bytes well below the logical gathers), so its bound is the vector ALU: achieved = algorithmic
+    FP32 FLOPs per call over the call's HIP-event time, against the unpacked FP32 rate. Beside it:
+    the VALU issue rate from the committed counters (hash-gated to the evolve sources) and the
+    logical-gather bandwidth against the HBM peak."""
+    secs = ev_ms * 1e-3
+    tf = vu_per_call * FLOP_PER_VU[d] / secs / 1e12
+    traffic = float(ctr["hbm_bytes_per_evolve"]) if ctr else None
+    valu = float(ctr["sq_insts_valu_per_evolve"]) if ctr and "sq_insts_valu_per_evolve" in ctr else None
+    return {"bound": "alu", "achieved": tf, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / VALU_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": f"evolve_kernel<{d},*,false>", "launches_per_evolve": launches,
+            "per": "one evolve call: its launches back to back on one stream, HIP events around them",
+            "algorithmic_flops": f"{FLOP_PER_VU[d]} FP32 FLOPs per vertex-update (L = 16 points x "
+                                 f"{FLOP_PER_VU[d] // 16} per point)",
+            "peak_basis": "256 CUs x 64 lanes x 2 FLOPs (FMA) x 2.4 GHz, unpacked FP32 (published 157.3 "
+                          "counts packed FP32, which this build does not emit)",
+            "frac_of_published_fp32": tf / 157.3,
+            "counters_source": ("profiles/evolve_slab_counters.json: rocprofv3 --pmc counters of the same "
+                                "evolve sources and launch shape, committed with their source hash; null when "
+                                "the sources have changed since") ,
+            "traffic_gbs": traffic / secs / 1e9 if traffic else None,
+            "hbm_frac": traffic / secs / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "valu_busy_pct": ctr.get("valu_busy_pct") if ctr else None,
+            "valu_issue_frac": valu * 64 / secs / LANE_ISSUE_PEAK if valu else None,
+            "logical_gather": {"achieved": logical_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": logical_gbs / HBM_PEAK_GBS,
+                               "bytes": f"{16 * 2 ** d * 4} B per vertex-update (L x 2^d taps x 4 B); above 1 "
+                                        "means LDS and caches serve the gathers, not HBM"}}
 
 
 def match_truth(kept, truth, dmax):
@@ -602,162 +663,392 @@ def plain_pass(snk, ctx, wl, raw_dev):
     return ctx.read()
 
 
-def bench_batched(args):
-    """256 cubic u16 subvolumes (edge 32..160, 10..800 nuclei, D 162 or 642): the engine's captured
-    batched run against the plain per-volume loop on the same resident inputs."""
+KEYS = ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep")
+
+
+def oracle_run(wl, raw_np):
+    """The FP64 oracle's whole run of one workload (pre-pass, evolution, exact energy, selection);
+    returns its state, kept flags, vertex-updates and seconds."""
+    import oracle
+    p = wl.params
+    t0 = time.perf_counter()
+    J = oracle.prepass(raw_np, p)
+    st = oracle.init_state(p, wl.seeds, ids=wl.ids, shape_zyx=raw_np.shape)
+    _, done = oracle.evolve(J, p, wl.dirs, st, wl.n_iter)
+    oracle.finalize_status(st)
+    e_vox, _ = oracle.energy_vox(J, p, st.c, st.R)
+    keep = oracle.cull(p, st.c, st.R, e_vox, st.status, st.ids)
+    return st, keep, done * p.n_rays, time.perf_counter() - t0
+
+
+def compare_with_oracle(outs, refs):
+    """Free-run agreement of GPU results with the oracle's runs of the same contours: the worst radius
+    and centre differences over every contour, the fraction with identical iteration counts and of
+    identical keep flags."""
+    import numpy as np
+    dR, dc, same, n, kept_same = 0.0, 0.0, 0, 0, 0
+    for got, (st, keep) in zip(outs, refs):
+        if len(st.R) == 0:
+            continue
+        dR = max(dR, float(np.max(np.abs(got["radii"] - st.R))))
+        dc = max(dc, float(np.max(np.linalg.norm(got["centers"] - st.c, axis=1))))
+        same += int(np.sum(got["iters"] == st.iters))
+        kept_same += int(np.sum(got["keep"] == keep))
+        n += len(st.R)
+    return {"contours": n, "max_abs_dR": dR, "max_abs_dc": dc, "same_iters_frac": same / max(n, 1),
+            "same_keep_frac": kept_same / max(n, 1),
+            "ok": bool(dR <= 0.05 and dc <= 0.5 and same >= 0.99 * n)}
+
+
+def run_plane(args):
+    """The 2D workload (8192^2 u8, 40,000 touching cells, 300 iterations) through the plain path:
+    vertex-updates/s per step and the evolve kernel's rates, the FP64 oracle over the whole workload
+    (the CPU figure) and its agreement with the GPU's run."""
     import numpy as np
     import torch
 
+    import oracle
     import synth
     from paper_1804_06304_amd import snk
 
     t0 = time.perf_counter()
-    jobs = synth.subvolume_batch()
-    log(f"batched workload: {len(jobs)} subvolumes, {sum(len(w.seeds) for w in jobs)} contours, "
-        f"{sum(w.raw.size for w in jobs) / 1e6:.0f} M voxels, generated in {time.perf_counter() - t0:.1f} s")
-    stream = torch.cuda.current_stream()
-    raws = [torch.from_numpy(w.raw).to("cuda:0") for w in jobs]
+    wl = synth.plane_config()
+    log(f"plane: {wl.name} generated in {time.perf_counter() - t0:.1f} s")
+    p = wl.params
+    raw = torch.from_numpy(wl.raw).to("cuda:0")
+    ctx = snk.Context(0, torch.cuda.current_stream())
+    ctx.set_params(p)
+    ctx.set_directions(wl.dirs)
+    ctx.load_volume(raw)
+    ev, evolved, wall = [], 0, 0.0
+    for k in range(1 + args.extra_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.load_seeds(wl.seeds, ids=wl.ids)
+        ctx.prepass()
+        ctx.evolve(wl.n_iter)
+        ctx.finalize()
+        out = ctx.read()
+        tm = ctx.get_timing()
+        if k > 0:
+            wall += time.perf_counter() - t0
+            ev.append(tm["evolve_ms"])
+            evolved += tm["evolved"]
+    ctx.close()
+    steps = args.extra_steps
+    vu = evolved * p.n_rays
+    ev_ms = float(np.mean(ev))
+    res = {"workload": wl.name, "value": vu / wall, "unit": "vertex-updates/s", "steps": steps,
+           "ms_per_step": wall / steps * 1e3, "evolve_ms": ev_ms,
+           "evolve_vertex_updates_per_s": vu / steps / (ev_ms * 1e-3),
+           "evolve_tflops": vu / steps * FLOP_PER_VU[2] / (ev_ms * 1e-3) / 1e12,
+           "launch": {"lanes_per_contour": tm["lanes_per_contour"], "pairs_in_flight": tm["pairs_in_flight"],
+                      "layout": tm["layout"], "tile_voxels": tm["tile_voxels"]}}
+    log(f"plane: {res['ms_per_step']:.2f} ms per step, evolve {ev_ms:.3f} ms, {res['value']:.4g} vu/s")
+    if not args.no_cpu_baseline:
+        log("plane: FP64 oracle over the whole workload ...")
+        st, keep, ovu, secs = oracle_run(wl, wl.raw)
+        res["cpu_baseline"] = {"value": ovu / secs, "unit": "vertex-updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"the whole workload ({len(wl.seeds)} contours, "
+                                                           f"{wl.n_iter} iterations, pre-pass, energy, selection), "
+                                                           f"{secs:.1f} s"}
+        res["parity_vs_oracle"] = compare_with_oracle([out], [(st, keep)])
+        log(f"plane: oracle {secs:.1f} s; parity {res['parity_vs_oracle']}")
+    return res
+
+
+def run_batched(args, steps, warmup):
+    """256 cubic u16 subvolumes (edge 32..160, 10..800 nuclei, D 162 or 642, 200 iterations): the
+    engine's captured batched run against the plain per-volume loop on the same resident inputs,
+    with the engine's result checked against the plain path and, on every 8th subvolume, against
+    the FP64 oracle (whose time on that 1/8 subset gives the CPU figure, extrapolated)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from synth.volumes import subvolume_workloads
+    from paper_1804_06304_amd import snk
+
+    t0 = time.perf_counter()
+    jobs = subvolume_workloads(synth.CONFIG_SEED_BASE + 4, device="cuda:0")
     torch.cuda.synchronize()
+    n_contours = sum(len(w.seeds) for w in jobs)
+    log(f"batched: {len(jobs)} subvolumes, {n_contours} contours, "
+        f"{sum(w.raw.numel() for w in jobs) / 1e6:.0f} M voxels, generated in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
     vu_of = lambda outs: sum(int(o["iters"].sum()) * w.params.n_rays for w, o in zip(jobs, outs))
 
     ctx = snk.Context(0, stream)
     ctx.set_tile(args.tile)
-    outs = [plain_pass(snk, ctx, w, r) for w, r in zip(jobs[:8], raws[:8])]   # warm up
+    for w in jobs[:8]:
+        plain_pass(snk, ctx, w, w.raw)   # warm up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain_outs = [plain_pass(snk, ctx, w, r) for w, r in zip(jobs, raws)]
+    plain_outs = [plain_pass(snk, ctx, w, w.raw) for w in jobs]
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
     ctx.close()
     plain_vu = vu_of(plain_outs)
-    log(f"plain per-volume loop: {plain_s * 1e3:.1f} ms, {plain_vu / plain_s:.4g} vertex-updates/s")
+    log(f"batched: plain per-volume loop {plain_s * 1e3:.1f} ms, {plain_vu / plain_s:.4g} vertex-updates/s")
 
     eng = snk.Engine(0, stream, 64 << 30)
-    ids = [eng.submit(w.params, w.dirs, r, w.seeds, ids=w.ids, n_iter=w.n_iter) for w, r in zip(jobs, raws)]
+    ids = [eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter) for w in jobs]
     t0 = time.perf_counter()
     eng.run()   # autotune per launch class + capture
-    log(f"engine first run (autotune + capture): {(time.perf_counter() - t0) * 1e3:.1f} ms")
-    for _ in range(args.warmup):
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    log(f"batched: engine first run (autotune + capture) {tune_ms:.1f} ms")
+    for _ in range(warmup):
         eng.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         eng.run()
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     outs = [eng.read(j) for j in ids]
     st = eng.get_stats()
+    classes = eng.tuned_classes() if hasattr(eng, "tuned_classes") else None
     eng.close()
-    vu = vu_of(outs) * args.steps
+    vu = vu_of(outs) * steps
     same = all(np.array_equal(a["iters"], b["iters"]) for a, b in zip(outs, plain_outs))
     drift = max(float(np.max(np.abs(a["radii"] - b["radii"]), initial=0.0)) for a, b in zip(outs, plain_outs))
-    line = {
-        "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched-256-subvolumes-u16", "volumes": len(jobs),
-                   "contours": sum(len(w.seeds) for w in jobs), "n_iter": jobs[0].n_iter,
-                   "launch": {"lanes_per_contour": st["lanes_per_contour"],
-                              "pairs_in_flight": st["pairs_in_flight"], "persistent": st["persistent"],
-                              "layout": st["layout"]}},
-        "graph_ms": st["last_ms"],
-        "plain_loop": {"value": plain_vu / plain_s, "ms": plain_s * 1e3},
-        "speedup_vs_plain_loop": (vu / secs) / (plain_vu / plain_s),
-        "parity_vs_plain": {"same_iters": same, "max_abs_dR": drift},
-    }
+    res = {"workload": "batched-256-subvolumes-u16", "value": vu / secs, "unit": "vertex-updates/s",
+           "steps": steps, "ms_per_step": secs / steps * 1e3, "volumes": len(jobs), "contours": n_contours,
+           "n_iter": jobs[0].n_iter, "graph_ms": st["last_ms"], "autotune_and_capture_ms": tune_ms,
+           "launch_last_class": {"lanes_per_contour": st["lanes_per_contour"],
+                                 "pairs_in_flight": st["pairs_in_flight"], "persistent": st["persistent"],
+                                 "layout": st["layout"]},
+           "plain_loop": {"value": plain_vu / plain_s, "ms": plain_s * 1e3},
+           "speedup_vs_plain_loop": (vu / secs) / (plain_vu / plain_s),
+           "parity_vs_plain": {"same_iters": bool(same), "max_abs_dR": drift}}
+    if classes is not None:
+        res["tuned_classes"] = classes
+    log(f"batched: engine {secs / steps * 1e3:.1f} ms per pass, {res['value']:.4g} vu/s, "
+        f"{res['speedup_vs_plain_loop']:.2f}x the plain loop")
+    if not args.no_cpu_baseline:
+        sub = jobs[::8]
+        log(f"batched: FP64 oracle on every 8th subvolume ({len(sub)}) ...")
+        refs, ovu, osecs = [], 0, 0.0
+        for w in sub:
+            o_st, o_keep, v, sec = oracle_run(w, w.raw.cpu().numpy())
+            refs.append((o_st, o_keep))
+            ovu += v
+            osecs += sec
+        res["cpu_baseline"] = {"value": ovu / osecs, "unit": "vertex-updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"every 8th subvolume ({len(sub)} of {len(jobs)}, "
+                                         f"{sum(len(w.seeds) for w in sub)} contours), whole runs, {osecs:.1f} s; "
+                                         f"the whole batch extrapolates to {osecs * len(jobs) / len(sub):.0f} s"}
+        res["parity_vs_oracle"] = compare_with_oracle(outs[::8], refs)
+        log(f"batched: oracle {osecs:.1f} s; parity {res['parity_vs_oracle']}")
+    return res
+
+
+def bench_batched(args):
+    res = run_batched(args, args.steps, args.warmup)
+    line = {"metric": METRIC, "value": res["value"], "unit": "vertex-updates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": res["workload"], "volumes": res["volumes"], "contours": res["contours"],
+                       "n_iter": res["n_iter"]}}
+    line.update({k: v for k, v in res.items() if k not in line and k not in ("workload", "volumes", "contours")})
     print(json.dumps(line), flush=True)
 
 
-def bench_served(args):
-    """Poisson stream of tile requests (cubic u16 tiles 96^3..288^3 from a pool generated once and
-    resident on the device; every request has its own contour ids, so its samples differ) through
-    the engine's continuous batching; reports p50/p99 latency (arrival to results on the host) and
-    throughput, against serving the same requests one at a time through the plain path."""
+def serve_stream(snk, eng, vol_dev, V, arrivals, reqs, chunk, keep_outputs=(), chunk_idle=0):
+    """Serve `arrivals` (times in seconds, request indices into `reqs`) through the engine: each
+    request's tile is cut from the resident volume when it arrives, submitted, and stepped with the
+    others until done (continuous batching). A step advances every running contour by `chunk`
+    iterations, or by `chunk_idle` when a single job runs and none waits (fewer round trips at low
+    load; a request arriving meanwhile joins at the next step). Returns latencies (s),
+    vertex-updates, the wall time and the outputs of the requests listed in keep_outputs."""
     import numpy as np
     import torch
-
-    import synth
-    from paper_1804_06304_amd import snk
-
-    t0 = time.perf_counter()
-    pool = synth.served_tiles()
-    log(f"served workload: pool of {len(pool)} tiles ({min(w.raw.shape[0] for w in pool)}^3.."
-        f"{max(w.raw.shape[0] for w in pool)}^3), generated in {time.perf_counter() - t0:.1f} s")
-    stream = torch.cuda.current_stream()
-    raws = [torch.from_numpy(w.raw).to("cuda:0") for w in pool]
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(0x5E)
-    arrivals, t = [], 0.0
-    while True:
-        t += rng.exponential(1.0 / args.rate)
-        if t > args.serve_seconds:
-            break
-        arrivals.append((t, int(rng.integers(len(pool)))))
-    log(f"{len(arrivals)} requests over {args.serve_seconds:.0f} s (rate {args.rate}/s)")
-
-    free_b, total_b = torch.cuda.mem_get_info(0)
-    budget = min(64 << 30, free_b // 2)
-    log(f"device memory: {free_b / 2**30:.1f} GiB free of {total_b / 2**30:.1f} GiB; HBM budget {budget / 2**30:.1f} GiB")
-    eng = snk.Engine(0, stream, budget)
-    # warm-up: tune the launch class on a few pool tiles, then forget them
-    warm = [eng.submit(w.params, w.dirs, r, w.seeds, ids=w.ids, n_iter=w.n_iter) for w, r in zip(pool[:4], raws[:4])]
-    eng.run()
-    for j in warm:
-        eng.release(j)
-    eng.poll()
-
-    req_job, job_req, lat, vu = {}, {}, [], 0
+    job_req, held, lat, vu, kept = {}, {}, [], 0, {}
     nxt = 0
     t0 = time.perf_counter()
     while nxt < len(arrivals) or job_req:
         now = time.perf_counter() - t0
-        while nxt < len(arrivals) and arrivals[nxt][0] <= now:
-            w = pool[arrivals[nxt][1]]
-            ids = (np.uint32(nxt) << np.uint32(16)) + np.arange(len(w.seeds), dtype=np.uint32)
-            j = eng.submit(w.params, w.dirs, raws[arrivals[nxt][1]], w.seeds, ids=ids, n_iter=w.n_iter)
+        while nxt < len(arrivals) and arrivals[nxt] <= now:
+            wl, lo, hi = reqs[nxt]
+            tile = vol_dev[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous()
+            j = eng.submit(wl.params, wl.dirs, tile, wl.seeds, ids=wl.ids, n_iter=wl.n_iter)
             job_req[j] = nxt
+            held[j] = tile          # borrowed by the engine until the job completes
             nxt += 1
         st = eng.get_stats()
         if st["running"] or st["pending"]:
-            eng.step(args.chunk)
+            alone = st["pending"] + st["running"] <= 1
+            eng.step(chunk_idle if (chunk_idle > 0 and alone) else chunk)
         elif nxt < len(arrivals):
-            time.sleep(max(0.0, arrivals[nxt][0] - (time.perf_counter() - t0)))
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
         for j in eng.poll():
             r = job_req.pop(j)
-            done = time.perf_counter() - t0
-            lat.append(done - arrivals[r][0])
+            lat.append(time.perf_counter() - t0 - arrivals[r])
             out = eng.read(j)
-            vu += int(out["iters"].sum()) * pool[arrivals[r][1]].params.n_rays
+            if r in keep_outputs:
+                kept[r] = out
+            vu += int(out["iters"].sum()) * reqs[r][0].params.n_rays
             eng.release(j)
-    secs = time.perf_counter() - t0
-    eng.close()
-    lat_ms = np.array(lat) * 1e3
+            held.pop(j, None)
+    return np.asarray(lat), vu, time.perf_counter() - t0, kept
 
-    # the same kind of request served one at a time through the plain path
-    ctx = snk.Context(0, stream)
-    plain_pass(snk, ctx, pool[0], raws[0])
-    torch.cuda.synchronize()
+
+def poisson_arrivals(rng, rate, window):
+    import numpy as np
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > window:
+            return np.asarray(out)
+        out.append(t)
+
+
+def run_served(args):
+    """Tile-segmentation requests cut from a 2048 x 2048 x 512 uint16 volume (about 215,000 nuclei,
+    20-400 per 128^3 block, gain 0.7-1, Poisson counts) resident on the device: tile cores of edge
+    U{64..256} plus a 16-voxel halo, seeds at the true centres in the core, D 162, M 32, 200
+    iterations. Poisson arrivals at `rate` per second over `serve_seconds`, and at `rate_hi` (a load
+    the engine cannot keep up with), through the engine's continuous batching; the plain path serving
+    the first stream one request at a time; a sample of requests checked bit for bit against the plain
+    path and against the FP64 oracle, whose time on those tiles gives the CPU figure."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from synth.volumes import served_volume, tile_workload
+    from paper_1804_06304_amd import snk
+
+    t0 = time.perf_counter()
+    V = served_volume(synth.CONFIG_SEED_BASE + 5)
+    n_obj = len(V.objects().centers)
     t1 = time.perf_counter()
-    pvu, plat = 0, []
-    for i in range(min(48, len(arrivals))):
-        k = arrivals[i][1]
-        s0 = time.perf_counter()
-        o = plain_pass(snk, ctx, pool[k], raws[k])
-        plat.append(time.perf_counter() - s0)
-        pvu += int(o["iters"].sum()) * pool[k].params.n_rays
-    plain_s = time.perf_counter() - t1
+    vol = V.whole("cuda:0")
+    torch.cuda.synchronize()
+    log(f"served: volume {V.shape} with {n_obj} nuclei: objects {t1 - t0:.1f} s, voxels on the device "
+        f"{time.perf_counter() - t1:.1f} s")
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(0x5E7)
+
+    def requests(n):
+        out = []
+        for _ in range(n):
+            lo, hi, clo, chi, idx = V.tile(rng)
+            out.append((tile_workload(V, lo, hi, idx, None, seed=synth.CONFIG_SEED_BASE + 5), lo, hi))
+        return out
+
+    free_b, total_b = torch.cuda.mem_get_info(0)
+    budget = min(64 << 30, free_b // 2)
+    eng = snk.Engine(0, stream, budget)
+    warm = requests(4)
+    _, _, _, _ = serve_stream(snk, eng, vol, V, np.zeros(len(warm)), warm, args.chunk)
+    res = {"workload": "served-tiles-of-2048x2048x512-u16", "hbm_budget_gib": round(budget / 2**30, 1),
+           "nuclei": n_obj, "n_iter": 200, "chunk": args.chunk, "chunk_idle": args.chunk_idle, "streams": {}}
+    sample = tuple(range(args.served_check))
+    outs1, reqs1 = None, None
+    for rate, window in ((args.rate, args.serve_seconds), (args.rate_hi, args.serve_seconds_hi)):
+        arr = poisson_arrivals(rng, rate, window)
+        reqs = requests(len(arr))
+        log(f"served: {len(arr)} requests at {rate:g}/s over {window:g} s ...")
+        lat, vu, secs, kept = serve_stream(snk, eng, vol, V, arr, reqs, args.chunk, keep_outputs=sample,
+                                           chunk_idle=args.chunk_idle)
+        lat_ms = lat * 1e3
+        res["streams"][f"{rate:g}_per_s"] = {
+            "rate_per_s": rate, "window_s": window, "requests": len(arr), "wall_s": secs,
+            "vertex_updates_per_s": vu / secs,
+            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                           "max": float(lat_ms.max())},
+            "tile_voxels_mean": float(np.mean([np.prod(h - l) for _, l, h in reqs]))}
+        log(f"served: {rate:g}/s -> {vu / secs:.4g} vu/s, p50 {np.percentile(lat_ms, 50):.2f} ms, "
+            f"p99 {np.percentile(lat_ms, 99):.2f} ms")
+        if outs1 is None:
+            outs1, reqs1, arr1 = kept, reqs, arr
+    st = eng.get_stats()
+    res["engine_launch"] = {"lanes_per_contour": st["lanes_per_contour"], "pairs_in_flight": st["pairs_in_flight"],
+                            "persistent": st["persistent"], "layout": st["layout"]}
+    eng.close()
+
+    # the plain path serving the first stream's requests one at a time, in arrival order
+    ctx = snk.Context(0, stream)
+    n_plain = int(np.searchsorted(arr1, min(10.0, args.serve_seconds)))   # the stream's first 10 s
+    plat, pvu = [], 0
+    t0 = time.perf_counter()
+    for r in range(n_plain):
+        now = time.perf_counter() - t0
+        if arr1[r] > now:
+            time.sleep(arr1[r] - now)
+        wl, lo, hi = reqs1[r]
+        tile = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous()
+        o = plain_pass(snk, ctx, wl, tile)
+        plat.append(time.perf_counter() - t0 - arr1[r])
+        pvu += int(o["iters"].sum()) * wl.params.n_rays
+    psecs = time.perf_counter() - t0
+    plat = np.asarray(plat) * 1e3
+    res["plain_same_stream"] = {"requests": n_plain, "window_s": float(arr1[n_plain - 1]) if n_plain else 0.0,
+                                "vertex_updates_per_s": pvu / psecs,
+                                "latency_ms": {"p50": float(np.percentile(plat, 50)),
+                                               "p99": float(np.percentile(plat, 99))}}
+    log(f"served: plain path on the same stream {pvu / psecs:.4g} vu/s, p50 {np.percentile(plat, 50):.2f} ms")
+
+    # the plain path back to back (no arrival gaps) on the saturating stream's first requests: the
+    # per-volume launch at full load, to set beside the engine's delivered rate at that load
+    n_sat = min(len(reqs), 500)
+    svu = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(n_sat):
+        wl, lo, hi = reqs[r]
+        tile = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous()
+        o = plain_pass(snk, ctx, wl, tile)
+        svu += int(o["iters"].sum()) * wl.params.n_rays
+    ssecs = time.perf_counter() - t0
+    res["plain_back_to_back"] = {"requests": n_sat, "vertex_updates_per_s": svu / ssecs,
+                                 "ms_per_request": ssecs / n_sat * 1e3}
+    sat = res["streams"][f"{args.rate_hi:g}_per_s"]["vertex_updates_per_s"]
+    res["engine_vs_plain_at_saturation"] = sat / (svu / ssecs)
+    log(f"served: plain path back to back {svu / ssecs:.4g} vu/s; engine at {args.rate_hi:g}/s delivers "
+        f"{res['engine_vs_plain_at_saturation']:.2f}x that")
+
+    # bit-for-bit against the plain path in the engine's launch shape (no LDS boxes in the engine)
+    el = res["engine_launch"]
+    ctx.set_launch(el["lanes_per_contour"], el["pairs_in_flight"], 0)
+    ctx.set_tile(0)
+    bitwise, refs, outs, ovu, osecs = True, [], [], 0, 0.0
+    for r in sorted(outs1):
+        wl, lo, hi = reqs1[r]
+        tile = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous()
+        o = plain_pass(snk, ctx, wl, tile)
+        bitwise &= all(np.array_equal(o[k], outs1[r][k]) for k in KEYS)
+        if not args.no_cpu_baseline:
+            o_st, o_keep, v, sec = oracle_run(wl, tile.cpu().numpy())
+            refs.append((o_st, o_keep))
+            outs.append(outs1[r])
+            ovu += v
+            osecs += sec
     ctx.close()
-    line = {
-        "metric": METRIC, "value": vu / secs, "unit": "vertex-updates/s", "n_gpus": 1, "steps": len(arrivals),
-        "warmup": 4, "ms_per_step": secs / max(len(arrivals), 1) * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "served-poisson-tiles-u16", "hbm_budget_gib": round(budget / 2**30, 1), "rate_per_s": args.rate, "window_s": args.serve_seconds,
-                   "tiles_in_pool": len(pool), "n_iter": pool[0].n_iter, "chunk": args.chunk},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
-                       "max": float(lat_ms.max())},
-        "requests": len(arrivals), "wall_s": secs,
-        "plain_one_at_a_time": {"value": pvu / plain_s, "latency_ms_p50": float(np.median(plat) * 1e3)},
-    }
+    res["parity_vs_plain"] = {"requests": len(outs1), "bitwise": bool(bitwise)}
+    if not args.no_cpu_baseline and refs:
+        res["parity_vs_oracle"] = compare_with_oracle(outs, refs)
+        res["cpu_baseline"] = {"value": ovu / osecs, "unit": "vertex-updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{len(refs)} served tiles, whole runs, {osecs:.1f} s "
+                                                           "(throughput only)"}
+        log(f"served: oracle on {len(refs)} tiles {osecs:.1f} s; parity {res['parity_vs_oracle']}")
+    del vol
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_served(args):
+    res = run_served(args)
+    s0 = res["streams"][f"{args.rate:g}_per_s"]
+    line = {"metric": "contour vertex-updates/s at fixed accuracy; p50/p99 tile latency when served",
+            "value": s0["vertex_updates_per_s"], "unit": "vertex-updates/s", "n_gpus": 1, "steps": s0["requests"],
+            "warmup": 4, "ms_per_step": s0["wall_s"] / max(s0["requests"], 1) * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": res["workload"], "rate_per_s": args.rate, "window_s": args.serve_seconds}}
+    line.update({k: v for k, v in res.items() if k != "workload"})
     print(json.dumps(line), flush=True)
 
 

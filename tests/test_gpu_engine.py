@@ -195,3 +195,54 @@ def test_submit_rejects_non_unit_directions(snk, jobs):
     assert ex.value.code == snk.SNK_EINVAL
     assert eng.get_stats()["submitted"] == 0
     eng.close()
+
+
+def test_served_cut_tiles_alone_mix_and_oracle(snk):
+    """The served workload's requests: tiles (cores of 40..64 voxels plus a 16-voxel halo, clamped at
+    the faces) cut from a volume of the served recipe held on the device. Each cut equals the same box
+    generated on its own; each request's result is identical alone and in a mix where requests arrive
+    while others run; and each meets the free-run bar against the FP64 oracle's run of its tile."""
+    import torch
+
+    from synth.volumes import LargeVolume, tile_workload
+    V = LargeVolume(synth.CONFIG_SEED_BASE + 5, shape_xyz=(320, 320, 160))
+    vol = V.whole("cuda:0")
+    rng = np.random.default_rng(11)
+    reqs = []
+    while len(reqs) < 5:
+        lo, hi, clo, chi, idx = V.tile(rng, 40, 64, 16)
+        if len(idx) == 0:
+            continue
+        tile = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].contiguous()
+        assert torch.equal(tile, V.box(lo, hi, "cuda:0"))
+        reqs.append(tile_workload(V, lo, hi, idx, tile, n_iter=200, seed=synth.CONFIG_SEED_BASE + 5))
+    say("served cut tiles: " + ", ".join(w.name for w in reqs))
+    eng = snk.Engine(0, None, 8 << 30)
+    eng.set_launch(128, 2, 1)
+    alone = []
+    for w in reqs:
+        j = eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter)
+        done = []
+        while j not in done:
+            eng.step(25)
+            done += eng.poll()
+        alone.append(eng.read(j))
+        eng.release(j)
+    # mix: two at once, the others arriving one per step while those run
+    jobs = [eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter) for w in reqs[:2]]
+    for w in reqs[2:]:
+        eng.step(25)
+        jobs.append(eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter))
+    pending, guard = set(jobs), 0
+    while pending and guard < 100:
+        eng.step(25)
+        pending -= set(eng.poll())
+        guard += 1
+    assert not pending
+    for w, j, a in zip(reqs, jobs, alone):
+        mixed = eng.read(j)
+        for k in KEYS:
+            assert np.array_equal(a[k], mixed[k]), (w.name, k)
+        ref = oracle_reference(w.raw.cpu().numpy(), w.params, w.dirs, w.seeds, w.n_iter, ids=w.ids)
+        check_free_run(mixed, ref, w.params, f"served tile {w.name}")
+    eng.close()
