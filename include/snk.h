@@ -221,6 +221,19 @@ snk_status snk_evolve(snk_ctx *ctx, int32_t n_iter);
  * the lower (E_vox, id) surviving -- identical to sequential greedy in ascending order. */
 snk_status snk_finalize(snk_ctx *ctx);
 
+/* snk_finalize for callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. Same kernels, same results as snk_finalize, but
+ * the selection's scratch (grid cells, per-contour items, cells and decisions, counters) lives in a
+ * static device array of the library, about 6 MB, that each GPU the library runs on holds until the
+ * process ends; the call itself calls no hipMalloc, hipFree or allocating library routine. Limits:
+ * at most 131072 contours and 524288 cells of the selection grid (cell edge rho * r_max * 1.01 + 0.01
+ * physical, widened until the grid has at most 4,194,304 cells); beyond them SNK_EINVAL and nothing
+ * is enqueued. The pre-pass must already have run (snk_prepass, snk_evolve or snk_finalize since the
+ * volume or its parameters last changed), else SNK_ESTATE. Every call on one GPU shares that GPU's
+ * array and rewrites it before reading it: calls that overlap on one GPU (two streams, two contexts
+ * or two threads without ordering between them) race and give undefined selections. */
+snk_status snk_finalize_noalloc(snk_ctx *ctx);
+
 /* Unattended workflow (the initial configuration of Sec. II-A / II-B: contours placed on a lattice,
  * neighbours sqrt(1.5) R apart; culling while evolving, the remedy the Conclusion proposes for the
  * work spent on contours that are culled at the end).

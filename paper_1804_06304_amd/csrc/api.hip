@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -70,11 +71,53 @@ struct snk_ctx {
     size_t grid_cap = 0, grid_fill_cap = 0, sel_cap = 0;
 
     unsigned long long *d_counters = nullptr;  // [0] evolved, [1] kept, [2..3] selection round counters
+    unsigned char *scratch = nullptr;  // this device's copy of the static selection scratch (no-alloc finalize)
 
     hipEvent_t ev[6] = {};
     bool ev_pre = false, ev_evo = false, ev_fin = false;
     int64_t evolve_launches = 0;
 };
+
+// Scratch of snk_finalize_noalloc, a static device array so that the call allocates nothing: the
+// selection counters (kept count and the grid-wide round counters), the cell starts and fills of
+// the uniform grid, and the per-contour item, cell and decision arrays. Every device the library
+// runs on holds one copy until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (the array's name is a host-side stand-in).
+namespace {
+constexpr int64_t kNoAllocMaxContours = (int64_t)1 << 17;
+constexpr int64_t kNoAllocMaxCells = (int64_t)1 << 19;
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaCounters = 0;                                                   // 4 x u64
+constexpr size_t kNaCellStart = 256;                                                // cells + 1 ints
+constexpr size_t kNaCellFill = kNaCellStart + align256((kNoAllocMaxCells + 1) * 4); // cells + 1 ints
+constexpr size_t kNaItems = kNaCellFill + align256((kNoAllocMaxCells + 1) * 4);     // contours ints
+constexpr size_t kNaCellOf = kNaItems + align256(kNoAllocMaxContours * 4);
+constexpr size_t kNaDec = kNaCellOf + align256(kNoAllocMaxContours * 4);
+constexpr size_t kNoAllocScratchBytes = kNaDec + align256(kNoAllocMaxContours * 4);
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current), looked up once per device.
+hipError_t scratch_address(int device, unsigned char **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -585,7 +628,9 @@ void centre_of(const snk_ctx *c, const DevContour &s, double *out) {
 }
 
 // Exact energies and the final selection (mode 0), or a culling pass (mode 1) over every contour.
-snk_status run_select(snk_ctx *c, int mode, int grace) {
+// noalloc: the selection scratch and counters come from the device's static scratch array (checked
+// against its limits by the caller) and nothing is allocated.
+snk_status run_select(snk_ctx *c, int mode, int grace, bool noalloc = false) {
     snk_status st = SNK_OK;
     snk::JobDev a{};
     a.p = job_params(c);
@@ -599,6 +644,26 @@ snk_status run_select(snk_ctx *c, int mode, int grace) {
     const int64_t G = snk_grid_for(c->P, c->nx, c->ny, c->nz, G3, &cell);
     for (int i = 0; i < 3; ++i) a.G[i] = G3[i];
     a.cell = (float)cell;
+    a.mode = mode;
+    a.grace = grace;
+    if (noalloc) {
+        if (c->n > kNoAllocMaxContours || G > kNoAllocMaxCells)
+            return fail(c, SNK_EINVAL, "snk_finalize_noalloc: more than its maximum contours or grid cells");
+        unsigned char *base = c->scratch;
+        a.cell_start = reinterpret_cast<int *>(base + kNaCellStart);
+        a.cell_fill = reinterpret_cast<int *>(base + kNaCellFill);
+        a.items = reinterpret_cast<int *>(base + kNaItems);
+        a.cell_of = reinterpret_cast<int *>(base + kNaCellOf);
+        a.dec = reinterpret_cast<int *>(base + kNaDec);
+        unsigned long long *counters = reinterpret_cast<unsigned long long *>(base + kNaCounters);
+        a.kept = counters;
+        // a fill kernel, not a memset node, so the call can also be captured in a graph
+        HIPTRY(c, snk::launch_zero(counters, 4, c->stream));
+        if (mode == 0) HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, true, c->stream));
+        if (mode == 2) HIPTRY(c, snk::launch_mark_maxiter(a.st, a.n, c->stream));
+        HIPTRY(c, snk::launch_select(a, c->P.dim, reinterpret_cast<int *>(counters + 2), c->stream));
+        return SNK_OK;
+    }
     st = ensure(c, &c->d_cell_start, &c->grid_cap, (size_t)G + 1);
     if (st != SNK_OK) return st;
     st = ensure(c, &c->d_cell_fill, &c->grid_fill_cap, (size_t)G + 1);
@@ -621,8 +686,6 @@ snk_status run_select(snk_ctx *c, int mode, int grace) {
     a.dec = c->d_dec;
     a.kept = c->d_counters + 1;
     HIPTRY(c, hipMemsetAsync(c->d_counters + 1, 0, sizeof(unsigned long long), c->stream));
-    a.mode = mode;
-    a.grace = grace;
     // a culling pass ranks by the Monte-Carlo energy the last iteration left in the state
     if (mode == 0) HIPTRY(c, snk::launch_energy_vox(a.p, a.st, a.e_vox, a.n, c->P.dim, true, c->stream));
     if (mode == 2) HIPTRY(c, snk::launch_mark_maxiter(a.st, a.n, c->stream));
@@ -666,6 +729,11 @@ snk_status snk_create(snk_ctx **out, int device, void *hip_stream) {
     if (e != hipSuccess) {
         snk_destroy(c);
         return fail(nullptr, SNK_ENOMEM, "hipMalloc counters");
+    }
+    e = scratch_address(device, &c->scratch);
+    if (e != hipSuccess) {
+        snk_destroy(c);
+        return fail(nullptr, SNK_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
     }
     *out = c;
     return SNK_OK;
@@ -903,6 +971,22 @@ snk_status snk_finalize(snk_ctx *c) {
     HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
     // star contours rank by their last Monte-Carlo energy (no exact star energy is formed)
     st = run_select(c, c->star_lambda >= 0.0 ? 2 : 0, 0);
+    if (st != SNK_OK) return st;
+    HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
+    c->ev_fin = true;
+    return SNK_OK;
+}
+
+snk_status snk_finalize_noalloc(snk_ctx *c) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    snk_status st = need(c, true, false);
+    if (st != SNK_OK) return st;
+    if (c->n == 0) return SNK_OK;
+    if (c->J_dirty) return fail(c, SNK_ESTATE, "snk_finalize_noalloc: the pre-pass has not run (snk_prepass or snk_evolve first)");
+    if (!c->scratch) return fail(c, SNK_ESTATE, "snk_finalize_noalloc: no scratch address for this device");
+    (void)hipSetDevice(c->device);
+    HIPTRY(c, hipEventRecord(c->ev[4], c->stream));
+    st = run_select(c, c->star_lambda >= 0.0 ? 2 : 0, 0, true);
     if (st != SNK_OK) return st;
     HIPTRY(c, hipEventRecord(c->ev[5], c->stream));
     c->ev_fin = true;

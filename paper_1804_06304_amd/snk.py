@@ -25,7 +25,8 @@ TRACE_W = 16
 EXPORTS = [
     "snk_create", "snk_destroy", "snk_set_params", "snk_set_launch", "snk_set_tile", "snk_set_star",
     "snk_get_star_radii", "snk_set_star_radii", "snk_set_directions",
-    "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_read",
+    "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_finalize_noalloc",
+    "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
     "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull",
     "snk_engine_create", "snk_engine_destroy", "snk_engine_last_error", "snk_engine_set_launch",
@@ -92,6 +93,7 @@ def load(path: str = LIB_PATH):
         "snk_seed_lattice": [vp, C.c_double, C.POINTER(i64)],
         "snk_evolve_cull": [vp, i32, i32, i32],
         "snk_finalize": [vp],
+        "snk_finalize_noalloc": [vp],
         "snk_read": [vp, vp, vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64)],
         "snk_get_state": [vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64)],
         "snk_set_state": [vp, vp, vp, vp, vp, vp, i64],
@@ -265,6 +267,10 @@ def snk_evolve_cull(h, n_iter: int, cull_every: int, grace_iters: int) -> None:
 
 def snk_finalize(h) -> None:
     _check(h, load().snk_finalize(h))
+
+
+def snk_finalize_noalloc(h) -> None:
+    _check(h, load().snk_finalize_noalloc(h))
 
 
 def _count(h) -> int:
