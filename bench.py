@@ -273,7 +273,7 @@ def main():
     if args.sweep:
         for layout in (2, 1):
             for g in (16, 32, 64, 128, 256):
-                for u in (1, 2):
+                for u in ((1, 2, 4) if g in (32, 64, 128) else (1, 2)):
                     ctx.set_launch(g, u, layout)
                     ms = []
                     for _ in range(3):
@@ -808,8 +808,24 @@ def run_batched(args, steps, warmup):
     secs = time.perf_counter() - t0
     outs = [eng.read(j) for j in ids]
     st = eng.get_stats()
-    classes = eng.tuned_classes() if hasattr(eng, "tuned_classes") else None
+    classes = eng.tuned_shapes()
     eng.close()
+    # the tuned lanes and pair-points forced with and without the persistent work queue (no LDS box)
+    forced = {}
+    for pers in (0, 1):
+        e2 = snk.Engine(0, stream, 64 << 30)
+        e2.set_launch(st["lanes_per_contour"], st["pairs_in_flight"], pers, 0)
+        for w in jobs:
+            e2.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter)
+        e2.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e2.run()
+        torch.cuda.synchronize()
+        forced["persistent" if pers else "one_workgroup_per_contour"] = (time.perf_counter() - t0) / steps * 1e3
+        e2.close()
+    log(f"batched: forced shapes (ms per pass): {forced}")
     vu = vu_of(outs) * steps
     same = all(np.array_equal(a["iters"], b["iters"]) for a, b in zip(outs, plain_outs))
     drift = max(float(np.max(np.abs(a["radii"] - b["radii"]), initial=0.0)) for a, b in zip(outs, plain_outs))
@@ -822,8 +838,9 @@ def run_batched(args, steps, warmup):
            "plain_loop": {"value": plain_vu / plain_s, "ms": plain_s * 1e3},
            "speedup_vs_plain_loop": (vu / secs) / (plain_vu / plain_s),
            "parity_vs_plain": {"same_iters": bool(same), "max_abs_dR": drift}}
-    if classes is not None:
-        res["tuned_classes"] = classes
+    res["tuned_classes"] = classes
+    res["forced_shapes_ms"] = {"lanes_per_contour": st["lanes_per_contour"], "pairs_in_flight": st["pairs_in_flight"],
+                               "tile_voxels": 0, **forced}
     log(f"batched: engine {secs / steps * 1e3:.1f} ms per pass, {res['value']:.4g} vu/s, "
         f"{res['speedup_vs_plain_loop']:.2f}x the plain loop")
     if not args.no_cpu_baseline:

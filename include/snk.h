@@ -329,6 +329,14 @@ const char *snk_engine_last_error(const snk_engine *e);
 snk_status snk_engine_set_launch(snk_engine *e, int32_t lanes_per_contour, int32_t pairs_in_flight,
                                  int32_t persistent, int32_t layout);
 
+/* Gather tile and residency of the shape forced by snk_engine_set_launch (SNK_ESTATE if none is
+ * forced): each workgroup stages its contour's sample ball in an LDS box of tile_voxels FP32 voxels
+ * (0: none; at most 16384, and the workgroup's LDS must stay within 64 KiB, else SNK_EINVAL at the
+ * next run or step), re-staged when the ball leaves it, as snk_set_tile does for a context; a
+ * persistent launch keeps workgroups_per_cu workgroups per CU (0: as many as registers and LDS
+ * allow). Results are identical with and without a box. The autotuner searches both knobs itself. */
+snk_status snk_engine_set_tile(snk_engine *e, int32_t tile_voxels, int32_t workgroups_per_cu);
+
 /* Queue a job (arguments as in snk_set_params / snk_set_directions / snk_load_volume /
  * snk_load_seeds; host data is copied, a device volume with on_device = 1 is borrowed until the job
  * completes). n_iter is the job's iteration target. SNK_EBUSY if the job alone exceeds the budget. */
@@ -362,6 +370,17 @@ snk_status snk_engine_job_times(snk_engine *e, uint64_t job, double *submit_ms, 
 snk_status snk_engine_release(snk_engine *e, uint64_t job);
 
 snk_status snk_engine_get_stats(snk_engine *e, snk_engine_stats *s);
+
+/* The launch shape the autotuner picked for each launch class so far (rows in class order, a class
+ * being (dim, n_dirs, n_rays, n_radial)), SNK_TUNED_W int32 per row:
+ *   dim, D, M, L, lanes per contour, pair-points in flight, persistent (0: one workgroup per
+ *   contour, 1: a work queue), workgroups per CU of a persistent launch (0: as many as registers and
+ *   LDS allow), LDS box capacity in voxels (0: none), the winning trial's time in microseconds, the
+ *   number of shapes timed.
+ * rows may be NULL (only *n_out, the class count, is written); SNK_ERANGE if cap < the class count.
+ * Classes with a forced shape (snk_engine_set_launch) are not tuned and not listed. */
+#define SNK_TUNED_W 11
+snk_status snk_engine_tuned_shapes(snk_engine *e, int32_t *rows, int64_t cap, int64_t *n_out);
 
 /* Wait for all work enqueued on the context's stream. */
 snk_status snk_sync(snk_ctx *ctx);

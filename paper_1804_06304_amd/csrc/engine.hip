@@ -83,7 +83,11 @@ struct ClassKey {
 
 struct Launch {
     int lanes = 256, unroll = 1, persistent = 1;
-    int grid = 1;   // workgroups of a persistent launch
+    int grid = 1;       // workgroups of a persistent launch
+    int tile = 0;       // LDS box per workgroup, voxels (0: none)
+    int per_cu = 0;     // persistent: workgroups per CU (0: as many as registers and LDS allow)
+    float trial_ms = 0.0f;  // autotuned: time of the winning trial
+    int trials = 0;         // autotuned: shapes timed
 };
 
 constexpr int kMaxClasses = 64;            // launch classes per run (one queue head each)
@@ -480,8 +484,9 @@ snk_status upload_plan(snk_engine *e, const ItemPlan &pl) {
     return SNK_OK;
 }
 
-snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int cls, int chunk) {
+snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int cls, int chunk, int tile) {
     snk::BatchArgs a{};
+    a.tile_cap = tile;
     a.jobs = e->d_jobs;
     a.items = e->d_items + b;
     a.n_items = end - b;
@@ -494,7 +499,8 @@ snk::BatchArgs batch_args(snk_engine *e, const ClassKey &k, int b, int end, int 
 }
 
 int grid_for(snk_engine *e, const ClassKey &k, const Launch &L, int n_items) {
-    const int per_cu = snk::evolve_batch_max_blocks(k.dim, L.lanes, L.unroll, e->layout, k.M);
+    int per_cu = snk::evolve_batch_max_blocks(k.dim, L.lanes, L.unroll, e->layout, k.M, L.tile);
+    if (L.per_cu > 0) per_cu = std::min(per_cu, L.per_cu);
     return std::max(1, std::min(n_items, per_cu * e->cus));
 }
 
@@ -504,9 +510,9 @@ snk_status launch_classes(snk_engine *e, const ItemPlan &pl, int chunk, const st
         const ClassKey &k = pl.classes[c].first;
         const int b = pl.classes[c].second.first, end = pl.classes[c].second.second;
         const Launch &L = shapes[c];
-        if (snk::evolve_lds_bytes(k.dim, L.lanes, k.M, 0) > 65536)
+        if (snk::evolve_lds_bytes(k.dim, L.lanes, k.M, L.tile) > 65536)
             return efail(e, SNK_EINVAL, "n_rays too large for this launch shape's LDS");
-        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk);
+        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, chunk, L.tile);
         EHIP(e, snk::launch_evolve_batch(a, k.dim, L.lanes, L.unroll, e->layout, L.persistent != 0, L.grid,
                                          e->stream));
         e->last_launch = L;
@@ -528,32 +534,49 @@ snk_status shapes_for(snk_engine *e, const ItemPlan &pl, bool allow_trials, std:
         } else if (it != e->tuned.end()) {
             L = it->second;
         } else if (allow_trials) {
-            const int trial_iters = 6;
+            // every candidate evolves the class's items for a few iterations from their initial
+            // state: lanes per contour, pair-points in flight, LDS box capacity (the gather tile),
+            // and one workgroup per item or a persistent work queue with all or half of the
+            // workgroups per CU that registers and LDS allow (contours per CU)
+            const int trial_iters = 10;
             float best_ms = 1e30f;
+            int tried = 0;
             for (int g : {64, 128, 256}) {
-                if (snk::evolve_lds_bytes(k.dim, g, k.M, 0) > 65536) continue;
                 for (int u : {1, 2}) {
-                    for (int pers : {0, 1}) {
-                        Launch T{g, u, pers, 1};
-                        T.grid = grid_for(e, k, T, n_items);
-                        EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs,
-                                                        e->stream));
-                        EHIP(e, snk::launch_zero(reinterpret_cast<unsigned long long *>(e->d_queues), kQueueWords,
-                                                 e->stream));
-                        snk::BatchArgs a = batch_args(e, k, b, end, (int)c, trial_iters);
-                        EHIP(e, hipEventRecord(e->ev0, e->stream));
-                        EHIP(e, snk::launch_evolve_batch(a, k.dim, g, u, e->layout, pers != 0, T.grid, e->stream));
-                        EHIP(e, hipEventRecord(e->ev1, e->stream));
-                        EHIP(e, hipEventSynchronize(e->ev1));
-                        float ms = 0.0f;
-                        EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            L = T;
+                    for (int tile : {0, 2048, 4224, 8192}) {
+                        if (snk::evolve_lds_bytes(k.dim, g, k.M, tile) > 65536) continue;
+                        const int max_cu = snk::evolve_batch_max_blocks(k.dim, g, u, e->layout, k.M, tile);
+                        // -1: one workgroup per item; 0: persistent, all it can hold; else that many
+                        int cands[3] = {-1, 0, 0};
+                        int nc = 2;
+                        if (max_cu >= 2) cands[nc++] = max_cu / 2;
+                        for (int ci = 0; ci < nc; ++ci) {
+                            const int pc = cands[ci];
+                            Launch T{g, u, pc >= 0 ? 1 : 0, 1, tile, pc > 0 ? pc : 0};
+                            T.grid = grid_for(e, k, T, n_items);
+                            EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs,
+                                                            e->stream));
+                            EHIP(e, snk::launch_zero(reinterpret_cast<unsigned long long *>(e->d_queues), kQueueWords,
+                                                     e->stream));
+                            snk::BatchArgs a = batch_args(e, k, b, end, (int)c, trial_iters, tile);
+                            EHIP(e, hipEventRecord(e->ev0, e->stream));
+                            EHIP(e, snk::launch_evolve_batch(a, k.dim, g, u, e->layout, T.persistent != 0, T.grid,
+                                                             e->stream));
+                            EHIP(e, hipEventRecord(e->ev1, e->stream));
+                            EHIP(e, hipEventSynchronize(e->ev1));
+                            float ms = 0.0f;
+                            EHIP(e, hipEventElapsedTime(&ms, e->ev0, e->ev1));
+                            ++tried;
+                            if (ms < best_ms) {
+                                best_ms = ms;
+                                L = T;
+                            }
                         }
                     }
                 }
             }
+            L.trial_ms = best_ms;
+            L.trials = tried;
             EHIP(e, snk::launch_reset_items(e->d_jobs, e->d_items + b, n_items, e->d_init_ptrs, e->stream));
             EHIP(e, hipStreamSynchronize(e->stream));
             unstage(e);
@@ -675,7 +698,18 @@ snk_status snk_engine_set_launch(snk_engine *e, int32_t lanes_per_contour, int32
         (pairs_in_flight != 1 && pairs_in_flight != 2) || (persistent != 0 && persistent != 1))
         return efail(e, SNK_EINVAL, "lanes in {0,64,128,256}, pairs_in_flight in {1,2}, persistent in {0,1}");
     e->force = true;
-    e->forced = Launch{lanes_per_contour, pairs_in_flight, persistent, 1};
+    e->forced = Launch{lanes_per_contour, pairs_in_flight, persistent, 1, 0, 0};
+    drop_graph(e);
+    return SNK_OK;
+}
+
+snk_status snk_engine_set_tile(snk_engine *e, int32_t tile_voxels, int32_t workgroups_per_cu) {
+    if (!e) return SNK_EINVAL;
+    if (!e->force) return efail(e, SNK_ESTATE, "snk_engine_set_tile applies to a shape forced by snk_engine_set_launch");
+    if (tile_voxels < 0 || tile_voxels > 16384 || workgroups_per_cu < 0)
+        return efail(e, SNK_EINVAL, "tile_voxels in 0..16384, workgroups_per_cu >= 0");
+    e->forced.tile = tile_voxels;
+    e->forced.per_cu = workgroups_per_cu;
     drop_graph(e);
     return SNK_OK;
 }
@@ -985,6 +1019,33 @@ snk_status snk_engine_get_stats(snk_engine *e, snk_engine_stats *s) {
     s->persistent = e->last_launch.persistent;
     s->layout = e->layout == snk::kBufferPlain ? 1 : 2;
     s->graph_replays = e->graph_replays;
+    return SNK_OK;
+}
+
+snk_status snk_engine_tuned_shapes(snk_engine *e, int32_t *rows, int64_t cap, int64_t *n_out) {
+    if (!e) return SNK_EINVAL;
+    const int64_t n = (int64_t)e->tuned.size();
+    if (n_out) *n_out = n;
+    if (!rows) return SNK_OK;
+    if (cap < n) return efail(e, SNK_ERANGE, "capacity below the number of tuned classes");
+    int64_t i = 0;
+    for (const auto &kv : e->tuned) {
+        const ClassKey &k = kv.first;
+        const Launch &L = kv.second;
+        int32_t *r = rows + i * SNK_TUNED_W;
+        r[0] = k.dim;
+        r[1] = k.D;
+        r[2] = k.M;
+        r[3] = k.L;
+        r[4] = L.lanes;
+        r[5] = L.unroll;
+        r[6] = L.persistent;
+        r[7] = L.per_cu;
+        r[8] = L.tile;
+        r[9] = (int32_t)lrintf(L.trial_ms * 1000.0f);
+        r[10] = L.trials;
+        ++i;
+    }
     return SNK_OK;
 }
 

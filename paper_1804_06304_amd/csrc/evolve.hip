@@ -275,6 +275,57 @@ __device__ __forceinline__ float wave_max_to_63(float v) {
     return v;
 }
 
+// Adds a value's copies in the two halves of the wave (lane i and lane i ^ 32), then in the two rows
+// of each half (lane i and lane i ^ 16); both partners add the same two operands in the same order.
+__device__ __forceinline__ float cross_row_sum(float x) {
+    auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    const float y = __uint_as_float(h[0]) + __uint_as_float(h[1]);   // x[i mod 32] + x[32 + i mod 32]
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(y), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);            // even row + odd row of the half
+}
+
+// Totals over the 64 lanes of a wave of NR = 4 or 5 per-lane values, in scalar registers. Values 0..3
+// are reduced together: lanes exchange values so that after two quad steps each lane holds the
+// quad's sum of one value, j = 2 (lane & 1) + ((lane >> 1) & 1); the row and cross-row steps then
+// add the copies of that value (the same value sits in lanes i, i + 4, i + 8, ...). A fifth value
+// takes the same row and cross-row steps on its own. The order of every addition is fixed, so the
+// totals do not depend on timing.
+template <int NR>
+__device__ __forceinline__ void wave_sums(const float *v, float *tot) {
+    static_assert(NR == 4 || NR == 5, "four or five sums");
+    const int lane = __lane_id();
+    const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0;
+    // lane pairs (2i, 2i + 1): the even lane keeps values 0 and 1, the odd one 2 and 3
+    const float k0 = b0 ? v[2] : v[0], k1 = b0 ? v[3] : v[1];
+    const float s0 = b0 ? v[0] : v[2], s1 = b0 ? v[1] : v[3];
+    const float w0 = k0 + dpp<0xB1>(s0);   // quad_perm [1, 0, 3, 2]
+    const float w1 = k1 + dpp<0xB1>(s1);
+    // lanes i and i ^ 2: keep w_b1, add the partner's copy of the same value
+    const float keep = b1 ? w1 : w0, send = b1 ? w0 : w1;
+    float x = keep + dpp<0x4E>(send);     // quad_perm [2, 3, 0, 1]
+    float z = 0.0f;
+    if constexpr (NR == 5) {
+        z = v[4] + dpp<0xB1>(v[4]);
+        z = z + dpp<0x4E>(z);
+    }
+    x += dpp<0x128>(x);                   // row_ror:8
+    x += dpp<0x124>(x);                   // row_ror:4
+    if constexpr (NR == 5) {
+        z += dpp<0x128>(z);
+        z += dpp<0x124>(z);
+    }
+    x = cross_row_sum(x);
+    // value j's total sits in lane 0 (j = 0), 2 (j = 1), 1 (j = 2), 3 (j = 3)
+    tot[0] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    tot[1] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 2));
+    tot[2] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 1));
+    tot[3] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 3));
+    if constexpr (NR == 5) {
+        z = cross_row_sum(z);
+        tot[4] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(z)));
+    }
+}
+
 template <int G>
 __device__ __forceinline__ float group_sum_wave(float v) {
     if constexpr (G == 16) {
@@ -975,15 +1026,18 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
 
         // group totals
         float tot[NR];
-        if constexpr (G <= 64) {
+        if constexpr (G < 64) {
 #pragma unroll
             for (int k = 0; k < NR; ++k) tot[k] = group_sum_wave<G>(acc[k]);
+        } else if constexpr (G == 64) {
+            wave_sums<NR>(acc, tot);
         } else {
             float *red = lds_red + (it & 1) * NR * WAVES;
+            float wt[NR];
+            wave_sums<NR>(acc, wt);
+            if (lane == 0) {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                const float v = wave_sum_to_63(acc[k]);
-                if (lane == 63) red[k * WAVES + wave] = v;
+                for (int k = 0; k < NR; ++k) red[k * WAVES + wave] = wt[k];
             }
             __syncthreads();
 #pragma unroll
@@ -1147,11 +1201,13 @@ __host__ __device__ __forceinline__ int lds_floats(int MH) {
 }
 
 // Whole-wave groups with one pair-point in flight fit 64 vector registers: ask for 8 waves per SIMD
-// (a full CU of 4-wave groups holds 8 contours).
+// (a full CU of 4-wave groups holds 8 contours). Two-wave groups with four pair-points in flight
+// ask for 4 waves per SIMD (128 registers), so 8 contours per CU stay resident.
 // STAGE: the workgroup's LDS ends with a box of a.tile_cap voxels. GRADI: centre force in its
 // image-gradient form.
 template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT, bool STAGE, bool GRADI>
-__global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolve_kernel(EvolveArgs a) {
+__global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : ((U == 4 && G == 128) ? 4 : 1))
+void evolve_kernel(EvolveArgs a) {
     extern __shared__ float lds[];
     const int MH = a.p.M / 2;
     const int per = (draw_floats(G, MH) + 3) & ~3;
@@ -1166,8 +1222,9 @@ __global__ __launch_bounds__(Grp<G>::NT, (U == 1 && G >= 64) ? 8 : 1) void evolv
 
 // Batched launch over (job, contour) items, one workgroup (G >= 64 lanes) per item. PERSISTENT: a
 // fixed grid pops items from a device work queue until it is exhausted (every workgroup reaches
-// the exit); otherwise one workgroup per item.
-template <int DIM, int G, int U, int LAYOUT, bool PERSISTENT>
+// the exit); otherwise one workgroup per item. STAGE: the workgroup's LDS ends with a box of
+// a.tile_cap voxels for the contour it is running (restaged for each item).
+template <int DIM, int G, int U, int LAYOUT, bool PERSISTENT, bool STAGE>
 __global__ __launch_bounds__(G, U == 1 ? 8 : 1) void evolve_batch_kernel(BatchArgs a) {
     static_assert(G >= 64, "batched groups span whole waves");
     extern __shared__ float lds[];
@@ -1189,7 +1246,9 @@ __global__ __launch_bounds__(G, U == 1 ? 8 : 1) void evolve_batch_kernel(BatchAr
         const JobParams p = uniform_copy(&a.jobs[job].p);
         DevContour *st = uniform_copy(&a.jobs[job].st);
         const int target = __builtin_amdgcn_readfirstlane(a.jobs[job].target);
-        run_group<DIM, G, U, false, LAYOUT>(p, st + cid, a.chunk, target, nullptr, lds, lds + per, a.counter);
+        run_group<DIM, G, U, false, LAYOUT, false, STAGE>(p, st + cid, a.chunk, target, nullptr, lds, lds + per,
+                                                         a.counter, lds + lds_floats<DIM, G>(a.max_M / 2),
+                                                         STAGE ? a.tile_cap : 0);
         __syncthreads();
     }
 }
@@ -1268,11 +1327,11 @@ hipError_t launch_l(const EvolveArgs &a, int layout, hipStream_t s) {
     }
 }
 
-// Four pair-points in flight: one- and two-wave groups, outside the per-iteration trace (there the
+// Four pair-points in flight: half-wave, one- and two-wave groups, outside the per-iteration trace (there the
 // order of a lane's sums is the same as with two, so the trace runs the two-pair-point instance).
 template <int DIM, int G, bool TRACE>
 hipError_t launch_u(const EvolveArgs &a, int unroll, int layout, hipStream_t s) {
-    if constexpr (!TRACE && (G == 64 || G == 128))
+    if constexpr (!TRACE && (G == 32 || G == 64 || G == 128))
         if (unroll >= 4) return launch_l<DIM, G, 4, TRACE>(a, layout, s);
     return unroll >= 2 ? launch_l<DIM, G, 2, TRACE>(a, layout, s) : launch_l<DIM, G, 1, TRACE>(a, layout, s);
 }
@@ -1288,18 +1347,24 @@ hipError_t launch_g(const EvolveArgs &a, int lanes, int unroll, int layout, hipS
     }
 }
 
-template <int DIM, int G, int U, int LAYOUT, bool PERSISTENT>
+template <int DIM, int G, int U, int LAYOUT, bool PERSISTENT, bool STAGE>
 hipError_t batch_t(const BatchArgs &a, int grid, hipStream_t s) {
-    const size_t lds = sizeof(float) * (size_t)lds_floats<DIM, G>(a.max_M / 2);
+    const size_t lds = sizeof(float) * ((size_t)lds_floats<DIM, G>(a.max_M / 2) + (STAGE ? (size_t)a.tile_cap : 0));
     const int g = PERSISTENT ? grid : a.n_items;
     if (g <= 0) return hipSuccess;
-    hipLaunchKernelGGL((evolve_batch_kernel<DIM, G, U, LAYOUT, PERSISTENT>), dim3(g), dim3(G), lds, s, a);
+    hipLaunchKernelGGL((evolve_batch_kernel<DIM, G, U, LAYOUT, PERSISTENT, STAGE>), dim3(g), dim3(G), lds, s, a);
     return hipGetLastError();
+}
+
+template <int DIM, int G, int U, int LAYOUT, bool PERSISTENT>
+hipError_t batch_s(const BatchArgs &a, int grid, hipStream_t s) {
+    return a.tile_cap > 0 ? batch_t<DIM, G, U, LAYOUT, PERSISTENT, true>(a, grid, s)
+                          : batch_t<DIM, G, U, LAYOUT, PERSISTENT, false>(a, grid, s);
 }
 
 template <int DIM, int G, int U, int LAYOUT>
 hipError_t batch_p(const BatchArgs &a, bool persistent, int grid, hipStream_t s) {
-    return persistent ? batch_t<DIM, G, U, LAYOUT, true>(a, grid, s) : batch_t<DIM, G, U, LAYOUT, false>(a, grid, s);
+    return persistent ? batch_s<DIM, G, U, LAYOUT, true>(a, grid, s) : batch_s<DIM, G, U, LAYOUT, false>(a, grid, s);
 }
 
 template <int DIM, int G, int U>
@@ -1324,31 +1389,37 @@ hipError_t batch_g(const BatchArgs &a, int lanes, int unroll, int layout, bool p
     }
 }
 
-template <int DIM, int G, int U, int LAYOUT>
-int max_blocks_t(int max_M) {
+template <int DIM, int G, int U, int LAYOUT, bool STAGE>
+int max_blocks_t(int max_M, int tile_cap) {
     int blocks = 0;
-    const size_t lds = sizeof(float) * (size_t)lds_floats<DIM, G>(max_M / 2);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, evolve_batch_kernel<DIM, G, U, LAYOUT, true>, G, lds) !=
-        hipSuccess)
+    const size_t lds = sizeof(float) * ((size_t)lds_floats<DIM, G>(max_M / 2) + (STAGE ? (size_t)tile_cap : 0));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, evolve_batch_kernel<DIM, G, U, LAYOUT, true, STAGE>, G,
+                                                     lds) != hipSuccess)
         return 1;
     return blocks > 0 ? blocks : 1;
 }
 
+template <int DIM, int G, int U, int LAYOUT>
+int max_blocks_s(int max_M, int tile_cap) {
+    return tile_cap > 0 ? max_blocks_t<DIM, G, U, LAYOUT, true>(max_M, tile_cap)
+                        : max_blocks_t<DIM, G, U, LAYOUT, false>(max_M, 0);
+}
+
 template <int DIM, int G>
-int max_blocks_u(int unroll, int layout, int max_M) {
+int max_blocks_u(int unroll, int layout, int max_M, int tile_cap) {
     if (unroll >= 2)
-        return layout == kBufferQuad ? max_blocks_t<DIM, G, 2, kBufferQuad>(max_M)
-                                     : max_blocks_t<DIM, G, 2, kBufferPlain>(max_M);
-    return layout == kBufferQuad ? max_blocks_t<DIM, G, 1, kBufferQuad>(max_M)
-                                 : max_blocks_t<DIM, G, 1, kBufferPlain>(max_M);
+        return layout == kBufferQuad ? max_blocks_s<DIM, G, 2, kBufferQuad>(max_M, tile_cap)
+                                     : max_blocks_s<DIM, G, 2, kBufferPlain>(max_M, tile_cap);
+    return layout == kBufferQuad ? max_blocks_s<DIM, G, 1, kBufferQuad>(max_M, tile_cap)
+                                 : max_blocks_s<DIM, G, 1, kBufferPlain>(max_M, tile_cap);
 }
 
 template <int DIM>
-int max_blocks_g(int lanes, int unroll, int layout, int max_M) {
+int max_blocks_g(int lanes, int unroll, int layout, int max_M, int tile_cap) {
     switch (lanes) {
-        case 64: return max_blocks_u<DIM, 64>(unroll, layout, max_M);
-        case 128: return max_blocks_u<DIM, 128>(unroll, layout, max_M);
-        default: return max_blocks_u<DIM, 256>(unroll, layout, max_M);
+        case 64: return max_blocks_u<DIM, 64>(unroll, layout, max_M, tile_cap);
+        case 128: return max_blocks_u<DIM, 128>(unroll, layout, max_M, tile_cap);
+        default: return max_blocks_u<DIM, 256>(unroll, layout, max_M, tile_cap);
     }
 }
 
@@ -1828,8 +1899,9 @@ size_t star_lds_bytes(int dim, int D, int M, int lanes) {
     return sizeof(float) * (size_t)(dim == 2 ? star_lds_floats<2>(D, M, lanes) : star_lds_floats<3>(D, M, lanes));
 }
 
-int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M) {
-    return dim == 2 ? max_blocks_g<2>(lanes, unroll, layout, max_M) : max_blocks_g<3>(lanes, unroll, layout, max_M);
+int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M, int tile_cap) {
+    return dim == 2 ? max_blocks_g<2>(lanes, unroll, layout, max_M, tile_cap)
+                    : max_blocks_g<3>(lanes, unroll, layout, max_M, tile_cap);
 }
 
 namespace {

@@ -118,6 +118,7 @@ struct BatchArgs {
     int chunk;                   // iterations per contour in this launch
     unsigned long long *counter;
     int max_D, max_M;
+    int tile_cap;                // voxels of each workgroup's LDS box (0: corners read from the volumes)
 };
 
 struct PrepassArgs {
@@ -144,9 +145,11 @@ hipError_t launch_pack_quad(const float *J, float4 *Jq, int nx, int ny, int nz, 
 // (whole-wave groups, Monte-Carlo sums) stages each contour's ball in an LDS box of that many voxels.
 hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, int layout, bool trace,
                          hipStream_t s);
+// a.tile_cap > 0: each workgroup stages its contour's ball in an LDS box of that many voxels.
 hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unroll, int layout, bool persistent,
                                int grid, hipStream_t s);
-int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M);
+// Workgroups per CU of a batched launch shape (registers and LDS, including a box of tile_cap voxels).
+int evolve_batch_max_blocks(int dim, int lanes, int unroll, int layout, int max_M, int tile_cap);
 size_t evolve_lds_bytes(int dim, int lanes, int M, int tile_cap);
 // Star-shaped contours (one wave per contour, n_radial 16).
 hipError_t launch_star(const EvolveArgs &a, const StarArgs &sa, int dim, int lanes, int layout, hipStream_t s);

@@ -29,9 +29,9 @@ EXPORTS = [
     "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
     "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull",
-    "snk_engine_create", "snk_engine_destroy", "snk_engine_last_error", "snk_engine_set_launch",
+    "snk_engine_create", "snk_engine_destroy", "snk_engine_last_error", "snk_engine_set_launch", "snk_engine_set_tile",
     "snk_engine_submit", "snk_engine_run", "snk_engine_step", "snk_engine_poll", "snk_engine_read",
-    "snk_engine_job_times", "snk_engine_release", "snk_engine_get_stats",
+    "snk_engine_job_times", "snk_engine_release", "snk_engine_get_stats", "snk_engine_tuned_shapes",
 ]
 
 
@@ -116,6 +116,8 @@ def load(path: str = LIB_PATH):
         "snk_engine_job_times": [vp, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "snk_engine_release": [vp, C.c_uint64],
         "snk_engine_get_stats": [vp, C.POINTER(snk_engine_stats)],
+        "snk_engine_set_tile": [vp, i32, i32],
+        "snk_engine_tuned_shapes": [vp, vp, i64, C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -372,6 +374,10 @@ def snk_engine_set_launch(e, lanes_per_contour: int = 0, pairs_in_flight: int = 
                                             int(layout)))
 
 
+def snk_engine_set_tile(e, tile_voxels: int = 0, workgroups_per_cu: int = 0) -> None:
+    _echeck(e, load().snk_engine_set_tile(e, int(tile_voxels), int(workgroups_per_cu)))
+
+
 def snk_engine_submit(e, params, dirs, vol, centers, r0=None, ids=None, n_iter: int = 100,
                       on_device: bool | None = None) -> int:
     s = params if isinstance(params, snk_params) else to_params(params)
@@ -433,6 +439,20 @@ def snk_engine_job_times(e, job: int):
 
 def snk_engine_release(e, job: int) -> None:
     _echeck(e, load().snk_engine_release(e, int(job)))
+
+
+TUNED_W = 11
+TUNED_FIELDS = ("dim", "n_dirs", "n_rays", "n_radial", "lanes_per_contour", "pairs_in_flight", "persistent",
+                "workgroups_per_cu", "tile_voxels", "trial_us", "trials")
+
+
+def snk_engine_tuned_shapes(e) -> list:
+    """The autotuned launch shape of every class so far, one dict per class."""
+    n = C.c_int64(0)
+    _echeck(e, load().snk_engine_tuned_shapes(e, None, 0, C.byref(n)))
+    rows = np.zeros((max(n.value, 1), TUNED_W), np.int32)
+    _echeck(e, load().snk_engine_tuned_shapes(e, _ptr(rows), n.value, C.byref(n)))
+    return [dict(zip(TUNED_FIELDS, (int(v) for v in r))) for r in rows[: n.value]]
 
 
 def snk_engine_get_stats(e) -> dict:

@@ -93,6 +93,49 @@ def test_autotuned_batched_within_tolerance(snk, jobs):
         ref = plain(snk, w, 256, 2)
         assert np.array_equal(got["iters"], ref["iters"])
         assert np.max(np.abs(got["radii"] - ref["radii"]), initial=0.0) <= 0.05
+    # one tuned shape per launch class (dim, D, M, L), each picked among lanes, pair-points, LDS box
+    # capacities and work-queue residencies
+    classes = {(3, w.params.n_dirs, w.params.n_rays, 16) for w in jobs}
+    shapes = eng.tuned_shapes()
+    say(f"  tuned classes: {shapes}")
+    assert {(r["dim"], r["n_dirs"], r["n_rays"], r["n_radial"]) for r in shapes} == classes
+    for r in shapes:
+        assert r["lanes_per_contour"] in (64, 128, 256) and r["pairs_in_flight"] in (1, 2)
+        assert r["persistent"] in (0, 1) and r["tile_voxels"] in (0, 2048, 4224, 8192)
+        assert r["workgroups_per_cu"] >= 0 and r["trials"] >= 18 and r["trial_us"] > 0
+    eng.close()
+
+
+@pytest.mark.parametrize("shape", [(128, 2, 1, 4224, 2), (256, 1, 0, 2048, 0), (64, 2, 1, 8192, 0)])
+def test_batched_lds_box_and_queue_equal_plain(snk, jobs, shape):
+    """Forced gather tile (LDS box per workgroup) and work-queue residency: the batched run equals the
+    plain path with the same lanes and pair-points bit for bit (a box changes where corners are
+    read, never the arithmetic)."""
+    lanes, unroll, pers, tile, per_cu = shape
+    say(f"engine batched with an LDS box: lanes {lanes}, pair-points {unroll}, persistent {pers}, "
+        f"box {tile}, workgroups per CU {per_cu}")
+    eng = snk.Engine(0, None, 8 << 30)
+    eng.set_launch(lanes, unroll, pers)
+    eng.set_tile(tile, per_cu)
+    ids = [eng.submit(w.params, w.dirs, w.raw, w.seeds, ids=w.ids, n_iter=w.n_iter) for w in jobs]
+    eng.run()
+    for w, j in zip(jobs, ids):
+        got = eng.read(j)
+        ref = plain(snk, w, lanes, unroll)
+        for k in KEYS:
+            assert np.array_equal(got[k], ref[k]), (w.name, k)
+    eng.close()
+
+
+def test_engine_set_tile_errors(snk, jobs):
+    eng = snk.Engine(0, None, 1 << 30)
+    with pytest.raises(snk.SnkError) as ex:
+        eng.set_tile(2048, 0)                    # no forced shape
+    assert ex.value.code == snk.SNK_ESTATE
+    eng.set_launch(128, 1, 1)
+    with pytest.raises(snk.SnkError) as ex:
+        eng.set_tile(20000, 0)
+    assert ex.value.code == snk.SNK_EINVAL
     eng.close()
 
 
