@@ -248,13 +248,25 @@ snk_status snk_seed_lattice(snk_ctx *ctx, double pitch, int64_t *n_out);
  * A pass ranks the live contours (ACTIVE or CONVERGED) by the Monte-Carlo energy of their last
  * iteration (e_mc of snk_read; the exact energy is left to snk_finalize): candidates are the live
  * contours with a finite energy, all of them while fewer than `grace_iters` iterations of this call
- * have run, afterwards those with e_mc <= params.e0 (a contour that stopped early is judged like the
- * others once the grace period is over); overlapping candidates compete as in snk_finalize (the
- * lower (e_mc, id) survives); the losers and the live non-candidates become SNK_CULLED (clamp flag
- * kept) and stop.
+ * have run, afterwards those with e_mc <= the culling threshold (params.e0 unless snk_set_cull
+ * sets another; a contour that stopped early is judged like the others once the grace period is
+ * over); overlapping candidates compete as in snk_finalize (the lower (e_mc, id) survives) unless
+ * snk_set_cull switches the competition off; the losers and the live non-candidates become
+ * SNK_CULLED (clamp flag kept) and stop.
  * n_iter = 0 runs one culling pass. Timing (snk_get_timing): evolve_ms covers the evolve launches
- * and the passes; evolved counts every contour-iteration of the call. */
+ * and the passes; evolved counts every contour-iteration of the call. After each pass the next chunk
+ * launches only the contours still active (their indices compacted on the device; star contours
+ * launch every slot), which changes where contours run, never their results. */
 snk_status snk_evolve_cull(snk_ctx *ctx, int32_t n_iter, int32_t cull_every, int32_t grace_iters);
+
+/* Threshold and competition of the culling passes of snk_evolve_cull (the Conclusion's dynamic
+ * culling leaves both open). After the grace period a pass's candidates are the live contours with
+ * e_mc <= e_cull (NaN, the default: params.e0); a laxer threshold (e.g. e0 / 4) retires only contours
+ * still far from being cells, so the final selection (at e0, by the exact energy) loses none of
+ * the cells it would find without culling. compete = 1 (default): overlapping candidates compete
+ * as in snk_finalize and the losers are retired too; 0: every candidate survives the pass.
+ * SNK_EINVAL for an infinite e_cull or compete outside {0, 1}. */
+snk_status snk_set_cull(snk_ctx *ctx, double e_cull, int32_t compete);
 
 /* Read back (synchronises). Any output pointer may be NULL. radii, e_mc (last Monte-Carlo
  * energy), e_vox (exact energy, valid after snk_finalize), iters, status, keep (1 = detected

@@ -96,6 +96,8 @@ def lib():
         L.orc_lattice_seeds.restype = i64
         L.orc_cull_pass.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, i32]
         L.orc_cull_pass.restype = i64
+        L.orc_cull_pass_t.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, i32, C.c_double, i32]
+        L.orc_cull_pass_t.restype = i64
         _lib = L
     return _lib
 
@@ -467,16 +469,18 @@ def lattice_seeds(p, shape_zyx, pitch=None):
     return out
 
 
-def cull_pass(p, st: State, young: bool) -> int:
+def cull_pass(p, st: State, young: bool, e_cull=None, compete: bool = True) -> int:
     """One culling pass at the current state (in place, ranking by E_mc); young: the run is still in
-    its grace period, so every live contour with a finite energy competes, not only those at or
-    below E0. Returns the number retired."""
+    its grace period, so every live contour with a finite energy is a candidate, otherwise those with
+    E_mc <= e_cull (default E0); compete: overlapping candidates compete. Returns the number
+    retired."""
     ps = params_struct(p)
-    return int(lib().orc_cull_pass(C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.e_mc), _ptr(st.status),
-                                   _ptr(st.ids), int(bool(young))))
+    thr = float(p.e0 if e_cull is None else e_cull)
+    return int(lib().orc_cull_pass_t(C.byref(ps), len(st.R), _ptr(st.c), _ptr(st.R), _ptr(st.e_mc),
+                                     _ptr(st.status), _ptr(st.ids), int(bool(young)), thr, int(bool(compete))))
 
 
-def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int):
+def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int, e_cull=None, compete: bool = True):
     """Evolution in chunks of `every` iterations with a culling pass after each chunk (the pass after
     `done` iterations of the run is young while done < grace); returns the number of
     contour-iterations run."""
@@ -487,7 +491,7 @@ def evolve_cull(J, p, dirs, st: State, n_iter: int, every: int, grace: int):
             _, ran = evolve(J, p, dirs, st, k)
             total += ran
             done += k
-        cull_pass(p, st, done < grace)
+        cull_pass(p, st, done < grace, e_cull, compete)
         if done >= n_iter:
             return total
 

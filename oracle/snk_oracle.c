@@ -1010,12 +1010,13 @@ int64_t orc_lattice_seeds(const orc_params *p, int64_t nx, int64_t ny, int64_t n
  * Monte-Carlo energy of their last iteration (the exact energy stays with the final selection):
  * candidates are the live contours with a finite energy, all of them while the run is young (its
  * grace period, counted in the run's iterations, has not ended), afterwards only those with
- * E_mc <= E0; overlapping candidates compete as in the final selection (sequential greedy in
- * ascending (E_mc, id)) and the losers are retired, as are the live contours that are not
- * candidates. Retired contours keep their state with status CULLED (clamp flag kept). Returns the
- * number retired. */
-int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const double *R, const double *e_mc,
-                      uint8_t *status, const uint32_t *ids, int32_t young)
+ * E_mc <= e_cull (the pass's own threshold: E0, or a laxer value that only retires contours still
+ * far from being cells); with compete set, overlapping candidates compete as in the final selection
+ * (sequential greedy in ascending (E_mc, id)) and the losers are retired; the live contours that are
+ * not candidates are retired too. Retired contours keep their state with status CULLED (clamp flag
+ * kept). Returns the number retired. */
+int64_t orc_cull_pass_t(const orc_params *p, int64_t n, const double *c, const double *R, const double *e_mc,
+                        uint8_t *status, const uint32_t *ids, int32_t young, double e_cull, int32_t compete)
 {
     int dim = p->dim;
     double rho = rho_of(dim);
@@ -1024,7 +1025,7 @@ int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const dou
     for (int64_t i = 0; i < n; ++i) {
         int st = status[i] & 0x0f;
         if (st != ORC_ACTIVE && st != ORC_CONVERGED) continue;
-        if (isfinite(e_mc[i]) && (young || e_mc[i] <= p->e0)) {
+        if (isfinite(e_mc[i]) && (young || e_mc[i] <= e_cull)) {
             keys[nc].e = e_mc[i]; keys[nc].id = ids[i]; keys[nc].idx = i; ++nc;
         } else {
             status[i] = (uint8_t)((status[i] & ORC_CLAMPED) | ORC_CULLED);
@@ -1037,7 +1038,7 @@ int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const dou
     for (int64_t t = 0; t < nc; ++t) {
         int64_t i = keys[t].idx;
         int ok = 1;
-        for (int64_t u = 0; u < na && ok; ++u) {
+        for (int64_t u = 0; u < na && ok && compete; ++u) {
             int64_t j = acc[u];
             double d2 = 0.0;
             for (int a = 0; a < dim; ++a) d2 += (c[i * 3 + a] - c[j * 3 + a]) * (c[i * 3 + a] - c[j * 3 + a]);
@@ -1054,6 +1055,13 @@ int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const dou
     free(acc);
     free(keys);
     return retired;
+}
+
+/* The pass with the final selection's threshold E0 and competition. */
+int64_t orc_cull_pass(const orc_params *p, int64_t n, const double *c, const double *R, const double *e_mc,
+                      uint8_t *status, const uint32_t *ids, int32_t young)
+{
+    return orc_cull_pass_t(p, n, c, R, e_mc, status, ids, young, p->e0, 1);
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -30,6 +30,10 @@ struct snk_ctx {
     int stage_key = -1, stage_blocks = 0;  // registers-limited workgroups per CU of the last staged shape
     int last_lanes = 0, last_unroll = 0, last_layout = 0, last_tile = 0;  // last evolve launch
 
+    // culling passes of snk_evolve_cull: threshold (NaN: params.e0) and competition
+    double cull_thr = NAN;
+    int cull_compete = 1;
+
     // star-shaped contours (lambda < 0: off)
     double star_lambda = -1.0;
     int *d_anti = nullptr;
@@ -72,6 +76,8 @@ struct snk_ctx {
 
     unsigned long long *d_counters = nullptr;  // [0] evolved, [1] kept, [2..3] selection round counters
     unsigned char *scratch = nullptr;  // this device's copy of the static selection scratch (no-alloc finalize)
+    int *d_live = nullptr;             // snk_evolve_cull: indices of the active contours, then their count
+    size_t live_cap = 0;
 
     hipEvent_t ev[6] = {};
     bool ev_pre = false, ev_evo = false, ev_fin = false;
@@ -539,7 +545,9 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
 
 // standalone: zero the contour-iteration counter and record the evolve events around the launch
 // (off for the chunks of snk_evolve_cull, which brackets the whole call).
-snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = true) {
+// idx (device, n_launch entries): evolve only those contours (the shape is still chosen for all n).
+snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = true, const int *idx = nullptr,
+                      int n_launch = -1) {
     if (c->D != c->P.n_dirs) return fail(c, SNK_ESTATE, "direction table size != params.n_dirs");
     if (c->J_dirty) {
         snk_status st = run_prepass(c);
@@ -554,7 +562,8 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     snk::EvolveArgs a{};
     a.p = job_params(c);
     a.st = c->d_st;
-    a.n = (int)c->n;
+    a.n = idx ? n_launch : (int)c->n;
+    a.idx = idx;
     a.n_iter = n_iter;
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
@@ -646,6 +655,8 @@ snk_status run_select(snk_ctx *c, int mode, int grace, bool noalloc = false) {
     a.cell = (float)cell;
     a.mode = mode;
     a.grace = grace;
+    a.e_cull = (float)(std::isnan(c->cull_thr) ? c->P.e0 : c->cull_thr);
+    a.compete = c->cull_compete;
     if (noalloc) {
         if (c->n > kNoAllocMaxContours || G > kNoAllocMaxCells)
             return fail(c, SNK_EINVAL, "snk_finalize_noalloc: more than its maximum contours or grid cells");
@@ -745,7 +756,7 @@ snk_status snk_destroy(snk_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->Jq, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
                     c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters, c->d_anti, c->d_nb,
-                    c->d_Rk};
+                    c->d_Rk, c->d_live};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &ev : c->ev)
@@ -1022,6 +1033,15 @@ snk_status snk_seed_lattice(snk_ctx *c, double pitch, int64_t *n_out) {
     return snk_load_seeds(c, cen.data(), nullptr, nullptr, n);
 }
 
+snk_status snk_set_cull(snk_ctx *c, double e_cull, int32_t compete) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (isinf(e_cull) || (compete != 0 && compete != 1))
+        return fail(c, SNK_EINVAL, "e_cull must be finite (NaN: params.e0) and compete 0 or 1");
+    c->cull_thr = e_cull;
+    c->cull_compete = compete;
+    return SNK_OK;
+}
+
 snk_status snk_evolve_cull(snk_ctx *c, int32_t n_iter, int32_t cull_every, int32_t grace_iters) {
     if (!c) return fail(c, SNK_EINVAL, "NULL context");
     if (n_iter < 0 || grace_iters < 0 || (n_iter > 0 && cull_every <= 0))
@@ -1034,13 +1054,21 @@ snk_status snk_evolve_cull(snk_ctx *c, int32_t n_iter, int32_t cull_every, int32
         st = run_prepass(c);
         if (st != SNK_OK) return st;
     }
+    // after each pass the next chunk launches only the contours still active (sphere contours; star
+    // contours run every slot), so the dwindling population is not spread over slots that only exit
+    const bool compact = c->star_lambda < 0.0;
+    if (compact) {
+        st = ensure(c, &c->d_live, &c->live_cap, (size_t)c->n + 1);
+        if (st != SNK_OK) return st;
+    }
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     int32_t done = 0;
+    int live = -1;   // active contours after the last pass (-1: every contour, before the first)
     do {
         const int32_t k = std::min(cull_every > 0 ? cull_every : 0, n_iter - done);
-        if (k > 0) {
-            st = run_evolve(c, k, false, false);
+        if (k > 0 && live != 0) {
+            st = live < 0 ? run_evolve(c, k, false, false) : run_evolve(c, k, false, false, c->d_live, live);
             if (st != SNK_OK) return st;
         }
         // the grace period counts the iterations of this call: until it ends every live contour
@@ -1048,6 +1076,13 @@ snk_status snk_evolve_cull(snk_ctx *c, int32_t n_iter, int32_t cull_every, int32
         done += k;
         st = run_select(c, 1, done < grace_iters ? INT32_MAX : 0);
         if (st != SNK_OK) return st;
+        if (compact && done < n_iter) {
+            int *count = c->d_live + c->n;
+            HIPTRY(c, hipMemsetAsync(count, 0, sizeof(int), c->stream));
+            HIPTRY(c, snk::launch_compact_active(c->d_st, (int)c->n, c->d_live, count, c->stream));
+            HIPTRY(c, hipMemcpyAsync(&live, count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPTRY(c, hipStreamSynchronize(c->stream));
+        }
     } while (done < n_iter);
     HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
     c->ev_evo = true;

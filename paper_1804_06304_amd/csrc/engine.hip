@@ -354,6 +354,8 @@ snk_status admit(snk_engine *e, EJob &j) {
     d.n = j.n;
     d.target = j.n_iter;
     d.e0 = (float)j.P.e0;
+    d.e_cull = d.e0;
+    d.compete = 1;
     const size_t G1 = (size_t)j.grid_cells + 1;
     d.cell_start = j.d_sel;
     d.cell_fill = j.d_sel + G1;

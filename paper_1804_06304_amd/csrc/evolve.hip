@@ -1212,8 +1212,9 @@ void evolve_kernel(EvolveArgs a) {
     const int MH = a.p.M / 2;
     const int per = (draw_floats(G, MH) + 3) & ~3;
     const int sub = G < 64 ? (int)threadIdx.x / G : 0;
-    const int cid = blockIdx.x * Grp<G>::CPB + sub;
-    DevContour *slot = cid < a.n ? a.st + cid : nullptr;
+    const int k = blockIdx.x * Grp<G>::CPB + sub;
+    const int cid = k < a.n ? (a.idx ? a.idx[k] : k) : k;
+    DevContour *slot = k < a.n ? a.st + cid : nullptr;
     run_group<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE, GRADI>(a.p, slot, a.n_iter, 0x7fffffff,
                                                       TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
                                                       lds + sub * per, lds + Grp<G>::CPB * per, a.counter,

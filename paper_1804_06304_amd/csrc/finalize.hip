@@ -217,8 +217,9 @@ __device__ __forceinline__ void bin_one(const JobDev &a, int i) {
     // of them during the run's grace period (the host passes a grace above every count then, else 0)
     const bool cand = a.mode != 1 ? (st == SNK_CONVERGED || st == SNK_MAXITER) && isfinite(e) && e <= (double)a.e0
                                   : (st == SNK_ACTIVE || st == SNK_CONVERGED) && isfinite(e) &&
-                                        (s.iters < a.grace || e <= (double)a.e0);
-    a.dec[i] = cand ? DEC_UNDECIDED : DEC_NONE;
+                                        (s.iters < a.grace || e <= (double)a.e_cull);
+    // a culling pass without competition keeps every candidate
+    a.dec[i] = cand ? (a.mode == 1 && !a.compete ? DEC_ACCEPT : DEC_UNDECIDED) : DEC_NONE;
     int cell = -1;
     if (cand) {
         int gi[3] = {0, 0, 0};
@@ -430,6 +431,26 @@ __global__ __launch_bounds__(256) void mark_maxiter_kernel(DevContour *st, int n
     if (i < n && (st[i].status & 0x0f) == SNK_ACTIVE) st[i].status = (uint8_t)((st[i].status & SNK_CLAMPED) | SNK_MAXITER);
 }
 }  // namespace
+
+namespace {
+__global__ __launch_bounds__(256) void compact_active_kernel(const DevContour *st, int n, int *idx, int *count) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const bool act = i < n && (st[i].status & 0x0f) == SNK_ACTIVE;
+    // one atomic per wave: the active lanes take consecutive slots in lane order
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(act);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (act) idx[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+}
+}  // namespace
+
+hipError_t launch_compact_active(const DevContour *st, int n, int *idx, int *count, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(compact_active_kernel, dim3((n + 255) / 256), dim3(256), 0, s, st, n, idx, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_mark_maxiter(DevContour *st, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

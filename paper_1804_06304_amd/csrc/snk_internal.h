@@ -91,6 +91,7 @@ struct EvolveArgs {
     float *trace;                // n x SNK_TRACE_W or null
     unsigned long long *counter; // contour-iterations evolved
     int tile_cap;                // voxels of the per-contour LDS box (0: corners read from the volume)
+    const int *idx;              // contour of each launch slot, n of them (null: slot i is contour i)
 };
 
 // One job of a batch, resident in device memory.
@@ -107,7 +108,9 @@ struct JobDev {
     unsigned long long *kept;    // final selection: contours kept; culling pass: contours retired
     int mode;                    // 0: final selection, 1: culling pass during evolution, 2: final
                                  // selection ranked by the last Monte-Carlo energy (star contours)
-    int grace;                   // culling pass: iterations before E_vox > e0 retires a contour
+    int grace;                   // culling pass: iterations before E_mc > e_cull retires a contour
+    float e_cull;                // culling pass: threshold of its candidates (E0 or laxer)
+    int compete;                 // culling pass: overlapping candidates compete (else all survive)
 };
 
 struct BatchArgs {
@@ -170,6 +173,9 @@ hipError_t launch_energy_vox(const JobParams &p, DevContour *st, double *e_vox, 
                              hipStream_t s);
 // Contours still ACTIVE become MAXITER (the end of evolution without the exact energy).
 hipError_t launch_mark_maxiter(DevContour *st, int n, hipStream_t s);
+// Indices of the ACTIVE contours among st[0..n-1] into idx, their number into *count (which must be
+// zero beforehand); the order of the indices is unspecified.
+hipError_t launch_compact_active(const DevContour *st, int n, int *idx, int *count, hipStream_t s);
 // rounds: 3 ints of device scratch for the grid-wide rounds (null: one workgroup does everything).
 hipError_t launch_select(const JobDev &j, int dim, int *rounds, hipStream_t s);
 hipError_t launch_energy_vox_batch(const JobDev *jobs, const int2 *items, int n_items, int dim, hipStream_t s);

@@ -100,16 +100,23 @@ def test_cull_pass_parity(snk, which, n_iter, grace):
     assert not np.any(diff & ~amb), np.where(diff & ~amb)[0][:10]
 
 
-@pytest.mark.parametrize("which,grace", [("tiny", 5), ("tiny", 0), ("plane", 10)])
-def test_cull_pass_dense_lattice(snk, which, grace):
+@pytest.mark.parametrize("which,grace,e_cull,compete", [("tiny", 5, None, True), ("tiny", 0, None, True),
+                                                         ("plane", 10, None, True), ("tiny", 0, 0.25, True),
+                                                         ("tiny", 0, 0.25, False), ("plane", 0, 0.25, False),
+                                                         ("plane", 0, 1.0, False)])
+def test_cull_pass_dense_lattice(snk, which, grace, e_cull, compete):
     """A lattice dense enough for neighbours to overlap (pitch 0.6 R0), 8 iterations on the GPU, then
     one culling pass alone (snk_evolve_cull with no iterations: inside the grace period unless it is
-    0). The oracle's pass on the GPU's own pre-pass state (centres, radii, E_mc, statuses) must
-    retire the same contours: in a dense set one flipped decision would cascade, so the pass is
-    checked on identical inputs here; decisions within rounding of a threshold are excluded."""
+    0), with the final threshold E0 or a laxer culling threshold (e_cull times E0), with or without
+    the competition. The oracle's pass on the GPU's own pre-pass state (centres, radii, E_mc,
+    statuses) must retire the same contours: in a dense set one flipped decision would cascade, so
+    the pass is checked on identical inputs here; decisions within rounding of a threshold are
+    excluded."""
     wl = synth.tiny_config() if which == "tiny" else synth.plane_config(n_target=200, size=320, n_iter=60)
     p = wl.params
+    thr = None if e_cull is None else e_cull * p.e0
     ctx = make_ctx(snk, wl)
+    ctx.set_cull(thr, compete)
     n = ctx.seed_lattice(0.6 * p.r_init)
     ctx.evolve(8)
     pre = ctx.read()
@@ -119,11 +126,12 @@ def test_cull_pass_dense_lattice(snk, which, grace):
     st = oracle.State(c=pre["centers"].astype(np.float64), R=pre["radii"].astype(np.float64),
                       iters=pre["iters"].copy(), status=pre["status"].copy(), streak=np.zeros(n, np.uint8),
                       e_mc=pre["e_mc"].astype(np.float64), ids=np.arange(n, dtype=np.uint32))
-    k = oracle.cull_pass(p, st, grace > 0)
+    k = oracle.cull_pass(p, st, grace > 0, e_cull=thr, compete=compete)
     live = np.isin(pre["status"] & 0x0F, [oracle.ACTIVE, oracle.CONVERGED])
     amb = np.zeros(n, bool)
     li = np.where(live)[0]
-    amb[li] = oracle.cull_ambiguity(p, st.c[li], st.R[li], st.e_mc[li]) != 0
+    pa = p if thr is None else p.replace(e0=thr)   # threshold decisions are flagged at the pass's threshold
+    amb[li] = oracle.cull_ambiguity(pa, st.c[li], st.R[li], st.e_mc[li]) != 0
     diff = got["status"] != st.status
     say(f"dense cull pass {which} grace {grace}: {n} contours, {int(live.sum())} live, oracle retired {k}, "
         f"ambiguous {int(amb.sum())}, differing {int(diff.sum())}")
@@ -150,6 +158,43 @@ def test_cull_free_run(snk):
     assert np.max(np.abs(got["radii"] - st.R)[both]) <= 0.05
     assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[both]) <= 0.5
     assert abs(t["evolved"] - ran) <= 0.05 * ran
+
+
+def test_cull_free_run_lax_threshold(snk):
+    """Culling with a laxer threshold (E0 / 4) and no competition: the free run agrees with the
+    oracle's run under the same rule (statuses, and where they and the counts agree, radii and
+    centres)."""
+    wl = synth.tiny_config()
+    thr = 0.25 * wl.params.e0
+    ctx = make_ctx(snk, wl)
+    ctx.set_cull(thr, False)
+    ctx.seed_lattice()
+    ctx.evolve_cull(wl.n_iter, 20, 40)
+    got = ctx.get_state()
+    t = ctx.get_timing()
+    ctx.close()
+    J = oracle.prepass(wl.raw, wl.params)
+    st = _oracle_lattice_state(wl, J, 0)
+    ran = oracle.evolve_cull(J, wl.params, wl.dirs, st, wl.n_iter, 20, 40, e_cull=thr, compete=False)
+    same = got["status"] == st.status
+    say(f"lax culled free run: {len(st.R)} contours, {int((st.status & 0x0F == oracle.CULLED).sum())} culled "
+        f"(oracle), status agreement {same.mean():.3f}, contour-iterations GPU {t['evolved']} oracle {ran}")
+    assert int((st.status & 0x0F == oracle.CULLED).sum()) > 0
+    assert same.mean() >= 0.95
+    both = same & (got["iters"] == st.iters)
+    assert np.max(np.abs(got["radii"] - st.R)[both]) <= 0.05
+    assert np.max(np.linalg.norm(got["centers"] - st.c, axis=1)[both]) <= 0.5
+    assert abs(t["evolved"] - ran) <= 0.05 * ran
+
+
+def test_set_cull_errors(snk):
+    wl = synth.tiny_config()
+    ctx = make_ctx(snk, wl)
+    with pytest.raises(snk.SnkError) as ex:
+        ctx.set_cull(float("inf"), True)
+    assert ex.value.code == snk.SNK_EINVAL
+    assert snk.load().snk_set_cull(ctx.h, 0.0, 2) == snk.SNK_EINVAL
+    ctx.close()
 
 
 def test_cull_without_losers_equals_plain_evolve(snk):

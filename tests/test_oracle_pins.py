@@ -1006,16 +1006,52 @@ def test_lattice_seeds(orc):
     assert np.all(pts2[:, 2] == 0.0) and len(pts2) == int(29 // np.sqrt(37.5)) * int(39 // np.sqrt(37.5))
 
 
-def _greedy_cull(c, R, e, live, ids, young, e0, dim):
+def _greedy_cull(c, R, e, live, ids, young, e0, dim, compete=True):
     """Brute-force reference of one culling pass: which live contours survive."""
     rho = 2.0 ** (-1.0 / dim)
     cand = [i for i in range(len(R)) if live[i] and np.isfinite(e[i]) and (young or e[i] <= e0)]
     cand.sort(key=lambda i: (e[i], ids[i]))
     acc = []
     for i in cand:
-        if all(np.linalg.norm(c[i, :dim] - c[j, :dim]) >= rho * max(R[i], R[j]) for j in acc):
+        if not compete or all(np.linalg.norm(c[i, :dim] - c[j, :dim]) >= rho * max(R[i], R[j]) for j in acc):
             acc.append(i)
     return set(acc)
+
+
+@pytest.mark.parametrize("seed,young,e_cull,compete", [(4, False, -0.0025, True), (5, False, -0.0025, False),
+                                                      (6, True, -0.0025, False), (7, False, 0.01, False)])
+def test_cull_pass_threshold_and_competition_options(orc, seed, young, e_cull, compete):
+    """The pass's own threshold e_cull replaces E0 for its candidates (a laxer one keeps contours
+    that are not yet cells), and with the competition switched off every candidate survives: the
+    pass retires exactly the live contours the brute force retires, and nothing else."""
+    rng = np.random.default_rng(seed)
+    p = synth.Params(dim=3, dR=1.0, e0=-0.01)
+    n = 150
+    c = np.column_stack([rng.uniform(2, 31, n), rng.uniform(2, 29, n), rng.uniform(2, 17, n)])
+    R = rng.uniform(4.4, 8.0, n)
+    status = rng.choice([orc.ACTIVE, orc.CONVERGED, orc.MAXITER, orc.OUT], size=n, p=[0.5, 0.3, 0.1, 0.1])
+    status = status.astype(np.uint8) | np.where(rng.random(n) < 0.2, orc.CLAMPED, 0).astype(np.uint8)
+    ids = rng.permutation(n).astype(np.uint32)
+    e_mc = rng.uniform(-0.03, 0.02, n)
+    e_mc[::31] = np.nan
+    st = orc.State(c=c.copy(), R=R.copy(), iters=np.zeros(n, np.int32), status=status.copy(),
+                   streak=np.zeros(n, np.uint8), e_mc=e_mc.copy(), ids=ids)
+    k = orc.cull_pass(p, st, young, e_cull=e_cull, compete=compete)
+    live = np.isin(status & 0x0F, [orc.ACTIVE, orc.CONVERGED])
+    keep = _greedy_cull(c, R, e_mc, live, ids, young, e_cull, 3, compete)
+    for i in range(n):
+        if not live[i] or i in keep:
+            assert st.status[i] == status[i]
+        else:
+            assert st.status[i] == (status[i] & orc.CLAMPED) | orc.CULLED
+    assert k == int(live.sum()) - len(keep)
+    # the laxer threshold keeps every live contour between E0 and e_cull that the E0 pass retires
+    if not young and not compete and e_cull > p.e0:
+        between = live & np.isfinite(e_mc) & (e_mc > p.e0) & (e_mc <= e_cull)
+        assert between.sum() > 0 and all(i in keep for i in np.where(between)[0])
+    # without competition and outside the grace period the pass is a pure threshold
+    if not compete and not young:
+        assert keep == set(np.where(live & np.isfinite(e_mc) & (e_mc <= e_cull))[0].tolist())
 
 
 @pytest.mark.parametrize("seed,young", [(0, False), (1, False), (2, True), (3, True)])
