@@ -259,6 +259,20 @@ snk_status snk_seed_lattice(snk_ctx *ctx, double pitch, int64_t *n_out);
  * launch every slot), which changes where contours run, never their results. */
 snk_status snk_evolve_cull(snk_ctx *ctx, int32_t n_iter, int32_t cull_every, int32_t grace_iters);
 
+/* Soft repulsion between neighbouring contours (not in the paper: its contours are independent
+ * while they evolve, Sec. II-D, and compete only afterwards). With kappa > 0, contour i descends its
+ * energy plus kappa * sum_j w(t_ij), t_ij = |c_i - c_j| / (rho (R_i + R_j)), w(t) = (1 - t)^2 for
+ * t < 1 and 0 beyond: the inner spheres (radius rho R, the cell estimates) of overlapping contours
+ * push each other apart and shrink. The neighbours (the live contours, ACTIVE or CONVERGED) are held
+ * at a snapshot taken every `every` iterations (1: every iteration); the gradient joins the energy's
+ * in the step of Eqs. (12)-(15). kappa = 0 (default) is the paper's contour exactly. Applies to
+ * snk_evolve, snk_evolve_cull and snk_trace_step on sphere contours with lanes_per_contour >= 64
+ * (else SNK_EINVAL at the evolve); a contour overlapping more than 64 neighbours makes the evolve
+ * return SNK_ERANGE (its list keeps the 64 lowest indices). Evolving with repulsion synchronises the
+ * context's stream at the end of the call. SNK_EINVAL for a negative or non-finite kappa or
+ * every < 1. */
+snk_status snk_set_repulsion(snk_ctx *ctx, double kappa, int32_t every);
+
 /* Threshold and competition of the culling passes of snk_evolve_cull (the Conclusion's dynamic
  * culling leaves both open). After the grace period a pass's candidates are the live contours with
  * e_mc <= e_cull (NaN, the default: params.e0); a laxer threshold (e.g. e0 / 4) retires only contours

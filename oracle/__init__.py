@@ -98,6 +98,13 @@ def lib():
         L.orc_cull_pass.restype = i64
         L.orc_cull_pass_t.argtypes = [P(_Params), i64, vp, vp, vp, vp, vp, i32, C.c_double, i32]
         L.orc_cull_pass_t.restype = i64
+        L.orc_evolve_repel.argtypes = [vp, i64, i64, i64, P(_Params), vp, i64, vp, vp, vp, vp, vp, vp, vp, i32, i32,
+                                       C.c_double, vp, P(i64)]
+        L.orc_evolve_repel.restype = i64
+        L.orc_repel_energy.argtypes = [P(_Params), i64, vp, vp, vp, i64, vp, C.c_double, C.c_double]
+        L.orc_repel_energy.restype = C.c_double
+        L.orc_repel_grad.argtypes = [P(_Params), i64, vp, vp, vp, i64, vp, C.c_double, C.c_double, vp]
+        L.orc_repel_grad.restype = None
         _lib = L
     return _lib
 
@@ -364,6 +371,52 @@ def evolve(J, p, dirs, st: State, n_iter: int, trace: bool = False, moves: np.nd
     if mism:
         raise AssertionError(f"p,q and c,R gradient forms disagree on {mism} contour-iterations")
     return tr, int(done.value)
+
+
+def evolve_repel(J, p, dirs, st: State, n_iter: int, every: int, kappa: float, trace: bool = False):
+    """evolve() with soft repulsion of strength kappa between neighbouring contours, the neighbours
+    held at a snapshot taken every `every` iterations (not in the paper). Returns (trace or None,
+    contour-iterations run)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    nz, ny, nx = J.shape
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    ps = params_struct(p)
+    n = len(st.R)
+    tr = np.zeros((n, TRACE_W)) if trace else None
+    done = C.c_int64(0)
+    mism = lib().orc_evolve_repel(_ptr(J), nx, ny, nz, C.byref(ps), _ptr(d), n, _ptr(st.ids), _ptr(st.c),
+                                  _ptr(st.R), _ptr(st.iters), _ptr(st.status), _ptr(st.streak), _ptr(st.e_mc),
+                                  int(n_iter), int(every), float(kappa), _ptr(tr) if trace else None,
+                                  C.byref(done))
+    if mism:
+        raise AssertionError(f"p,q and c,R gradient forms disagree on {mism} contour-iterations")
+    return tr, int(done.value)
+
+
+def repel_energy(p, c_s, R_s, live_s, self: int, c, R: float, kappa: float) -> float:
+    """The repulsion penalty of contour `self` at (c, R) against snapshot contours (c_s, R_s, live_s)."""
+    ps = params_struct(p)
+    cs = np.ascontiguousarray(c_s, np.float64)
+    rs = np.ascontiguousarray(R_s, np.float64)
+    ls = np.ascontiguousarray(live_s, np.uint8)
+    cc = np.zeros(3)
+    cc[: len(c)] = c
+    return float(lib().orc_repel_energy(C.byref(ps), len(rs), _ptr(cs), _ptr(rs), _ptr(ls), int(self), _ptr(cc),
+                                        float(R), float(kappa)))
+
+
+def repel_grad(p, c_s, R_s, live_s, self: int, c, R: float, kappa: float):
+    """(dP/dc (3), dP/dR) of that penalty, as the evolution forms it."""
+    ps = params_struct(p)
+    cs = np.ascontiguousarray(c_s, np.float64)
+    rs = np.ascontiguousarray(R_s, np.float64)
+    ls = np.ascontiguousarray(live_s, np.uint8)
+    cc = np.zeros(3)
+    cc[: len(c)] = c
+    out = np.zeros(4)
+    lib().orc_repel_grad(C.byref(ps), len(rs), _ptr(cs), _ptr(rs), _ptr(ls), int(self), _ptr(cc), float(R),
+                         float(kappa), _ptr(out))
+    return out[:3], float(out[3])
 
 
 def stop_ranges(moves: np.ndarray, p, delta: float):

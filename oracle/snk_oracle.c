@@ -580,8 +580,27 @@ static double contour_sums(const orc_vol *vol, const double c[3], double R, uint
 /* ------------------------------------------------------------------------------------------ */
 /* One gradient-descent iteration of one contour (Eqs. (7)-(15)).                               */
 /* ------------------------------------------------------------------------------------------ */
+/* Repulsion from neighbouring contours (not in the paper; the block before orc_evolve_repel):
+ * gradient of the contour's penalty with respect to its centre and radius, and the sums of the
+ * magnitudes of the terms (for tolerances). NULL: no repulsion. */
+typedef struct {
+    double gc[3], gR;
+    double gc_abs[3], gR_abs;
+} orc_repel;
+
+static int step_contour_r(const orc_vol *vol, double c[3], double *R, int32_t *iter, uint8_t *status,
+                          uint8_t *streak, double *e_mc, uint32_t id, double *trace, double *move_out,
+                          const orc_repel *rep);
+
 static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *iter, uint8_t *status,
                         uint8_t *streak, double *e_mc, uint32_t id, double *trace, double *move_out)
+{
+    return step_contour_r(vol, c, R, iter, status, streak, e_mc, id, trace, move_out, NULL);
+}
+
+static int step_contour_r(const orc_vol *vol, double c[3], double *R, int32_t *iter, uint8_t *status,
+                          uint8_t *streak, double *e_mc, uint32_t id, double *trace, double *move_out,
+                          const orc_repel *rep)
 {
     const orc_params *p = vol->p;
     int dim = p->dim;
@@ -602,6 +621,11 @@ static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *ite
     double dR_step = -0.5 * eps * gR;
     double dc[3] = {0, 0, 0};
     for (int i = 0; i < dim; ++i) dc[i] = -0.5 * eps * Bc[i] / twoR_d;
+    /* repulsion: its gradient joins the energy's, with the same step */
+    if (rep) {
+        dR_step += -0.5 * eps * rep->gR;
+        for (int i = 0; i < dim; ++i) dc[i] += -0.5 * eps * rep->gc[i];
+    }
 
     /* p,q form, literally: p = c - R e_x, q = c + R e_x (Eq. (6)), gamma = (q_x - p_x)^-d (Eq. (11)) */
     double pp[3], qq[3];
@@ -615,6 +639,15 @@ static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *ite
     for (int i = 1; i < dim; ++i) {
         dEdp[i] = gamma * scale * sm.Sp[i];
         dEdq[i] = gamma * scale * sm.Sq[i];
+    }
+    if (rep) {
+        /* c = (p + q)/2, R = (q_x - p_x)/2: d/dp = dc/2 - dR/2 e_x, d/dq = dc/2 + dR/2 e_x */
+        for (int i = 0; i < dim; ++i) {
+            dEdp[i] += 0.5 * rep->gc[i];
+            dEdq[i] += 0.5 * rep->gc[i];
+        }
+        dEdp[0] -= 0.5 * rep->gR;
+        dEdq[0] += 0.5 * rep->gR;
     }
     double pn[3], qn[3];
     for (int i = 0; i < 3; ++i) { pn[i] = pp[i] - eps * dEdp[i]; qn[i] = qq[i] - eps * dEdq[i]; }
@@ -640,6 +673,10 @@ static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *ite
         for (int i = 0; i < 3; ++i) {
             trace[14 + i] = dc[i];
             trace[17 + i] = 0.5 * eps * scale * sm.Bcabs[i] / twoR_d;
+        }
+        if (rep) {
+            trace[13] += 0.5 * eps * rep->gR_abs;
+            for (int i = 0; i < dim; ++i) trace[17 + i] += 0.5 * eps * rep->gc_abs[i];
         }
         trace[20] = scale * sm.slBR;
         for (int i = 0; i < 3; ++i) trace[21 + i] = scale * sm.slBc[i];
@@ -684,6 +721,119 @@ static int step_contour(const orc_vol *vol, double c[3], double *R, int32_t *ite
     }
     *status = (uint8_t)(st | flag);
     return mismatch;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Soft repulsion between neighbouring contours (not in the paper: a builder-defined extension;  */
+/* the paper's contours are independent during evolution, Sec. II-D, and compete only after it).  */
+/* Neighbours are held at a snapshot (c_s, R_s) taken at the start of each chunk of iterations.   */
+/* Contour i at (c, R) pays kappa * sum over the live snapshot contours j != i of w(t_ij),          */
+/*   t_ij = |c - c_j| / (rho (R + R_j)),   w(t) = (1 - t)^2 for t < 1, else 0:                   */
+/* its inner sphere (radius rho R, the cell estimate) and each neighbour's overlap exactly when  */
+/* t < 1. With the neighbour fixed, dw/dc = -2 (1 - t) (c - c_j) / (|c - c_j| rho (R + R_j)) and   */
+/* dw/dR = 2 (1 - t) t / (R + R_j); coincident centres give no centre force. The gradient joins the */
+/* energy's in the descent step of Eqs. (12)-(15); kappa = 0 is the paper's contour exactly.      */
+/* ------------------------------------------------------------------------------------------ */
+
+/* The repulsion gradient of contour `self` at (c, R) from snapshot contours j in ascending order. */
+static void repel_grad(const orc_params *p, int64_t n_s, const double *c_s, const double *R_s,
+                       const uint8_t *live_s, int64_t self, const double c[3], double R, double kappa,
+                       orc_repel *out)
+{
+    int dim = p->dim;
+    double rho = rho_of(dim);
+    memset(out, 0, sizeof(*out));
+    for (int64_t j = 0; j < n_s; ++j) {
+        if (j == self || !live_s[j]) continue;
+        double dv[3] = {0, 0, 0}, d2 = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            dv[a] = c[a] - c_s[j * 3 + a];
+            d2 += dv[a] * dv[a];
+        }
+        double d = sqrt(d2), span = rho * (R + R_s[j]);
+        double t = d / span;
+        if (!(t < 1.0)) continue;
+        double gR = kappa * 2.0 * (1.0 - t) * t / (R + R_s[j]);
+        out->gR += gR;
+        out->gR_abs += fabs(gR);
+        if (d > 0.0) {
+            for (int a = 0; a < dim; ++a) {
+                double g = -kappa * 2.0 * (1.0 - t) * dv[a] / (d * span);
+                out->gc[a] += g;
+                out->gc_abs[a] += fabs(g);
+            }
+        }
+    }
+}
+
+/* The penalty kappa * sum_j w(t_ij) of contour `self` at (c, R) (for finite-difference pins). */
+double orc_repel_energy(const orc_params *p, int64_t n_s, const double *c_s, const double *R_s,
+                        const uint8_t *live_s, int64_t self, const double *c, double R, double kappa)
+{
+    int dim = p->dim;
+    double rho = rho_of(dim), e = 0.0;
+    for (int64_t j = 0; j < n_s; ++j) {
+        if (j == self || !live_s[j]) continue;
+        double d2 = 0.0;
+        for (int a = 0; a < dim; ++a) d2 += (c[a] - c_s[j * 3 + a]) * (c[a] - c_s[j * 3 + a]);
+        double t = sqrt(d2) / (rho * (R + R_s[j]));
+        if (t < 1.0) e += kappa * (1.0 - t) * (1.0 - t);
+    }
+    return e;
+}
+
+/* The repulsion gradient at (c, R) as orc_repel_grad computes it: gc[0..2], gR. */
+void orc_repel_grad(const orc_params *p, int64_t n_s, const double *c_s, const double *R_s,
+                    const uint8_t *live_s, int64_t self, const double *c, double R, double kappa, double *out4)
+{
+    orc_repel r;
+    repel_grad(p, n_s, c_s, R_s, live_s, self, c, R, kappa, &r);
+    for (int a = 0; a < 3; ++a) out4[a] = r.gc[a];
+    out4[3] = r.gR;
+}
+
+/* Evolve every ACTIVE contour for up to n_iter further iterations with repulsion of strength kappa:
+ * in chunks of `every` iterations, each starting from a snapshot of the centres, radii and live
+ * flags (ACTIVE or CONVERGED) of all contours; within a chunk each contour steps against that
+ * snapshot. trace as in orc_evolve (its step terms include the repulsion). Returns the number of
+ * contour-iterations whose p,q and c,R forms disagreed (must be 0). */
+int64_t orc_evolve_repel(const double *J, int64_t nx, int64_t ny, int64_t nz, const orc_params *p,
+                         const double *dirs, int64_t n, const uint32_t *ids, double *c, double *R,
+                         int32_t *iters, uint8_t *status, uint8_t *streak, double *e_mc, int32_t n_iter,
+                         int32_t every, double kappa, double *trace, int64_t *evolved)
+{
+    orc_vol vol = {J, nx, ny, nz, p, dirs};
+    int64_t mism = 0, done_all = 0;
+    double *c_s = (double *)malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    double *R_s = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    uint8_t *live_s = (uint8_t *)malloc(n > 0 ? n : 1);
+    if (every < 1) every = 1;
+    for (int32_t done = 0; done < n_iter;) {
+        int32_t k = n_iter - done < every ? n_iter - done : every;
+        for (int64_t i = 0; i < n; ++i) {
+            for (int a = 0; a < 3; ++a) c_s[i * 3 + a] = c[i * 3 + a];
+            R_s[i] = R[i];
+            int st = status[i] & 0x0f;
+            live_s[i] = (uint8_t)(st == ORC_ACTIVE || st == ORC_CONVERGED);
+        }
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : mism, done_all)
+        for (int64_t i = 0; i < n; ++i) {
+            for (int32_t it = 0; it < k; ++it) {
+                if ((status[i] & 0x0f) != ORC_ACTIVE) break;
+                orc_repel rep;
+                repel_grad(p, n, c_s, R_s, live_s, i, &c[i * 3], R[i], kappa, &rep);
+                mism += step_contour_r(&vol, &c[i * 3], &R[i], &iters[i], &status[i], &streak[i], &e_mc[i],
+                                       ids[i], trace ? &trace[i * ORC_TRACE_W] : NULL, NULL, &rep);
+                ++done_all;
+            }
+        }
+        done += k;
+    }
+    free(c_s);
+    free(R_s);
+    free(live_s);
+    if (evolved) *evolved = done_all;
+    return mism;
 }
 
 /* Clamp of the initial radius R0 into [max(r_min, geometric minimum), r_max]. */

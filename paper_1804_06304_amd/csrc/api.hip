@@ -34,6 +34,13 @@ struct snk_ctx {
     double cull_thr = NAN;
     int cull_compete = 1;
 
+    // soft repulsion (kappa 0: off): strength, iterations per neighbour snapshot, buffers
+    double repel_kappa = 0.0;
+    int repel_every = 1;
+    float4 *d_snap = nullptr;
+    int *d_nbgrid = nullptr, *d_nbitems = nullptr, *d_rnb = nullptr;
+    size_t snap_cap = 0, nbgrid_cap = 0, nbitems_cap = 0, rnb_cap = 0;
+
     // star-shaped contours (lambda < 0: off)
     double star_lambda = -1.0;
     int *d_anti = nullptr;
@@ -545,6 +552,46 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
 
 // standalone: zero the contour-iteration counter and record the evolve events around the launch
 // (off for the chunks of snk_evolve_cull, which brackets the whole call).
+constexpr int kNbCap = 64;   // neighbours per contour of the repulsion (one lane each)
+
+// Buffers and grid of the repulsion's neighbour lists for the current contours.
+snk_status neighbour_args(snk_ctx *c, snk::NeighbourArgs &b) {
+    const double rho = rho_of(c->P.dim);
+    double cell = 2.0 * rho * c->P.r_max * 1.01 + 0.01;
+    const int64_t nn[3] = {c->nx, c->ny, c->nz};
+    int64_t total = 1;
+    for (int it = 0; it < 64; ++it) {
+        total = 1;
+        for (int i = 0; i < 3; ++i) {
+            b.G[i] = i < c->P.dim ? (int)(floor((double)(nn[i] - 1) * c->P.spacing[i] / cell) + 1) : 1;
+            total *= b.G[i];
+        }
+        if (total <= ((int64_t)1 << 20)) break;
+        cell *= 1.5;
+    }
+    b.cell = (float)cell;
+    const size_t n = (size_t)c->n;
+    snk_status st = ensure(c, &c->d_snap, &c->snap_cap, 2 * n);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_nbgrid, &c->nbgrid_cap, 2 * (size_t)(total + 1) + 1);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_nbitems, &c->nbitems_cap, 3 * n);
+    if (st != SNK_OK) return st;
+    st = ensure(c, &c->d_rnb, &c->rnb_cap, n * kNbCap);
+    if (st != SNK_OK) return st;
+    b.snap = c->d_snap;
+    b.cell_start = c->d_nbgrid;
+    b.cell_fill = c->d_nbgrid + total + 1;
+    b.overflow = c->d_nbgrid + 2 * (total + 1);
+    b.items = c->d_nbitems;
+    b.cell_of = c->d_nbitems + n;
+    b.nbn = c->d_nbitems + 2 * n;
+    b.nb = c->d_rnb;
+    b.cap = kNbCap;
+    b.status = c->d_st;
+    return SNK_OK;
+}
+
 // idx (device, n_launch entries): evolve only those contours (the shape is still chosen for all n).
 snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = true, const int *idx = nullptr,
                       int n_launch = -1) {
@@ -557,6 +604,7 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     if (lst != SNK_OK) return lst;
     if (c->star_lambda >= 0.0) {
         if (trace) return fail(c, SNK_EINVAL, "snk_trace_step does not cover star contours");
+        if (c->repel_kappa > 0.0) return fail(c, SNK_EINVAL, "repulsion applies to sphere contours");
         return run_star(c, n_iter, standalone);
     }
     snk::EvolveArgs a{};
@@ -592,6 +640,18 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
             unroll = 2;
         }
     }
+    const bool repel = c->repel_kappa > 0.0;
+    snk::NeighbourArgs nbargs{};
+    if (repel) {
+        if (lanes < 64) return fail(c, SNK_EINVAL, "repulsion needs lanes_per_contour >= 64");
+        snk_status rs = neighbour_args(c, nbargs);
+        if (rs != SNK_OK) return rs;
+        a.snap = nbargs.snap;
+        a.nb = nbargs.nb;
+        a.nbn = nbargs.nbn;
+        a.nb_cap = kNbCap;
+        a.kappa = (float)c->repel_kappa;
+    }
     if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M, 0) > 65536)
         return fail(c, SNK_EINVAL, "n_rays too large for the evolve kernel's LDS (64 KiB per workgroup)");
     if (snk::evolve_lds_bytes(c->P.dim, lanes, a.p.M, a.tile_cap) > 65536)
@@ -604,11 +664,24 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     // the contours still active, spread over every CU, instead of leaving them on the CUs the
     // first launch gave them (the results are identical: every draw depends on the contour's id
     // and iteration only).
-    const int parts = (!trace && n_iter >= 64) ? 2 : 1;
-    for (int part = 0, done = 0; part < parts; ++part) {
-        a.n_iter = (int)((int64_t)n_iter * (part + 1) / parts) - done;
-        done += a.n_iter;
-        HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
+    int parts = (!trace && n_iter >= 64) ? 2 : 1;
+    if (repel) {
+        // the neighbours' snapshot and lists are rebuilt before every chunk of repel_every iterations
+        parts = 0;
+        const float rho = (float)rho_of(c->P.dim);
+        for (int done = 0; done < n_iter; ++parts) {
+            a.n_iter = std::min(c->repel_every, n_iter - done);
+            done += a.n_iter;
+            HIPTRY(c, snk::launch_neighbours(c->d_st, (int)c->n, geometry(c), c->P.dim, rho, nbargs, c->stream));
+            HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
+        }
+        parts = std::max(parts, 1);
+    } else {
+        for (int part = 0, done = 0; part < parts; ++part) {
+            a.n_iter = (int)((int64_t)n_iter * (part + 1) / parts) - done;
+            done += a.n_iter;
+            HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
+        }
     }
     c->evolve_launches += parts - 1;
     c->last_lanes = lanes;
@@ -620,6 +693,13 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
         c->ev_evo = true;
     }
     c->evolve_launches += 1;
+    if (repel && n_iter > 0) {
+        int over = 0;
+        HIPTRY(c, hipMemcpyAsync(&over, nbargs.overflow, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPTRY(c, hipStreamSynchronize(c->stream));
+        if (over)
+            return fail(c, SNK_ERANGE, "a contour overlapped more than 64 neighbours (repulsion lists truncated)");
+    }
     return SNK_OK;
 }
 
@@ -756,7 +836,7 @@ snk_status snk_destroy(snk_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     void *bufs[] = {c->d_dirs, c->raw_owned, c->J, c->Jq, c->d_st, c->d_evox, c->d_trace, c->d_cell_start,
                     c->d_cell_fill, c->d_items, c->d_cell_of, c->d_dec, c->d_counters, c->d_anti, c->d_nb,
-                    c->d_Rk, c->d_live};
+                    c->d_Rk, c->d_live, c->d_snap, c->d_nbgrid, c->d_nbitems, c->d_rnb};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &ev : c->ev)
@@ -1031,6 +1111,15 @@ snk_status snk_seed_lattice(snk_ctx *c, double pitch, int64_t *n_out) {
             }
     if (n_out) *n_out = n;
     return snk_load_seeds(c, cen.data(), nullptr, nullptr, n);
+}
+
+snk_status snk_set_repulsion(snk_ctx *c, double kappa, int32_t every) {
+    if (!c) return fail(c, SNK_EINVAL, "NULL context");
+    if (!(kappa >= 0.0) || !isfinite(kappa) || every < 1)
+        return fail(c, SNK_EINVAL, "kappa must be finite and >= 0, every >= 1");
+    c->repel_kappa = kappa;
+    c->repel_every = every;
+    return SNK_OK;
 }
 
 snk_status snk_set_cull(snk_ctx *c, double e_cull, int32_t compete) {

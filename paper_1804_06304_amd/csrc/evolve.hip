@@ -884,10 +884,19 @@ __device__ __forceinline__ int uni(int v) {
 // and its barriers are workgroup-uniform.
 // STAGE (whole-wave groups): iterations whose ball fits a box of tile_cap voxels read their corners
 // from an LDS box at lds_tile, the others from the volume in LAYOUT.
+// Soft repulsion of one contour (kappa > 0): the snapshot of every contour and this contour's
+// neighbour list (cnt indices, ascending).
+struct Repel {
+    const float4 *snap = nullptr;
+    const int *nb = nullptr;
+    int cnt = 0;
+    float kappa = 0.0f;
+};
+
 template <int DIM, int G, int U, bool TRACE, int LAYOUT, bool EXACT = false, bool STAGE = false, bool GRADI = false>
 __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int target, float *trace_row,
                           float *lds_draws, float *lds_red, unsigned long long *counter, float *lds_tile = nullptr,
-                          int tile_cap = 0) {
+                          int tile_cap = 0, const Repel rp = Repel{}) {
     static_assert(!STAGE || (G >= 64 && !EXACT), "LDS boxes are staged by whole-wave Monte-Carlo groups");
     constexpr int NR = 2 + DIM;
     constexpr int WAVES = Grp<G>::WAVES;
@@ -1061,6 +1070,9 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
         // descent step, identical in every lane of the group (multi-wave groups: wave 0 only, the
         // others take the new state from LDS below)
         if (active && (G <= 64 || wave == 0)) {
+            // no multiply-add contraction in the step: every instance (with or without the optional
+            // terms below) rounds it operation by operation, so their results agree bit for bit
+#pragma clang fp contract(off)
             n += 1;
             const float smax = fr.smax;
             float smax_d = smax;
@@ -1078,7 +1090,7 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             const float gR = (BR - (2.0f * DIM) * inv2R * A) * inv_norm;
             const float eps = p.eps0 * __builtin_amdgcn_rsqf((float)n);
             const float half_eps = 0.5f * eps;
-            const float dRs = -half_eps * gR;
+            float dRs = -half_eps * gR;
             const float kc = -half_eps * scale * inv_norm;
             float doff[3] = {0.0f, 0.0f, 0.0f}, dc[3] = {0.0f, 0.0f, 0.0f};
             float dc2 = 0.0f;
@@ -1086,8 +1098,51 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             for (int i = 0; i < DIM; ++i) {
                 doff[i] = kc * tot[2 + i];   // voxel units (B_c was accumulated against u / h)
                 dc[i] = doff[i] * hh[i];
-                dc2 = fmaf(dc[i], dc[i], dc2);
             }
+            if constexpr (G >= 64) {
+                if (rp.kappa > 0.0f) {
+                    // repulsion of the neighbours' snapshot: lane k takes neighbour k; with t = |c - c_j| /
+                    // (rho (R + R_j)) < 1 the penalty (1 - t)^2 has dP/dc = -2 (1 - t) (c - c_j) /
+                    // (|c - c_j| rho (R + R_j)) and dP/dR = 2 (1 - t) t / (R + R_j)
+                    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (lane < rp.cnt) {
+                        const int j = rp.nb[lane];
+                        const float4 s0 = rp.snap[2 * j], s1 = rp.snap[2 * j + 1];
+                        const int aj[3] = {__float_as_int(s0.x), __float_as_int(s0.y), __float_as_int(s0.z)};
+                        const float oj[3] = {s1.x, s1.y, s1.z};
+                        float dv[3] = {0.0f, 0.0f, 0.0f}, d2 = 0.0f;
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) {
+                            dv[a] = ((float)(anc[a] - aj[a]) + (off[a] - oj[a])) * hh[a];
+                            d2 = fmaf(dv[a], dv[a], d2);
+                        }
+                        const float d = __builtin_amdgcn_sqrtf(d2);
+                        const float span = RHO * (R + s0.w);
+                        const float t = d / span;
+                        if (t < 1.0f) {
+                            const float om = 1.0f - t;
+                            v[3] = 2.0f * om * t / (R + s0.w);
+                            if (d > 0.0f) {
+                                const float f = -2.0f * om / (d * span);
+#pragma unroll
+                                for (int a = 0; a < DIM; ++a) v[a] = f * dv[a];
+                            }
+                        }
+                    }
+                    float rt[4];
+                    wave_sums<4>(v, rt);
+                    const float kr = -half_eps * rp.kappa;
+                    dRs = dRs + kr * rt[3];
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) {
+                        const float dcr = kr * rt[i];
+                        dc[i] = dc[i] + dcr;
+                        doff[i] = doff[i] + dcr * inv_h[i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) dc2 = fmaf(dc[i], dc[i], dc2);
             if (TRACE && gl == 0) {
                 float *row = trace_row;
                 row[0] = A;
@@ -1215,10 +1270,17 @@ void evolve_kernel(EvolveArgs a) {
     const int k = blockIdx.x * Grp<G>::CPB + sub;
     const int cid = k < a.n ? (a.idx ? a.idx[k] : k) : k;
     DevContour *slot = k < a.n ? a.st + cid : nullptr;
+    Repel rp;
+    if (G >= 64 && a.kappa > 0.0f && slot) {
+        rp.snap = a.snap;
+        rp.nb = a.nb + (long)cid * a.nb_cap;
+        rp.cnt = __builtin_amdgcn_readfirstlane(a.nbn[cid]);
+        rp.kappa = a.kappa;
+    }
     run_group<DIM, G, U, TRACE, LAYOUT, EXACT, STAGE, GRADI>(a.p, slot, a.n_iter, 0x7fffffff,
                                                       TRACE && slot ? a.trace + (long)cid * SNK_TRACE_W : nullptr,
                                                       lds + sub * per, lds + Grp<G>::CPB * per, a.counter,
-                                                      lds + lds_floats<DIM, G>(MH), STAGE ? a.tile_cap : 0);
+                                                      lds + lds_floats<DIM, G>(MH), STAGE ? a.tile_cap : 0, rp);
 }
 
 // Batched launch over (job, contour) items, one workgroup (G >= 64 lanes) per item. PERSISTENT: a

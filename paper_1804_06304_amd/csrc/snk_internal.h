@@ -92,7 +92,27 @@ struct EvolveArgs {
     unsigned long long *counter; // contour-iterations evolved
     int tile_cap;                // voxels of the per-contour LDS box (0: corners read from the volume)
     const int *idx;              // contour of each launch slot, n of them (null: slot i is contour i)
+    // soft repulsion (kappa > 0): snapshot of every contour, each contour's neighbour list
+    const float4 *snap;          // 2 per contour: (anchor bits x3, R), (offset x3, live)
+    const int *nb, *nbn;         // nb_cap neighbour indices per contour (ascending), their counts
+    int nb_cap;
+    float kappa;
 };
+
+// Neighbour lists of the soft repulsion (neighbours.hip): a grid of cell >= 2 rho r_max over the live
+// contours, then per ACTIVE contour the live contours whose inner sphere overlaps its own.
+struct NeighbourArgs {
+    float4 *snap;
+    int *cell_start, *cell_fill, *items, *cell_of;   // grid: G + 1, G, n, n
+    int *nb, *nbn;               // n x cap, n
+    int *overflow;               // set when a contour has more than cap neighbours
+    int cap;
+    int G[3];
+    float cell;
+    const DevContour *status;
+};
+hipError_t launch_neighbours(const DevContour *st, int n, const Geometry &g, int dim, float rho,
+                             const NeighbourArgs &b, hipStream_t s);
 
 // One job of a batch, resident in device memory.
 struct JobDev {

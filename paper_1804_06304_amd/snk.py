@@ -28,7 +28,7 @@ EXPORTS = [
     "snk_load_volume", "snk_prepass", "snk_load_seeds", "snk_evolve", "snk_finalize", "snk_finalize_noalloc",
     "snk_read",
     "snk_get_state", "snk_set_state", "snk_trace_step", "snk_read_volume", "snk_get_timing",
-    "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull", "snk_set_cull",
+    "snk_sync", "snk_last_error", "snk_version", "snk_seed_lattice", "snk_evolve_cull", "snk_set_cull", "snk_set_repulsion",
     "snk_engine_create", "snk_engine_destroy", "snk_engine_last_error", "snk_engine_set_launch", "snk_engine_set_tile",
     "snk_engine_submit", "snk_engine_run", "snk_engine_step", "snk_engine_poll", "snk_engine_read",
     "snk_engine_job_times", "snk_engine_release", "snk_engine_get_stats", "snk_engine_tuned_shapes",
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
         "snk_seed_lattice": [vp, C.c_double, C.POINTER(i64)],
         "snk_evolve_cull": [vp, i32, i32, i32],
         "snk_set_cull": [vp, C.c_double, i32],
+        "snk_set_repulsion": [vp, C.c_double, i32],
         "snk_finalize": [vp],
         "snk_finalize_noalloc": [vp],
         "snk_read": [vp, vp, vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64)],
@@ -271,6 +272,11 @@ def snk_evolve_cull(h, n_iter: int, cull_every: int, grace_iters: int) -> None:
 def snk_set_cull(h, e_cull=None, compete: bool = True) -> None:
     """Culling passes' threshold (None: params.e0) and competition."""
     _check(h, load().snk_set_cull(h, float("nan") if e_cull is None else float(e_cull), int(bool(compete))))
+
+
+def snk_set_repulsion(h, kappa: float = 0.0, every: int = 1) -> None:
+    """Soft repulsion between neighbouring contours (0: off), neighbours refreshed every `every` iterations."""
+    _check(h, load().snk_set_repulsion(h, float(kappa), int(every)))
 
 
 def snk_finalize(h) -> None:
