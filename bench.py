@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per contour: 16..256 (0: automatic)")
     ap.add_argument("--unroll", type=int, default=0, help="pair-points in flight per lane (0: automatic)")
-    ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad")
+    ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad, 3 plain with 64-bit addressing, 4 column pairs (2D)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="LDS box per contour in voxels (-1: automatic, 0: off)")
     ap.add_argument("--exact", action="store_true",
@@ -169,7 +169,7 @@ def main():
                          "that every capacity reproduces the box-free result bit for bit")
     ap.add_argument("--smooth", type=float, default=0.3, help="star: smoothing weight of the star contours")
     ap.add_argument("--workload", default="slab",
-                    choices=["slab", "plane", "batched", "served", "lattice", "gradient", "star"],
+                    choices=["slab", "plane", "batched", "served", "lattice", "gradient", "star", "repel"],
                     help="slab: the plain path on the slab volume (default); plane: the plain path on the "
                          "8192^2 2D image; batched: 256 uneven subvolumes through the engine vs the plain "
                          "per-volume loop; served: Poisson tile requests; lattice: the slab volume seeded with "
@@ -178,7 +178,9 @@ def main():
                          "form (flags bit 2): variance of one iteration's force at fixed states, and "
                          "accuracy and time of free runs with 64, 32 and 16 rays; star: the slab with "
                          "star-shaped contours (per-direction radii) against the sphere: time and fit to the "
-                         "generator's ellipsoids")
+                         "generator's ellipsoids; repel: the slab with two seeds per nucleus and the slab "
+                         "lattice, evolved with soft repulsion between neighbours at several strengths: time, "
+                         "separation of the seed pairs, recall and precision")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="served: arrival window (s)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: mean arrivals per second")
     ap.add_argument("--rate-hi", type=float, default=2000.0,
@@ -197,6 +199,8 @@ def main():
                     help="lattice: iterations before the culling threshold retires a contour")
     ap.add_argument("--e-cull-factor", type=float, default=0.25,
                     help="lattice: culling threshold of the lax rules as a multiple of E0")
+    ap.add_argument("--repel-every", type=int, default=5,
+                    help="repel: iterations between refreshes of the neighbours' snapshot")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -232,6 +236,8 @@ def main():
         return bench_gradient(args)
     if args.workload == "star":
         return bench_star(args)
+    if args.workload == "repel":
+        return bench_repel(args)
     t0 = time.perf_counter()
     wl = synth.slab_config() if args.workload == "slab" else synth.plane_config()
     if args.exact:
@@ -337,11 +343,11 @@ def main():
                    "contours": len(wl.seeds),
                    "n_iter": wl.n_iter, "n_dirs": p.n_dirs, "n_rays": M, "n_radial": L,
                    "lanes_per_contour": args.lanes or "auto", "pairs_in_flight": args.unroll or "auto",
-                   "layout": {0: "auto", 1: "plain", 2: "quad"}[args.layout],
+                   "layout": {0: "auto", 1: "plain", 2: "quad", 3: "plain64", 4: "pairs"}[args.layout],
                    "tile_voxels": "auto" if args.tile < 0 else args.tile,
                    "resolved_launch": {"lanes_per_contour": tm["lanes_per_contour"],
                                        "pairs_in_flight": tm["pairs_in_flight"],
-                                       "layout": {0: "plain64", 1: "plain", 2: "quad"}[tm["layout"]],
+                                       "layout": {0: "plain64", 1: "plain", 2: "quad", 3: "pairs"}[tm["layout"]],
                                        "tile_voxels": tm["tile_voxels"]}},
         "kernels_ms": {"prepass": float(np.mean(prepass_ms)), "evolve": ev_ms,
                        "finalize": float(np.mean(finalize_ms))},
@@ -497,6 +503,79 @@ def bench_star(args):
             "unit": "relative radial error", "value": rows[1]["median_fit_error"], "n_gpus": 1,
             "data": "synthetic", "config": {"workload": wl.name, "n_dirs": p.n_dirs, "n_rays": p.n_rays,
                                             "n_iter": wl.n_iter},
+            "runs": rows}
+    print(json.dumps(line), flush=True)
+
+
+def bench_repel(args):
+    """Soft repulsion between neighbouring contours (snk_set_repulsion) on the slab volume, 500
+    iterations, exact energy and selection, at kappa = 0 (the paper's contour) and two strengths.
+    Two seed sets: every nucleus seeded twice (the slab's seeds and a copy displaced by up to 1.5
+    voxels along each axis, distinct ids), and the initial lattice (pitch sqrt(1.5) R0, whose
+    neighbours' inner spheres overlap from the start). Reports evolve time and contour-iterations/s,
+    the median final distance between the two copies of a seed, detections, and recall / precision
+    against the generator's nuclei (a kept centre within 4 voxels of a nucleus centre, one to one)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1804_06304_amd import snk
+
+    wl = synth.slab_config()
+    p = wl.params
+    raw = torch.from_numpy(wl.raw).to("cuda:0")
+    truth = wl.truth["centers"]
+    rng = np.random.default_rng(synth.CONFIG_SEED_BASE + 7)
+    n0 = len(wl.seeds)
+    shift = rng.uniform(-1.5, 1.5, size=wl.seeds.shape) * np.asarray(p.spacing)[None, :]
+    doubled = np.concatenate([wl.seeds, wl.seeds + shift])
+    ids = np.concatenate([wl.ids, wl.ids + np.uint32(1 << 20)]).astype(np.uint32)
+    ctx = snk.Context(0, torch.cuda.current_stream())
+    ctx.set_params(p)
+    ctx.set_directions(wl.dirs)
+    ctx.load_volume(raw)
+    rows = []
+    for seeding in ("doubled", "lattice"):
+        for kappa in (0.0, 0.02, 0.1):
+            ctx.set_repulsion(kappa, args.repel_every)
+            ms = []
+            try:
+                for _ in range(args.warmup + max(1, args.steps)):
+                    if seeding == "doubled":
+                        ctx.load_seeds(doubled, ids=ids)
+                        n = len(doubled)
+                    else:
+                        n = ctx.seed_lattice()
+                    ctx.evolve(wl.n_iter)
+                    ms.append(ctx.get_timing()["evolve_ms"])
+            except snk.SnkError as e:
+                # a neighbour list over its cap (SNK_ERANGE) ends this run, not the bench
+                rows.append({"seeding": seeding, "kappa": kappa, "error": str(e)})
+                log(f"repel {seeding} kappa {kappa}: {e}")
+                continue
+            evolved = ctx.get_timing()["evolved"]
+            ctx.finalize()
+            out = ctx.read()
+            kept = out["centers"][out["keep"] == 1]
+            m = match_truth(kept, truth, 4.0)
+            ev = float(np.mean(ms[args.warmup:]))
+            row = {"seeding": seeding, "kappa": kappa, "every": args.repel_every if kappa > 0 else None,
+                   "contours": int(n), "evolve_ms": ev, "contour_iterations_per_s": evolved / (ev * 1e-3),
+                   "kept": int(len(kept)), "recall": m / len(truth), "precision": m / max(1, len(kept))}
+            if seeding == "doubled":
+                c = out["centers"]
+                row["median_pair_distance"] = float(np.median(np.linalg.norm(c[:n0] - c[n0:], axis=1)))
+            rows.append(row)
+            log(f"repel {row}")
+    ctx.close()
+    base = next(r for r in rows if r["seeding"] == "doubled" and r["kappa"] == 0.0)
+    strong = next(r for r in rows if r["seeding"] == "doubled" and r["kappa"] == 0.1)
+    line = {"metric": "soft repulsion on the slab: time, seed-pair separation, recall and precision",
+            "unit": "evolve time ratio (kappa 0.1 / kappa 0, doubled seeds)",
+            "value": strong["evolve_ms"] / base["evolve_ms"] if "evolve_ms" in strong else None, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "n_iter": wl.n_iter, "every": args.repel_every,
+                       "nuclei": int(len(truth))},
             "runs": rows}
     print(json.dumps(line), flush=True)
 

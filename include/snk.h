@@ -134,10 +134,14 @@ snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
  * contours share one wave64; 64: one wave; 128 or 256: a workgroup of 2 or 4 waves), antithetic
  * pair-points whose gathers one lane issues before consuming them (0 = automatic, 1, 2 or 4; 4 is
  * taken with 64 or 128 lanes and outside snk_trace_step, otherwise it runs as 2), and the
- * layout the kernel reads the smoothed volume from (0 = automatic: quad when it fits, 1 = plain FP32,
+ * layout the kernel reads the smoothed volume from (0 = automatic: quad in 3D and column pairs in 2D
+ * when they fit, else plain; 1 = plain FP32,
  * 2 = quad: one 16-byte record per voxel with its +x, +y, +xy neighbours, 4x the FP32 volume; needs
  * 16 * nx*ny*nz below 2 GiB and ny, nz <= 65535, else SNK_EINVAL at the next evolve; 3 = plain FP32
- * with 64-bit addressing, the path of volumes beyond 2 GiB). Layouts change only how voxels are
+ * with 64-bit addressing, the path of volumes beyond 2 GiB; 4 = column pairs, 2D only: (J(x,y),
+ * J(x,y+1)) per pixel, twice the FP32 image, so one 16-byte load fetches a cell's four corners; needs
+ * 8 * nx*ny below 2 GiB and ny <= 65535, else SNK_EINVAL at the next evolve; the exact and
+ * gradient-form sums read the plain copy instead). Layouts change only how voxels are
  * fetched: results are bit-identical across layouts and across pair-point counts, and depend on
  * lanes_per_contour only through FP32 summation order. */
 snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs_in_flight, int32_t layout);

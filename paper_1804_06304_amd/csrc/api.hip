@@ -233,7 +233,8 @@ namespace {
 snk::Geometry geometry(const snk_ctx *c) {
     snk::Geometry g;
     g.J = c->J;
-    g.Jq = c->layout == snk::kBufferQuad ? c->Jq : nullptr;
+    // quad records, or the column pairs of a 2D image (8 bytes per pixel in the same buffer)
+    g.Jq = (c->layout == snk::kBufferQuad || c->layout == snk::kBufferPair) ? c->Jq : nullptr;
     g.nx = (int)c->nx;
     g.ny = (int)c->ny;
     g.nz = (int)c->nz;
@@ -275,6 +276,15 @@ snk_status need(snk_ctx *c, bool vol, bool seeds) {
     return SNK_OK;
 }
 
+// The second copy of J that the layout reads (quad records, or the column pairs of a 2D image, in
+// one float4 buffer), allocated once.
+snk_status ensure_layout_buffer(snk_ctx *c, int layout) {
+    const size_t vox = (size_t)(c->nx * c->ny * c->nz);
+    if (layout == snk::kBufferQuad) return ensure(c, &c->Jq, &c->Jq_cap, vox);
+    if (layout == snk::kBufferPair) return ensure(c, &c->Jq, &c->Jq_cap, (vox + 1) / 2);
+    return SNK_OK;
+}
+
 snk_status run_prepass(snk_ctx *c) {
     snk::PrepassArgs a{};
     a.raw = c->raw;
@@ -305,12 +315,11 @@ snk_status run_prepass(snk_ctx *c) {
     if (!snk::prepass_lds_limit_ok(a.rx, a.ry, a.rz))
         return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
-    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the quad layout");
-    if (layout == snk::kBufferQuad) {
-        snk_status st = ensure(c, &c->Jq, &c->Jq_cap, (size_t)(c->nx * c->ny * c->nz));
-        if (st != SNK_OK) return st;
-    }
+    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the requested layout");
+    snk_status lst = ensure_layout_buffer(c, layout);
+    if (lst != SNK_OK) return lst;
     a.Jq = layout == snk::kBufferQuad ? c->Jq : nullptr;
+    a.Jp = layout == snk::kBufferPair ? reinterpret_cast<float2 *>(c->Jq) : nullptr;
     HIPTRY(c, hipEventRecord(c->ev[0], c->stream));
     HIPTRY(c, snk::launch_prepass(a, c->stream));
     HIPTRY(c, hipEventRecord(c->ev[1], c->stream));
@@ -408,13 +417,14 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
 // Re-packs the current J when the requested layout changed after the pre-pass.
 snk_status ensure_layout(snk_ctx *c) {
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
-    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the quad layout");
+    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the requested layout");
     if (layout == c->layout) return SNK_OK;
-    if (layout == snk::kBufferQuad) {
-        snk_status st = ensure(c, &c->Jq, &c->Jq_cap, (size_t)(c->nx * c->ny * c->nz));
-        if (st != SNK_OK) return st;
+    snk_status st = ensure_layout_buffer(c, layout);
+    if (st != SNK_OK) return st;
+    if (layout == snk::kBufferQuad)
         HIPTRY(c, snk::launch_pack_quad(c->J, c->Jq, (int)c->nx, (int)c->ny, (int)c->nz, c->stream));
-    }
+    if (layout == snk::kBufferPair)
+        HIPTRY(c, snk::launch_pack_pair(c->J, reinterpret_cast<float2 *>(c->Jq), (int)c->nx, (int)c->ny, c->stream));
     c->layout = layout;
     return SNK_OK;
 }
@@ -537,14 +547,15 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
         HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
         HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     }
-    HIPTRY(c, snk::launch_star(a, sa, c->P.dim, lanes, c->layout, c->stream));
+    const int layout = c->layout == snk::kBufferPair ? snk::kBufferPlain : c->layout;  // star: single voxels
+    HIPTRY(c, snk::launch_star(a, sa, c->P.dim, lanes, layout, c->stream));
     if (standalone) {
         HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
         c->ev_evo = true;
     }
     c->last_lanes = lanes;
     c->last_unroll = 2;
-    c->last_layout = c->layout;
+    c->last_layout = layout;
     c->last_tile = 0;
     c->evolve_launches += 1;
     return SNK_OK;
@@ -616,8 +627,12 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     a.trace = trace ? c->d_trace : nullptr;
     a.counter = c->d_counters;
     const bool exact = (c->P.flags & snk::kFlagExact) != 0;
-    // exact sums read single voxels from J (the plain layout)
-    const int layout = exact && c->layout == snk::kBufferQuad ? snk::kBufferPlain : c->layout;
+    // exact sums read single voxels from J (the plain layout); so does the gradient-form kernel in
+    // place of column pairs
+    const bool gradi = (c->P.flags & snk::kFlagGradI) != 0;
+    int layout = (exact && c->layout == snk::kBufferQuad) || ((exact || gradi) && c->layout == snk::kBufferPair)
+                     ? snk::kBufferPlain
+                     : c->layout;
     int lanes, unroll;
     if (exact) {
         lanes = c->lanes > 0 ? c->lanes : 256;
@@ -629,6 +644,8 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
         // LDS boxes: whole-wave groups over a buffer layout
         if (sh.tile > 0 && (lanes < 64 || layout == snk::kGlobalPlain))
             return fail(c, SNK_EINVAL, "LDS boxes need lanes_per_contour >= 64 and layout 1 or 2");
+        // with a box, the iterations whose ball does not fit read the plain copy
+        if (sh.tile > 0 && layout == snk::kBufferPair) layout = snk::kBufferPlain;
         a.tile_cap = sh.tile;
         if (c->P.flags & snk::kFlagGradI) {
             // gradient-form centre force: whole-wave groups, two pair-points in flight
@@ -864,8 +881,9 @@ snk_status snk_set_launch(snk_ctx *c, int32_t lanes_per_contour, int32_t pairs_i
         return fail(c, SNK_EINVAL, "lanes_per_contour must be 0 (auto), 16, 32, 64, 128 or 256");
     if (pairs_in_flight < 0 || pairs_in_flight > 4 || pairs_in_flight == 3)
         return fail(c, SNK_EINVAL, "pairs_in_flight must be 0 (auto), 1, 2 or 4");
-    if (layout < 0 || layout > 3)
-        return fail(c, SNK_EINVAL, "layout must be 0 (auto), 1 (plain), 2 (quad) or 3 (plain, 64-bit addressing)");
+    if (layout < 0 || layout > 4)
+        return fail(c, SNK_EINVAL,
+                    "layout must be 0 (auto), 1 (plain), 2 (quad), 3 (plain, 64-bit addressing) or 4 (column pairs, 2D)");
     c->lanes = lanes_per_contour;
     c->unroll = pairs_in_flight;
     c->layout_req = layout;

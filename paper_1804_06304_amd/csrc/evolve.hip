@@ -379,12 +379,16 @@ struct Vol {
             so2 = nxy * 16;
             rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.Jq, (short)0, (int)((long)nxy * g.nz * 16),
                                                      (int)kBufferWord3);
+        } else if constexpr (LAYOUT == kBufferPair) {
+            rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.Jq, (short)0, (int)((long)nxy * 8), (int)kBufferWord3);
         }
     }
     // One voxel value (plain layouts).
     __device__ __forceinline__ float load1(long idx) const {
         if constexpr (LAYOUT == kBufferPlain) {
             return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)idx * 4, 0, 0));
+        } else if constexpr (LAYOUT == kBufferPair) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)idx * 8, 0, 0));
         } else {
             return J[idx];
         }
@@ -406,6 +410,13 @@ struct Vol {
                 c.v[6] = __uint_as_float(b.z);
                 c.v[7] = __uint_as_float(b.w);
             }
+        } else if constexpr (LAYOUT == kBufferPair) {
+            // (J(x,y), J(x,y+1)) then (J(x+1,y), J(x+1,y+1))
+            const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)idx * 8, 0, 0);
+            c.v[0] = __uint_as_float(a.x);
+            c.v[2] = __uint_as_float(a.y);
+            c.v[1] = __uint_as_float(a.z);
+            c.v[3] = __uint_as_float(a.w);
         } else if constexpr (LAYOUT == kBufferPlain) {
             const int vo = (int)idx * 4;
             const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rsrc, vo, 0, 0);
@@ -592,14 +603,18 @@ __device__ __forceinline__ float cube_or_square_root(float tau) {
 
 // Sums of one lane for one iteration over pair-points q = gl, gl + G, ... < P (pair m = q / L,
 // radial index l = q % L), U pair-points in flight.
+// FULL: L divides G and G U divides P, so every pass of every lane holds U valid pair-points, all at
+// the lane's radial index l0 (pairs m0 + k G / L), and the passes are uniform: no per-pair-point
+// index stepping or validity tests. The arithmetic of each pair-point is the same in both forms.
 // GRADI: the centre sums are sum S grad I (voxel-coordinate gradient of the interpolant, zero along
 // axes beyond a face) instead of sum -dS/dr I u / h.
-template <int DIM, int G, int U, bool CLAMP, bool GRADI = false, typename V>
+template <int DIM, int G, int U, bool CLAMP, bool GRADI = false, bool FULL = false, typename V>
 __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, const float4 *pu,
                                           int P, int L, float invL, int gl, int l0, int m0, int dl, int dm,
                                           float acc[2 + DIM]) {
     int l = l0, m = m0;
-    for (int q = gl; q < P; q += G * U) {
+    const float lf = (float)l0;
+    for (int q = FULL ? 0 : gl; q < P; q += G * U) {
         Corners<DIM> cp[U], cm[U];
         float fp[U][3], fm[U][3], d1s[U], d2s[U];
         float inp[U][3], inm[U][3];
@@ -607,10 +622,15 @@ __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, co
         bool ok[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            ok[k] = q + k * G < P;
-            mk[k] = ok[k] ? m : 0;
+            if constexpr (FULL) {
+                ok[k] = true;
+                mk[k] = m + k * dm;
+            } else {
+                ok[k] = q + k * G < P;
+                mk[k] = ok[k] ? m : 0;
+            }
             const float4 d = pu[mk[k]];
-            const float tau = ((float)l + d.w) * invL;
+            const float tau = ((FULL ? lf : (float)l) + d.w) * invL;
             const float e = cube_or_square_root<DIM>(tau);
             const float rad = fr.smax * e;
             // offsets from the ramp centres, fused explicitly so every instance rounds them alike
@@ -630,13 +650,16 @@ __device__ __forceinline__ void lane_sums(const V &vol, const Frame<DIM> &fr, co
                                                       GRADI && CLAMP ? inm[k] : nullptr);
             vol.load(ip, cp[k]);
             vol.load(im, cm[k]);
-            l += dl;
-            m += dm;
-            if (l >= L) {
-                l -= L;
-                m += 1;
+            if constexpr (!FULL) {
+                l += dl;
+                m += dm;
+                if (l >= L) {
+                    l -= L;
+                    m += 1;
+                }
             }
         }
+        if constexpr (FULL) m += U * dm;
         // branch-free: a pair-point past P (it read pair 0, in bounds) gets zero weights, so its
         // gathers are consumed unconditionally and those of all U pair-points stay in flight
         // together
@@ -933,6 +956,9 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
     const float invL = 1.0f / (float)L;
     const int l0 = gl % L, m0 = gl / L;
     const int dl = G % L, dm = G / L;
+    // every lane's passes hold only valid pair-points at one radial index (lane_sums FULL; in 2D:
+    // the second copy of the sums loop costs the 3D instances registers they do not have)
+    const bool full = DIM == 2 && dl == 0 && P % (G * U) == 0;
 
     int anc[3] = {s.anc[0], s.anc[1], s.anc[2]};
     float off[3] = {s.off[0], s.off[1], s.off[2]};
@@ -1024,9 +1050,15 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                     Frame<DIM> ft = fr;
                     ft.base = (anc[0] - tile.lo[0]) + (anc[1] - tile.lo[1]) * tv.nx;
                     if constexpr (DIM == 3) ft.base += (anc[2] - tile.lo[2]) * tv.nxy;
-                    lane_sums<DIM, G, U, false, GRADI>(tv, ft, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    if (full)
+                        lane_sums<DIM, G, U, false, GRADI, true>(tv, ft, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    else
+                        lane_sums<DIM, G, U, false, GRADI>(tv, ft, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
                 } else if (interior) {
-                    lane_sums<DIM, G, U, false, GRADI>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    if (full)
+                        lane_sums<DIM, G, U, false, GRADI, true>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
+                    else
+                        lane_sums<DIM, G, U, false, GRADI>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
                 } else {
                     lane_sums<DIM, G, U, true, GRADI>(vol, fr, pu, P, L, invL, gl, l0, m0, dl, dm, acc);
                 }
@@ -1383,10 +1415,14 @@ hipError_t launch_l(const EvolveArgs &a, int layout, hipStream_t s) {
     } else {
         if (a.tile_cap > 0) return hipErrorInvalidValue;
     }
+    if constexpr (DIM == 2) {
+        if (layout == kBufferPair) return launch_t<DIM, G, U, TRACE, kBufferPair>(a, s);
+    }
     switch (layout) {
         case kBufferQuad: return launch_t<DIM, G, U, TRACE, kBufferQuad>(a, s);
         case kBufferPlain: return launch_t<DIM, G, U, TRACE, kBufferPlain>(a, s);
-        default: return launch_t<DIM, G, U, TRACE, kGlobalPlain>(a, s);
+        case kGlobalPlain: return launch_t<DIM, G, U, TRACE, kGlobalPlain>(a, s);
+        default: return hipErrorInvalidValue;
     }
 }
 

@@ -1,6 +1,6 @@
 // Pre-pass: affine intensity map and separable Gaussian low-pass (the paper's low-pass filter that
 // keeps Monte-Carlo integration well behaved, Sec. II-E), clamp-to-edge, raw u8/u16/f32 -> FP32,
-// optionally also written in the evolve kernels' quad layout.
+// optionally also written in the evolve kernels' quad layout, or (2D) their column-pair layout.
 //
 // One workgroup evaluates the filters on a 64 x EY (x, y) tile (EY = 16, 8 or 4: the tallest whose
 // LDS fits) and marches along a chunk of z; it outputs the first 63 x (EY - 1) of it, the extra
@@ -8,7 +8,8 @@
 // tile column to each lane. Per input plane: stage the plane with its x/y halo in LDS from
 // registers that were fetched while the previous plane was filtered (A), filter along x (B), filter
 // along y into a ring of 2*rz+1 planes that each thread reads back for the z filter (C, D), then
-// write J and the quad records of the tile from an LDS copy of the filtered plane (E). Each thread
+// write J and the quad records or column pairs of the tile from an LDS copy of the filtered plane
+// (E). Each thread
 // z-filters only the elements it y-filtered, so with compile-time radii the ring lives in its
 // registers (less LDS per workgroup, more workgroups per CU); the generic instance keeps it in LDS.
 // Thread-to-element maps use shifts only: no integer division in any loop. HBM traffic: the raw read (halo re-reads mostly hit L2), 4 B of J and 16 B of quad
@@ -32,9 +33,9 @@ __device__ __forceinline__ T raw_value(const void *raw, long i) {
 }
 
 // RXY / RZ >= 0: the filter radii are compile-time constants (tap loops unroll, taps live in scalar
-// registers); -1: taken from the arguments. EY: evaluated rows per tile. QUAD: also write the quad
-// records.
-template <typename T, int EY, int RXY, int RZ, bool QUAD>
+// registers); -1: taken from the arguments. EY: evaluated rows per tile. SECOND: also write the quad
+// records (1) or the column pairs of a 2D image (2).
+template <typename T, int EY, int RXY, int RZ, int SECOND>
 __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk) {
     constexpr int TY = EY - 1;  // output rows (the last evaluated one is the +y neighbour)
     constexpr bool REG_RING = RZ >= 0;
@@ -179,8 +180,8 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
             }
         }
         __syncthreads();
-        // E: J and the quad records of the tile (rows past the tile or the volume store the last
-        // row inside both again)
+        // E: J and the quad records or column pairs of the tile (rows past the tile or the volume
+        // store the last row inside both again)
 #pragma unroll
         for (int i = 0; i < (TY + RS - 1) / RS; ++i) {
             const int y = min(y0 + min(ty + RS * i, TY - 1), a.ny - 1);
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(NT) void prepass_kernel(PrepassArgs a, int z_chunk)
             const long o = zo * nxy + (long)y * a.nx + xc;
             const float v = out[r * EX + tc];
             a.J[o] = v;
-            if constexpr (QUAD) a.Jq[o] = make_float4(v, out[r * EX + cx1], out[r1 * EX + tc], out[r1 * EX + cx1]);
+            if constexpr (SECOND == 1) a.Jq[o] = make_float4(v, out[r * EX + cx1], out[r1 * EX + tc], out[r1 * EX + cx1]);
+            if constexpr (SECOND == 2) a.Jp[o] = make_float2(v, out[r1 * EX + tc]);
         }
         slot = slot + 1 == K ? 0 : slot + 1;
     }
@@ -207,7 +209,7 @@ int prepass_rows(int rx, int ry, int rz) {
     return 0;
 }
 
-template <typename T, int EY, int RXY, int RZ, bool QUAD>
+template <typename T, int EY, int RXY, int RZ, int SECOND>
 hipError_t launch_q(const PrepassArgs &a, hipStream_t s) {
     const int bx = (a.nx + TX - 1) / TX;
     const int by = (a.ny + EY - 2) / (EY - 1);
@@ -219,14 +221,15 @@ hipError_t launch_q(const PrepassArgs &a, hipStream_t s) {
     z_chunk = std::max(z_chunk, std::min(a.nz, 4));
     const int bz = (a.nz + z_chunk - 1) / z_chunk;
     const size_t lds = prepass_lds_bytes(a.rx, a.ry, a.rz, EY, RZ < 0);
-    hipLaunchKernelGGL((prepass_kernel<T, EY, RXY, RZ, QUAD>), dim3(bx, by, bz), dim3(NT), lds, s, a, z_chunk);
+    hipLaunchKernelGGL((prepass_kernel<T, EY, RXY, RZ, SECOND>), dim3(bx, by, bz), dim3(NT), lds, s, a, z_chunk);
     return hipGetLastError();
 }
 
 template <typename T, int EY, int RXY, int RZ>
 hipError_t launch_ty(const PrepassArgs &a, hipStream_t s) {
-    if (!a.Jq) return launch_q<T, EY, RXY, RZ, false>(a, s);
-    return launch_q<T, EY, RXY, RZ, true>(a, s);
+    if (a.Jq) return launch_q<T, EY, RXY, RZ, 1>(a, s);
+    if (a.Jp) return launch_q<T, EY, RXY, RZ, 2>(a, s);
+    return launch_q<T, EY, RXY, RZ, 0>(a, s);
 }
 
 // Radii of sigma_pre = 1 on unit (x, y) spacing with z spacing 1, 2 or a 2D image get unrolled
@@ -268,6 +271,24 @@ hipError_t launch_pack_quad(const float *J, float4 *Jq, int nx, int ny, int nz, 
     if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
     if (ny > 65535 || nz > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(pack_quad_kernel, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, s, J, Jq, nx, ny, nz);
+    return hipGetLastError();
+}
+
+namespace {
+// Column pairs of a 2D image: Jp[y][x] = (J[y][x], J[y + 1][x]), the last row paired with itself.
+__global__ __launch_bounds__(256) void pack_pair_kernel(const float *__restrict__ J, float2 *__restrict__ Jp,
+                                                        int nx, int ny) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= nx) return;
+    const long row = (long)y * nx, row1 = (long)min(y + 1, ny - 1) * nx;
+    Jp[row + x] = make_float2(J[row + x], J[row1 + x]);
+}
+}  // namespace
+
+hipError_t launch_pack_pair(const float *J, float2 *Jp, int nx, int ny, hipStream_t s) {
+    if (nx <= 0 || ny <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_pair_kernel, dim3((nx + 255) / 256, ny), dim3(256), 0, s, J, Jp, nx, ny);
     return hipGetLastError();
 }
 

@@ -193,7 +193,7 @@ def test_one_step_parity_aniso_u16(snk, stream):
     one_step_parity(snk, stream, wl, [0, 3, 30])
 
 
-@pytest.mark.parametrize("lanes,layout", [(0, 0), (64, 2), (16, 1), (32, 2)])
+@pytest.mark.parametrize("lanes,layout", [(0, 0), (64, 2), (16, 1), (32, 2), (64, 4), (32, 4)])
 def test_one_step_parity_2d(snk, stream, lanes, layout):
     wl = synth.plane_config(n_target=120, size=256, n_iter=50)
     say(f"one-step parity 2D (256^2 u8, D 64, M 16), lanes {lanes}, layout {layout}")
@@ -227,6 +227,31 @@ def test_layouts_bitwise(snk, stream):
     for o in outs[1:]:
         for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
             assert np.array_equal(outs[0][k], o[k]), k
+
+
+@pytest.mark.parametrize("size", [256, 203])
+def test_layouts_bitwise_2d(snk, stream, size):
+    """2D: the column pairs and the quad records hold exact copies of the image, so a free run reads
+    identical results from the plain, quad, 64-bit-addressed and column-pair layouts; the automatic
+    layout of a 2D image is the column pairs. A ragged size puts cells on the last row and column."""
+    wl = synth.plane_config(n_target=120, size=size, n_iter=60)
+    say(f"free run 2D {size}^2: plain vs quad vs 64-bit plain vs column pairs")
+    outs = []
+    for layout in (1, 2, 3, 4, 0):
+        for lanes, unroll in ((64, 2), (32, 4), (16, 1)):
+            ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout)
+            ctx.load_seeds(wl.seeds, ids=wl.ids)
+            ctx.evolve(wl.n_iter)
+            tm = ctx.get_timing()
+            if layout == 0:
+                assert tm["layout"] == 3, tm["layout"]   # column pairs
+            ctx.finalize()
+            outs.append(((lanes, unroll), ctx.read()))
+            ctx.close()
+    for shape, o in outs:
+        ref = next(r for sh, r in outs if sh == shape)
+        for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
+            assert np.array_equal(ref[k], o[k]), (shape, k)
 
 
 @pytest.mark.parametrize("which", ["tiny", "aniso", "plane"])
