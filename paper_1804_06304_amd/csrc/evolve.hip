@@ -46,9 +46,11 @@ constexpr uint32_t kBufferWord3 = 0x00020000u;  // raw buffer descriptor, gfx9 f
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// The rounds stay a loop: unrolled, the compiler keeps all twenty round keys in scalar registers for
+// the whole kernel and spills other uniform values to make room.
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                          uint32_t k1, uint32_t out[4]) {
-#pragma unroll
+#pragma unroll 1
     for (int r = 0; r < 10; ++r) {
         // one 32 x 32 -> 64-bit product gives both halves
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
@@ -75,8 +77,11 @@ __device__ __forceinline__ float unit_open(uint32_t x) {
 }
 
 // Rotation Q (row-major, acting on column vectors) from the Philox words of counter (0, n, id, 0).
+// Evaluated operation by operation (no multiply-add contraction), so every kernel instance and build
+// rounds it alike.
 template <int DIM>
 __device__ __forceinline__ void rotation_from(const uint32_t x[4], float Q[9]) {
+#pragma clang fp contract(off)
     if constexpr (DIM == 2) {
         float s, c;
         sincospif(2.0f * unit_open(x[0]), &s, &c);
