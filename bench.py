@@ -280,7 +280,7 @@ def main():
         return
 
     if args.sweep:
-        for layout in (2, 1):
+        for layout in ((2, 1) if p.dim == 3 else (4, 1, 2)):
             for g in (16, 32, 64, 128, 256):
                 for u in ((1, 2, 4) if g in (32, 64, 128) else (1, 2)):
                     ctx.set_launch(g, u, layout)
