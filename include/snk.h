@@ -207,7 +207,9 @@ snk_status snk_prepass(snk_ctx *ctx);
 /* Seed n contours (host pointers): centres n x 3 physical (double), optional per-seed initial
  * radii r0 (NULL: params.r_init), optional 32-bit ids (NULL: 0..n-1) that key the Philox
  * streams, so a contour's samples do not depend on its position in the list. Radii are clamped
- * into the bounds; seeds outside the volume start as SNK_OUT. Resets iteration counters. */
+ * into the bounds; seeds outside the volume start as SNK_OUT. Resets iteration counters. The host
+ * arrays are read before the call returns; the upload is enqueued on the stream (from pinned
+ * memory, without waiting for it). */
 snk_status snk_load_seeds(snk_ctx *ctx, const double *centers, const float *r0, const uint32_t *ids,
                           int64_t n);
 
@@ -299,7 +301,8 @@ snk_status snk_get_state(snk_ctx *ctx, double *centers, float *radii, int32_t *i
                          uint8_t *status, uint8_t *streak, int64_t cap, int64_t *n_out);
 
 /* Resume / teacher forcing: overwrite the state of the n loaded contours (n must equal the
- * seeded count). streak may be NULL (zeros). */
+ * seeded count). streak may be NULL (zeros). Reads the current state back first (synchronises);
+ * the upload of the new one is enqueued like snk_load_seeds'. */
 snk_status snk_set_state(snk_ctx *ctx, const double *centers, const float *radii, const int32_t *iters,
                          const uint8_t *status, const uint8_t *streak, int64_t n);
 

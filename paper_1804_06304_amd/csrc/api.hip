@@ -86,6 +86,13 @@ struct snk_ctx {
     int *d_live = nullptr;             // snk_evolve_cull: indices of the active contours, then their count
     size_t live_cap = 0;
 
+    // pinned staging of contour records for host <-> device copies; ev_stage marks the end of the
+    // last upload from it, which must complete before the buffer is written again
+    DevContour *h_stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t ev_stage = nullptr;
+    bool stage_busy = false;
+
     hipEvent_t ev[6] = {};
     bool ev_pre = false, ev_evo = false, ev_fin = false;
     int64_t evolve_launches = 0;
@@ -720,11 +727,44 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     return SNK_OK;
 }
 
+// The pinned staging buffer with room for n records, free to write (the last upload from it done).
+snk_status stage(snk_ctx *c, size_t n, DevContour **out) {
+    if (c->stage_busy) {
+        HIPTRY(c, hipEventSynchronize(c->ev_stage));
+        c->stage_busy = false;
+    }
+    if (c->stage_cap < n || !c->h_stage) {
+        if (c->h_stage) HIPTRY(c, hipHostFree(c->h_stage));
+        c->h_stage = nullptr;
+        c->stage_cap = 0;
+        void *q = nullptr;
+        hipError_t e = hipHostMalloc(&q, std::max<size_t>(n, 1) * sizeof(DevContour), hipHostMallocDefault);
+        if (e != hipSuccess) return fail(c, SNK_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        c->h_stage = static_cast<DevContour *>(q);
+        c->stage_cap = n;
+    }
+    *out = c->h_stage;
+    return SNK_OK;
+}
+
+// Uploads the first n staged records to the contour state without waiting for the copy: the
+// stream orders it before every later launch, and the next use of the staging buffer waits for it.
+snk_status upload_stage(snk_ctx *c, size_t n) {
+    if (n == 0) return SNK_OK;
+    HIPTRY(c, hipMemcpyAsync(c->d_st, c->h_stage, sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
+    HIPTRY(c, hipEventRecord(c->ev_stage, c->stream));
+    c->stage_busy = true;
+    return SNK_OK;
+}
+
 snk_status unpack(snk_ctx *c, std::vector<DevContour> &h) {
-    h.resize((size_t)c->n);
+    DevContour *buf = nullptr;
+    snk_status st = stage(c, (size_t)c->n, &buf);
+    if (st != SNK_OK) return st;
     if (c->n > 0)
-        HIPTRY(c, hipMemcpyAsync(h.data(), c->d_st, sizeof(DevContour) * c->n, hipMemcpyDeviceToHost, c->stream));
+        HIPTRY(c, hipMemcpyAsync(buf, c->d_st, sizeof(DevContour) * c->n, hipMemcpyDeviceToHost, c->stream));
     HIPTRY(c, hipStreamSynchronize(c->stream));
+    h.assign(buf, buf + c->n);
     return SNK_OK;
 }
 
@@ -833,6 +873,11 @@ snk_status snk_create(snk_ctx **out, int device, void *hip_stream) {
             return fail(nullptr, SNK_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
         }
     }
+    e = hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        snk_destroy(c);
+        return fail(nullptr, SNK_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+    }
     e = hipMalloc(&c->d_counters, 4 * sizeof(unsigned long long));
     if (e != hipSuccess) {
         snk_destroy(c);
@@ -858,6 +903,8 @@ snk_status snk_destroy(snk_ctx *c) {
         if (b) (void)hipFree(b);
     for (auto &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
+    if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
     delete c;
     return SNK_OK;
 }
@@ -1011,7 +1058,9 @@ snk_status snk_load_seeds(snk_ctx *c, const double *centers, const float *r0, co
     if (st != SNK_OK) return st;
     if (n >= (int64_t)1 << 31) return fail(c, SNK_EINVAL, "too many seeds");
     (void)hipSetDevice(c->device);
-    std::vector<DevContour> h((size_t)n);
+    DevContour *h = nullptr;
+    st = stage(c, (size_t)n, &h);
+    if (st != SNK_OK) return st;
     const double lo = r_low(c->P), hi = c->P.r_max;
     for (int64_t i = 0; i < n; ++i) {
         DevContour &s = h[i];
@@ -1033,9 +1082,8 @@ snk_status snk_load_seeds(snk_ctx *c, const double *centers, const float *r0, co
     if (st != SNK_OK) return st;
     st = ensure(c, &c->d_evox, &c->evox_cap, (size_t)n);
     if (st != SNK_OK) return st;
-    if (n > 0)
-        HIPTRY(c, hipMemcpyAsync(c->d_st, h.data(), sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
-    HIPTRY(c, hipStreamSynchronize(c->stream));
+    st = upload_stage(c, (size_t)n);
+    if (st != SNK_OK) return st;
     c->n = n;
     c->Rk_valid = false;
     return SNK_OK;
@@ -1258,9 +1306,12 @@ snk_status snk_set_state(snk_ctx *c, const double *centers, const float *radii, 
         h[i].streak = streak ? streak[i] : 0;
         h[i].keep = 0;
     }
-    if (n > 0)
-        HIPTRY(c, hipMemcpyAsync(c->d_st, h.data(), sizeof(DevContour) * n, hipMemcpyHostToDevice, c->stream));
-    HIPTRY(c, hipStreamSynchronize(c->stream));
+    DevContour *buf = nullptr;
+    st = stage(c, (size_t)n, &buf);
+    if (st != SNK_OK) return st;
+    if (n > 0) memcpy(buf, h.data(), sizeof(DevContour) * n);
+    st = upload_stage(c, (size_t)n);
+    if (st != SNK_OK) return st;
     c->Rk_valid = false;
     return SNK_OK;
 }

@@ -233,21 +233,26 @@ def test_layouts_bitwise(snk, stream):
 def test_layouts_bitwise_2d(snk, stream, size):
     """2D: the column pairs and the quad records hold exact copies of the image, so a free run reads
     identical results from the plain, quad, 64-bit-addressed and column-pair layouts; the automatic
-    layout of a 2D image is the column pairs. A ragged size puts cells on the last row and column."""
+    layout of a 2D image is the column pairs, and with an LDS box the iterations whose ball does not fit
+    read the plain copy. A ragged size puts cells on the last row and column."""
     wl = synth.plane_config(n_target=120, size=size, n_iter=60)
-    say(f"free run 2D {size}^2: plain vs quad vs 64-bit plain vs column pairs")
+    say(f"free run 2D {size}^2: plain vs quad vs 64-bit plain vs column pairs, with and without LDS boxes")
     outs = []
-    for layout in (1, 2, 3, 4, 0):
-        for lanes, unroll in ((64, 2), (32, 4), (16, 1)):
-            ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout)
-            ctx.load_seeds(wl.seeds, ids=wl.ids)
-            ctx.evolve(wl.n_iter)
-            tm = ctx.get_timing()
-            if layout == 0:
-                assert tm["layout"] == 3, tm["layout"]   # column pairs
-            ctx.finalize()
-            outs.append(((lanes, unroll), ctx.read()))
-            ctx.close()
+    runs = [(layout, lanes, unroll, -1) for layout in (1, 2, 3, 4, 0) for lanes, unroll in ((64, 2), (32, 4), (16, 1))]
+    # an LDS box with the automatic layout: the iterations whose ball does not fit read the plain copy
+    runs += [(0, 64, 2, 1024), (4, 64, 2, 2048)]
+    for layout, lanes, unroll, tile in runs:
+        ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout, tile=tile)
+        ctx.load_seeds(wl.seeds, ids=wl.ids)
+        ctx.evolve(wl.n_iter)
+        tm = ctx.get_timing()
+        if layout == 0 and tile < 0:
+            assert tm["layout"] == 3, tm["layout"]   # column pairs
+        if tile > 0:
+            assert tm["layout"] == 1 and tm["tile_voxels"] == tile, tm
+        ctx.finalize()
+        outs.append(((lanes, unroll), ctx.read()))
+        ctx.close()
     for shape, o in outs:
         ref = next(r for sh, r in outs if sh == shape)
         for k in ("radii", "centers", "e_mc", "e_vox", "iters", "status", "keep"):
