@@ -1086,14 +1086,13 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                 for (int k = 0; k < NR; ++k) red[k * WAVES + wave] = wt[k];
             }
             __syncthreads();
+            // every wave adds the partials in wave order, so all of them hold the same totals and
+            // take the same step below (no second barrier to hand wave 0's result to the others)
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
-                float v = 0.0f;
-                if (wave == 0) {
-                    v = red[k * WAVES];
+                float v = red[k * WAVES];
 #pragma unroll
-                    for (int w = 1; w < WAVES; ++w) v += red[k * WAVES + w];
-                }
+                for (int w = 1; w < WAVES; ++w) v += red[k * WAVES + w];
                 tot[k] = v;
             }
         }
@@ -1104,9 +1103,9 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             for (int a = 0; a < DIM; ++a) tot[2 + a] *= inv_h[a] * inv_h[a];
         }
 
-        // descent step, identical in every lane of the group (multi-wave groups: wave 0 only, the
-        // others take the new state from LDS below)
-        if (active && (G <= 64 || wave == 0)) {
+        // descent step, identical in every lane of the group (multi-wave groups: every wave, from the
+        // same totals)
+        if (active) {
             // no multiply-add contraction in the step: every instance (with or without the optional
             // terms below) rounds it operation by operation, so their results agree bit for bit
 #pragma clang fp contract(off)
@@ -1242,29 +1241,6 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             }
             ++ran;
         }
-        if constexpr (G > 64) {
-            // broadcast of wave 0's new state: centre anchor / offset, R, status
-            float *bc = lds_red + 2 * NR * WAVES + (it & 1) * 8;
-            if (active && t == 0) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    bc[i] = off[i];
-                    bc[3 + i] = __int_as_float(anc[i]);
-                }
-                bc[6] = R;
-                bc[7] = __int_as_float((int)status);
-            }
-            __syncthreads();
-            if (active && wave != 0) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    off[i] = uni<G>(bc[i]);
-                    anc[i] = uni<G>(__float_as_int(bc[3 + i]));
-                }
-                R = uni<G>(bc[6]);
-                status = (uint8_t)uni<G>(__float_as_int(bc[7]));
-            }
-        }
         if constexpr (G <= 64) __syncthreads();  // orders this iteration's LDS draws before later reads
     }
 
@@ -1289,7 +1265,7 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
 template <int DIM, int G>
 __host__ __device__ __forceinline__ int lds_floats(int MH) {
     const int per = (draw_floats(G, MH) + 3) & ~3;
-    return Grp<G>::CPB * per + (G > 64 ? 2 * (2 + DIM) * Grp<G>::WAVES + 16 : 0);
+    return Grp<G>::CPB * per + (G > 64 ? 2 * (2 + DIM) * Grp<G>::WAVES : 0);
 }
 
 // Whole-wave groups with one pair-point in flight fit 64 vector registers: ask for 8 waves per SIMD
@@ -2051,7 +2027,7 @@ size_t evolve_lds_bytes(int dim, int lanes, int M, int tile_cap) {
     const int per = (draw_floats(G, MH) + 3) & ~3;
     const int cpb = G < 64 ? 64 / G : 1;
     const int waves = G > 64 ? G / 64 : 1;
-    return sizeof(float) * ((size_t)cpb * per + (G > 64 ? 2 * (2 + dim) * waves + 16 : 0) + (size_t)tile_cap);
+    return sizeof(float) * ((size_t)cpb * per + (G > 64 ? 2 * (2 + dim) * waves : 0) + (size_t)tile_cap);
 }
 
 }  // namespace snk
