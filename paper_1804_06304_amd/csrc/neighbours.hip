@@ -87,58 +87,121 @@ __global__ __launch_bounds__(NB_T) void nb_scatter_kernel(int n, NeighbourArgs b
     if (cell >= 0) b.items[b.cell_start[cell] + atomicAdd(&b.cell_fill[cell], 1)] = i;
 }
 
-// The list of contour i (ACTIVE only; others get none): live contours j != i with
-// |c_i - c_j| < rho (R_i + R_j), ascending j, at most b.cap (more sets the overflow flag).
+// Whether live contour j (snapshot records sj0, sj1) overlaps contour i: |c_i - c_j| < rho (R_i + R_j).
 template <int DIM>
-__global__ __launch_bounds__(NB_T) void nb_list_kernel(int n, Geometry g, float rho, NeighbourArgs b) {
-    const int i = blockIdx.x * NB_T + threadIdx.x;
-    if (i >= n) return;
-    const float4 si0 = b.snap[2 * i], si1 = b.snap[2 * i + 1];
-    int *list = b.nb + (long)i * b.cap;
+__device__ __forceinline__ bool overlaps(const int ai[3], const float oi[3], float Ri, float4 sj0, float4 sj1,
+                                         const Geometry &g, float rho) {
+    const int aj[3] = {__float_as_int(sj0.x), __float_as_int(sj0.y), __float_as_int(sj0.z)};
+    const float oj[3] = {sj1.x, sj1.y, sj1.z};
+    float d2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const float dv = ((float)(ai[a] - aj[a]) + (oi[a] - oj[a])) * g.h[a];
+        d2 = fmaf(dv, dv, d2);
+    }
+    const float span = rho * (Ri + sj0.w);
+    return d2 < span * span;
+}
+
+// The list of one contour by one lane: the 3^d cells around it, inserting each overlapping j so the
+// list stays ascending and keeps the lowest cap indices (more sets the overflow flag).
+template <int DIM>
+__device__ int list_serial(int i, const int gi[3], const int ai[3], const float oi[3], float Ri, const Geometry &g,
+                           float rho, const NeighbourArgs &b, int *list) {
     int count = 0;
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cx = gi[0] + dx, cy = gi[1] + dy, cz = gi[2] + dz;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= b.G[0] || cy >= b.G[1] || cz >= b.G[2]) continue;
+                const int c = (cz * b.G[1] + cy) * b.G[0] + cx;
+                for (int q = b.cell_start[c]; q < b.cell_start[c + 1]; ++q) {
+                    const int j = b.items[q];
+                    if (j == i || !overlaps<DIM>(ai, oi, Ri, b.snap[2 * j], b.snap[2 * j + 1], g, rho)) continue;
+                    if (count == b.cap) {
+                        atomicOr(b.overflow, 1);
+                        if (j > list[count - 1]) continue;
+                        --count;   // drop the largest index to keep the lowest cap
+                    }
+                    int k = count;
+                    while (k > 0 && list[k - 1] > j) {
+                        list[k] = list[k - 1];
+                        --k;
+                    }
+                    list[k] = j;
+                    ++count;
+                }
+            }
+    return count;
+}
+
+constexpr int NB_LIST_WAVES = 4;   // contours per workgroup, one wave each
+constexpr int NB_BUF = 256;        // matches a wave collects before ranking them
+
+// The list of contour i (ACTIVE only; others get none): live contours j != i with
+// |c_i - c_j| < rho (R_i + R_j), ascending j, at most b.cap (more sets the overflow flag). One wave
+// per contour: the lanes test a cell's candidates 64 at a time and append the matches to an LDS
+// buffer (in whatever order the grid holds them), then each match's rank among all of them gives
+// its place, so the list does not depend on that order. A contour with more matches than the buffer
+// holds falls back to one lane inserting them one by one (same list).
+template <int DIM>
+__global__ __launch_bounds__(64 * NB_LIST_WAVES) void nb_list_kernel(int n, Geometry g, float rho, NeighbourArgs b) {
+    __shared__ int buf[NB_LIST_WAVES][NB_BUF];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int i = blockIdx.x * NB_LIST_WAVES + w;
+    if (i >= n) return;   // whole waves leave; no barrier follows
+    int *list = b.nb + (long)i * b.cap;
     const int cell = b.cell_of[i];
     const bool active = cell >= 0 && (b.status ? (b.status[i].status & 0x0f) == SNK_ACTIVE : true);
-    if (active) {
-        const int gi[3] = {cell % b.G[0], (cell / b.G[0]) % b.G[1], cell / (b.G[0] * b.G[1])};
-        const int ai[3] = {__float_as_int(si0.x), __float_as_int(si0.y), __float_as_int(si0.z)};
-        const float oi[3] = {si1.x, si1.y, si1.z};
-        for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int cx = gi[0] + dx, cy = gi[1] + dy, cz = gi[2] + dz;
-                    if (cx < 0 || cy < 0 || cz < 0 || cx >= b.G[0] || cy >= b.G[1] || cz >= b.G[2]) continue;
-                    const int c = (cz * b.G[1] + cy) * b.G[0] + cx;
-                    for (int q = b.cell_start[c]; q < b.cell_start[c + 1]; ++q) {
-                        const int j = b.items[q];
-                        if (j == i) continue;
-                        const float4 sj0 = b.snap[2 * j], sj1 = b.snap[2 * j + 1];
-                        const int aj[3] = {__float_as_int(sj0.x), __float_as_int(sj0.y), __float_as_int(sj0.z)};
-                        const float oj[3] = {sj1.x, sj1.y, sj1.z};
-                        float d2 = 0.0f;
-#pragma unroll
-                        for (int a = 0; a < DIM; ++a) {
-                            const float dv = ((float)(ai[a] - aj[a]) + (oi[a] - oj[a])) * g.h[a];
-                            d2 = fmaf(dv, dv, d2);
-                        }
-                        const float span = rho * (si0.w + sj0.w);
-                        if (!(d2 < span * span)) continue;
-                        // insert j keeping the list ascending
-                        if (count == b.cap) {
-                            atomicOr(b.overflow, 1);
-                            if (j > list[count - 1]) continue;
-                            --count;   // drop the largest index to keep the lowest cap
-                        }
-                        int k = count;
-                        while (k > 0 && list[k - 1] > j) {
-                            list[k] = list[k - 1];
-                            --k;
-                        }
-                        list[k] = j;
-                        ++count;
-                    }
-                }
+    if (!active) {
+        if (lane == 0) b.nbn[i] = 0;
+        return;
     }
-    b.nbn[i] = count;
+    const float4 si0 = b.snap[2 * i], si1 = b.snap[2 * i + 1];
+    const int gi[3] = {cell % b.G[0], (cell / b.G[0]) % b.G[1], cell / (b.G[0] * b.G[1])};
+    const int ai[3] = {__float_as_int(si0.x), __float_as_int(si0.y), __float_as_int(si0.z)};
+    const float oi[3] = {si1.x, si1.y, si1.z};
+    int *mine = buf[w];
+    int total = 0;
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cx = gi[0] + dx, cy = gi[1] + dy, cz = gi[2] + dz;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= b.G[0] || cy >= b.G[1] || cz >= b.G[2]) continue;
+                const int c = (cz * b.G[1] + cy) * b.G[0] + cx;
+                const int q1 = b.cell_start[c + 1];
+                for (int q0 = b.cell_start[c]; q0 < q1; q0 += 64) {
+                    const int q = q0 + lane;
+                    bool hit = false;
+                    int j = -1;
+                    if (q < q1) {
+                        j = b.items[q];
+                        hit = j != i && overlaps<DIM>(ai, oi, si0.w, b.snap[2 * j], b.snap[2 * j + 1], g, rho);
+                    }
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    const int pos = total + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (hit && pos < NB_BUF) mine[pos] = j;
+                    total += __builtin_popcountll(m);
+                }
+            }
+    int count;
+    if (total <= NB_BUF) {
+        // the lanes' buffer writes before any lane reads the buffer
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int e = lane; e < total; e += 64) {
+            const int j = mine[e];
+            int rank = 0;
+            for (int k = 0; k < total; ++k) rank += mine[k] < j ? 1 : 0;
+            if (rank < b.cap) list[rank] = j;
+        }
+        count = min(total, b.cap);
+        if (total > b.cap && lane == 0) atomicOr(b.overflow, 1);
+    } else {
+        count = lane == 0 ? list_serial<DIM>(i, gi, ai, oi, si0.w, g, rho, b, list) : 0;
+    }
+    if (lane == 0) b.nbn[i] = count;
 }
 
 }  // namespace
@@ -155,8 +218,9 @@ hipError_t launch_neighbours(const DevContour *st, int n, const Geometry &g, int
     else hipLaunchKernelGGL(nb_snap_kernel<3>, dim3(blocks), dim3(NB_T), 0, s, st, n, g, b);
     hipLaunchKernelGGL(nb_scan_kernel, dim3(1), dim3(1024), 0, s, b);
     hipLaunchKernelGGL(nb_scatter_kernel, dim3(blocks), dim3(NB_T), 0, s, n, b);
-    if (dim == 2) hipLaunchKernelGGL(nb_list_kernel<2>, dim3(blocks), dim3(NB_T), 0, s, n, g, rho, b);
-    else hipLaunchKernelGGL(nb_list_kernel<3>, dim3(blocks), dim3(NB_T), 0, s, n, g, rho, b);
+    const int lblocks = (n + NB_LIST_WAVES - 1) / NB_LIST_WAVES;
+    if (dim == 2) hipLaunchKernelGGL(nb_list_kernel<2>, dim3(lblocks), dim3(64 * NB_LIST_WAVES), 0, s, n, g, rho, b);
+    else hipLaunchKernelGGL(nb_list_kernel<3>, dim3(lblocks), dim3(64 * NB_LIST_WAVES), 0, s, n, g, rho, b);
     return hipGetLastError();
 }
 
