@@ -322,7 +322,9 @@ snk_status run_prepass(snk_ctx *c) {
     if (!snk::prepass_lds_limit_ok(a.rx, a.ry, a.rz))
         return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
-    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the requested layout");
+    if (layout < 0)
+        return fail(c, SNK_EINVAL, c->layout_req == 4 && c->P.dim == 3 ? "the column-pair layout is 2D only"
+                                                                       : "volume too large for the requested layout");
     snk_status lst = ensure_layout_buffer(c, layout);
     if (lst != SNK_OK) return lst;
     a.Jq = layout == snk::kBufferQuad ? c->Jq : nullptr;
@@ -424,7 +426,9 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
 // Re-packs the current J when the requested layout changed after the pre-pass.
 snk_status ensure_layout(snk_ctx *c) {
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
-    if (layout < 0) return fail(c, SNK_EINVAL, "volume too large for the requested layout");
+    if (layout < 0)
+        return fail(c, SNK_EINVAL, c->layout_req == 4 && c->P.dim == 3 ? "the column-pair layout is 2D only"
+                                                                       : "volume too large for the requested layout");
     if (layout == c->layout) return SNK_OK;
     snk_status st = ensure_layout_buffer(c, layout);
     if (st != SNK_OK) return st;

@@ -1741,17 +1741,34 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
             }
         }
         __syncthreads();
-        // sampled directions: the first ray of each direction sums its rays in order (every lane
-        // walks all rays, reading each at one address, so the reads do not wait on each other)
+        // sampled directions: the first ray of each direction sums its rays in order. Every lane
+        // walks all rays, eight at a time with their loads issued together and no branch on the
+        // loaded values (a ray of another direction adds +0, which leaves the sum unchanged: it
+        // starts at +0 and so is never -0)
         for (int r = t; r < M; r += NT) {
             const int dk = ray_dir[r];
             bool first = true;
             float g = 0.0f;
-            for (int r2 = 0; r2 < M; ++r2) {
-                if (ray_dir[r2] == dk) {
-                    if (r2 < r) first = false;
-                    else g += ray_g[r2];
+            int r2 = 0;
+            for (; r2 + 8 <= M; r2 += 8) {
+                int dd[8];
+                float gg[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    dd[u] = ray_dir[r2 + u];
+                    gg[u] = ray_g[r2 + u];
                 }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const bool same = dd[u] == dk;
+                    first = first && !(same && r2 + u < r);
+                    g += same && r2 + u >= r ? gg[u] : 0.0f;
+                }
+            }
+            for (; r2 < M; ++r2) {
+                const bool same = ray_dir[r2] == dk;
+                first = first && !(same && r2 < r);
+                g += same && r2 >= r ? ray_g[r2] : 0.0f;
             }
             if (first) gk[dk] = g;
         }

@@ -538,6 +538,13 @@ def test_edge_cases(snk, stream):
     with pytest.raises(snk.SnkError):
         ctx.set_params(bad)
     ctx.close()
+    # the column-pair layout is 2D only: a 3D volume refuses it at the next evolve
+    ctx = make_ctx(snk, stream, wl, layout=4)
+    ctx.load_seeds(wl.seeds, ids=wl.ids)
+    with pytest.raises(snk.SnkError) as ex:
+        ctx.evolve(1)
+    assert ex.value.code == snk.SNK_EINVAL and "2D only" in str(ex.value)
+    ctx.close()
 
 
 def test_full_size_slab_sampled(snk, stream):
