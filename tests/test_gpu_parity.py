@@ -538,6 +538,20 @@ def test_edge_cases(snk, stream):
     with pytest.raises(snk.SnkError):
         ctx.set_params(bad)
     ctx.close()
+    # seeds go up from one pinned staging buffer without a host wait: back-to-back loads (each
+    # reusing the buffer while the previous upload may still be in flight) leave the last one
+    ctx = make_ctx(snk, stream, wl)
+    many = np.random.default_rng(5).uniform(8.0, 56.0, size=(4000, 3))
+    ctx.load_seeds(many)
+    ctx.load_seeds(wl.seeds, ids=wl.ids)
+    ctx.evolve(3)
+    a = ctx.get_state()
+    ctx.load_seeds(wl.seeds, ids=wl.ids)
+    ctx.evolve(3)
+    b = ctx.get_state()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    ctx.close()
     # the column-pair layout is 2D only: a 3D volume refuses it at the next evolve
     ctx = make_ctx(snk, stream, wl, layout=4)
     ctx.load_seeds(wl.seeds, ids=wl.ids)
