@@ -234,51 +234,58 @@ __device__ __forceinline__ void bin_one(const JobDev &a, int i) {
     a.cell_of[i] = cell;
 }
 
-// Inclusive running sum of the cell counts cell_start[1..G], in place, by one workgroup: tiles of
-// SEL_T * 8 cells, 8 consecutive cells per thread, a shuffle scan of the thread sums inside each
-// wave, the wave totals scanned through LDS (ws: SEL_T / 64 + 1 ints), a carry across tiles.
-__device__ void scan_cells(const JobDev &a, int G, int *ws) {
+// Inclusive running sum of one tile of SEL_T * 8 cell counts cs[base ..] (in place), plus carry: 8
+// consecutive cells per thread, a shuffle scan of the thread sums inside each wave, the wave totals
+// scanned through LDS (ws: SEL_T / 64 + 1 ints). Returns the tile's total (every thread).
+__device__ int scan_tile(int *cs, int G, int base, int carry, int *ws) {
     constexpr int V = 8;
     constexpr int W = SEL_T / 64;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int i0 = base + t * V;
+    int v[V];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        s += i0 + k < G ? cs[i0 + k] : 0;
+        v[k] = s;
+    }
+    int incl = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    if (lane == 63) ws[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+        const int x = lane < W ? ws[lane] : 0;
+        int sc = x;
+#pragma unroll
+        for (int d = 1; d < W; d <<= 1) {
+            const int y = __shfl_up(sc, d, 64);
+            if (lane >= d) sc += y;
+        }
+        if (lane < W) ws[lane] = sc - x;  // exclusive prefix of the wave totals
+        if (lane == W - 1) ws[W] = sc;    // tile total
+    }
+    __syncthreads();
+    const int off = carry + ws[w] + (incl - s);
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+        if (i0 + k < G) cs[i0 + k] = v[k] + off;
+    const int total = ws[W];
+    __syncthreads();
+    return total;
+}
+
+constexpr int SCAN_TILE = SEL_T * 8;
+
+// Inclusive running sum of the cell counts cell_start[1..G], in place, by one workgroup (tile by
+// tile, carrying the total across).
+__device__ void scan_cells(const JobDev &a, int G, int *ws) {
     int *cs = a.cell_start + 1;
     int carry = 0;
-    for (int base = 0; base < G; base += SEL_T * V) {
-        const int i0 = base + t * V;
-        int v[V];
-        int s = 0;
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            s += i0 + k < G ? cs[i0 + k] : 0;
-            v[k] = s;
-        }
-        int incl = s;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
-        if (lane == 63) ws[w] = incl;
-        __syncthreads();
-        if (w == 0) {
-            const int x = lane < W ? ws[lane] : 0;
-            int sc = x;
-#pragma unroll
-            for (int d = 1; d < W; d <<= 1) {
-                const int y = __shfl_up(sc, d, 64);
-                if (lane >= d) sc += y;
-            }
-            if (lane < W) ws[lane] = sc - x;  // exclusive prefix of the wave totals
-            if (lane == W - 1) ws[W] = sc;    // tile total
-        }
-        __syncthreads();
-        const int off = carry + ws[w] + (incl - s);
-#pragma unroll
-        for (int k = 0; k < V; ++k)
-            if (i0 + k < G) cs[i0 + k] = v[k] + off;
-        carry += ws[W];
-        __syncthreads();
-    }
+    for (int base = 0; base < G; base += SCAN_TILE) carry += scan_tile(cs, G, base, carry, ws);
 }
 
 __device__ __forceinline__ void scatter_one(const JobDev &a, int i) {
@@ -383,6 +390,44 @@ __global__ __launch_bounds__(SEL_T) void sel_scan_kernel(JobDev a, int G) {
     scan_cells(a, G, chunk_sum);
 }
 
+// The same running sum by one workgroup per tile, for grids of several tiles: (1) each tile's own
+// running sum, its total parked in cell_fill[tile] (zero until the scatter counts in it); (2) one
+// workgroup turns the totals into each tile's offset; (3) each tile adds its offset and puts the
+// zero back in cell_fill[tile].
+__global__ __launch_bounds__(SEL_T) void sel_scan_tiles_kernel(JobDev a, int G) {
+    __shared__ int ws[SEL_T / 64 + 1];
+    const int total = scan_tile(a.cell_start + 1, G, blockIdx.x * SCAN_TILE, 0, ws);
+    if (threadIdx.x == 0) a.cell_fill[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SEL_T) void sel_scan_totals_kernel(JobDev a, int ntiles) {
+    __shared__ int ws[SEL_T / 64 + 1];
+    // ntiles <= SEL_T * 8: one tile of totals; inclusive, then shifted to the exclusive offsets
+    const int t = threadIdx.x;
+    int own[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) own[k] = t * 8 + k < ntiles ? a.cell_fill[t * 8 + k] : 0;
+    __syncthreads();
+    scan_tile(a.cell_fill, ntiles, 0, 0, ws);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (t * 8 + k < ntiles) a.cell_fill[t * 8 + k] -= own[k];
+}
+
+__global__ __launch_bounds__(SEL_T) void sel_scan_add_kernel(JobDev a, int G) {
+    __shared__ int off_sh;
+    if (threadIdx.x == 0) {
+        off_sh = a.cell_fill[blockIdx.x];
+        a.cell_fill[blockIdx.x] = 0;
+    }
+    __syncthreads();
+    const int off = off_sh;
+    if (off == 0) return;
+    int *cs = a.cell_start + 1;
+    const int base = blockIdx.x * SCAN_TILE;
+    for (int i = base + (int)threadIdx.x; i < min(base + SCAN_TILE, G); i += SEL_T) cs[i] += off;
+}
+
 __global__ __launch_bounds__(SG_T) void sel_scatter_kernel(JobDev a) {
     const int i = blockIdx.x * SG_T + threadIdx.x;
     if (i < a.n) scatter_one(a, i);
@@ -414,7 +459,14 @@ hipError_t select_grid(const JobDev &j, int *rounds, hipStream_t s) {
     const int bn = (j.n + SG_T - 1) / SG_T;
     hipLaunchKernelGGL(sel_zero_kernel, dim3((G + 1 + SG_T - 1) / SG_T), dim3(SG_T), 0, s, j, G, rounds);
     hipLaunchKernelGGL(sel_bin_kernel<DIM>, dim3(bn), dim3(SG_T), 0, s, j);
-    hipLaunchKernelGGL(sel_scan_kernel, dim3(1), dim3(SEL_T), 0, s, j, G);
+    const int ntiles = (G + SCAN_TILE - 1) / SCAN_TILE;
+    if (ntiles <= 1) {
+        hipLaunchKernelGGL(sel_scan_kernel, dim3(1), dim3(SEL_T), 0, s, j, G);
+    } else {
+        hipLaunchKernelGGL(sel_scan_tiles_kernel, dim3(ntiles), dim3(SEL_T), 0, s, j, G);
+        hipLaunchKernelGGL(sel_scan_totals_kernel, dim3(1), dim3(SEL_T), 0, s, j, ntiles);
+        hipLaunchKernelGGL(sel_scan_add_kernel, dim3(ntiles), dim3(SEL_T), 0, s, j, G);
+    }
     hipLaunchKernelGGL(sel_scatter_kernel, dim3(bn), dim3(SG_T), 0, s, j);
     for (int r = 0; r < kSelectGridRounds; ++r)
         hipLaunchKernelGGL(sel_round_kernel<DIM>, dim3(bn), dim3(SG_T), 0, s, j, r, rounds);
