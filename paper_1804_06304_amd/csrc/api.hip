@@ -44,7 +44,7 @@ struct snk_ctx {
     // star-shaped contours (lambda < 0: off)
     double star_lambda = -1.0;
     int *d_anti = nullptr;
-    uint16_t *d_nb = nullptr;  // neighbour rows, nb_chunks x 8 entries each, 0xffff past the last
+    uint16_t *d_nb = nullptr;  // neighbour rows, nb_chunks x 8 entries each, padded with D
     int nb_chunks = 0;
     size_t anti_cap = 0, nb_cap = 0;
     std::vector<float> star_dirs;    // the table the star tables were built from
@@ -499,13 +499,14 @@ snk_status star_tables(snk_ctx *c) {
     }
     snk_status st = ensure(c, &c->d_anti, &c->anti_cap, (size_t)D);
     if (st != SNK_OK) return st;
-    // rows of whole 16-byte chunks (8 entries, in the order above, 0xffff after the last), so the
-    // kernel loads a direction's neighbours with independent vector loads
+    // rows of whole 16-byte chunks (8 entries, in the order above, padded with the index D, whose
+    // radius entry the kernel holds at zero), so the kernel loads a direction's neighbours with
+    // independent vector loads and reads every entry without a branch
     if (D >= 0xffff) return fail(c, SNK_EINVAL, "star contours need fewer than 65535 directions");
     int maxdeg = 1;
     for (int k = 0; k < D; ++k) maxdeg = std::max(maxdeg, off[k + 1] - off[k]);
     const int chunks = (maxdeg + 7) / 8;
-    std::vector<uint16_t> nb((size_t)D * chunks * 8, 0xffff);
+    std::vector<uint16_t> nb((size_t)D * chunks * 8, (uint16_t)D);
     for (int k = 0; k < D; ++k)
         for (int b = off[k]; b < off[k + 1]; ++b) nb[(size_t)k * chunks * 8 + (b - off[k])] = (uint16_t)idx[b];
     st = ensure(c, &c->d_nb, &c->nb_cap, nb.size());

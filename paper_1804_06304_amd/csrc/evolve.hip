@@ -1520,7 +1520,7 @@ int max_blocks_g(int lanes, int unroll, int layout, int max_M, int tile_cap) {
 template <int DIM>
 __host__ __device__ __forceinline__ int star_lds_floats(int D, int M, int NT) {
     const int per = (draw_floats(NT, M / 2) + 3) & ~3;
-    return per + 3 * D + 2 * M + (M / 2) * (2 + DIM) + 8 * (NT / 64);
+    return per + 4 * D + 2 + 2 * M + (M / 2) * (2 + DIM) + 8 * (NT / 64);
 }
 
 // NT threads per contour (64: one wave; 128: two waves, whose partial sums meet in LDS in wave
@@ -1542,9 +1542,11 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
     const int budget = (s.status & 0x0f) == SNK_ACTIVE ? a.n_iter : 0;
     const int per = (draw_floats(NT, MH) + 3) & ~3;
     const Draws dr(lds, NT, MH);
+    // two radius buffers of D + 1 entries: entry D stays +0, so a neighbour row's padding (index D)
+    // reads a zero
     float *Ra = lds + per;
-    float *Rb = Ra + D;
-    float *gk = Rb + D;
+    float *Rb = Ra + D + 1;
+    float *gk = Rb + D + 1;
     int *ray_dir = reinterpret_cast<int *>(gk + D);
     float *ray_g = reinterpret_cast<float *>(ray_dir + M);
     // this iteration's ray pairs: direction, antipode, unit vector
@@ -1552,10 +1554,17 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
     int *rka = rk + MH;
     float *ru = reinterpret_cast<float *>(rka + MH);
     float *red = ru + MH * DIM;  // per-wave partials, 8 per wave
+    // lowest ray of each direction this iteration (INT_MAX for none; reset by that ray after use)
+    int *own = reinterpret_cast<int *>(red + 8 * NW);
     float *Rg = sa.Rk + (long)cid * D;
     for (int k = t; k < D; k += NT) {
         Ra[k] = Rg[k];
         gk[k] = 0.0f;
+        own[k] = 0x7fffffff;
+    }
+    if (t == 0) {
+        Ra[D] = 0.0f;
+        Rb[D] = 0.0f;
     }
     const Vol<DIM, LAYOUT> vol(p.g);
     const float inv_h[3] = {p.g.inv_h[0], p.g.inv_h[1], p.g.inv_h[2]};
@@ -1741,36 +1750,62 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
             }
         }
         __syncthreads();
-        // sampled directions: the first ray of each direction sums its rays in order. Every lane
-        // walks all rays, eight at a time with their loads issued together and no branch on the
-        // loaded values (a ray of another direction adds +0, which leaves the sum unchanged: it
-        // starts at +0 and so is never -0)
-        for (int r = t; r < M; r += NT) {
-            const int dk = ray_dir[r];
-            bool first = true;
-            float g = 0.0f;
-            int r2 = 0;
-            for (; r2 + 8 <= M; r2 += 8) {
-                int dd[8];
-                float gg[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    dd[u] = ray_dir[r2 + u];
-                    gg[u] = ray_g[r2 + u];
+        // sampled directions: the first ray of each direction sums its rays in order (the sum starts
+        // at +0, so it is never -0 and adding +0 leaves it unchanged).
+        if (M <= 64) {
+            // all rays in wave 0: the lowest ray of each direction comes from an LDS minimum; the few
+            // later rays of a direction are then added, lowest first, by that direction's first ray
+            if (wave == 0) {
+                const bool has = lane < M;
+                const int dk = has ? ray_dir[lane] : 0;
+                const float gr = has ? ray_g[lane] : 0.0f;
+                if (has) atomicMin(&own[dk], lane);
+                // one wave's LDS operations complete in order: every lane's minimum is in
+                const bool first = has && own[dk] == lane;
+                float g = 0.0f + gr;
+                uint64_t later = __builtin_amdgcn_ballot_w64(has && !first);
+                while (later) {
+                    const int j = __builtin_amdgcn_readfirstlane(__builtin_ctzll(later));
+                    later &= later - 1;
+                    const int dj = __builtin_amdgcn_readlane(dk, j);
+                    const float gj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gr), j));
+                    if (first && dk == dj) g += gj;
                 }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const bool same = dd[u] == dk;
-                    first = first && !(same && r2 + u < r);
-                    g += same && r2 + u >= r ? gg[u] : 0.0f;
+                if (first) {
+                    gk[dk] = g;
+                    own[dk] = 0x7fffffff;
                 }
             }
-            for (; r2 < M; ++r2) {
-                const bool same = ray_dir[r2] == dk;
-                first = first && !(same && r2 < r);
-                g += same && r2 >= r ? ray_g[r2] : 0.0f;
+        } else {
+            // Every lane walks all rays, eight at a time with their loads issued together and no branch
+            // on the loaded values (a ray of another direction adds +0)
+            for (int r = t; r < M; r += NT) {
+                const int dk = ray_dir[r];
+                bool first = true;
+                float g = 0.0f;
+                int r2 = 0;
+                for (; r2 + 8 <= M; r2 += 8) {
+                    int dd[8];
+                    float gg[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        dd[u] = ray_dir[r2 + u];
+                        gg[u] = ray_g[r2 + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const bool same = dd[u] == dk;
+                        first = first && !(same && r2 + u < r);
+                        g += same && r2 + u >= r ? gg[u] : 0.0f;
+                    }
+                }
+                for (; r2 < M; ++r2) {
+                    const bool same = ray_dir[r2] == dk;
+                    first = first && !(same && r2 < r);
+                    g += same && r2 >= r ? ray_g[r2] : 0.0f;
+                }
+                if (first) gk[dk] = g;
             }
-            if (first) gk[dk] = g;
         }
         __syncthreads();
         n += 1;
@@ -1779,16 +1814,15 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
         const float relax = fminf(1.0f, half_eps * sa.lambda);
         float mv = 0.0f, sum = 0.0f, mx = 0.0f;
         int clamped = 0, finite_r = 1;
-        // neighbour rows of four directions are loaded before any of them is used
+        // neighbour rows of four directions are loaded before any of them is used; every entry is
+        // read without a branch (the padding index D reads +0, which leaves the sum unchanged), so
+        // a row's LDS reads are all issued before the first is added
+        // (a direction past D loads the last row, unused)
         const uint4 *nbrow = reinterpret_cast<const uint4 *>(sa.nb);
-        const uint4 none = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
         for (int k0 = t; k0 < D; k0 += 4 * NT) {
             uint4 pre[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int k = k0 + NT * b;
-                pre[b] = k < D ? nbrow[(long)k * sa.nb_chunks] : none;
-            }
+            for (int b = 0; b < 4; ++b) pre[b] = nbrow[min(k0 + NT * b, D - 1) * sa.nb_chunks];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int k = k0 + NT * b;
@@ -1797,16 +1831,17 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
                     float ms = 0.0f;
                     int cnt = 0;
                     for (int ch = 0; ch < sa.nb_chunks; ++ch) {
-                        const uint4 w = ch == 0 ? pre[b] : nbrow[(long)k * sa.nb_chunks + ch];
+                        const uint4 w = ch == 0 ? pre[b] : nbrow[k * sa.nb_chunks + ch];
                         const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+                        float rv[8];
 #pragma unroll
                         for (int t8 = 0; t8 < 8; ++t8) {
                             const uint32_t j = (wv[t8 >> 1] >> (16 * (t8 & 1))) & 0xffffu;
-                            if (j != 0xffffu) {
-                                ms += Rold[j];
-                                ++cnt;
-                            }
+                            rv[t8] = Rold[j];
+                            cnt += j != (uint32_t)D;
                         }
+#pragma unroll
+                        for (int t8 = 0; t8 < 8; ++t8) ms += rv[t8];
                     }
                     const float Rk0 = Rold[k];
                     const float mk = cnt > 0 ? ms / (float)cnt : Rk0;

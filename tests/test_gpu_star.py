@@ -53,6 +53,10 @@ def make_ctx(snk, stream, wl, smooth, lanes=0):
 def workload(which):
     if which == "tiny":
         wl = synth.tiny_config()
+    elif which == "tiny96":
+        # more rays than one wave holds: the duplicate-direction pass scans every ray
+        wl = synth.tiny_config()
+        wl.params = wl.params.replace(n_rays=96)
     elif which == "aniso":
         wl = synth.slab_config(n_target=40, shape_xyz=(96, 80, 40), n_iter=50)
     else:
@@ -72,12 +76,14 @@ def inner_seeds(wl, n, rng):
 
 
 @pytest.mark.parametrize("which,smooth,lanes", [("tiny", 0.0, 0), ("tiny", 0.6, 64), ("aniso", 0.3, 0),
-                                                ("aniso", 0.3, 64), ("plane", 0.3, 0), ("plane", 0.3, 64)])
+                                                ("aniso", 0.3, 64), ("plane", 0.3, 0), ("plane", 0.3, 64),
+                                                ("tiny96", 0.3, 0), ("tiny96", 0.3, 64)])
 def test_star_one_step_parity(snk, stream, which, smooth, lanes):
     """Teacher forced: both sides start from the oracle's state after a few star iterations (and,
     for the first check, from untied random radii), rounded to FP32; one GPU iteration must give
     every direction's radius step, the centre step and the energy of the oracle's iteration; one
-    wave (64 lanes) or two (the automatic 128) per contour."""
+    wave (64 lanes) or two (the automatic 128) per contour; up to 64 rays (one wave's duplicate-
+    direction pass) or 96 (every lane scanning all rays)."""
     wl = workload(which)
     p = wl.params
     rng = np.random.default_rng(2)
