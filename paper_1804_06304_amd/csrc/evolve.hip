@@ -1935,7 +1935,9 @@ __global__ __launch_bounds__(NT, NT == 128 ? 4 : 1) void star_kernel(EvolveArgs 
         Rold = Rnew;
         Rnew = t;
         ++ran;
-        __syncthreads();
+        // no barrier here: the next iteration first writes the ray tables and the next block's
+        // draws, which nothing reads after this iteration's last barrier, and its barrier after
+        // the ray tables orders everything else
     }
     if (budget > 0) {
         for (int k = t; k < D; k += NT) Rg[k] = Rold[k];
