@@ -262,7 +262,11 @@ snk_status snk_seed_lattice(snk_ctx *ctx, double pitch, int64_t *n_out);
  * n_iter = 0 runs one culling pass. Timing (snk_get_timing): evolve_ms covers the evolve launches
  * and the passes; evolved counts every contour-iteration of the call. After each pass the next chunk
  * launches only the contours still active (their indices compacted on the device; star contours
- * launch every slot), which changes where contours run, never their results. */
+ * launch every slot), which changes where contours run, never their results. Without competition
+ * (sphere contours, no repulsion, n_iter > 0) a pass decides each contour alone, so the call runs
+ * one evolution that applies the passes between chunks itself (an active contour above the
+ * threshold at a pass point retires in the evolve kernel, whose workgroup slot then goes to the
+ * next contour) and one pass after it: the same outcome, with no relaunches. */
 snk_status snk_evolve_cull(snk_ctx *ctx, int32_t n_iter, int32_t cull_every, int32_t grace_iters);
 
 /* Soft repulsion between neighbouring contours (not in the paper: its contours are independent

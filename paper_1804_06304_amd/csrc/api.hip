@@ -33,6 +33,8 @@ struct snk_ctx {
     // culling passes of snk_evolve_cull: threshold (NaN: params.e0) and competition
     double cull_thr = NAN;
     int cull_compete = 1;
+    // passes applied inside the evolve kernel (every 0: none): pass interval, grace, run length
+    int cull_in_every = 0, cull_in_grace = 0, cull_in_end = 0;
 
     // soft repulsion (kappa 0: off): strength, iterations per neighbour snapshot, buffers
     double repel_kappa = 0.0;
@@ -632,6 +634,12 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     }
     snk::EvolveArgs a{};
     a.p = job_params(c);
+    if (c->cull_in_every > 0) {
+        a.p.cull_every = c->cull_in_every;
+        a.p.cull_grace = c->cull_in_grace;
+        a.p.cull_end = c->cull_in_end;
+        a.p.cull_thr = (float)(std::isnan(c->cull_thr) ? c->P.e0 : c->cull_thr);
+    }
     a.st = c->d_st;
     a.n = idx ? n_launch : (int)c->n;
     a.idx = idx;
@@ -708,6 +716,7 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     } else {
         for (int part = 0, done = 0; part < parts; ++part) {
             a.n_iter = (int)((int64_t)n_iter * (part + 1) / parts) - done;
+            a.p.cull_base = done;
             done += a.n_iter;
             HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
         }
@@ -1223,6 +1232,23 @@ snk_status snk_evolve_cull(snk_ctx *c, int32_t n_iter, int32_t cull_every, int32
     }
     HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
     HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
+    if (!c->cull_compete && compact && c->repel_kappa <= 0.0 && n_iter > 0) {
+        // without competition a pass judges each contour alone, so one evolution applies the
+        // passes between its chunks itself (an active contour above the threshold at a pass point
+        // retires at once and its workgroup slot goes to the next contour) and one pass at the end
+        // judges the rest: the same outcome as chunks and passes, with no relaunches
+        c->cull_in_every = cull_every;
+        c->cull_in_grace = grace_iters;
+        c->cull_in_end = n_iter;
+        st = run_evolve(c, n_iter, false, false);
+        c->cull_in_every = 0;
+        if (st != SNK_OK) return st;
+        st = run_select(c, 1, n_iter < grace_iters ? INT32_MAX : 0);
+        if (st != SNK_OK) return st;
+        HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
+        c->ev_evo = true;
+        return SNK_OK;
+    }
     int32_t done = 0;
     int live = -1;   // active contours after the last pass (-1: every contour, before the first)
     do {

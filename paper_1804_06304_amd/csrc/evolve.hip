@@ -1230,6 +1230,14 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
                 streak = small ? min(streak + 1, 255) : 0;
                 if (p.conv_window > 0 && streak >= p.conv_window) st = SNK_CONVERGED;
             }
+            // a culling pass without competition judges each contour alone: at the run's pass
+            // points an active contour above the threshold retires here and frees its slot at once
+            // (the pass after the evolution treats the others as the passes between chunks would)
+            if (p.cull_every > 0 && st == SNK_ACTIVE) {
+                const int r = p.cull_base + it + 1;
+                if (r % p.cull_every == 0 && r >= p.cull_grace && r < p.cull_end && !(E <= p.cull_thr))
+                    st = SNK_CULLED;
+            }
             status = (uint8_t)uni<G>((int)(st | flag));
             streak = uni<G>(streak);
             R = uni<G>(R);

@@ -187,6 +187,41 @@ def test_cull_free_run_lax_threshold(snk):
     assert abs(t["evolved"] - ran) <= 0.05 * ran
 
 
+@pytest.mark.parametrize("grace", [0, 50])
+def test_cull_in_kernel_equals_chunked_passes(snk, grace):
+    """Without competition one snk_evolve_cull call applies the passes inside the evolution (two
+    launches of 50 iterations, passes every 20, so one pass point falls inside each launch); a
+    chain of 20-iteration calls, each ending with its own pass and its grace shifted by the
+    iterations already run, takes every pass between launches instead. Both must retire the same
+    contours at the same iterations, bit for bit."""
+    wl = synth.tiny_config()
+    thr = 0.25 * wl.params.e0
+    N, k = 100, 20
+    a = make_ctx(snk, wl)
+    a.set_cull(thr, False)
+    a.seed_lattice()
+    a.evolve_cull(N, k, grace)
+    ga, ra, ta = a.get_state(), a.read(), a.get_timing()
+    a.close()
+    b = make_ctx(snk, wl)
+    b.set_cull(thr, False)
+    b.seed_lattice()
+    evolved = 0
+    for j in range(N // k):
+        b.evolve_cull(k, k, max(0, grace - j * k))
+        evolved += b.get_timing()["evolved"]
+    gb, rb = b.get_state(), b.read()
+    b.close()
+    culled = int(((ga["status"] & 0x0F) == oracle.CULLED).sum())
+    say(f"in-kernel culling, grace {grace}: {len(ga['radii'])} contours, {culled} culled, "
+        f"contour-iterations {ta['evolved']} (chunked {evolved})")
+    assert culled > 0
+    for key in ("centers", "radii", "iters", "status", "streak"):
+        assert np.array_equal(ga[key], gb[key]), key
+    assert np.array_equal(ra["e_mc"], rb["e_mc"])
+    assert ta["evolved"] == evolved
+
+
 def test_set_cull_errors(snk):
     wl = synth.tiny_config()
     ctx = make_ctx(snk, wl)
