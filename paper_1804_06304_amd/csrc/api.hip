@@ -634,12 +634,21 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     }
     snk::EvolveArgs a{};
     a.p = job_params(c);
-    if (c->cull_in_every > 0) {
-        a.p.cull_every = c->cull_in_every;
-        a.p.cull_grace = c->cull_in_grace;
-        a.p.cull_end = c->cull_in_end;
-        a.p.cull_thr = (float)(std::isnan(c->cull_thr) ? c->P.e0 : c->cull_thr);
-    }
+    a.p.cull_first = -1;
+    if (c->cull_in_every > 0) a.p.cull_thr = (float)(std::isnan(c->cull_thr) ? c->P.e0 : c->cull_thr);
+    // the pass points r = every, 2 every, ... of the run with grace <= r < end that fall in the
+    // launch's iterations base + 1 .. base + len, as 0-based iterations of the launch
+    auto cull_points = [&](int base, int len) {
+        a.p.cull_first = -1;
+        if (c->cull_in_every <= 0) return;
+        const int every = c->cull_in_every;
+        const int lo = std::max(base + 1, c->cull_in_grace), hi = std::min(base + len, c->cull_in_end - 1);
+        const int first = (lo + every - 1) / every * every;
+        if (lo > hi || first > hi) return;
+        a.p.cull_first = first - base - 1;
+        a.p.cull_every = every;
+        a.p.cull_last = hi / every * every - base - 1;
+    };
     a.st = c->d_st;
     a.n = idx ? n_launch : (int)c->n;
     a.idx = idx;
@@ -716,7 +725,7 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     } else {
         for (int part = 0, done = 0; part < parts; ++part) {
             a.n_iter = (int)((int64_t)n_iter * (part + 1) / parts) - done;
-            a.p.cull_base = done;
+            cull_points(done, a.n_iter);
             done += a.n_iter;
             HIPTRY(c, snk::launch_evolve(a, c->P.dim, lanes, unroll, layout, trace, c->stream));
         }

@@ -975,6 +975,7 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
     const float inv_npts = 1.0f / (float)(p.M * p.L);
     const float tol2 = p.conv_tol * p.conv_tol;
     int ran = 0;
+    int cull_next = p.cull_first;  // this launch's next culling pass point (-1: none)
     Tile tile;
     tile.valid = false;
 
@@ -1233,10 +1234,12 @@ __device__ void run_group(const JobParams &p, DevContour *slot, int n_iter, int 
             // a culling pass without competition judges each contour alone: at the run's pass
             // points an active contour above the threshold retires here and frees its slot at once
             // (the pass after the evolution treats the others as the passes between chunks would)
-            if (p.cull_every > 0 && st == SNK_ACTIVE) {
-                const int r = p.cull_base + it + 1;
-                if (r % p.cull_every == 0 && r >= p.cull_grace && r < p.cull_end && !(E <= p.cull_thr))
-                    st = SNK_CULLED;
+            if (it == cull_next) {
+                // kept a branch (an empty volatile statement cannot be executed speculatively):
+                // selects in its place would cost every iteration of every run
+                __asm__ volatile("");
+                if (st == SNK_ACTIVE && !(E <= p.cull_thr)) st = SNK_CULLED;
+                cull_next = cull_next + p.cull_every <= p.cull_last ? cull_next + p.cull_every : -1;
             }
             status = (uint8_t)uni<G>((int)(st | flag));
             streak = uni<G>(streak);

@@ -44,11 +44,11 @@ struct JobParams {
     float dR, eps0, r_lo, r_hi, conv_tol;
     int conv_window;
     float in_slope, out_slope;   // 2 / (rho dR) and 1 / dR
-    // culling passes without competition applied inside the evolution (cull_every 0: off): after
-    // run iteration r = cull_base + (iterations of this launch) with r a multiple of cull_every,
-    // cull_grace <= r < cull_end, an active contour whose energy is not <= cull_thr retires
-    int cull_every, cull_base, cull_end, cull_grace;
-    float cull_thr;
+    // culling passes without competition applied inside the evolution: after the launch's
+    // iterations cull_first, cull_first + cull_every, ... up to cull_last (0-based, cull_first < 0:
+    // none) an active contour whose energy is not <= cull_thr retires
+    int cull_first = -1, cull_every = 0, cull_last = -1;
+    float cull_thr = 0.0f;
 };
 
 // snk_params.flags bits.
