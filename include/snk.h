@@ -89,7 +89,7 @@ typedef enum { SNK_U8 = 0, SNK_U16 = 1, SNK_F32 = 2 } snk_dtype;
  *                the weight form (Eqs. (7)-(10)), every sample contributes instead of only those
  *                in the two ramps; A and B_R are unchanged (not in the paper: a variance-reduction
  *                option). Monte-Carlo only (SNK_EINVAL with bit 1); lanes_per_contour >= 64 and
- *                layout 1 or 2 (two pair-points in flight are used); plain context path only.
+ *                layout 1, 2 or 4 (two pair-points in flight are used); plain context path only.
  *                Other bits must be zero.
  */
 typedef struct snk_params {
@@ -134,19 +134,20 @@ snk_status snk_set_params(snk_ctx *ctx, const snk_params *params);
  * contours share one wave64; 64: one wave; 128 or 256: a workgroup of 2 or 4 waves), antithetic
  * pair-points whose gathers one lane issues before consuming them (0 = automatic, 1, 2 or 4; 4 is
  * taken with 64 or 128 lanes and outside snk_trace_step, otherwise it runs as 2), and the
- * layout the kernel reads the smoothed volume from (0 = automatic: quad in 3D and column pairs in 2D
- * when they fit, else plain; 1 = plain FP32,
+ * layout the kernel reads the smoothed volume from (0 = automatic: column pairs when they fit, else
+ * plain; 1 = plain FP32,
  * 2 = quad: one 16-byte record per voxel with its +x, +y, +xy neighbours, 4x the FP32 volume; needs
  * 16 * nx*ny*nz below 2 GiB and ny, nz <= 65535, else SNK_EINVAL at the next evolve; 3 = plain FP32
- * with 64-bit addressing, the path of volumes beyond 2 GiB; 4 = column pairs, 2D only: (J(x,y),
- * J(x,y+1)) per pixel, twice the FP32 image, so one 16-byte load fetches a cell's four corners; needs
- * 8 * nx*ny below 2 GiB and ny <= 65535, else SNK_EINVAL at the next evolve; the exact and
- * gradient-form sums read the plain copy instead). Layouts change only how voxels are
+ * with 64-bit addressing, the path of volumes beyond 2 GiB; 4 = column pairs: (J(x,y,z),
+ * J(x,y+1,z)) per voxel, twice the FP32 volume, so one 16-byte load fetches the four corners of a
+ * cell's plane; needs 8 * nx*ny*nz below 2 GiB and ny, nz <= 65535, else SNK_EINVAL at the next
+ * evolve; the exact sums, and in 2D the gradient-form sums and LDS boxes, read the plain copy
+ * instead). Layouts change only how voxels are
  * fetched: results are bit-identical across layouts and across pair-point counts, and depend on
  * lanes_per_contour only through FP32 summation order. */
 snk_status snk_set_launch(snk_ctx *ctx, int32_t lanes_per_contour, int32_t pairs_in_flight, int32_t layout);
 
-/* LDS box of the Monte-Carlo evolution (whole-wave launch shapes, layouts 1 and 2): each contour
+/* LDS box of the Monte-Carlo evolution (whole-wave launch shapes, layouts 1, 2 and 4): each contour
  * keeps a box of the smoothed volume around its sample ball (Sec. II-E) in on-chip memory, staged
  * with a margin and re-staged only when the ball leaves it, and reads the trilinear corners of its
  * samples from there. tile_voxels = -1: automatic (boxes only when more than four contours per

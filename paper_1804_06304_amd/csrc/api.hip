@@ -325,8 +325,7 @@ snk_status run_prepass(snk_ctx *c) {
         return fail(c, SNK_EINVAL, "sigma_pre too large for the pre-pass tile (LDS > 64 KiB)");
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
     if (layout < 0)
-        return fail(c, SNK_EINVAL, c->layout_req == 4 && c->P.dim == 3 ? "the column-pair layout is 2D only"
-                                                                       : "volume too large for the requested layout");
+        return fail(c, SNK_EINVAL, "volume too large for the requested layout");
     snk_status lst = ensure_layout_buffer(c, layout);
     if (lst != SNK_OK) return lst;
     a.Jq = layout == snk::kBufferQuad ? c->Jq : nullptr;
@@ -394,7 +393,8 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
         return s;
     }
     if (c->tile_req == 0 || c->n <= 0 || c->cus <= 0 || c->lds_per_cu <= 0) return s;
-    if (layout != snk::kBufferQuad && layout != snk::kBufferPlain) return s;
+    if (layout != snk::kBufferQuad && layout != snk::kBufferPlain && !(c->P.dim == 3 && layout == snk::kBufferPair))
+        return s;
     const int64_t pairs = (int64_t)(M / 2) * c->P.n_radial;
     const int64_t per_cu = (c->n + c->cus - 1) / c->cus;
     if (per_cu <= 4) return s;
@@ -429,15 +429,15 @@ McShape mc_shape(snk_ctx *c, int M, int layout) {
 snk_status ensure_layout(snk_ctx *c) {
     const int layout = snk::volume_layout(c->P.dim, c->nx, c->ny, c->nz, c->layout_req);
     if (layout < 0)
-        return fail(c, SNK_EINVAL, c->layout_req == 4 && c->P.dim == 3 ? "the column-pair layout is 2D only"
-                                                                       : "volume too large for the requested layout");
+        return fail(c, SNK_EINVAL, "volume too large for the requested layout");
     if (layout == c->layout) return SNK_OK;
     snk_status st = ensure_layout_buffer(c, layout);
     if (st != SNK_OK) return st;
     if (layout == snk::kBufferQuad)
         HIPTRY(c, snk::launch_pack_quad(c->J, c->Jq, (int)c->nx, (int)c->ny, (int)c->nz, c->stream));
     if (layout == snk::kBufferPair)
-        HIPTRY(c, snk::launch_pack_pair(c->J, reinterpret_cast<float2 *>(c->Jq), (int)c->nx, (int)c->ny, c->stream));
+        HIPTRY(c, snk::launch_pack_pair(c->J, reinterpret_cast<float2 *>(c->Jq), (int)c->nx, (int)c->ny, (int)c->nz,
+                                          c->stream));
     c->layout = layout;
     return SNK_OK;
 }
@@ -561,7 +561,7 @@ snk_status run_star(snk_ctx *c, int32_t n_iter, bool standalone) {
         HIPTRY(c, hipMemsetAsync(c->d_counters, 0, sizeof(unsigned long long), c->stream));
         HIPTRY(c, hipEventRecord(c->ev[2], c->stream));
     }
-    const int layout = c->layout == snk::kBufferPair ? snk::kBufferPlain : c->layout;  // star: single voxels
+    const int layout = c->layout;
     HIPTRY(c, snk::launch_star(a, sa, c->P.dim, lanes, layout, c->stream));
     if (standalone) {
         HIPTRY(c, hipEventRecord(c->ev[3], c->stream));
@@ -659,7 +659,8 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
     // exact sums read single voxels from J (the plain layout); so does the gradient-form kernel in
     // place of column pairs
     const bool gradi = (c->P.flags & snk::kFlagGradI) != 0;
-    int layout = (exact && c->layout == snk::kBufferQuad) || ((exact || gradi) && c->layout == snk::kBufferPair)
+    int layout = (exact && (c->layout == snk::kBufferQuad || c->layout == snk::kBufferPair)) ||
+                         (gradi && c->P.dim == 2 && c->layout == snk::kBufferPair)
                      ? snk::kBufferPlain
                      : c->layout;
     int lanes, unroll;
@@ -672,16 +673,16 @@ snk_status run_evolve(snk_ctx *c, int32_t n_iter, bool trace, bool standalone = 
         unroll = sh.unroll;
         // LDS boxes: whole-wave groups over a buffer layout
         if (sh.tile > 0 && (lanes < 64 || layout == snk::kGlobalPlain))
-            return fail(c, SNK_EINVAL, "LDS boxes need lanes_per_contour >= 64 and layout 1 or 2");
+            return fail(c, SNK_EINVAL, "LDS boxes need lanes_per_contour >= 64 and layout 1, 2 or 4");
         // with a box, the iterations whose ball does not fit read the plain copy
-        if (sh.tile > 0 && layout == snk::kBufferPair) layout = snk::kBufferPlain;
+        if (sh.tile > 0 && layout == snk::kBufferPair && c->P.dim == 2) layout = snk::kBufferPlain;
         a.tile_cap = sh.tile;
         if (c->P.flags & snk::kFlagGradI) {
             // gradient-form centre force: whole-wave groups, two pair-points in flight
             if (c->lanes > 0 && c->lanes < 64)
                 return fail(c, SNK_EINVAL, "the gradient-form centre force needs lanes_per_contour >= 64");
             if (layout == snk::kGlobalPlain)
-                return fail(c, SNK_EINVAL, "the gradient-form centre force needs layout 1 or 2");
+                return fail(c, SNK_EINVAL, "the gradient-form centre force needs layout 1, 2 or 4");
             lanes = std::max(lanes, 64);
             unroll = 2;
         }

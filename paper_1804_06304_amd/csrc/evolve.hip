@@ -385,7 +385,9 @@ struct Vol {
             rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.Jq, (short)0, (int)((long)nxy * g.nz * 16),
                                                      (int)kBufferWord3);
         } else if constexpr (LAYOUT == kBufferPair) {
-            rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.Jq, (short)0, (int)((long)nxy * 8), (int)kBufferWord3);
+            so2 = nxy * 8;
+            rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.Jq, (short)0, (int)((long)nxy * (DIM == 3 ? g.nz : 1) * 8),
+                                                     (int)kBufferWord3);
         }
     }
     // One voxel value (plain layouts).
@@ -416,12 +418,20 @@ struct Vol {
                 c.v[7] = __uint_as_float(b.w);
             }
         } else if constexpr (LAYOUT == kBufferPair) {
-            // (J(x,y), J(x,y+1)) then (J(x+1,y), J(x+1,y+1))
-            const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)idx * 8, 0, 0);
+            // (J(x,y), J(x,y+1)) then (J(x+1,y), J(x+1,y+1)), of plane z and then of plane z+1
+            const int vo = (int)idx * 8;
+            const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vo, 0, 0);
             c.v[0] = __uint_as_float(a.x);
             c.v[2] = __uint_as_float(a.y);
             c.v[1] = __uint_as_float(a.z);
             c.v[3] = __uint_as_float(a.w);
+            if constexpr (DIM == 3) {
+                const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rsrc, vo, so2, 0);
+                c.v[4] = __uint_as_float(b.x);
+                c.v[6] = __uint_as_float(b.y);
+                c.v[5] = __uint_as_float(b.z);
+                c.v[7] = __uint_as_float(b.w);
+            }
         } else if constexpr (LAYOUT == kBufferPlain) {
             const int vo = (int)idx * 4;
             const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(rsrc, vo, 0, 0);
@@ -1364,6 +1374,10 @@ hipError_t launch_gradi_l(const EvolveArgs &a, int layout, hipStream_t s) {
     if (layout == kBufferPlain)
         return stage ? launch_t<DIM, G, 2, TRACE, kBufferPlain, false, true, true>(a, s)
                      : launch_t<DIM, G, 2, TRACE, kBufferPlain, false, false, true>(a, s);
+    if constexpr (DIM == 3)
+        if (layout == kBufferPair)
+            return stage ? launch_t<DIM, G, 2, TRACE, kBufferPair, false, true, true>(a, s)
+                         : launch_t<DIM, G, 2, TRACE, kBufferPair, false, false, true>(a, s);
     return hipErrorInvalidValue;
 }
 
@@ -1402,15 +1416,15 @@ hipError_t launch_l(const EvolveArgs &a, int layout, hipStream_t s) {
         if (a.tile_cap > 0) {
             if (layout == kBufferQuad) return launch_t<DIM, G, U, TRACE, kBufferQuad, false, true>(a, s);
             if (layout == kBufferPlain) return launch_t<DIM, G, U, TRACE, kBufferPlain, false, true>(a, s);
+            if constexpr (DIM == 3)
+                if (layout == kBufferPair) return launch_t<DIM, G, U, TRACE, kBufferPair, false, true>(a, s);
             return hipErrorInvalidValue;
         }
     } else {
         if (a.tile_cap > 0) return hipErrorInvalidValue;
     }
-    if constexpr (DIM == 2) {
-        if (layout == kBufferPair) return launch_t<DIM, G, U, TRACE, kBufferPair>(a, s);
-    }
     switch (layout) {
+        case kBufferPair: return launch_t<DIM, G, U, TRACE, kBufferPair>(a, s);
         case kBufferQuad: return launch_t<DIM, G, U, TRACE, kBufferQuad>(a, s);
         case kBufferPlain: return launch_t<DIM, G, U, TRACE, kBufferPlain>(a, s);
         case kGlobalPlain: return launch_t<DIM, G, U, TRACE, kGlobalPlain>(a, s);
@@ -1976,6 +1990,9 @@ hipError_t launch_star_t(const EvolveArgs &a, const StarArgs &sa, int layout, hi
         case kBufferQuad:
             hipLaunchKernelGGL((star_kernel<DIM, kBufferQuad, NT>), dim3(a.n), dim3(NT), lds, s, a, sa);
             break;
+        case kBufferPair:
+            hipLaunchKernelGGL((star_kernel<DIM, kBufferPair, NT>), dim3(a.n), dim3(NT), lds, s, a, sa);
+            break;
         case kBufferPlain:
             hipLaunchKernelGGL((star_kernel<DIM, kBufferPlain, NT>), dim3(a.n), dim3(NT), lds, s, a, sa);
             break;
@@ -2054,11 +2071,17 @@ namespace {
 template <int DIM, int G, int U>
 int stage_blocks_t(int layout) {
     int nb = 0;
-    hipError_t e = layout == kBufferQuad
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, evolve_kernel<DIM, G, U, false, kBufferQuad, false, true, false>, Grp<G>::NT, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, evolve_kernel<DIM, G, U, false, kBufferPlain, false, true, false>, Grp<G>::NT, 0);
+    hipError_t e;
+    if (layout == kBufferQuad)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, evolve_kernel<DIM, G, U, false, kBufferQuad, false, true, false>, Grp<G>::NT, 0);
+    else if (DIM == 3 && layout == kBufferPair)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, evolve_kernel<DIM, G, U, false, DIM == 3 ? kBufferPair : kBufferPlain, false, true, false>,
+            Grp<G>::NT, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, evolve_kernel<DIM, G, U, false, kBufferPlain, false, true, false>, Grp<G>::NT, 0);
     return e == hipSuccess ? nb : 0;
 }
 
@@ -2082,7 +2105,7 @@ int stage_blocks_g(int lanes, int unroll, int layout) {
 }  // namespace
 
 int evolve_stage_blocks_per_cu(int dim, int lanes, int unroll, int layout) {
-    if (layout != kBufferQuad && layout != kBufferPlain) return 0;
+    if (layout != kBufferQuad && layout != kBufferPlain && !(dim == 3 && layout == kBufferPair)) return 0;
     return dim == 2 ? stage_blocks_g<2>(lanes, unroll, layout) : stage_blocks_g<3>(lanes, unroll, layout);
 }
 

@@ -287,15 +287,16 @@ __global__ __launch_bounds__(256) void pack_pair_kernel(const float *__restrict_
                                                         int nx, int ny) {
     const int x = blockIdx.x * 256 + threadIdx.x;
     const int y = blockIdx.y;
+    const long plane = (long)blockIdx.z * ny * nx;
     if (x >= nx) return;
-    const long row = (long)y * nx, row1 = (long)min(y + 1, ny - 1) * nx;
+    const long row = plane + (long)y * nx, row1 = plane + (long)min(y + 1, ny - 1) * nx;
     Jp[row + x] = make_float2(J[row + x], J[row1 + x]);
 }
 }  // namespace
 
-hipError_t launch_pack_pair(const float *J, float2 *Jp, int nx, int ny, hipStream_t s) {
-    if (nx <= 0 || ny <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_pair_kernel, dim3((nx + 255) / 256, ny), dim3(256), 0, s, J, Jp, nx, ny);
+hipError_t launch_pack_pair(const float *J, float2 *Jp, int nx, int ny, int nz, hipStream_t s) {
+    if (nx <= 0 || ny <= 0 || nz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_pair_kernel, dim3((nx + 255) / 256, ny, nz), dim3(256), 0, s, J, Jp, nx, ny);
     return hipGetLastError();
 }
 

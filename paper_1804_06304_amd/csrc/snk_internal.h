@@ -61,27 +61,27 @@ enum VolumeLayout {
     kGlobalPlain = 0,  // FP32 [z][y][x], 64-bit addressing (any size)
     kBufferPlain = 1,  // FP32 [z][y][x] through a buffer descriptor (< 2 GiB, 24-bit strides)
     kBufferQuad = 2,   // quad records through a buffer descriptor (< 2 GiB, 24-bit strides)
-    kBufferPair = 3,   // 2D: column pairs (J(x,y), J(x,y+1)) per pixel through a buffer descriptor
-                       // (< 2 GiB): one 16-byte load at (x, y) fetches the cell's four corners
+    kBufferPair = 3,   // column pairs (J(x,y,z), J(x,y+1,z)) per voxel through a buffer descriptor
+                       // (< 2 GiB): one 16-byte load at (x, y, z) fetches the four corners of the
+                       // cell's plane z
 };
 
-// Layout for a volume: `requested` 0 = automatic (quad in 3D when it fits, where one load fetches two
-// of the four corner pairs; column pairs in 2D, where one load fetches all four corners at twice the
-// plain footprint, while the quad records' 4x footprint falls out of the caches), 1 = plain, 2 = quad,
-// 3 = plain with 64-bit addressing, 4 = column pairs (2D). Returns the layout, or -1 if the request
-// cannot be met.
+// Layout for a volume: `requested` 0 = automatic (column pairs when they fit: one 16-byte load
+// fetches the four corners of a cell's plane, as from the quad records, at half their footprint, so
+// more of the volume stays in the caches and the pre-pass writes less; else plain), 1 = plain,
+// 2 = quad, 3 = plain with 64-bit addressing, 4 = column pairs. Returns the layout, or -1 if the
+// request cannot be met.
 inline int volume_layout(int dim, int64_t nx, int64_t ny, int64_t nz, int requested) {
     const int64_t vox = nx * ny * nz;
     const bool strides = nx < (1 << 23) && (dim == 2 || nx * ny < (1 << 23));
     const bool plain_ok = strides && vox * 4 < ((int64_t)1 << 31);
     const bool quad_ok = strides && vox * 16 < ((int64_t)1 << 31) && ny <= 65535 && nz <= 65535;
-    const bool pair_ok = dim == 2 && strides && vox * 8 < ((int64_t)1 << 31) && ny <= 65535;
+    const bool pair_ok = strides && vox * 8 < ((int64_t)1 << 31) && ny <= 65535 && nz <= 65535;
     if (requested == 4) return pair_ok ? kBufferPair : -1;
     if (requested == 3) return kGlobalPlain;
     if (requested == 2) return quad_ok ? kBufferQuad : -1;
     if (requested == 1) return plain_ok ? kBufferPlain : kGlobalPlain;
-    if (dim == 2) return pair_ok ? kBufferPair : (plain_ok ? kBufferPlain : kGlobalPlain);
-    return quad_ok ? kBufferQuad : (plain_ok ? kBufferPlain : kGlobalPlain);
+    return pair_ok ? kBufferPair : (plain_ok ? kBufferPlain : kGlobalPlain);
 }
 
 // Star-shaped contours: direction tables (antipode, symmetric neighbour graph in CSR form), the
@@ -175,7 +175,7 @@ hipError_t launch_prepass(const PrepassArgs &a, hipStream_t s);
 bool prepass_lds_limit_ok(int rx, int ry, int rz);
 // Pack J into the quad layout (one record per voxel, neighbours clamped at the upper edges).
 hipError_t launch_pack_quad(const float *J, float4 *Jq, int nx, int ny, int nz, hipStream_t s);
-hipError_t launch_pack_pair(const float *J, float2 *Jp, int nx, int ny, hipStream_t s);
+hipError_t launch_pack_pair(const float *J, float2 *Jp, int nx, int ny, int nz, hipStream_t s);
 // lanes: contour group size 16, 32, 64, 128 or 256; unroll: pair-points in flight (1 or 2);
 // layout: a VolumeLayout (batched launches and LDS boxes: buffer layouts only). a.tile_cap > 0
 // (whole-wave groups, Monte-Carlo sums) stages each contour's ball in an LDS box of that many voxels.

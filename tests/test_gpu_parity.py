@@ -202,7 +202,7 @@ def test_one_step_parity_2d(snk, stream, lanes, layout):
 
 @pytest.mark.parametrize("lanes,unroll,layout", [(16, 1, 0), (16, 2, 1), (32, 1, 2), (32, 2, 3), (64, 1, 1),
                                                  (64, 2, 2), (64, 4, 3), (128, 1, 3), (128, 2, 1), (128, 4, 2),
-                                                 (256, 1, 2), (256, 2, 0)])
+                                                 (256, 1, 2), (256, 2, 0), (16, 2, 4), (64, 2, 4), (128, 4, 4)])
 def test_one_step_parity_launch_shapes(snk, stream, lanes, unroll, layout):
     """Every contour group size (several contours per wave, one wave, 2 and 4 waves per contour),
     one, two or four pair-points in flight, and every volume layout."""
@@ -212,12 +212,12 @@ def test_one_step_parity_launch_shapes(snk, stream, lanes, unroll, layout):
 
 
 def test_layouts_bitwise(snk, stream):
-    """The quad records hold exact copies of the volume and the arithmetic is the same, so a free
-    run reads identical results from every layout (same launch shape otherwise)."""
+    """The quad records and column pairs hold exact copies of the volume and the arithmetic is the
+    same, so a free run reads identical results from every layout (same launch shape otherwise)."""
     wl = synth.tiny_config()
-    say("free run tiny: plain vs quad vs 64-bit-addressed plain layout")
+    say("free run tiny: plain vs quad vs 64-bit-addressed plain vs column-pair layout")
     outs = []
-    for layout in (1, 2, 3):
+    for layout in (1, 2, 3, 4):
         ctx = make_ctx(snk, stream, wl, lanes=128, unroll=1, layout=layout)
         ctx.load_seeds(wl.seeds, ids=wl.ids)
         ctx.evolve(wl.n_iter)
@@ -293,7 +293,8 @@ def test_lds_box_bitwise(snk, stream, which):
     """LDS boxes hold exact copies of the volume and the corner arithmetic is unchanged, so a free
     run gives identical results with boxes of any capacity (tiny ones: most iterations read the
     volume; mid-sized ones: iterations switch between box and volume as R changes) and without
-    them, for every whole-wave launch shape; seeds near and on the faces take the clamped path."""
+    them, for every whole-wave launch shape, from quad records and column pairs alike in 3D; seeds
+    near and on the faces take the clamped path."""
     rng = np.random.default_rng(11)
     if which == "tiny":
         wl = synth.tiny_config()
@@ -304,11 +305,11 @@ def test_lds_box_bitwise(snk, stream, which):
     seeds = np.concatenate([wl.seeds, extra_seeds(wl, 24, rng)])
     ids = np.arange(len(seeds), dtype=np.uint32)
     n_iter = min(wl.n_iter, 60)
-    layout = 2 if wl.params.dim == 3 else 1
+    layouts = (2, 4) if wl.params.dim == 3 else (1,)
     for lanes, unroll in ((64, 2), (128, 1), (128, 4), (256, 2)):
         ref = None
-        for tile in (0, 512, 3000, 12000, -1):
-            say(f"lds box {which}: lanes {lanes} pairs {unroll} tile {tile}")
+        for tile, layout in [(t, lay) for t in (0, 512, 3000, 12000, -1) for lay in layouts]:
+            say(f"lds box {which}: lanes {lanes} pairs {unroll} tile {tile} layout {layout}")
             ctx = make_ctx(snk, stream, wl, lanes=lanes, unroll=unroll, layout=layout, tile=tile)
             ctx.load_seeds(seeds, ids=ids)
             ctx.evolve(n_iter)
@@ -551,13 +552,6 @@ def test_edge_cases(snk, stream):
     b = ctx.get_state()
     for k in a:
         assert np.array_equal(a[k], b[k]), k
-    ctx.close()
-    # the column-pair layout is 2D only: a 3D volume refuses it at the next evolve
-    ctx = make_ctx(snk, stream, wl, layout=4)
-    ctx.load_seeds(wl.seeds, ids=wl.ids)
-    with pytest.raises(snk.SnkError) as ex:
-        ctx.evolve(1)
-    assert ex.value.code == snk.SNK_EINVAL and "2D only" in str(ex.value)
     ctx.close()
 
 
