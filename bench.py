@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per contour: 16..256 (0: automatic)")
     ap.add_argument("--unroll", type=int, default=0, help="pair-points in flight per lane (0: automatic)")
-    ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad, 3 plain with 64-bit addressing, 4 column pairs (2D)")
+    ap.add_argument("--layout", type=int, default=0, help="volume layout: 0 auto, 1 plain, 2 quad, 3 plain with 64-bit addressing, 4 column pairs")
     ap.add_argument("--tile", type=int, default=-1,
                     help="LDS box per contour in voxels (-1: automatic, 0: off)")
     ap.add_argument("--exact", action="store_true",
