@@ -362,7 +362,7 @@ snk_status snk_engine_destroy(snk_engine *e);
 const char *snk_engine_last_error(const snk_engine *e);
 
 /* Force the evolve launch shape (lanes per contour 64/128/256, pair-points in flight 1/2,
- * persistent 0/1, layout 0 = quad / 1 = plain / 2 = quad), or lanes = 0 to pick lanes, pair-points
+ * persistent 0/1, layout 0 = column pairs / 1 = plain / 2 = quad), or lanes = 0 to pick lanes, pair-points
  * and persistence per launch class (dim, D, M, L) by timing short trials of every shape. */
 snk_status snk_engine_set_launch(snk_engine *e, int32_t lanes_per_contour, int32_t pairs_in_flight,
                                  int32_t persistent, int32_t layout);

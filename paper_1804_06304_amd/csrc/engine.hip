@@ -10,8 +10,9 @@
 //    per launch class (dim, D, M, L) -> exact energy over all items -> selection, one workgroup per
 //    job. The graph is replayed while the job set is unchanged. The launch shape of each class
 //    (lanes per contour, pair-points in flight, persistent work queue or one workgroup per item) is
-//    picked once by timing short trials of every candidate. Every job keeps its volume in the quad
-//    layout next to the FP32 one; launches read the quad copy unless the plain layout is forced.
+//    picked once by timing short trials of every candidate. Every job keeps its volume in column
+//    pairs (or quad records, on request) next to the FP32 one; launches read that copy unless the
+//    plain layout is forced.
 //  - snk_engine_step (served): continuous batching. Newly admitted jobs get their pre-pass and join
 //    the running set; every running contour advances by at most `chunk` iterations in one launch
 //    per class; jobs whose contours have all stopped are finalised, copied to the host and their
@@ -140,7 +141,7 @@ struct snk_engine {
     // launch shapes
     Launch forced;
     bool force = false;
-    int layout = snk::kBufferQuad;             // volume layout of every evolve launch
+    int layout = snk::kBufferPair;             // volume layout of every evolve launch
     std::map<ClassKey, Launch> tuned;
 
     // captured batched run
@@ -419,7 +420,9 @@ snk_status prepass_job(snk_engine *e, const EJob &j) {
     a.raw = j.d_raw;
     a.dtype = (int)j.dtype;
     a.J = j.d_J;
-    a.Jq = j.d_Jq;
+    // column pairs (8 bytes per voxel) or quad records in the same buffer
+    if (e->layout == snk::kBufferPair) a.Jp = reinterpret_cast<float2 *>(j.d_Jq);
+    else a.Jq = j.d_Jq;
     a.nx = (int)j.nx;
     a.ny = (int)j.ny;
     a.nz = (int)j.nz;
@@ -686,7 +689,7 @@ snk_status snk_engine_set_launch(snk_engine *e, int32_t lanes_per_contour, int32
                                  int32_t persistent, int32_t layout) {
     if (!e) return SNK_EINVAL;
     if (layout < 0 || layout > 2) return efail(e, SNK_EINVAL, "layout in {0,1,2}");
-    const int lay = layout == 1 ? snk::kBufferPlain : snk::kBufferQuad;
+    const int lay = layout == 1 ? snk::kBufferPlain : (layout == 2 ? snk::kBufferQuad : snk::kBufferPair);
     if (lay != e->layout) {
         e->layout = lay;
         e->tuned.clear();
@@ -1019,7 +1022,7 @@ snk_status snk_engine_get_stats(snk_engine *e, snk_engine_stats *s) {
     s->lanes_per_contour = e->last_launch.lanes;
     s->pairs_in_flight = e->last_launch.unroll;
     s->persistent = e->last_launch.persistent;
-    s->layout = e->layout == snk::kBufferPlain ? 1 : 2;
+    s->layout = e->layout == snk::kBufferPlain ? 1 : (e->layout == snk::kBufferQuad ? 2 : 0);
     s->graph_replays = e->graph_replays;
     return SNK_OK;
 }

@@ -1474,6 +1474,7 @@ hipError_t batch_p(const BatchArgs &a, bool persistent, int grid, hipStream_t s)
 
 template <int DIM, int G, int U>
 hipError_t batch_l(const BatchArgs &a, int layout, bool persistent, int grid, hipStream_t s) {
+    if (layout == kBufferPair) return batch_p<DIM, G, U, kBufferPair>(a, persistent, grid, s);
     return layout == kBufferQuad ? batch_p<DIM, G, U, kBufferQuad>(a, persistent, grid, s)
                                  : batch_p<DIM, G, U, kBufferPlain>(a, persistent, grid, s);
 }
@@ -1512,9 +1513,12 @@ int max_blocks_s(int max_M, int tile_cap) {
 
 template <int DIM, int G>
 int max_blocks_u(int unroll, int layout, int max_M, int tile_cap) {
-    if (unroll >= 2)
+    if (unroll >= 2) {
+        if (layout == kBufferPair) return max_blocks_s<DIM, G, 2, kBufferPair>(max_M, tile_cap);
         return layout == kBufferQuad ? max_blocks_s<DIM, G, 2, kBufferQuad>(max_M, tile_cap)
                                      : max_blocks_s<DIM, G, 2, kBufferPlain>(max_M, tile_cap);
+    }
+    if (layout == kBufferPair) return max_blocks_s<DIM, G, 1, kBufferPair>(max_M, tile_cap);
     return layout == kBufferQuad ? max_blocks_s<DIM, G, 1, kBufferQuad>(max_M, tile_cap)
                                  : max_blocks_s<DIM, G, 1, kBufferPlain>(max_M, tile_cap);
 }
@@ -2033,7 +2037,7 @@ hipError_t launch_evolve(const EvolveArgs &a, int dim, int lanes, int unroll, in
 hipError_t launch_evolve_batch(const BatchArgs &a, int dim, int lanes, int unroll, int layout, bool persistent,
                                int grid, hipStream_t s) {
     if (a.n_items <= 0 || a.chunk <= 0) return hipSuccess;
-    if (layout != kBufferQuad && layout != kBufferPlain) return hipErrorInvalidValue;
+    if (layout != kBufferQuad && layout != kBufferPlain && layout != kBufferPair) return hipErrorInvalidValue;
     if (dim == 2) return batch_g<2>(a, lanes, unroll, layout, persistent, grid, s);
     return batch_g<3>(a, lanes, unroll, layout, persistent, grid, s);
 }
